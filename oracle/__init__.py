@@ -1,0 +1,278 @@
+"""FP64 CPU oracle of the laser-cluster MD step (test infrastructure only).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import this
+package.  It shares no code with the GPU library (``paper_1307_3711_amd``): the C core
+``lc_oracle.c`` and the unit conversions in ``units.py`` are written separately, and the
+only common input is what ``workloads`` generates.
+
+Parity status: every step is pinned by tests in ``tests/test_oracle_*.py`` against closed
+forms, invariants, brute force at high precision or library routines (see each test's
+docstring).  The absolute physics outputs the paper plots (ion energy spectra, charge-state
+fractions) are not available, so agreement with the paper's figures is not pinned.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+from . import units
+from workloads.species import SPECIES
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lc_oracle.c")
+_LIB = os.path.join(_HERE, "liblc_oracle.so")
+
+ENVELOPES = {"gauss_field": 0, "gauss_intensity": 1, "sin2": 2, "flat": 3}
+PHASES = {"dipole": 0, "plane_wave": 1}
+OFI = {"laser_only": 0, "local": 1}
+MAX_Z = 16
+REC = 48
+
+# record field indices (see lc_oracle.c)
+R_T, R_STEP, R_N, R_NION, R_NEL = 0, 1, 2, 3, 4
+R_KE_HALF, R_KE_BAR, R_PE, R_WL, R_WC, R_WSP = 5, 6, 7, 8, 9, 10
+R_P, R_F, R_FABS, R_MEANZ, R_ABS_EV, R_DROPPED, R_EVENTS, R_ENV = 11, 14, 17, 18, 19, 20, 21, 22
+R_ZHIST = 24
+
+
+def build(force=False):
+    """Compile the oracle with g++-free plain C: gcc -O2 -fopenmp -ffp-contract=off."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+           "-std=gnu11", "-o", tmp, _SRC, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("dt", ctypes.c_double), ("t0", ctypes.c_double), ("eps2", ctypes.c_double),
+        ("kappa", ctypes.c_double), ("a0", ctypes.c_double),
+        ("envelope", ctypes.c_int32), ("phase", ctypes.c_int32),
+        ("tau", ctypes.c_double), ("t_sin2", ctypes.c_double),
+        ("weight", ctypes.c_double), ("mass_ion", ctypes.c_double),
+        ("ionize", ctypes.c_int32), ("ofi_field", ctypes.c_int32),
+        ("z_max", ctypes.c_int32), ("diag_every", ctypes.c_int32),
+        ("ip_au", ctypes.c_double * MAX_Z),
+        ("field_au", ctypes.c_double), ("rate_scale", ctypes.c_double),
+        ("delta", ctypes.c_double), ("n_atoms", ctypes.c_double), ("mec2_ev", ctypes.c_double),
+        ("seed", ctypes.c_uint64), ("cluster", ctypes.c_uint64), ("n_ion", ctypes.c_int64),
+    ]
+
+
+_lib_handle = None
+
+
+def lib():
+    global _lib_handle
+    if _lib_handle is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        i8p = ctypes.POINTER(ctypes.c_int8)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        pp = ctypes.POINTER(Params)
+        L.or_philox4x64_10.argtypes = [u64p, u64p, u64p]
+        L.or_u01.argtypes = [ctypes.c_uint64]
+        L.or_u01.restype = ctypes.c_double
+        L.or_adk_rate.argtypes = [ctypes.c_double] * 3
+        L.or_adk_rate.restype = ctypes.c_double
+        L.or_envelope.argtypes = [pp, ctypes.c_double]
+        L.or_envelope.restype = ctypes.c_double
+        L.or_laser.argtypes = [pp, ctypes.c_double, ctypes.c_double, dp, dp]
+        L.or_boris_push.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
+        L.or_coulomb_field.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, dp, dp, dp, dp]
+        L.or_start.argtypes = [pp, ctypes.c_int64, dp, dp, dp, dp, dp, dp, i8p, dp]
+        L.or_start.restype = ctypes.c_double
+        L.or_run.argtypes = [pp, ctypes.c_int64, i64p, dp, dp, dp, dp, dp, dp, i8p, dp, dp, dp,
+                             ctypes.c_int64, ctypes.c_int64, dp, dp, dp, ctypes.c_int64]
+        L.or_run.restype = ctypes.c_int64
+        L.or_state_field.argtypes = [pp, ctypes.c_int64, dp, dp, dp, i8p, dp, dp, dp, dp, dp]
+        _lib_handle = L
+    return _lib_handle
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# ----------------------------------------------------------------------------- primitives
+
+def philox4x64_10(key, ctr):
+    """Philox4x64-10 of one counter block: key (2 words), counter (4 words) -> 4 words."""
+    k = (ctypes.c_uint64 * 2)(*[int(v) & (2**64 - 1) for v in key])
+    c = (ctypes.c_uint64 * 4)(*[int(v) & (2**64 - 1) for v in ctr])
+    o = (ctypes.c_uint64 * 4)()
+    lib().or_philox4x64_10(k, c, o)
+    return [int(v) for v in o]
+
+
+def u01(x):
+    return lib().or_u01(ctypes.c_uint64(int(x)))
+
+
+def adk_rate(ip_au, zc, f_au):
+    """Static ADK rate (atomic units) of a level with potential ip_au and residual charge zc."""
+    return lib().or_adk_rate(float(ip_au), float(zc), float(f_au))
+
+
+def boris_push(zm, dt, E, B, u):
+    E = np.ascontiguousarray(E, np.float64)
+    B = np.ascontiguousarray(B, np.float64)
+    u = np.ascontiguousarray(u, np.float64)
+    out = np.zeros(3)
+    lib().or_boris_push(float(zm), float(dt), _dp(E), _dp(B), _dp(u), _dp(out))
+    return out
+
+
+def coulomb_field(x, q, eps2, want_phi=True):
+    """Direct-sum softened field of sources q (field units) at positions x (n x 3)."""
+    x = np.ascontiguousarray(x, np.float64)
+    n = x.shape[0]
+    xs = [np.ascontiguousarray(x[:, k]) for k in range(3)]
+    q = np.ascontiguousarray(q, np.float64)
+    e = [np.zeros(n) for _ in range(3)]
+    phi = np.zeros(n) if want_phi else None
+    lib().or_coulomb_field(n, _dp(xs[0]), _dp(xs[1]), _dp(xs[2]), _dp(q), float(eps2), _dp(e[0]),
+                           _dp(e[1]), _dp(e[2]), _dp(phi) if want_phi else None)
+    return np.stack(e, axis=1), phi
+
+
+# ----------------------------------------------------------------------------- parameters
+
+def make_params(cluster, run, cluster_index=0, weight=None, **override):
+    """Dimensionless parameters of one cluster from its physical description."""
+    lam = cluster.laser.lambda_um
+    sp = SPECIES[cluster.species]
+    p = Params()
+    p.dt = run.dt
+    p.t0 = run.t0
+    p.eps2 = units.nm_to_norm(run.softening_nm, lam) ** 2
+    p.kappa = units.kappa(lam)
+    p.a0 = units.a0_from_intensity(cluster.laser.intensity_wcm2, lam)
+    p.envelope = ENVELOPES[cluster.laser.envelope]
+    p.phase = PHASES[cluster.laser.phase]
+    p.tau = units.fs_to_norm(cluster.laser.fwhm_fs, lam)
+    p.t_sin2 = 2.0 * np.pi * cluster.laser.n_cycles
+    natoms = units.n_atoms(cluster.r0_nm, sp["rw_angstrom"])
+    p.weight = natoms / cluster.n_ion if weight is None else weight
+    p.mass_ion = sp["mass_u"] * units.U_PER_ME
+    p.ionize = 1 if run.ionize else 0
+    p.ofi_field = OFI[run.ofi_field]
+    if cluster.z_max > MAX_Z:
+        raise ValueError("z_max above the oracle's table size")
+    p.z_max = cluster.z_max
+    p.diag_every = run.diag_every
+    for k in range(MAX_Z):
+        p.ip_au[k] = units.ev_to_hartree(sp["ip_ev"][k]) if k < len(sp["ip_ev"]) else 0.0
+    p.field_au = units.field_au_per_a0(lam)
+    p.rate_scale = units.rate_scale(lam)
+    p.delta = units.nm_to_norm(cluster.electron_offset_nm, lam)
+    p.n_atoms = natoms
+    p.mec2_ev = units.MEC2_EV
+    p.seed = run.seed
+    p.cluster = cluster_index
+    p.n_ion = cluster.n_ion
+    for k, v in override.items():
+        setattr(p, k, v)
+    return p
+
+
+def envelope(p, t):
+    return lib().or_envelope(ctypes.byref(p), float(t))
+
+
+def laser(p, t, z=0.0):
+    E = np.zeros(3)
+    B = np.zeros(3)
+    lib().or_laser(ctypes.byref(p), float(t), float(z), _dp(E), _dp(B))
+    return E, B
+
+
+# ----------------------------------------------------------------------------- simulation
+
+class Sim:
+    """One cluster integrated by the oracle.  State arrays are in dimensionless units."""
+
+    def __init__(self, params, capacity, x, u, Z):
+        self.p = params
+        self.cap = int(capacity)
+        n = x.shape[0]
+        if n > self.cap:
+            raise ValueError("state larger than capacity")
+        self.n = ctypes.c_int64(n)
+        self.x = [np.zeros(self.cap) for _ in range(3)]
+        self.u = [np.zeros(self.cap) for _ in range(3)]
+        for k in range(3):
+            self.x[k][:n] = x[:, k]
+            self.u[k][:n] = u[:, k]
+        self.Z = np.zeros(self.cap, np.int8)
+        self.Z[:n] = Z
+        self.wl = np.zeros(self.cap)
+        self.wc = np.zeros(self.cap)
+        self.wsp = np.zeros(self.cap)
+        self.work = np.zeros(7 * self.cap)
+        self.counters = np.zeros(2)
+        self.step_index = 0
+        self.ke_start = None
+
+    @classmethod
+    def from_workload(cls, cluster, run, state, cluster_index=0, **override):
+        p = make_params(cluster, run, cluster_index, **override)
+        x = units.nm_to_norm(np.asarray(state["x_nm"], np.float64), cluster.laser.lambda_um)
+        return cls(p, cluster.capacity, x, np.asarray(state["u"], np.float64), state["Z"])
+
+    def start(self):
+        """Leap-frog start (backward half kick); returns KE at t0 - dt/2."""
+        n = self.n.value
+        i8p = ctypes.POINTER(ctypes.c_int8)
+        self.ke_start = lib().or_start(ctypes.byref(self.p), n, _dp(self.x[0]), _dp(self.x[1]),
+                                       _dp(self.x[2]), _dp(self.u[0]), _dp(self.u[1]), _dp(self.u[2]),
+                                       self.Z.ctypes.data_as(i8p), _dp(self.work))
+        return self.ke_start
+
+    def run(self, nsteps):
+        """Advance nsteps; returns the diagnostic records written (k x REC array)."""
+        i8p = ctypes.POINTER(ctypes.c_int8)
+        de = self.p.diag_every
+        max_rec = (nsteps // de + 2) if de > 0 else 0
+        rec = np.zeros((max(max_rec, 1), REC))
+        k = lib().or_run(ctypes.byref(self.p), self.cap, ctypes.byref(self.n), _dp(self.x[0]),
+                         _dp(self.x[1]), _dp(self.x[2]), _dp(self.u[0]), _dp(self.u[1]),
+                         _dp(self.u[2]), self.Z.ctypes.data_as(i8p), _dp(self.wl), _dp(self.wc),
+                         _dp(self.wsp), self.step_index, nsteps, _dp(self.work), _dp(self.counters),
+                         _dp(rec), max_rec)
+        self.step_index += nsteps
+        return rec[:k]
+
+    def field(self):
+        """Coulomb field and potential of the current state."""
+        n = self.n.value
+        i8p = ctypes.POINTER(ctypes.c_int8)
+        q = np.zeros(n)
+        e = [np.zeros(n) for _ in range(3)]
+        phi = np.zeros(n)
+        lib().or_state_field(ctypes.byref(self.p), n, _dp(self.x[0]), _dp(self.x[1]), _dp(self.x[2]),
+                             self.Z.ctypes.data_as(i8p), _dp(q), _dp(e[0]), _dp(e[1]), _dp(e[2]),
+                             _dp(phi))
+        return np.stack(e, axis=1), phi
+
+    @property
+    def N(self):
+        return self.n.value
+
+    def positions(self):
+        n = self.n.value
+        return np.stack([a[:n] for a in self.x], axis=1)
+
+    def momenta(self):
+        n = self.n.value
+        return np.stack([a[:n] for a in self.u], axis=1)
+
+    def charges(self):
+        return self.Z[: self.n.value].copy()
