@@ -1,0 +1,164 @@
+"""Benchmark: whole time steps of one argon cluster of 20k macroparticles on one MI355X.
+
+Workload (synthetic, seeded): Ar cluster, R0 = 8 nm, 10,000 Ar+ + 10,000 electrons at
+0.01 nm, 1e16 W/cm^2 at 800 nm, 30 fs FWHM Gaussian (Eq.(3)), dt = 0.05/w, softening
+0.1 nm, charges frozen so the count stays 20k.  A step is one pass of the whole path: laser
+value, Coulomb direct sum, Boris push, diagnostics every 100 steps (the ionization check is
+not launched because ionization is off in this workload).
+
+Prints one JSON line: G pair-interactions/s of the FP32+FP64-accumulation path (value), the
+FP64 path on the same steps, the error between them, the Coulomb kernel's roofline figures
+from HIP events recorded around its launches, and the FP64 CPU oracle timed on a bounded
+sample of the same workload on this host's cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOPS_PER_PAIR = 20.0          # N-body convention for one softened pair interaction
+FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector (published)
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector (published)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_sim(precision, c, run, st, graph):
+    import paper_1307_3711_amd as lc
+    from workloads.species import SPECIES
+    cfg = lc.make_config(precision, ionize=run.ionize, dt=run.dt, softening_nm=run.softening_nm,
+                         diag_every=run.diag_every, max_records=256, max_splits=64, seed=run.seed)
+    desc = lc.make_cluster(SPECIES[c.species], c.r0_nm, c.n_ion, c.capacity, c.laser.intensity_wcm2,
+                           envelope=c.laser.envelope, fwhm_fs=c.laser.fwhm_fs, z_max=c.z_max,
+                           electron_offset_nm=c.electron_offset_nm)
+    sim = lc.Simulation(cfg, [desc])
+    sim.init_from_host(0, st["x_nm"], st["u"], st["Z"])
+    sim.start()
+    tuned = sim.autotune()
+    if graph:
+        sim.set_graph(graph)
+    return sim, tuned
+
+
+def timed_steps(sim, steps):
+    import torch
+    sim.stream.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.stream.synchronize()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(c, run, st, n, target_s=15.0):
+    """The FP64 oracle, as it is, on a bounded number of steps of the same workload."""
+    import oracle
+    osim = oracle.Sim.from_workload(c, run, st)
+    osim.start()
+    t0 = time.perf_counter()
+    osim.run(1)
+    t1 = time.perf_counter() - t0
+    k = max(1, min(200, int(target_s / max(t1, 1e-6))))
+    t0 = time.perf_counter()
+    osim.run(k)
+    dt = time.perf_counter() - t0
+    return {"value": k * n * n / dt / 1e9, "unit": "Gpair/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{k} steps of the same 20k-macroparticle state after 1 calibration step "
+                      f"(FP64, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--profile-steps", type=int, default=400)
+    ap.add_argument("--graph", type=int, default=100)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1307_3711_amd as lc
+    from workloads import ar_20k, initial_state
+
+    c, run = ar_20k()
+    st = initial_state(c, run.seed)
+    n = st["x_nm"].shape[0]
+    pairs = float(n) * float(n)
+
+    log(f"bench: {n} macroparticles, fp32_acc64, autotune")
+    sim, tuned = make_sim("fp32_acc64", c, run, st, args.graph)
+    log(f"bench: tiling {tuned}; warmup {args.warmup}")
+    sim.step(args.warmup)
+    sim.stream.synchronize()
+    log(f"bench: timing {args.steps} steps")
+    wall = timed_steps(sim, args.steps)
+    log(f"bench: {wall:.3f} s; profiling {args.profile_steps} steps")
+    prof = sim.profile_steps(args.profile_steps)
+    rec32 = sim.diagnostics(0)
+    force_ms, force_n = prof["field"]
+    avg_force_s = force_ms / max(force_n, 1) * 1e-3
+    achieved = FLOPS_PER_PAIR * pairs / avg_force_s / 1e12
+    value = args.steps * pairs / wall / 1e9
+    out = {
+        "metric": "G pair-interactions/s (FP32 pair math + FP64 accumulation), one Ar cluster",
+        "value": round(value, 3), "unit": "Gpair/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "fp32+fp64acc", "data": "synthetic",
+        "config": {"workload": "Ar cluster R0=8nm, 20k macroparticles (10k Ar+ + 10k e-), 1e16 W/cm2, "
+                               "30 fs Gaussian, dt=0.05, softening 0.1 nm, charges frozen",
+                   "n_particles": n, "pairs_per_step": pairs, "tiling": tuned, "graph_steps": args.graph},
+        "cluster_steps_per_s": round(args.steps / wall, 2),
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                     "kernel": "k_force_f32", "avg_launch_ms": round(avg_force_s * 1e3, 5),
+                     "launches": force_n, "flops_per_pair": FLOPS_PER_PAIR},
+        "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 5) for k, v in prof.items() if v[1]},
+    }
+    total_steps = args.warmup + args.steps + args.profile_steps
+    if not args.no_fp64:
+        log("bench: fp64 path on the same steps")
+        sim64, tuned64 = make_sim("fp64", c, run, st, args.graph)
+        sim64.step(args.warmup)
+        wall64 = timed_steps(sim64, args.steps)
+        prof64 = sim64.profile_steps(args.profile_steps)
+        rec64 = sim64.diagnostics(0)
+        f64_ms, f64_n = prof64["field"]
+        ach64 = FLOPS_PER_PAIR * pairs / (f64_ms / max(f64_n, 1) * 1e-3) / 1e12
+        p32 = sim.particles(0)
+        p64 = sim64.particles(0)
+        r0n = c.r0_nm * lc.units(0.8)["k_per_nm"]
+        last32, last64 = rec32[-1], rec64[-1]
+
+        def rel(col):
+            return float(abs(last32[col] - last64[col]) / max(abs(last64[col]), 1e-300))
+
+        out["fp64"] = {"value": round(args.steps * pairs / wall64 / 1e9, 3), "unit": "Gpair/s",
+                       "ms_per_step": round(wall64 / args.steps * 1e3, 5), "tiling": tuned64,
+                       "roofline": {"bound": "alu", "achieved": round(ach64, 3), "peak": FP64_PEAK_TFLOPS,
+                                    "unit": "TFLOP/s", "frac": round(ach64 / FP64_PEAK_TFLOPS, 4)}}
+        out["error_vs_fp64"] = {"after_steps": total_steps, "t": float(last64[0]),
+                                "max_dx_over_R0": float(np.max(np.abs(p32["x"] - p64["x"])) / r0n),
+                                "rel_KE": rel(lc.R_KE_HALF), "rel_PE": rel(lc.R_PE),
+                                "rel_absorbed_eV_per_atom": rel(lc.R_ABS_EV)}
+    if not args.no_cpu_baseline:
+        log("bench: cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(c, run, st, n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

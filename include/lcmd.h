@@ -1,0 +1,232 @@
+/*
+ * lcmd.h -- C ABI of the MI355X laser-cluster molecular-dynamics library (liblcmd.so).
+ *
+ * Method: A. R. Holkundkar, "Parallel Implementation of 3D Molecular Dynamic Simulation
+ * for Laser-Cluster Interaction" (arXiv:1307.3711), Sec. II.  One time step of a cluster
+ * is: the Coulomb field on every macroparticle from every other charged macroparticle,
+ * the laser field of Eqs.(4)-(9) under the Eq.(3) envelope in the dipole approximation, a
+ * relativistic Boris push, and the Monte-Carlo optical-field-ionization check with the
+ * ADK rate (P = 1 - exp(-nu dt) against a uniform draw 0 < alpha <= 1), which spawns an
+ * electron next to each ionized atom.  Units are the paper's: fields in a0 = eE/(m_e w c)
+ * (b0 = a0), time in 1/w, length in c/w, momentum u = gamma v / c, energy in m_e c^2.
+ *
+ * Conventions for every entry point:
+ *   - Return value: LC_OK (0) or a negative lc_status.  No exceptions cross the ABI.
+ *     lc_last_error() gives a text for the last failure on a handle.
+ *   - Device memory is owned by the caller.  The library never allocates device memory:
+ *     the caller queries lc_state_bytes(), allocates that many bytes (any allocator; 256-B
+ *     alignment) and passes the pointer to lc_create(); lc_field() takes a caller-owned
+ *     workspace sized by lc_field_workspace_bytes().  Host pointers stay owned by the
+ *     caller and are only read or written during the call.
+ *   - Work is enqueued asynchronously on the HIP stream given at creation (a hipStream_t
+ *     passed as void*; NULL is the null stream).  Only lc_read_* and lc_autotune
+ *     synchronize that stream.
+ *   - Device-side failures (capacity overflow, non-finite state) are latched in device
+ *     flags and reported by the next synchronizing call.
+ *   - A handle is not thread-safe; use one handle per stream.
+ */
+#ifndef LCMD_H
+#define LCMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LC_API_VERSION 1
+#define LC_MAX_Z 16       /* size of the per-charge tables (charge states 0..15)        */
+#define LC_REC 48         /* doubles per diagnostic record                              */
+
+typedef enum {
+  LC_OK = 0,
+  LC_E_INVALID = -1,      /* bad argument or configuration                               */
+  LC_E_CAPACITY = -2,     /* a cluster ran out of slots for spawned electrons            */
+  LC_E_NONFINITE = -3,    /* a position or momentum became NaN/Inf                       */
+  LC_E_HIP = -4,          /* a HIP runtime call failed                                   */
+  LC_E_STATE = -5,        /* call out of order (e.g. step before start)                  */
+  LC_E_UNSUPPORTED = -6   /* valid request this build does not implement                 */
+} lc_status;
+
+/* Pair arithmetic of the Coulomb direct sum. */
+typedef enum {
+  LC_FP64 = 0,            /* FP64 everywhere                                             */
+  LC_FP32_ACC64 = 1,      /* FP32 pair terms, FP32 partial sums per source tile, FP64
+                             accumulation across tiles; FP64 push and diagnostics         */
+  LC_FP32_KAHAN = 2       /* as LC_FP32_ACC64 with Kahan-compensated FP32 partial sums    */
+} lc_precision;
+
+/* Envelope of the laser field amplitude a(t). */
+typedef enum {
+  LC_GAUSS_FIELD = 0,     /* Eq.(3) as printed: a0 exp[-2.77 (t - 2 tau)^2 / tau^2]       */
+  LC_GAUSS_INTENSITY = 1, /* same with exponent 1.385 (tau is the intensity FWHM)         */
+  LC_SIN2 = 2,            /* a0 sin^2(pi t / T), T = n_cycles * 2 pi, zero outside [0, T]  */
+  LC_FLAT = 3             /* a0                                                          */
+} lc_envelope;
+
+typedef enum {
+  LC_DIPOLE = 0,          /* field depends on time only (Sec. II dipole approximation)    */
+  LC_PLANE_WAVE = 1       /* test mode: phase t - z, wave along +z; ionization must be off */
+} lc_phase;
+
+typedef enum {
+  LC_LASER_ONLY = 0,      /* ADK driven by the laser field strength (Sec. II)              */
+  LC_LOCAL = 1            /* ADK driven by |E_Coulomb + E_laser| at the ion                */
+} lc_ofi_field;
+
+/* Run-wide settings. */
+typedef struct {
+  uint32_t struct_size;   /* sizeof(lc_config)                                          */
+  int32_t precision;      /* lc_precision                                               */
+  int32_t ionize;         /* 0: charges frozen; 1: ADK Monte-Carlo ionization each step */
+  int32_t ofi_field;      /* lc_ofi_field                                               */
+  double lambda_um;       /* laser wavelength (micrometres)                             */
+  double dt;              /* time step in 1/w (> 0)                                      */
+  double t0;              /* time of step 0 in 1/w                                       */
+  double softening_nm;    /* Plummer softening length (> 0)                              */
+  int32_t diag_every;     /* one diagnostic record every k steps (0: none)              */
+  int32_t max_records;    /* records kept per cluster (ring buffer)                     */
+  int32_t max_splits;     /* largest source split the tuner may use (1..64)             */
+  int32_t reserved;
+  uint64_t seed;          /* Philox key word 0 (word 1 is the cluster index)            */
+} lc_config;
+
+/* One cluster, in physical units.  Species data (Wigner-Seitz radius, mass, ionization
+ * potentials) is input: the paper lists R_W for D, Ne, Ar and Xe after Eq.(1). */
+typedef struct {
+  double r0_nm;               /* cluster radius                                         */
+  double rw_angstrom;         /* Wigner-Seitz radius: N_atoms = (R0/R_W)^3 (Eq.(1))      */
+  double mass_u;              /* ion mass in atomic mass units                          */
+  double ip_ev[LC_MAX_Z];     /* ionization potential of charge state k -> k+1 (eV)     */
+  double intensity_wcm2;      /* peak intensity; a0 from Eq.(2)                          */
+  int32_t envelope;           /* lc_envelope                                            */
+  int32_t phase;              /* lc_phase                                               */
+  double fwhm_fs;             /* tau of the Gaussian envelopes                          */
+  double n_cycles;            /* length of the sin^2 envelope in laser periods          */
+  int64_t n_ion;              /* ion macroparticles; they occupy slots [0, n_ion)       */
+  int64_t capacity;           /* slots for ions + electrons (spawns included)           */
+  double weight;              /* real particles per macroparticle; 0: N_atoms / n_ion   */
+  int32_t z_max;              /* highest ion charge (<= LC_MAX_Z - 1)                    */
+  int32_t reserved;
+  double electron_offset_nm;  /* distance of a spawned electron from its ion            */
+  int64_t n_steps;            /* the cluster retires after this many steps (0: never)   */
+} lc_cluster;
+
+/* Tiling of the Coulomb kernel (the autotuner's search space).  Zeros mean "default". */
+typedef struct {
+  int32_t targets_per_lane;   /* R: 1, 2, 4 or 8 register-blocked targets per lane      */
+  int32_t waves_per_target;   /* WJ: 1, 2 or 4 waves of a block share targets and split  */
+                              /*     each LDS source tile, then reduce through LDS       */
+  int32_t tile_sources;       /* T: sources staged in LDS per step (256..4096)          */
+  int32_t j_splits;           /* S: source range split over S blocks (partials in HBM)  */
+  int32_t persistent;         /* 1: persistent grid pulling tiles from a device queue   */
+  int32_t reserved[3];
+} lc_tuning;
+
+typedef struct lc_sim lc_sim;
+
+/* ---------------------------------------------------------------- simulation */
+
+/* Bytes of caller-owned device memory lc_create() needs; 0 if the arguments are invalid. */
+size_t lc_state_bytes(const lc_config* cfg, const lc_cluster* clusters, int32_t n_clusters);
+
+/* Create a handle over caller-owned device memory d_state (>= lc_state_bytes bytes) on
+ * stream hip_stream.  Converts units on the host (Eq.(1), Eq.(2), kappa = r_e k, ADK
+ * constants) and uploads the per-cluster tables.  LC_E_INVALID on a bad configuration
+ * (non-positive dt or softening, z_max out of range, capacity < 2 n_ion, ...). */
+int lc_create(lc_sim** out, const lc_config* cfg, const lc_cluster* clusters, int32_t n_clusters,
+              void* d_state, size_t bytes, void* hip_stream);
+
+/* Copy one cluster's initial macroparticles from host memory: n particles, positions
+ * x_nm (n x 3, row-major, nanometres), momenta u (n x 3, gamma v / c), charge numbers Z
+ * (ions >= 0 in slots [0, n_ion), electrons -1 after them).  LC_E_INVALID if n exceeds
+ * the capacity or the ion/electron layout is violated. */
+int lc_init_from_host(lc_sim* sim, int32_t cluster, int64_t n, const double* x_nm, const double* u,
+                      const int8_t* Z);
+
+/* Leap-frog start for every cluster: a field pass at t0, then the backward half kick
+ * u^{-1/2} = u^0 - (Z/M)(dt/2)(E + v^0 x B).  Must follow lc_init_from_host. */
+int lc_start(lc_sim* sim);
+
+/* Enqueue n_steps time steps (field, push, diagnostics every diag_every steps,
+ * ionization).  Asynchronous. */
+int lc_step(lc_sim* sim, int64_t n_steps);
+
+/* Capture steps_per_graph steps into one hipGraph that lc_step replays (0 turns graph
+ * replay off).  Replays are used only where they line up with the diagnostic cadence. */
+int lc_set_graph(lc_sim* sim, int32_t steps_per_graph);
+
+/* Copy up to max_records diagnostic records (LC_REC doubles each, oldest first) of one
+ * cluster to host memory; synchronizes the stream.  Returns a latched device error
+ * (LC_E_CAPACITY, LC_E_NONFINITE) if one occurred.  Record layout:
+ *  0 t  1 step  2 N  3 N_ion  4 N_electron  5 KE(n+1/2)  6 KE(n)  7 PE(n)
+ *  8 W_laser  9 W_coulomb  10 spawn KE  11-13 momentum  14-16 sum w Z E_C  17 sum w|Z||E_C|
+ *  18 mean ion charge  19 absorbed eV per atom  20 dropped spawns  21 ionizations
+ *  22 envelope a(t)  23 KE(-1/2) at start  24..40 macro-ion count per charge 0..16 */
+int lc_read_diagnostics(lc_sim* sim, int32_t cluster, double* records, int32_t max_records,
+                        int32_t* n_out);
+
+/* Copy one cluster's state to host memory (any pointer may be NULL): positions x (n x 3,
+ * units of c/w), momenta u (n x 3), Z (n), cumulative laser and Coulomb work per particle
+ * wl, wc (n each).  cap bounds the rows written; *n_out receives the live count.
+ * Synchronizes the stream. */
+int lc_read_particles(lc_sim* sim, int32_t cluster, double* x, double* u, int8_t* Z, double* wl,
+                      double* wc, int64_t cap, int64_t* n_out);
+
+/* Current time-step index (host mirror of the device counter). */
+int64_t lc_step_index(const lc_sim* sim);
+
+/* Set or read the Coulomb kernel tiling used by this handle. */
+int lc_set_tuning(lc_sim* sim, const lc_tuning* t);
+int lc_get_tuning(const lc_sim* sim, lc_tuning* t);
+
+/* Time candidate tilings of the Coulomb kernel on the handle's current state (restoring
+ * it afterwards), keep the fastest one whose field matches the default tiling's to the
+ * precision's tolerance, and append the result to cache_json (may be NULL).  Synchronizes
+ * the stream. */
+int lc_autotune(lc_sim* sim, const char* cache_json, lc_tuning* chosen);
+
+/* Run n_steps steps directly (no graph) with HIP events recorded on the handle's stream
+ * around each kernel group, and return per group the summed device time in ms and the
+ * number of launches: index 0 the Coulomb kernel, 1 push, 2 diagnostics, 3 ionization.  Advances the simulation like lc_step.  Synchronizes the stream. */
+int lc_profile_steps(lc_sim* sim, int64_t n_steps, double out_ms[4], int64_t out_launches[4]);
+
+/* Write the whole device state and step index to a file / restore it into a handle
+ * created with the same configuration.  Synchronize the stream. */
+int lc_save_state(lc_sim* sim, const char* path);
+int lc_load_state(lc_sim* sim, const char* path);
+
+void lc_destroy(lc_sim* sim);
+
+/* ---------------------------------------------------------------- the field alone */
+
+/* Workspace bytes for lc_field with n particles, a precision and a tiling (NULL: default). */
+size_t lc_field_workspace_bytes(int32_t precision, int64_t n, const lc_tuning* t);
+
+/* Softened Coulomb field of n point sources on themselves (Sec. II force from every other
+ * charged particle; Plummer softening eps):
+ *   E_i = sum_{j != i} q_j (r_i - r_j) / (|r_i - r_j|^2 + eps^2)^{3/2}
+ *   phi_i = sum_{j != i} q_j / (|r_i - r_j|^2 + eps^2)^{1/2}        (if d_phi != NULL)
+ * d_xyzq: device, 4 n doubles laid out x[n], y[n], z[n], q[n] (q in field units).
+ * d_E: device, 3 n doubles out, laid out Ex[n], Ey[n], Ez[n].  d_work: caller-owned device
+ * workspace of at least lc_field_workspace_bytes().  Asynchronous on hip_stream.
+ * LC_E_INVALID for n < 0, eps2 <= 0, a too small workspace or an unknown tiling. */
+int lc_field(int32_t precision, int64_t n, const double* d_xyzq, double eps2, double* d_E,
+             double* d_phi, void* d_work, size_t work_bytes, const lc_tuning* t, void* hip_stream);
+
+/* ---------------------------------------------------------------- constants and errors */
+
+/* Unit conversions the library uses (for cross-checks): out[0] kappa = r_e k,
+ * out[1] atomic field units per a0, out[2] rate scale (1/w per atomic time unit),
+ * out[3] a0 from Eq.(2) for intensity_wcm2, out[4] k in 1/nm, out[5] m_e c^2 in eV. */
+int lc_units(double lambda_um, double intensity_wcm2, double out[6]);
+
+const char* lc_error_string(int code);
+const char* lc_last_error(const lc_sim* sim);
+int lc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LCMD_H */

@@ -87,14 +87,22 @@ def lib():
         L.or_laser.argtypes = [pp, ctypes.c_double, ctypes.c_double, dp, dp]
         L.or_boris_push.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
         L.or_coulomb_field.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, dp, dp, dp, dp]
+        L.or_coulomb_field_at.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int64,
+                                          i64p, dp, dp, dp, dp]
         L.or_start.argtypes = [pp, ctypes.c_int64, dp, dp, dp, dp, dp, dp, i8p, dp]
         L.or_start.restype = ctypes.c_double
         L.or_run.argtypes = [pp, ctypes.c_int64, i64p, dp, dp, dp, dp, dp, dp, i8p, dp, dp, dp,
                              ctypes.c_int64, ctypes.c_int64, dp, dp, dp, ctypes.c_int64]
         L.or_run.restype = ctypes.c_int64
         L.or_state_field.argtypes = [pp, ctypes.c_int64, dp, dp, dp, i8p, dp, dp, dp, dp, dp]
+        L.or_threads.restype = ctypes.c_int
         _lib_handle = L
     return _lib_handle
+
+
+def threads():
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().or_threads())
 
 
 def _dp(a):
@@ -140,6 +148,22 @@ def coulomb_field(x, q, eps2, want_phi=True):
     phi = np.zeros(n) if want_phi else None
     lib().or_coulomb_field(n, _dp(xs[0]), _dp(xs[1]), _dp(xs[2]), _dp(q), float(eps2), _dp(e[0]),
                            _dp(e[1]), _dp(e[2]), _dp(phi) if want_phi else None)
+    return np.stack(e, axis=1), phi
+
+
+def coulomb_field_at(x, q, eps2, idx, want_phi=True):
+    """The direct sum evaluated at the targets idx only (sampled checks of large states)."""
+    x = np.ascontiguousarray(x, np.float64)
+    n = x.shape[0]
+    xs = [np.ascontiguousarray(x[:, k]) for k in range(3)]
+    q = np.ascontiguousarray(q, np.float64)
+    idx = np.ascontiguousarray(idx, np.int64)
+    m = idx.shape[0]
+    e = [np.zeros(m) for _ in range(3)]
+    phi = np.zeros(m) if want_phi else None
+    lib().or_coulomb_field_at(n, _dp(xs[0]), _dp(xs[1]), _dp(xs[2]), _dp(q), float(eps2), m,
+                              idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(e[0]), _dp(e[1]),
+                              _dp(e[2]), _dp(phi) if want_phi else None)
     return np.stack(e, axis=1), phi
 
 

@@ -24,6 +24,7 @@
  *   or_philox4x64_10  - Philox4x64-10 counter-based generator (Salmon et al., SC'11).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <string.h>
 
@@ -126,6 +127,36 @@ void or_coulomb_field(int64_t n, const double* x, const double* y, const double*
     ey[i] = sy;
     ez[i] = sz;
     if (phi) phi[i] = sp;
+  }
+}
+
+/* The same sum evaluated only at the m targets listed in idx (for sampled checks of large
+ * states); outputs are indexed by position in idx. */
+void or_coulomb_field_at(int64_t n, const double* x, const double* y, const double* z, const double* q,
+                         double eps2, int64_t m, const int64_t* idx, double* ex, double* ey, double* ez,
+                         double* phi) {
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < m; ++k) {
+    int64_t i = idx[k];
+    double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      double dx = x[i] - x[j];
+      double dy = y[i] - y[j];
+      double dz = z[i] - z[j];
+      double r2 = dx * dx + dy * dy + dz * dz + eps2;
+      double inv = 1.0 / sqrt(r2);
+      double inv3 = inv * inv * inv;
+      double s = q[j] * inv3;
+      sx += s * dx;
+      sy += s * dy;
+      sz += s * dz;
+      sp += q[j] * inv;
+    }
+    ex[k] = sx;
+    ey[k] = sy;
+    ez[k] = sz;
+    if (phi) phi[k] = sp;
   }
 }
 
@@ -455,4 +486,5 @@ void or_state_field(const or_params* p, int64_t n, const double* x, const double
 }
 
 int or_record_size(void) { return OR_REC; }
+int or_threads(void) { return omp_get_max_threads(); }
 int or_max_z(void) { return OR_MAX_Z; }

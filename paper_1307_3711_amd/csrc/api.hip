@@ -1,0 +1,928 @@
+// api.hip -- host runtime behind the C ABI in include/lcmd.h: validation, unit conversion
+// (Sec. II dimensionless units, Eq.(1), Eq.(2)), carving of the caller-owned device state,
+// the step sequence, hipGraph capture, the Coulomb-kernel autotuner, checkpoints.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "lc_internal.h"
+
+using namespace lc;
+
+namespace {
+
+// CODATA 2018 constants.
+constexpr double kC = 299792458.0;                 // m/s
+constexpr double kRe = 2.8179403262e-15;           // classical electron radius (m)
+constexpr double kMec2Ev = 510998.95000;           // eV
+constexpr double kQe = 1.602176634e-19;            // C
+constexpr double kMe = 9.1093837015e-31;           // kg
+constexpr double kEau = 5.14220674763e11;          // V/m
+constexpr double kTau = 2.4188843265857e-17;       // s
+constexpr double kHartreeEv = 27.211386245988;     // eV
+constexpr double kMuOverMe = 1822.888486209;       // atomic mass unit / electron mass
+constexpr double kEq2 = 1.366e18;                  // Eq.(2)
+constexpr double kPi = 3.14159265358979323846;
+
+struct Units {
+  double k;         // 1/m
+  double omega;     // rad/s
+  double kappa;     // r_e k
+  double field_au;  // atomic field units per a0
+  double rate;      // 1/w per atomic time unit
+};
+
+Units make_units(double lambda_um) {
+  Units u;
+  u.k = 2.0 * kPi / (lambda_um * 1e-6);
+  u.omega = kC * u.k;
+  u.kappa = kRe * u.k;
+  u.field_au = kMe * u.omega * kC / kQe / kEau;
+  u.rate = 1.0 / (u.omega * kTau);
+  return u;
+}
+
+double a0_of(double intensity, double lambda_um) { return std::sqrt(intensity * lambda_um * lambda_um / kEq2); }
+
+size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t x, y, z, ux, uy, uz, wl, wc, wsp, kebar, pos4, posq, Z, cid, part, flag, ib_count, ib_cluster;
+  size_t cp, dyn, order, tile_start, tile_total, queue, err, step, diag_part, records, total;
+  int64_t n_total;
+  int n_ion_blocks;
+};
+
+bool valid_config(const lc_config* cfg, std::string* why) {
+  if (!cfg) { *why = "null config"; return false; }
+  if (cfg->struct_size != sizeof(lc_config)) { *why = "lc_config.struct_size mismatch"; return false; }
+  if (cfg->precision < LC_FP64 || cfg->precision > LC_FP32_KAHAN) { *why = "unknown precision"; return false; }
+  if (!(cfg->lambda_um > 0.0)) { *why = "lambda_um must be > 0"; return false; }
+  if (!(cfg->dt > 0.0) || !std::isfinite(cfg->dt)) { *why = "dt must be > 0"; return false; }
+  if (!(cfg->softening_nm > 0.0)) { *why = "softening_nm must be > 0"; return false; }
+  if (!std::isfinite(cfg->t0)) { *why = "t0 must be finite"; return false; }
+  if (cfg->diag_every < 0) { *why = "diag_every must be >= 0"; return false; }
+  if (cfg->diag_every > 0 && cfg->max_records < 1) { *why = "max_records must be >= 1"; return false; }
+  if (cfg->max_splits < 1 || cfg->max_splits > 64) { *why = "max_splits must be in [1, 64]"; return false; }
+  if (cfg->ionize != 0 && cfg->ionize != 1) { *why = "ionize must be 0 or 1"; return false; }
+  if (cfg->ofi_field != LC_LASER_ONLY && cfg->ofi_field != LC_LOCAL) { *why = "unknown ofi_field"; return false; }
+  return true;
+}
+
+bool valid_cluster(const lc_config* cfg, const lc_cluster& c, std::string* why) {
+  if (!(c.r0_nm > 0.0) || !(c.rw_angstrom > 0.0) || !(c.mass_u > 0.0)) { *why = "r0, rw and mass must be > 0"; return false; }
+  if (!(c.intensity_wcm2 >= 0.0)) { *why = "intensity must be >= 0"; return false; }
+  if (c.envelope < LC_GAUSS_FIELD || c.envelope > LC_FLAT) { *why = "unknown envelope"; return false; }
+  if (c.phase != LC_DIPOLE && c.phase != LC_PLANE_WAVE) { *why = "unknown phase"; return false; }
+  if (c.phase == LC_PLANE_WAVE && cfg->ionize) { *why = "plane-wave phase is a test mode without ionization"; return false; }
+  if ((c.envelope == LC_GAUSS_FIELD || c.envelope == LC_GAUSS_INTENSITY) && !(c.fwhm_fs > 0.0)) { *why = "fwhm_fs must be > 0"; return false; }
+  if (c.envelope == LC_SIN2 && !(c.n_cycles > 0.0)) { *why = "n_cycles must be > 0"; return false; }
+  if (c.n_ion < 0 || c.capacity < 1 || c.capacity < c.n_ion) { *why = "need 0 <= n_ion <= capacity, capacity >= 1"; return false; }
+  if (c.capacity > (int64_t)1 << 30) { *why = "capacity too large"; return false; }
+  if (!(c.weight >= 0.0)) { *why = "weight must be >= 0"; return false; }
+  if (c.weight == 0.0 && c.n_ion == 0) { *why = "weight 0 (automatic) needs n_ion > 0"; return false; }
+  if (c.z_max < 0 || c.z_max > LC_MAX_Z - 1) { *why = "z_max out of range"; return false; }
+  if (!(c.electron_offset_nm >= 0.0)) { *why = "electron_offset_nm must be >= 0"; return false; }
+  if (c.n_steps < 0) { *why = "n_steps must be >= 0"; return false; }
+  return true;
+}
+
+Layout make_layout(const lc_config* cfg, const lc_cluster* cl, int C) {
+  Layout L{};
+  int64_t NT = 0;
+  int ib = 0;
+  for (int c = 0; c < C; ++c) {
+    NT += cl[c].capacity;
+    ib += (int)((cl[c].n_ion + kBlock - 1) / kBlock);
+  }
+  L.n_total = NT;
+  L.n_ion_blocks = ib;
+  size_t p = 0;
+  auto take = [&](size_t bytes) { size_t o = p; p += al(bytes); return o; };
+  const size_t d = sizeof(double) * (size_t)NT;
+  L.x = take(d); L.y = take(d); L.z = take(d);
+  L.ux = take(d); L.uy = take(d); L.uz = take(d);
+  L.wl = take(d); L.wc = take(d); L.wsp = take(d); L.kebar = take(d);
+  L.pos4 = take(cfg->precision == LC_FP64 ? 0 : sizeof(float4) * (size_t)NT);
+  L.posq = take(cfg->precision == LC_FP64 ? sizeof(double4) * (size_t)NT : 0);
+  L.Z = take((size_t)NT);
+  L.cid = take(sizeof(int32_t) * (size_t)NT);
+  L.part = take(sizeof(double) * (size_t)cfg->max_splits * kComp * (size_t)NT);
+  L.flag = take(sizeof(int32_t) * (size_t)NT);
+  L.ib_count = take(sizeof(int32_t) * (size_t)std::max(ib, 1));
+  L.ib_cluster = take(sizeof(int32_t) * (size_t)std::max(ib, 1));
+  L.cp = take(sizeof(ClusterParams) * C);
+  L.dyn = take(sizeof(ClusterDyn) * C);
+  L.order = take(sizeof(int32_t) * C);
+  L.tile_start = take(sizeof(int32_t) * (C + 1));
+  L.tile_total = take(sizeof(int32_t));
+  L.queue = take(sizeof(int32_t));
+  L.err = take(sizeof(int32_t));
+  L.step = take(sizeof(int64_t));
+  L.diag_part = take(sizeof(double) * (size_t)C * kDiagBlocks * kDiagQ);
+  const int mr = cfg->diag_every > 0 ? cfg->max_records : 1;
+  L.records = take(sizeof(double) * (size_t)C * mr * LC_REC);
+  L.total = p;
+  return L;
+}
+
+ForceTiling default_tiling(int precision) {
+  ForceTiling ft;
+  ft.R = (precision == LC_FP64) ? 2 : 4;
+  ft.WJ = 1;
+  ft.T = 1024;
+  ft.S = 0;  // automatic
+  ft.persistent = 0;
+  return ft;
+}
+
+int device_cus() {
+  // queried once (outside any stream capture, at handle creation); one device per process
+  static int cached = 0;
+  if (cached > 0) return cached;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 256;
+  cached = cus;
+  return cus;
+}
+
+__global__ void k_fill_f64(double* p, int64_t n, double v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_i8(int8_t* p, int64_t n, int8_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_set_count(ClusterDyn* dyn, int c, int64_t n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    dyn[c].n_cur = n;
+    dyn[c].n_base = n;
+  }
+}
+
+}  // namespace
+
+struct lc_sim {
+  lc_config cfg;
+  std::vector<lc_cluster> cl;
+  int C = 0;
+  hipStream_t stream = nullptr;
+  Layout L;
+  DevState s;
+  RunConst rc;
+  ForceTiling ft;
+  int S_eff = 1;                   // splits in use
+  std::vector<int64_t> n_host;     // host view of counts (exact when ionization is off)
+  std::vector<int> inited;
+  std::vector<int32_t> order;
+  int64_t step = 0;
+  bool started = false;
+  int graph_steps = 0;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  std::string last_error;
+  Units u;
+};
+
+namespace {
+
+int fail(lc_sim* s, int code, const std::string& msg) {
+  if (s) s->last_error = msg;
+  return code;
+}
+
+int hip_fail(lc_sim* s, hipError_t e, const char* where) {
+  return fail(s, LC_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+int choose_splits(const lc_sim* s, const ForceTiling& ft) {
+  if (ft.S > 0) return std::min(ft.S, s->cfg.max_splits);
+  const int TI = force_tile_targets(ft);
+  int64_t tiles = 0;
+  for (int c = 0; c < s->C; ++c) tiles += (std::max<int64_t>(s->n_host[c], 1) + TI - 1) / TI;
+  const int64_t want = 4LL * device_cus();
+  int S = (int)std::min<int64_t>(s->cfg.max_splits, std::max<int64_t>(1, (want + tiles - 1) / tiles));
+  return S;
+}
+
+int force_grid(const lc_sim* s, const ForceTiling& ft) {
+  const int TI = force_tile_targets(ft);
+  if (ft.persistent) return device_cus() * 4;
+  int64_t tiles = 0;
+  for (int c = 0; c < s->C; ++c) {
+    const int64_t n = s->cfg.ionize ? s->cl[c].capacity : s->n_host[c];
+    tiles += (std::max<int64_t>(n, 1) + TI - 1) / TI;
+  }
+  return (int)std::min<int64_t>(tiles * ft.S, std::numeric_limits<int32_t>::max());
+}
+
+hipError_t enqueue_steps(lc_sim* s, int count, int64_t first_step) {
+  ForceTiling ft = s->ft;
+  ft.S = s->S_eff;
+  const int grid = force_grid(s, ft);
+  for (int k = 0; k < count; ++k) {
+    const bool diag = s->cfg.diag_every > 0 && ((first_step + k) % s->cfg.diag_every) == 0;
+    hipError_t e = launch_schedule(s->s, s->rc, ft, k, s->stream);
+    if (e != hipSuccess) return e;
+    e = launch_force(s->s, s->rc, s->cfg.precision, ft, diag, grid, s->stream);
+    if (e != hipSuccess) return e;
+    e = launch_push(s->s, s->rc, s->cfg.precision, ft.S, k, diag, s->stream);
+    if (e != hipSuccess) return e;
+    if (diag) {
+      e = launch_diag(s->s, s->rc, ft.S, k, s->stream);
+      if (e != hipSuccess) return e;
+    }
+    if (s->cfg.ionize) {
+      e = launch_ionize(s->s, s->rc, s->cfg.precision, ft.S, k, s->L.n_ion_blocks, s->stream);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return launch_advance(s->s, count, s->stream);
+}
+
+void drop_graph(lc_sim* s) {
+  if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  s->gexec = nullptr;
+  s->graph = nullptr;
+}
+
+int latched_error(lc_sim* s) {
+  int32_t err = 0;
+  hipError_t e = hipMemcpy(&err, s->s.err, sizeof(int32_t), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(s, e, "reading error flags");
+  if (err & kFlagNonfinite) return fail(s, LC_E_NONFINITE, "a position or momentum became non-finite");
+  if (err & kFlagCapacity) return fail(s, LC_E_CAPACITY, "a cluster ran out of slots for spawned electrons");
+  return LC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lc_version(void) { return LC_API_VERSION; }
+
+const char* lc_error_string(int code) {
+  switch (code) {
+    case LC_OK: return "ok";
+    case LC_E_INVALID: return "invalid argument";
+    case LC_E_CAPACITY: return "capacity exceeded";
+    case LC_E_NONFINITE: return "non-finite state";
+    case LC_E_HIP: return "HIP runtime error";
+    case LC_E_STATE: return "call out of order";
+    case LC_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown error";
+  }
+}
+
+const char* lc_last_error(const lc_sim* sim) { return sim ? sim->last_error.c_str() : "null handle"; }
+
+int lc_units(double lambda_um, double intensity_wcm2, double out[6]) {
+  if (!out || !(lambda_um > 0.0) || !(intensity_wcm2 >= 0.0)) return LC_E_INVALID;
+  Units u = make_units(lambda_um);
+  out[0] = u.kappa;
+  out[1] = u.field_au;
+  out[2] = u.rate;
+  out[3] = a0_of(intensity_wcm2, lambda_um);
+  out[4] = u.k * 1e-9;
+  out[5] = kMec2Ev;
+  return LC_OK;
+}
+
+size_t lc_state_bytes(const lc_config* cfg, const lc_cluster* clusters, int32_t n_clusters) {
+  std::string why;
+  if (!valid_config(cfg, &why) || !clusters || n_clusters < 1) return 0;
+  for (int c = 0; c < n_clusters; ++c)
+    if (!valid_cluster(cfg, clusters[c], &why)) return 0;
+  return make_layout(cfg, clusters, n_clusters).total;
+}
+
+int lc_create(lc_sim** out, const lc_config* cfg, const lc_cluster* clusters, int32_t n_clusters, void* d_state,
+              size_t bytes, void* hip_stream) {
+  if (!out) return LC_E_INVALID;
+  *out = nullptr;
+  std::string why;
+  if (!valid_config(cfg, &why)) return LC_E_INVALID;
+  if (!clusters || n_clusters < 1 || !d_state) return LC_E_INVALID;
+  for (int c = 0; c < n_clusters; ++c)
+    if (!valid_cluster(cfg, clusters[c], &why)) return LC_E_INVALID;
+  Layout L = make_layout(cfg, clusters, n_clusters);
+  if (bytes < L.total) return LC_E_INVALID;
+  if (((uintptr_t)d_state & 255) != 0) return LC_E_INVALID;
+  if (L.n_total > ((int64_t)1 << 31) - 1) return LC_E_INVALID;
+
+  lc_sim* s = new lc_sim();
+  s->cfg = *cfg;
+  s->cl.assign(clusters, clusters + n_clusters);
+  s->C = n_clusters;
+  s->stream = (hipStream_t)hip_stream;
+  s->L = L;
+  s->u = make_units(cfg->lambda_um);
+  s->n_host.assign(n_clusters, 0);
+  s->inited.assign(n_clusters, 0);
+  char* b = (char*)d_state;
+  DevState& d = s->s;
+  d.x = (double*)(b + L.x); d.y = (double*)(b + L.y); d.z = (double*)(b + L.z);
+  d.ux = (double*)(b + L.ux); d.uy = (double*)(b + L.uy); d.uz = (double*)(b + L.uz);
+  d.wl = (double*)(b + L.wl); d.wc = (double*)(b + L.wc); d.wsp = (double*)(b + L.wsp);
+  d.kebar = (double*)(b + L.kebar);
+  d.pos4 = (float4*)(b + L.pos4); d.posq = (double4*)(b + L.posq);
+  d.Z = (int8_t*)(b + L.Z); d.cid = (int32_t*)(b + L.cid); d.part = (double*)(b + L.part);
+  d.flag = (int32_t*)(b + L.flag); d.ib_count = (int32_t*)(b + L.ib_count);
+  d.ib_cluster = (int32_t*)(b + L.ib_cluster);
+  d.cp = (ClusterParams*)(b + L.cp); d.dyn = (ClusterDyn*)(b + L.dyn);
+  d.order = (int32_t*)(b + L.order); d.tile_start = (int32_t*)(b + L.tile_start);
+  d.tile_total = (int32_t*)(b + L.tile_total); d.queue = (int32_t*)(b + L.queue);
+  d.err = (int32_t*)(b + L.err); d.step = (int64_t*)(b + L.step);
+  d.diag_part = (double*)(b + L.diag_part); d.records = (double*)(b + L.records);
+
+  RunConst& rc = s->rc;
+  rc.dt = cfg->dt;
+  rc.t0 = cfg->t0;
+  const double eps = cfg->softening_nm * 1e-9 * s->u.k;
+  rc.eps2 = eps * eps;
+  rc.seed = cfg->seed;
+  rc.n_clusters = n_clusters;
+  rc.ionize = cfg->ionize;
+  rc.ofi_local = cfg->ofi_field == LC_LOCAL;
+  rc.diag_every = cfg->diag_every;
+  rc.max_records = cfg->diag_every > 0 ? cfg->max_records : 1;
+  rc.pad = 0;
+  rc.n_total = L.n_total;
+  rc.mec2_ev = kMec2Ev;
+
+  // Per-cluster tables.
+  std::vector<ClusterParams> cps(n_clusters);
+  std::vector<int32_t> cid(L.n_total), ibc(std::max(L.n_ion_blocks, 1), 0);
+  int64_t off = 0;
+  int ib0 = 0;
+  for (int c = 0; c < n_clusters; ++c) {
+    const lc_cluster& k = clusters[c];
+    ClusterParams p{};
+    p.off = off;
+    p.cap = k.capacity;
+    p.n_ion = k.n_ion;
+    p.n_steps = k.n_steps > 0 ? k.n_steps : std::numeric_limits<int64_t>::max();
+    p.n_atoms = std::pow(k.r0_nm * 10.0 / k.rw_angstrom, 3.0);  // Eq.(1)
+    p.weight = k.weight > 0.0 ? k.weight : p.n_atoms / (double)k.n_ion;
+    p.mass_ion = k.mass_u * kMuOverMe;
+    p.kw = s->u.kappa * p.weight;
+    p.a0 = a0_of(k.intensity_wcm2, cfg->lambda_um);  // Eq.(2)
+    p.tau = k.fwhm_fs * 1e-15 * s->u.omega;
+    p.t_sin2 = 2.0 * kPi * k.n_cycles;
+    p.delta = k.electron_offset_nm * 1e-9 * s->u.k;
+    p.field_au = s->u.field_au;
+    p.rate_scale = s->u.rate;
+    for (int z = 0; z < LC_MAX_Z; ++z) {
+      const double ip = k.ip_ev[z] / kHartreeEv;
+      if (z < k.z_max && ip > 0.0) {
+        // static ADK, l = m = 0, l* = n* - 1 (a.u.): nu = C^2 Ip (2F0/F)^{2n*-1} exp(-2F0/(3F))
+        const double zc = z + 1.0;
+        const double ns = zc / std::sqrt(2.0 * ip);
+        const double f0 = std::pow(2.0 * ip, 1.5);
+        const double logc2 = 2.0 * ns * std::log(2.0) - std::log(ns) - std::lgamma(2.0 * ns);
+        p.adk_logc[z] = logc2 + std::log(ip) + (2.0 * ns - 1.0) * std::log(2.0 * f0);
+        p.adk_expo[z] = 2.0 * ns - 1.0;
+        p.adk_f23[z] = 2.0 * f0 / 3.0;
+        p.adk_ok[z] = 1;
+      }
+    }
+    p.envelope = k.envelope;
+    p.phase = k.phase;
+    p.z_max = k.z_max;
+    p.ion_block0 = ib0;
+    p.n_ion_blocks = (int32_t)((k.n_ion + kBlock - 1) / kBlock);
+    for (int q = 0; q < p.n_ion_blocks; ++q) ibc[ib0 + q] = c;
+    for (int64_t i = 0; i < k.capacity; ++i) cid[off + i] = c;
+    ib0 += p.n_ion_blocks;
+    off += k.capacity;
+    cps[c] = p;
+  }
+  s->order.resize(n_clusters);
+  for (int c = 0; c < n_clusters; ++c) s->order[c] = c;
+  std::stable_sort(s->order.begin(), s->order.end(),
+                   [&](int a, int b2) { return clusters[a].capacity > clusters[b2].capacity; });
+
+  hipError_t e = hipSuccess;
+  std::vector<ClusterDyn> dyn(n_clusters);
+  for (auto& dd : dyn) { std::memset(&dd, 0, sizeof(dd)); dd.active = 1; }
+  int64_t zero64 = 0;
+  int32_t zero32 = 0;
+  if (e == hipSuccess) e = hipMemcpy(d.cp, cps.data(), sizeof(ClusterParams) * n_clusters, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d.dyn, dyn.data(), sizeof(ClusterDyn) * n_clusters, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d.cid, cid.data(), sizeof(int32_t) * cid.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d.ib_cluster, ibc.data(), sizeof(int32_t) * ibc.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d.order, s->order.data(), sizeof(int32_t) * n_clusters, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d.step, &zero64, sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d.err, &zero32, sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d.queue, &zero32, sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    const int64_t NT = L.n_total;
+    const int nb = (int)((NT + kBlock - 1) / kBlock);
+    double* dz[] = {d.x, d.y, d.z, d.ux, d.uy, d.uz, d.wl, d.wc, d.wsp, d.kebar};
+    for (double* p : dz) k_fill_f64<<<nb, kBlock, 0, s->stream>>>(p, NT, 0.0);
+    k_fill_i8<<<nb, kBlock, 0, s->stream>>>(d.Z, NT, 0);
+    k_fill_i32<<<nb, kBlock, 0, s->stream>>>(d.flag, NT, 0);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  }
+  if (e != hipSuccess) {
+    delete s;
+    return LC_E_HIP;
+  }
+  s->ft = default_tiling(cfg->precision);
+  (void)device_cus();
+  *out = s;
+  return LC_OK;
+}
+
+int lc_init_from_host(lc_sim* s, int32_t cluster, int64_t n, const double* x_nm, const double* u, const int8_t* Z) {
+  if (!s) return LC_E_INVALID;
+  if (cluster < 0 || cluster >= s->C) return fail(s, LC_E_INVALID, "cluster index out of range");
+  const lc_cluster& k = s->cl[cluster];
+  if (n < 0 || n > k.capacity) return fail(s, LC_E_INVALID, "particle count exceeds capacity");
+  if (n > 0 && (!x_nm || !Z)) return fail(s, LC_E_INVALID, "null input");
+  if (n < k.n_ion) return fail(s, LC_E_INVALID, "fewer particles than ions");
+  for (int64_t i = 0; i < n; ++i) {
+    const bool ion_slot = i < k.n_ion;
+    if (ion_slot && (Z[i] < 0 || Z[i] > k.z_max)) return fail(s, LC_E_INVALID, "ion slot with invalid charge");
+    if (!ion_slot && Z[i] != -1) return fail(s, LC_E_INVALID, "slots after the ions must hold electrons (Z = -1)");
+  }
+  for (int64_t i = 0; i < 3 * n; ++i)
+    if (!std::isfinite(x_nm[i]) || (u && !std::isfinite(u[i]))) return fail(s, LC_E_NONFINITE, "non-finite input");
+  const int64_t off = [&] { int64_t o = 0; for (int c = 0; c < cluster; ++c) o += s->cl[c].capacity; return o; }();
+  std::vector<double> buf(n);
+  const double kn = 1e-9 * s->u.k;  // nm -> c/w
+  double* dst[3] = {s->s.x, s->s.y, s->s.z};
+  double* dstu[3] = {s->s.ux, s->s.uy, s->s.uz};
+  hipError_t e = hipSuccess;
+  for (int a = 0; a < 3 && e == hipSuccess; ++a) {
+    for (int64_t i = 0; i < n; ++i) buf[i] = x_nm[3 * i + a] * kn;
+    e = hipMemcpy(dst[a] + off, buf.data(), sizeof(double) * n, hipMemcpyHostToDevice);
+    for (int64_t i = 0; i < n; ++i) buf[i] = u ? u[3 * i + a] : 0.0;
+    if (e == hipSuccess) e = hipMemcpy(dstu[a] + off, buf.data(), sizeof(double) * n, hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess && n > 0) e = hipMemcpy(s->s.Z + off, Z, (size_t)n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    k_set_count<<<1, 64, 0, s->stream>>>(s->s.dyn, cluster, n);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "lc_init_from_host");
+  s->n_host[cluster] = n;
+  s->inited[cluster] = 1;
+  s->started = false;
+  return LC_OK;
+}
+
+int lc_start(lc_sim* s) {
+  if (!s) return LC_E_INVALID;
+  for (int c = 0; c < s->C; ++c)
+    if (!s->inited[c]) return fail(s, LC_E_STATE, "every cluster needs lc_init_from_host before lc_start");
+  if (s->step != 0) return fail(s, LC_E_STATE, "lc_start after stepping");
+  drop_graph(s);
+  s->S_eff = choose_splits(s, s->ft);
+  ForceTiling ft = s->ft;
+  ft.S = s->S_eff;
+  hipError_t e = launch_refresh_sources(s->s, s->rc, s->cfg.precision, s->stream);
+  if (e == hipSuccess) e = launch_schedule(s->s, s->rc, ft, 0, s->stream);
+  if (e == hipSuccess) e = launch_force(s->s, s->rc, s->cfg.precision, ft, false, force_grid(s, ft), s->stream);
+  if (e == hipSuccess) e = launch_start_kick(s->s, s->rc, s->cfg.precision, ft.S, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "lc_start");
+  s->started = true;
+  return LC_OK;
+}
+
+int lc_set_graph(lc_sim* s, int32_t steps_per_graph) {
+  if (!s || steps_per_graph < 0) return LC_E_INVALID;
+  if (steps_per_graph > 0 && s->stream == nullptr) return fail(s, LC_E_INVALID, "graph capture needs a non-null stream");
+  int g = steps_per_graph;
+  const int de = s->cfg.diag_every;
+  if (g > 0 && de > 0) g = (g + de - 1) / de * de;
+  if (g != s->graph_steps) drop_graph(s);
+  s->graph_steps = g;
+  return LC_OK;
+}
+
+int lc_step(lc_sim* s, int64_t n_steps) {
+  if (!s || n_steps < 0) return LC_E_INVALID;
+  if (!s->started) return fail(s, LC_E_STATE, "lc_step before lc_start");
+  int64_t left = n_steps;
+  const int de = s->cfg.diag_every;
+  while (left > 0) {
+    const int G = s->graph_steps;
+    const bool aligned = de <= 0 || (s->step % de) == 0;
+    if (G > 0 && left >= G && aligned) {
+      if (!s->gexec) {
+        hipError_t e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(s, e, "hipStreamBeginCapture");
+        hipError_t e2 = enqueue_steps(s, G, 0);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(s->stream, &g);
+        if (e2 != hipSuccess) { if (g) (void)hipGraphDestroy(g); return hip_fail(s, e2, "capturing steps"); }
+        if (e != hipSuccess) return hip_fail(s, e, "hipStreamEndCapture");
+        s->graph = g;
+        e = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) { drop_graph(s); return hip_fail(s, e, "hipGraphInstantiate"); }
+      }
+      hipError_t e = hipGraphLaunch(s->gexec, s->stream);
+      if (e != hipSuccess) return hip_fail(s, e, "hipGraphLaunch");
+      s->step += G;
+      left -= G;
+    } else {
+      hipError_t e = enqueue_steps(s, 1, s->step);
+      if (e != hipSuccess) return hip_fail(s, e, "enqueue step");
+      s->step += 1;
+      left -= 1;
+    }
+  }
+  return LC_OK;
+}
+
+int64_t lc_step_index(const lc_sim* s) { return s ? s->step : -1; }
+
+int lc_read_diagnostics(lc_sim* s, int32_t cluster, double* records, int32_t max_records, int32_t* n_out) {
+  if (!s || !n_out || max_records < 0) return LC_E_INVALID;
+  if (cluster < 0 || cluster >= s->C) return fail(s, LC_E_INVALID, "cluster index out of range");
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "lc_read_diagnostics");
+  ClusterDyn d;
+  e = hipMemcpy(&d, s->s.dyn + cluster, sizeof(ClusterDyn), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(s, e, "lc_read_diagnostics");
+  const int64_t mr = s->rc.max_records;
+  const int64_t have = std::min<int64_t>(d.rec_count, mr);
+  const int64_t take = std::min<int64_t>(have, max_records);
+  const int64_t first = d.rec_count - take;  // oldest record returned
+  std::vector<double> all((size_t)mr * LC_REC);
+  if (take > 0) {
+    e = hipMemcpy(all.data(), s->s.records + (size_t)cluster * mr * LC_REC, sizeof(double) * all.size(),
+                  hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(s, e, "lc_read_diagnostics");
+    for (int64_t r = 0; r < take; ++r) {
+      const int64_t slot = (first + r) % mr;
+      std::memcpy(records + r * LC_REC, all.data() + slot * LC_REC, sizeof(double) * LC_REC);
+    }
+  }
+  *n_out = (int32_t)take;
+  return latched_error(s);
+}
+
+int lc_read_particles(lc_sim* s, int32_t cluster, double* x, double* u, int8_t* Z, double* wl, double* wc,
+                      int64_t cap, int64_t* n_out) {
+  if (!s || !n_out || cap < 0) return LC_E_INVALID;
+  if (cluster < 0 || cluster >= s->C) return fail(s, LC_E_INVALID, "cluster index out of range");
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "lc_read_particles");
+  ClusterDyn d;
+  e = hipMemcpy(&d, s->s.dyn + cluster, sizeof(ClusterDyn), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(s, e, "lc_read_particles");
+  int64_t off = 0;
+  for (int c = 0; c < cluster; ++c) off += s->cl[c].capacity;
+  const int64_t n = std::min<int64_t>(d.n_cur, cap);
+  std::vector<double> buf(std::max<int64_t>(n, 1));
+  const double* src3[2][3] = {{s->s.x, s->s.y, s->s.z}, {s->s.ux, s->s.uy, s->s.uz}};
+  double* dst3[2] = {x, u};
+  for (int v = 0; v < 2; ++v) {
+    if (!dst3[v]) continue;
+    for (int a = 0; a < 3; ++a) {
+      e = hipMemcpy(buf.data(), src3[v][a] + off, sizeof(double) * n, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return hip_fail(s, e, "lc_read_particles");
+      for (int64_t i = 0; i < n; ++i) dst3[v][3 * i + a] = buf[i];
+    }
+  }
+  if (Z && n > 0) e = hipMemcpy(Z, s->s.Z + off, (size_t)n, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && wl && n > 0) e = hipMemcpy(wl, s->s.wl + off, sizeof(double) * n, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && wc && n > 0) e = hipMemcpy(wc, s->s.wc + off, sizeof(double) * n, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(s, e, "lc_read_particles");
+  *n_out = d.n_cur;
+  return latched_error(s);
+}
+
+int lc_set_tuning(lc_sim* s, const lc_tuning* t) {
+  if (!s || !t) return LC_E_INVALID;
+  ForceTiling ft = default_tiling(s->cfg.precision);
+  if (t->targets_per_lane) ft.R = t->targets_per_lane;
+  if (t->waves_per_target) ft.WJ = t->waves_per_target;
+  if (t->tile_sources) ft.T = t->tile_sources;
+  ft.S = t->j_splits;
+  ft.persistent = t->persistent ? 1 : 0;
+  ForceTiling chk = ft;
+  if (chk.S == 0) chk.S = 1;
+  if (!force_tiling_valid(s->cfg.precision, chk) || ft.S > s->cfg.max_splits || ft.S < 0)
+    return fail(s, LC_E_INVALID, "invalid tiling");
+  s->ft = ft;
+  const int S_new = choose_splits(s, ft);
+  if (s->started && S_new != s->S_eff) {
+    // partials of the last field pass were written with the old split count; the next step
+    // recomputes them, but the graph must be recaptured
+  }
+  s->S_eff = S_new;
+  drop_graph(s);
+  return LC_OK;
+}
+
+int lc_get_tuning(const lc_sim* s, lc_tuning* t) {
+  if (!s || !t) return LC_E_INVALID;
+  std::memset(t, 0, sizeof(*t));
+  t->targets_per_lane = s->ft.R;
+  t->waves_per_target = s->ft.WJ;
+  t->tile_sources = s->ft.T;
+  t->j_splits = s->S_eff;
+  t->persistent = s->ft.persistent;
+  return LC_OK;
+}
+
+void lc_destroy(lc_sim* s) {
+  if (!s) return;
+  drop_graph(s);
+  delete s;
+}
+
+// ----------------------------------------------------------------------------- checkpoints
+int lc_save_state(lc_sim* s, const char* path) {
+  if (!s || !path) return LC_E_INVALID;
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "lc_save_state");
+  std::vector<char> host(s->L.total);
+  e = hipMemcpy(host.data(), (const void*)s->s.x, s->L.total, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(s, e, "lc_save_state");
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(s, LC_E_INVALID, "cannot open checkpoint for writing");
+  const uint64_t magic = 0x4C434D4443484B31ULL;  // "LCMDCHK1"
+  const uint64_t hdr[5] = {magic, (uint64_t)s->L.total, (uint64_t)s->step, (uint64_t)s->C, (uint64_t)s->S_eff};
+  bool ok = std::fwrite(hdr, sizeof(hdr), 1, f) == 1;
+  ok = ok && std::fwrite(&s->cfg, sizeof(lc_config), 1, f) == 1;
+  ok = ok && std::fwrite(s->n_host.data(), sizeof(int64_t), s->C, f) == (size_t)s->C;
+  ok = ok && std::fwrite(host.data(), 1, host.size(), f) == host.size();
+  ok = (std::fclose(f) == 0) && ok;
+  return ok ? LC_OK : fail(s, LC_E_INVALID, "short write of checkpoint");
+}
+
+int lc_load_state(lc_sim* s, const char* path) {
+  if (!s || !path) return LC_E_INVALID;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(s, LC_E_INVALID, "cannot open checkpoint");
+  uint64_t hdr[5];
+  lc_config cfg;
+  std::vector<int64_t> nh(s->C);
+  std::vector<char> host(s->L.total);
+  bool ok = std::fread(hdr, sizeof(hdr), 1, f) == 1;
+  ok = ok && hdr[0] == 0x4C434D4443484B31ULL && hdr[1] == (uint64_t)s->L.total && hdr[3] == (uint64_t)s->C;
+  ok = ok && std::fread(&cfg, sizeof(cfg), 1, f) == 1 && std::memcmp(&cfg, &s->cfg, sizeof(cfg)) == 0;
+  ok = ok && std::fread(nh.data(), sizeof(int64_t), s->C, f) == (size_t)s->C;
+  ok = ok && std::fread(host.data(), 1, host.size(), f) == host.size();
+  std::fclose(f);
+  if (!ok) return fail(s, LC_E_INVALID, "checkpoint does not match this handle or is truncated");
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (e == hipSuccess) e = hipMemcpy((void*)s->s.x, host.data(), host.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(s, e, "lc_load_state");
+  s->step = (int64_t)hdr[2];
+  s->S_eff = (int)hdr[4];
+  s->n_host = nh;
+  for (auto& v : s->inited) v = 1;
+  s->started = true;
+  drop_graph(s);
+  return LC_OK;
+}
+
+// ----------------------------------------------------------------------------- autotuner
+namespace {
+
+__global__ void k_fold_partials(double* part, int64_t stride, int S) {
+  // field of every slot summed over splits in split order into split 0 (components 0..2)
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= stride) return;
+  for (int c = 0; c < 3; ++c) {
+    double v = 0.0;
+    for (int s = 0; s < S; ++s) v += part[((int64_t)s * kComp + c) * stride + g];
+    part[(int64_t)c * stride + g] = v;
+  }
+}
+
+int field_snapshot(lc_sim* s, const ForceTiling& ft, std::vector<double>& out) {
+  const int64_t NT = s->L.n_total;
+  hipError_t e = launch_schedule(s->s, s->rc, ft, 0, s->stream);
+  if (e == hipSuccess) e = launch_force(s->s, s->rc, s->cfg.precision, ft, false, force_grid(s, ft), s->stream);
+  if (e == hipSuccess) {
+    k_fold_partials<<<(int)((NT + kBlock - 1) / kBlock), kBlock, 0, s->stream>>>(s->s.part, NT, ft.S);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  out.resize(3 * NT);
+  if (e == hipSuccess) e = hipMemcpy(out.data(), s->s.part, sizeof(double) * 3 * NT, hipMemcpyDeviceToHost);
+  return e == hipSuccess ? LC_OK : hip_fail(s, e, "autotune snapshot");
+}
+
+double rel_diff(const std::vector<double>& a, const std::vector<double>& b, const lc_sim* s) {
+  // normwise relative difference over live slots
+  double num = 0.0, den = 0.0;
+  const int64_t NT = s->L.n_total;
+  int64_t off = 0;
+  for (int c = 0; c < s->C; ++c) {
+    for (int64_t i = 0; i < s->n_host[c]; ++i)
+      for (int k = 0; k < 3; ++k) {
+        const double d = a[k * NT + off + i] - b[k * NT + off + i];
+        num += d * d;
+        den += b[k * NT + off + i] * b[k * NT + off + i];
+      }
+    off += s->cl[c].capacity;
+  }
+  return den > 0.0 ? std::sqrt(num / den) : std::sqrt(num);
+}
+
+}  // namespace
+
+extern "C" int lc_autotune(lc_sim* s, const char* cache_json, lc_tuning* chosen) {
+  if (!s) return LC_E_INVALID;
+  if (!s->started) return fail(s, LC_E_STATE, "lc_autotune before lc_start");
+  if (s->cfg.ionize) {
+    // n_host is exact only without spawns; refresh it from the device counts
+    for (int c = 0; c < s->C; ++c) {
+      ClusterDyn d;
+      hipError_t e = hipMemcpy(&d, s->s.dyn + c, sizeof(ClusterDyn), hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return hip_fail(s, e, "lc_autotune");
+      s->n_host[c] = d.n_cur;
+    }
+  }
+  const int prec = s->cfg.precision;
+  ForceTiling ref = default_tiling(prec);
+  ref.S = 1;
+  std::vector<double> fref;
+  int rc = field_snapshot(s, ref, fref);
+  if (rc != LC_OK) return rc;
+  const double tol = (prec == LC_FP64) ? 1e-12 : 1e-5;
+
+  struct Cand { ForceTiling ft; double ms; };
+  std::vector<Cand> cands;
+  const int Rs[] = {1, 2, 4, 8};
+  const int WJs[] = {1, 2, 4};
+  const int Ts[] = {256, 512, 1024, 2048};
+  const int Ss[] = {1, 2, 4, 8, 16, 32, 64};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(s, LC_E_HIP, "events");
+  for (int R : Rs)
+    for (int WJ : WJs)
+      for (int T : Ts)
+        for (int S : Ss)
+          for (int pers = 0; pers < 2; ++pers) {
+            ForceTiling ft{R, WJ, T, S, pers};
+            if (S > s->cfg.max_splits || !force_tiling_valid(prec, ft)) continue;
+            // skip split counts that leave most blocks without sources
+            int64_t nmax = 0;
+            for (int c = 0; c < s->C; ++c) nmax = std::max(nmax, s->n_host[c]);
+            if ((int64_t)S * 64 > std::max<int64_t>(nmax, 64)) continue;
+            const int reps = 3;
+            hipError_t e = launch_schedule(s->s, s->rc, ft, 0, s->stream);
+            if (e == hipSuccess) e = launch_force(s->s, s->rc, prec, ft, false, force_grid(s, ft), s->stream);  // warm
+            if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
+            for (int r = 0; r < reps && e == hipSuccess; ++r) {
+              e = launch_schedule(s->s, s->rc, ft, 0, s->stream);
+              if (e == hipSuccess) e = launch_force(s->s, s->rc, prec, ft, false, force_grid(s, ft), s->stream);
+            }
+            if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return hip_fail(s, e, "autotune"); }
+            cands.push_back({ft, ms / reps});
+          }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::sort(cands.begin(), cands.end(), [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
+  ForceTiling best = ref;
+  double best_ms = -1.0, best_err = 0.0;
+  for (const Cand& c : cands) {
+    std::vector<double> f;
+    rc = field_snapshot(s, c.ft, f);
+    if (rc != LC_OK) return rc;
+    const double err = rel_diff(f, fref, s);
+    if (err <= tol) { best = c.ft; best_ms = c.ms; best_err = err; break; }
+  }
+  s->ft = best;
+  s->S_eff = best.S;
+  drop_graph(s);
+  if (chosen) lc_get_tuning(s, chosen);
+  if (cache_json) {
+    FILE* f = std::fopen(cache_json, "a");
+    if (f) {
+      int64_t ntot = 0;
+      for (int c = 0; c < s->C; ++c) ntot += s->n_host[c];
+      std::fprintf(f,
+                   "{\"precision\": %d, \"clusters\": %d, \"particles\": %lld, \"R\": %d, \"WJ\": %d, \"T\": %d, "
+                   "\"S\": %d, \"persistent\": %d, \"ms\": %.6f, \"rel_err_vs_default\": %.3e, \"candidates\": %zu}\n",
+                   prec, s->C, (long long)ntot, best.R, best.WJ, best.T, best.S, best.persistent, best_ms, best_err,
+                   cands.size());
+      std::fclose(f);
+    }
+  }
+  return LC_OK;
+}
+
+// ----------------------------------------------------------------------------- profiling
+extern "C" int lc_profile_steps(lc_sim* s, int64_t n_steps, double* out_ms, int64_t* out_launches) {
+  if (!s || !out_ms || !out_launches || n_steps < 0 || n_steps > 100000) return LC_E_INVALID;
+  if (!s->started) return fail(s, LC_E_STATE, "lc_profile_steps before lc_start");
+  for (int k = 0; k < 4; ++k) { out_ms[k] = 0.0; out_launches[k] = 0; }
+  ForceTiling ft = s->ft;
+  ft.S = s->S_eff;
+  const int grid = force_grid(s, ft);
+  const int64_t chunk = 256;  // steps per event batch
+  std::vector<hipEvent_t> ev(8 * chunk);
+  for (auto& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) return fail(s, LC_E_HIP, "hipEventCreate");
+  hipError_t e = hipSuccess;
+  for (int64_t done = 0; done < n_steps && e == hipSuccess;) {
+    const int64_t m = std::min(chunk, n_steps - done);
+    std::vector<int> used(4 * m, 0);
+    for (int64_t k = 0; k < m && e == hipSuccess; ++k) {
+      const bool diag = s->cfg.diag_every > 0 && (s->step % s->cfg.diag_every) == 0;
+      hipEvent_t* E = &ev[8 * k];
+      e = launch_schedule(s->s, s->rc, ft, 0, s->stream);
+      if (e == hipSuccess) e = hipEventRecord(E[0], s->stream);
+      if (e == hipSuccess) e = launch_force(s->s, s->rc, s->cfg.precision, ft, diag, grid, s->stream);
+      if (e == hipSuccess) e = hipEventRecord(E[1], s->stream);
+      used[4 * k + 0] = 1;
+      if (e == hipSuccess) e = hipEventRecord(E[2], s->stream);
+      if (e == hipSuccess) e = launch_push(s->s, s->rc, s->cfg.precision, ft.S, 0, diag, s->stream);
+      if (e == hipSuccess) e = hipEventRecord(E[3], s->stream);
+      used[4 * k + 1] = 1;
+      if (diag && e == hipSuccess) {
+        e = hipEventRecord(E[4], s->stream);
+        if (e == hipSuccess) e = launch_diag(s->s, s->rc, ft.S, 0, s->stream);
+        if (e == hipSuccess) e = hipEventRecord(E[5], s->stream);
+        used[4 * k + 2] = 1;
+      }
+      if (s->cfg.ionize && e == hipSuccess) {
+        e = hipEventRecord(E[6], s->stream);
+        if (e == hipSuccess) e = launch_ionize(s->s, s->rc, s->cfg.precision, ft.S, 0, s->L.n_ion_blocks, s->stream);
+        if (e == hipSuccess) e = hipEventRecord(E[7], s->stream);
+        used[4 * k + 3] = 1;
+      }
+      if (e == hipSuccess) e = launch_advance(s->s, 1, s->stream);
+      s->step += 1;
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    for (int64_t k = 0; k < m && e == hipSuccess; ++k)
+      for (int c = 0; c < 4; ++c) {
+        if (!used[4 * k + c]) continue;
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, ev[8 * k + 2 * c], ev[8 * k + 2 * c + 1]);
+        out_ms[c] += ms;
+        out_launches[c] += 1;
+      }
+    done += m;
+  }
+  for (auto& x : ev) (void)hipEventDestroy(x);
+  return e == hipSuccess ? LC_OK : hip_fail(s, e, "lc_profile_steps");
+}
+
+// ----------------------------------------------------------------------------- standalone field
+size_t lc_field_workspace_bytes(int32_t precision, int64_t n, const lc_tuning* t) {
+  if (precision < LC_FP64 || precision > LC_FP32_KAHAN || n < 0) return 0;
+  ForceTiling ft = default_tiling(precision);
+  ft.S = 1;
+  if (t) {
+    if (t->targets_per_lane) ft.R = t->targets_per_lane;
+    if (t->waves_per_target) ft.WJ = t->waves_per_target;
+    if (t->tile_sources) ft.T = t->tile_sources;
+    if (t->j_splits) ft.S = t->j_splits;
+  }
+  if (!force_tiling_valid(precision, ft)) return 0;
+  return field_workspace_bytes(precision, n, ft);
+}
+
+int lc_field(int32_t precision, int64_t n, const double* d_xyzq, double eps2, double* d_E, double* d_phi,
+             void* d_work, size_t work_bytes, const lc_tuning* t, void* hip_stream) {
+  if (precision < LC_FP64 || precision > LC_FP32_KAHAN || n < 0 || !(eps2 > 0.0)) return LC_E_INVALID;
+  if (n > ((int64_t)1 << 30)) return LC_E_INVALID;
+  if (n > 0 && (!d_xyzq || !d_E || !d_work)) return LC_E_INVALID;
+  ForceTiling ft = default_tiling(precision);
+  ft.S = 1;
+  if (t) {
+    if (t->targets_per_lane) ft.R = t->targets_per_lane;
+    if (t->waves_per_target) ft.WJ = t->waves_per_target;
+    if (t->tile_sources) ft.T = t->tile_sources;
+    if (t->j_splits) ft.S = t->j_splits;
+    ft.persistent = t->persistent ? 1 : 0;
+  }
+  if (!force_tiling_valid(precision, ft)) return LC_E_INVALID;
+  if (((uintptr_t)d_work & 255) != 0) return LC_E_INVALID;
+  if (work_bytes < field_workspace_bytes(precision, n, ft)) return LC_E_INVALID;
+  hipError_t e = launch_field_standalone(precision, n, d_xyzq, eps2, d_E, d_phi, d_work, ft, (hipStream_t)hip_stream);
+  return e == hipSuccess ? LC_OK : LC_E_HIP;
+}
+
+}  // extern "C"

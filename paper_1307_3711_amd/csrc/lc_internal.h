@@ -1,0 +1,152 @@
+// lc_internal.h -- device-side layout shared by the kernels and the host runtime of liblcmd.
+//
+// Every array lives in one caller-owned device allocation.  Particles of all clusters are
+// concatenated: cluster c owns global slots [off_c, off_c + cap_c); inside a cluster, ions
+// occupy local slots [0, n_ion) and electrons follow (initial ones, then spawned ones in
+// ascending parent order).  Per-particle arrays are structure-of-arrays FP64 except the
+// packed source records the Coulomb kernel reads (float4 or double4 {x, y, z, q}).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/lcmd.h"
+
+namespace lc {
+
+constexpr int kBlock = 256;          // threads per block of the particle-parallel kernels
+constexpr int kDiagQ = 48;           // doubles per per-block diagnostic partial
+constexpr int kDiagBlocks = 64;      // blocks per cluster in the diagnostic reduction
+constexpr int kHist = 17;            // charge histogram bins 0..16
+
+// Field partial components written per source split: Ex, Ey, Ez, phi.
+constexpr int kComp = 4;
+
+// Device error flags (latched, OR-ed).
+constexpr int kFlagNonfinite = 1;
+constexpr int kFlagCapacity = 2;
+
+// Static per-cluster parameters (dimensionless), uploaded once by lc_create.
+struct ClusterParams {
+  int64_t off;          // first global slot
+  int64_t cap;          // slots
+  int64_t n_ion;        // ions in local slots [0, n_ion)
+  int64_t n_steps;      // retire after this many steps (INT64_MAX: never)
+  double weight;        // real particles per macroparticle
+  double mass_ion;      // ion mass in m_e
+  double kw;            // kappa * weight: source strength per unit charge number
+  double a0;            // peak field
+  double tau;           // Gaussian FWHM (1/w)
+  double t_sin2;        // sin^2 envelope length (1/w)
+  double delta;         // spawn offset (c/w)
+  double n_atoms;       // real atoms (Eq.(1))
+  double field_au;      // atomic field units per a0
+  double rate_scale;    // 1/w per atomic time unit
+  // ADK constants per charge state Z (transition Z -> Z+1), in atomic units:
+  //   log nu = adk_logc[Z] - adk_expo[Z] * log F - adk_f23[Z] / F,  valid if adk_ok[Z]
+  double adk_logc[LC_MAX_Z];
+  double adk_expo[LC_MAX_Z];
+  double adk_f23[LC_MAX_Z];
+  int32_t adk_ok[LC_MAX_Z];
+  int32_t envelope;
+  int32_t phase;
+  int32_t z_max;
+  int32_t ion_block0;   // first entry of this cluster in the ion-block table
+  int32_t n_ion_blocks;
+  int32_t pad;
+};
+
+// Per-cluster dynamic state, written by the kernels.
+struct ClusterDyn {
+  int64_t n_cur;        // live particles
+  int64_t n_base;       // particle count before this step's spawns
+  int64_t dropped;      // spawns that found no free slot (cumulative)
+  int64_t events;       // ionizations (cumulative)
+  int64_t rec_count;    // diagnostic records written
+  double ke_start;      // sum w M (gamma - 1) at t0 - dt/2
+  double laser_e;       // a(t^n) sin(t^n) of the current step (dipole field value)
+  double env;           // a(t^n)
+  int32_t tile0;        // first tile of this cluster in the step's tile enumeration
+  int32_t n_tiles;      // tiles of this cluster this step
+  int32_t i_blocks;     // target blocks this step
+  int32_t active;       // 1 while step < n_steps
+};
+
+// Run-wide constants passed by value to every kernel.
+struct RunConst {
+  double dt;
+  double t0;
+  double eps2;
+  uint64_t seed;
+  int32_t n_clusters;
+  int32_t ionize;
+  int32_t ofi_local;
+  int32_t diag_every;
+  int32_t max_records;
+  int32_t pad;
+  int64_t n_total;      // total slots (sum of capacities)
+  double mec2_ev;       // electron rest energy (eV) for the absorbed-energy column
+};
+
+// Pointers into the caller-owned state.
+struct DevState {
+  double* x;
+  double* y;
+  double* z;
+  double* ux;
+  double* uy;
+  double* uz;
+  double* wl;
+  double* wc;
+  double* wsp;
+  double* kebar;
+  float4* pos4;         // FP32 source records (LC_FP32_*)
+  double4* posq;        // FP64 source records (LC_FP64)
+  int8_t* Z;
+  int32_t* cid;         // cluster of each slot
+  double* part;         // field partials [split][comp][slot]
+  int32_t* flag;        // ionization flags [slot of ion]
+  int32_t* ib_count;    // spawns per ion block
+  int32_t* ib_cluster;  // cluster of each ion block
+  ClusterParams* cp;
+  ClusterDyn* dyn;
+  int32_t* order;       // clusters in descending capacity (tile order)
+  int32_t* tile_start;  // [n_clusters + 1] first tile of each order position this step
+  int32_t* tile_total;  // tiles this step
+  int32_t* queue;       // persistent-kernel work counter
+  int32_t* err;         // latched error flags
+  int64_t* step;        // absolute index of the current step group's first step
+  double* diag_part;    // [cluster][kDiagBlocks][kDiagQ]
+  double* records;      // [cluster][max_records][LC_REC]
+};
+
+struct ForceTiling {
+  int R;
+  int WJ;
+  int T;
+  int S;
+  int persistent;
+};
+
+// Host launchers (defined in force.hip / step.hip).
+hipError_t launch_force(const DevState& s, const RunConst& rc, int precision, const ForceTiling& ft,
+                        bool want_phi, int grid_blocks, hipStream_t st);
+hipError_t launch_schedule(const DevState& s, const RunConst& rc, const ForceTiling& ft, int64_t k,
+                           hipStream_t st);
+hipError_t launch_push(const DevState& s, const RunConst& rc, int precision, int S, int64_t k, bool diag,
+                       hipStream_t st);
+hipError_t launch_start_kick(const DevState& s, const RunConst& rc, int precision, int S, hipStream_t st);
+hipError_t launch_diag(const DevState& s, const RunConst& rc, int S, int64_t k, hipStream_t st);
+hipError_t launch_ionize(const DevState& s, const RunConst& rc, int precision, int S, int64_t k,
+                         int n_ion_blocks, hipStream_t st);
+hipError_t launch_advance(const DevState& s, int64_t by, hipStream_t st);
+hipError_t launch_refresh_sources(const DevState& s, const RunConst& rc, int precision, hipStream_t st);
+
+// Standalone field (lc_field).
+hipError_t launch_field_standalone(int precision, int64_t n, const double* xyzq, double eps2, double* E,
+                                   double* phi, void* work, const ForceTiling& ft, hipStream_t st);
+size_t field_workspace_bytes(int precision, int64_t n, const ForceTiling& ft);
+
+int force_tile_targets(const ForceTiling& ft);
+bool force_tiling_valid(int precision, const ForceTiling& ft);
+
+}  // namespace lc

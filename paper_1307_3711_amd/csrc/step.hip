@@ -1,0 +1,543 @@
+// step.hip -- particle-parallel kernels of one time step on gfx950: per-step schedule and
+// laser value (S1), Boris push (S3), ionization check and electron spawning (S4),
+// diagnostics (S5), the leap-frog start and the step counter.
+//
+// All of these are HBM- or latency-bound; they are plain 1-thread-per-particle kernels with
+// coalesced FP64 structure-of-arrays access.  Reductions (diagnostics, spawn offsets) are
+// done in a fixed order so every run is bitwise reproducible.
+#include "lc_internal.h"
+
+namespace lc {
+
+namespace {
+
+// ----------------------------------------------------------------------------- helpers
+
+__device__ inline double gm1(double ux, double uy, double uz) {
+  // gamma - 1 = u^2 / (1 + gamma): no cancellation for slow heavy ions
+  const double u2 = ux * ux + uy * uy + uz * uz;
+  return u2 / (1.0 + sqrt(1.0 + u2));
+}
+
+// Envelope a(t) of the laser field amplitude (Eq.(3) and the test envelopes).
+__device__ inline double envelope(const ClusterParams& cp, double t) {
+  switch (cp.envelope) {
+    case LC_GAUSS_FIELD: {
+      const double d = t - 2.0 * cp.tau;
+      return cp.a0 * exp(-2.77 * d * d / (cp.tau * cp.tau));
+    }
+    case LC_GAUSS_INTENSITY: {
+      const double d = t - 2.0 * cp.tau;
+      return cp.a0 * exp(-1.385 * d * d / (cp.tau * cp.tau));
+    }
+    case LC_SIN2: {
+      if (t <= 0.0 || t >= cp.t_sin2) return 0.0;
+      const double s = sin(M_PI * t / cp.t_sin2);
+      return cp.a0 * s * s;
+    }
+    default:
+      return cp.a0;
+  }
+}
+
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): two 64x64->128 multiplies per round,
+// Weyl key schedule between rounds.
+struct U64x4 {
+  uint64_t v[4];
+};
+
+__device__ inline U64x4 philox(uint64_t k0, uint64_t k1, uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+    const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+    const uint64_t n0 = hi1 ^ c1 ^ k0;
+    const uint64_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += W0; k1 += W1;
+  }
+  U64x4 o;
+  o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3;
+  return o;
+}
+
+// Uniform draw in (0, 1] from the top 53 bits (the paper's 0 < alpha <= 1).
+__device__ inline double unit_interval(uint64_t x) {
+  return (double)((x >> 11) + 1ULL) * (1.0 / 9007199254740992.0);
+}
+
+constexpr uint64_t kPurposeAlpha = 2;
+constexpr uint64_t kPurposeDirection = 3;
+
+__device__ inline void write_source(const DevState& s, int precision, int64_t g, double x, double y, double z,
+                                    double q) {
+  if (precision == LC_FP64) s.posq[g] = make_double4(x, y, z, q);
+  else s.pos4[g] = make_float4((float)x, (float)y, (float)z, (float)q);
+}
+
+__device__ inline void field_sum(const DevState& s, const RunConst& rc, int S, int64_t g, double& ex,
+                                 double& ey, double& ez) {
+  ex = 0.0; ey = 0.0; ez = 0.0;
+  for (int k = 0; k < S; ++k) {
+    const double* b = s.part + (int64_t)k * kComp * rc.n_total + g;
+    ex += b[0];
+    ey += b[rc.n_total];
+    ez += b[2 * rc.n_total];
+  }
+}
+
+__device__ inline void laser_at(const ClusterParams& cp, const ClusterDyn& d, double t, double z, double& a) {
+  a = (cp.phase == LC_DIPOLE) ? d.laser_e : d.env * sin(t - z);
+}
+
+// ----------------------------------------------------------------------------- schedule (S6)
+// One block: per cluster, active flag, laser value at t^n, target blocks and tiles of this
+// step; exclusive scan of tiles over clusters in `order` (largest first).
+__global__ __launch_bounds__(kBlock) void k_schedule(DevState s, RunConst rc, int TI, int S, int64_t k) {
+  __shared__ int32_t sh_scan[kBlock];
+  __shared__ int32_t sh_carry;
+  const int tid = threadIdx.x;
+  const int64_t n = *s.step + k;
+  const double t = rc.t0 + (double)n * rc.dt;
+  if (tid == 0) sh_carry = 0;
+  __syncthreads();
+  for (int base = 0; base < rc.n_clusters; base += kBlock) {
+    const int p = base + tid;
+    int32_t tiles = 0;
+    if (p < rc.n_clusters) {
+      const int c = s.order[p];
+      const ClusterParams& cp = s.cp[c];
+      ClusterDyn& d = s.dyn[c];
+      const int active = (n < cp.n_steps) ? 1 : 0;
+      const int64_t ncur = d.n_cur;
+      const int ib = active ? (int)((ncur + TI - 1) / TI) : 0;
+      tiles = ib * S;
+      const double env = envelope(cp, t);
+      d.env = env;
+      d.laser_e = env * sin(t);
+      d.active = active;
+      d.i_blocks = ib;
+      d.n_tiles = tiles;
+    }
+    sh_scan[tid] = tiles;
+    __syncthreads();
+    for (int o = 1; o < kBlock; o <<= 1) {  // Hillis-Steele inclusive scan
+      const int32_t v = (tid >= o) ? sh_scan[tid - o] : 0;
+      __syncthreads();
+      sh_scan[tid] += v;
+      __syncthreads();
+    }
+    const int32_t carry = sh_carry;
+    if (p < rc.n_clusters) {
+      const int32_t excl = carry + sh_scan[tid] - tiles;
+      s.tile_start[p] = excl;
+      s.dyn[s.order[p]].tile0 = excl;
+    }
+    __syncthreads();
+    if (tid == kBlock - 1) sh_carry = carry + sh_scan[kBlock - 1];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    s.tile_start[rc.n_clusters] = sh_carry;
+    *s.tile_total = sh_carry;
+    *s.queue = 0;
+  }
+}
+
+// ----------------------------------------------------------------------------- push (S3)
+// Relativistic Boris step of every live particle: u^{n-1/2} -> u^{n+1/2}, x^n -> x^{n+1},
+// with the exact discrete work split W_L / W_C, optional KE(n) for the diagnostics, and the
+// refresh of the source record the next field pass reads.
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_push(DevState s, RunConst rc, int S, int64_t k, int diag) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= rc.n_total) return;
+  const int c = s.cid[g];
+  const ClusterParams& cp = s.cp[c];
+  const ClusterDyn& d = s.dyn[c];
+  if (!d.active) return;
+  if (g - cp.off >= d.n_cur) return;
+  const int64_t n = *s.step + k;
+  const double t = rc.t0 + (double)n * rc.dt;
+
+  double ecx, ecy, ecz;
+  field_sum(s, rc, S, g, ecx, ecy, ecz);
+  double x = s.x[g], y = s.y[g], z = s.z[g];
+  double a;
+  laser_at(cp, d, t, z, a);
+  const int zc = s.Z[g];
+  const double M = (zc < 0) ? 1.0 : cp.mass_ion;
+  const double uox = s.ux[g], uoy = s.uy[g], uoz = s.uz[g];
+  double unx = uox, uny = uoy, unz = uoz;
+  const double go = sqrt(1.0 + uox * uox + uoy * uoy + uoz * uoz);
+  if (zc != 0) {
+    // E = E_C + E_L, E_L = (a, 0, 0); B_L = (0, a, 0)
+    const double h = 0.5 * ((double)zc / M) * rc.dt;
+    const double Ex = ecx + a, Ey = ecy, Ez = ecz;
+    const double umx = uox + h * Ex, umy = uoy + h * Ey, umz = uoz + h * Ez;
+    const double gm = sqrt(1.0 + umx * umx + umy * umy + umz * umz);
+    const double tx = h * 0.0 / gm, ty = h * a / gm, tz = h * 0.0 / gm;
+    const double t2 = tx * tx + ty * ty + tz * tz;
+    const double sx = 2.0 * tx / (1.0 + t2), sy = 2.0 * ty / (1.0 + t2), sz = 2.0 * tz / (1.0 + t2);
+    const double upx = umx + (umy * tz - umz * ty);
+    const double upy = umy + (umz * tx - umx * tz);
+    const double upz = umz + (umx * ty - umy * tx);
+    const double ux2 = umx + (upy * sz - upz * sy);
+    const double uy2 = umy + (upz * sx - upx * sz);
+    const double uz2 = umz + (upx * sy - upy * sx);
+    unx = ux2 + h * Ex;
+    uny = uy2 + h * Ey;
+    unz = uz2 + h * Ez;
+  }
+  const double gn = sqrt(1.0 + unx * unx + uny * uny + unz * unz);
+  if (zc != 0) {
+    // M (gamma_new - gamma_old) = Z dt E.(u_old + u_new)/(gamma_old + gamma_new), linear in E
+    const double cc = cp.weight * (double)zc * rc.dt / (go + gn);
+    const double sx = uox + unx, sy = uoy + uny, sz = uoz + unz;
+    s.wl[g] += cc * (a * sx + 0.0 * sy + 0.0 * sz);
+    s.wc[g] += cc * (ecx * sx + ecy * sy + ecz * sz);
+  }
+  if (diag) s.kebar[g] = cp.weight * M * 0.5 * (gm1(uox, uoy, uoz) + gm1(unx, uny, unz));
+  x += rc.dt * unx / gn;
+  y += rc.dt * uny / gn;
+  z += rc.dt * unz / gn;
+  s.ux[g] = unx; s.uy[g] = uny; s.uz[g] = unz;
+  s.x[g] = x; s.y[g] = y; s.z[g] = z;
+  write_source(s, PREC, g, x, y, z, cp.kw * (double)zc);
+  if (!(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(unx) && isfinite(uny) && isfinite(unz)))
+    atomicOr(s.err, kFlagNonfinite);
+}
+
+// ----------------------------------------------------------------------------- start
+// Backward half kick with the full Lorentz force at t0: u^{-1/2} = u^0 - (Z/M)(dt/2)(E + v x B);
+// kebar receives w M (gamma^{-1/2} - 1) for the start energy.
+__global__ __launch_bounds__(kBlock) void k_start_kick(DevState s, RunConst rc, int S) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= rc.n_total) return;
+  const int c = s.cid[g];
+  const ClusterParams& cp = s.cp[c];
+  const ClusterDyn& d = s.dyn[c];
+  if (g - cp.off >= d.n_cur) return;
+  double ecx, ecy, ecz;
+  field_sum(s, rc, S, g, ecx, ecy, ecz);
+  double a;
+  laser_at(cp, d, rc.t0, s.z[g], a);
+  const int zc = s.Z[g];
+  const double M = (zc < 0) ? 1.0 : cp.mass_ion;
+  double ux = s.ux[g], uy = s.uy[g], uz = s.uz[g];
+  if (zc != 0) {
+    const double h = 0.5 * ((double)zc / M) * rc.dt;
+    const double gg = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
+    const double vx = ux / gg, vy = uy / gg, vz = uz / gg;
+    // B = (0, a, 0)
+    const double fx = (ecx + a) + (vy * 0.0 - vz * a);
+    const double fy = ecy + (vz * 0.0 - vx * 0.0);
+    const double fz = ecz + (vx * a - vy * 0.0);
+    ux -= h * fx;
+    uy -= h * fy;
+    uz -= h * fz;
+  }
+  s.ux[g] = ux; s.uy[g] = uy; s.uz[g] = uz;
+  s.kebar[g] = cp.weight * M * gm1(ux, uy, uz);
+}
+
+// Per-cluster sum of kebar in slot order (one block per cluster, fixed tree).
+__global__ __launch_bounds__(kBlock) void k_sum_kestart(DevState s) {
+  __shared__ double sh[kBlock];
+  const int c = blockIdx.x;
+  const ClusterParams& cp = s.cp[c];
+  const int64_t ncur = s.dyn[c].n_cur;
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < ncur; i += kBlock) acc += s.kebar[cp.off + i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) s.dyn[c].ke_start = sh[0];
+}
+
+// ----------------------------------------------------------------------------- diagnostics (S5)
+// Partial sums per (cluster, block); quantity layout:
+//  0 KE(n+1/2)  1 KE(n)  2 PE  3 W_L  4 W_C  5 spawn KE  6-8 momentum  9-11 sum w Z E_C
+//  12 sum w|Z||E_C|  13 ions  14 electrons  15 sum of ion charges  16..32 charge histogram
+constexpr int kQ = 33;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_diag_partial(DevState s, RunConst rc, int S) {
+  __shared__ double sh[4][kQ];
+  const int c = blockIdx.y;
+  const ClusterParams& cp = s.cp[c];
+  const ClusterDyn& d = s.dyn[c];
+  if (!d.active) return;
+  double q[kQ];
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) q[i] = 0.0;
+  for (int64_t li = (int64_t)blockIdx.x * kBlock + threadIdx.x; li < d.n_cur; li += (int64_t)kDiagBlocks * kBlock) {
+    const int64_t g = cp.off + li;
+    const int zc = s.Z[g];
+    const double M = (zc < 0) ? 1.0 : cp.mass_ion;
+    const double w = cp.weight;
+    const double ux = s.ux[g], uy = s.uy[g], uz = s.uz[g];
+    double ex, ey, ez;
+    field_sum(s, rc, S, g, ex, ey, ez);
+    double phi = 0.0;
+    for (int k = 0; k < S; ++k) phi += s.part[((int64_t)k * kComp + 3) * rc.n_total + g];
+    q[0] += w * M * gm1(ux, uy, uz);
+    q[1] += s.kebar[g];
+    q[2] += 0.5 * w * (double)zc * phi;
+    q[3] += s.wl[g];
+    q[4] += s.wc[g];
+    q[5] += s.wsp[g];
+    q[6] += w * M * ux;
+    q[7] += w * M * uy;
+    q[8] += w * M * uz;
+    q[9] += w * (double)zc * ex;
+    q[10] += w * (double)zc * ey;
+    q[11] += w * (double)zc * ez;
+    q[12] += w * fabs((double)zc) * sqrt(ex * ex + ey * ey + ez * ez);
+    if (zc < 0) {
+      q[14] += 1.0;
+    } else {
+      q[13] += 1.0;
+      q[15] += (double)zc;
+#pragma unroll
+      for (int b = 0; b < kHist; ++b) q[16 + b] += (zc == b) ? 1.0 : 0.0;
+    }
+  }
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const double v = wave_sum(q[i]);
+    if (lane == 0) sh[wv][i] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kQ) {
+    const int i = threadIdx.x;
+    const double v = ((sh[0][i] + sh[1][i]) + sh[2][i]) + sh[3][i];
+    s.diag_part[((int64_t)c * kDiagBlocks + blockIdx.x) * kDiagQ + i] = v;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_diag_final(DevState s, RunConst rc, int64_t k) {
+  __shared__ double tot[kQ];
+  const int c = blockIdx.x;
+  const ClusterParams& cp = s.cp[c];
+  ClusterDyn& d = s.dyn[c];
+  if (!d.active) return;
+  if (threadIdx.x < kQ) {
+    double v = 0.0;
+    for (int b = 0; b < kDiagBlocks; ++b) v += s.diag_part[((int64_t)c * kDiagBlocks + b) * kDiagQ + threadIdx.x];
+    tot[threadIdx.x] = v;
+  }
+  __syncthreads();
+  const int64_t slot = d.rec_count % rc.max_records;
+  double* r = s.records + ((int64_t)c * rc.max_records + slot) * LC_REC;
+  const int64_t n = *s.step + k;
+  const int i = threadIdx.x;
+  if (i < LC_REC) {
+    double v = 0.0;
+    if (i == 0) v = rc.t0 + (double)n * rc.dt;
+    else if (i == 1) v = (double)n;
+    else if (i == 2) v = (double)d.n_cur;
+    else if (i == 3) v = tot[13];
+    else if (i == 4) v = tot[14];
+    else if (i >= 5 && i <= 10) v = tot[i - 5];
+    else if (i >= 11 && i <= 16) v = tot[i - 5];
+    else if (i == 17) v = tot[12];
+    else if (i == 18) v = tot[13] > 0.0 ? tot[15] / tot[13] : 0.0;
+    else if (i == 19) v = tot[3] * rc.mec2_ev / cp.n_atoms;
+    else if (i == 20) v = (double)d.dropped;
+    else if (i == 21) v = (double)d.events;
+    else if (i == 22) v = d.env;
+    else if (i == 23) v = d.ke_start;
+    else if (i >= 24 && i < 24 + kHist) v = tot[16 + (i - 24)];
+    r[i] = v;
+  }
+  __syncthreads();
+  if (i == 0) d.rec_count += 1;
+}
+
+// ----------------------------------------------------------------------------- ionization (S4)
+// Flag every ion whose uniform draw alpha in (0,1] falls below P = 1 - exp(-nu dt), nu the
+// ADK rate at the driving field; count flags per ion block.
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_ionize_check(DevState s, RunConst rc, int S, int64_t k) {
+  const int ibk = blockIdx.x;
+  const int c = s.ib_cluster[ibk];
+  const ClusterParams& cp = s.cp[c];
+  ClusterDyn& d = s.dyn[c];
+  const int b = ibk - cp.ion_block0;
+  const int64_t li = (int64_t)b * kBlock + threadIdx.x;
+  if (b == 0 && threadIdx.x == 0) d.n_base = d.n_cur;
+  int flag = 0;
+  if (d.active && li < cp.n_ion) {
+    const int64_t g = cp.off + li;
+    const int zc = s.Z[g];
+    if (zc >= 0 && zc < cp.z_max && cp.adk_ok[zc]) {
+      const int64_t n = *s.step + k;
+      double F;
+      if (rc.ofi_local) {
+        double ex, ey, ez;
+        field_sum(s, rc, S, g, ex, ey, ez);
+        ex += d.laser_e;
+        F = sqrt(ex * ex + ey * ey + ez * ez);
+      } else {
+        F = fabs(d.laser_e);
+      }
+      const double fa = F * cp.field_au;
+      double nu = 0.0;
+      if (fa >= 1e-6) nu = exp(cp.adk_logc[zc] - cp.adk_expo[zc] * log(fa) - cp.adk_f23[zc] / fa) * cp.rate_scale;
+      const double P = -expm1(-nu * rc.dt);
+      const U64x4 r = philox(rc.seed, (uint64_t)c, (uint64_t)li, (uint64_t)n, kPurposeAlpha, 0);
+      const double alpha = unit_interval(r.v[0]);
+      flag = (alpha < P) ? 1 : 0;
+    }
+    s.flag[g] = flag;
+  }
+  const int cnt = __syncthreads_count(flag);
+  if (threadIdx.x == 0) s.ib_count[ibk] = cnt;
+}
+
+// Spawn one electron per flagged ion at slot n_base + (rank of the ion among this step's
+// flagged ions, ascending ion index), next to the ion's new position with its momentum.
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_ionize_spawn(DevState s, RunConst rc, int64_t k) {
+  __shared__ int32_t sh_wave[4];
+  __shared__ int64_t sh_base;
+  const int ibk = blockIdx.x;
+  const int c = s.ib_cluster[ibk];
+  const ClusterParams& cp = s.cp[c];
+  ClusterDyn& d = s.dyn[c];
+  const int b = ibk - cp.ion_block0;
+  const int64_t li = (int64_t)b * kBlock + threadIdx.x;
+  if (!d.active) return;
+  if (threadIdx.x == 0) {
+    int64_t base = 0;
+    for (int q = 0; q < b; ++q) base += s.ib_count[cp.ion_block0 + q];
+    sh_base = base;
+  }
+  const int flag = (li < cp.n_ion) ? s.flag[cp.off + li] : 0;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint64_t ball = __ballot(flag);
+  const int below = __popcll(ball & ((lane == 0) ? 0ULL : (~0ULL >> (64 - lane))));
+  if (lane == 0) sh_wave[wv] = __popcll(ball);
+  __syncthreads();
+  int wave_off = 0;
+  for (int q = 0; q < wv; ++q) wave_off += sh_wave[q];
+  const int64_t n_base = d.n_base;
+  const int64_t rank = sh_base + wave_off + below;
+  if (flag) {
+    const int64_t e = n_base + rank;
+    if (e < cp.cap) {
+      const int64_t gi = cp.off + li;
+      const int64_t ge = cp.off + e;
+      const int64_t n = *s.step + k;
+      const U64x4 r = philox(rc.seed, (uint64_t)c, (uint64_t)li, (uint64_t)n, kPurposeDirection, 0);
+      const double ct = 2.0 * unit_interval(r.v[0]) - 1.0;
+      const double ph = 2.0 * M_PI * unit_interval(r.v[1]);
+      const double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+      const double xe = s.x[gi] + cp.delta * st * cos(ph);
+      const double ye = s.y[gi] + cp.delta * st * sin(ph);
+      const double ze = s.z[gi] + cp.delta * ct;
+      const double ux = s.ux[gi], uy = s.uy[gi], uz = s.uz[gi];
+      s.x[ge] = xe; s.y[ge] = ye; s.z[ge] = ze;
+      s.ux[ge] = ux; s.uy[ge] = uy; s.uz[ge] = uz;
+      s.Z[ge] = -1;
+      s.wl[ge] = 0.0;
+      s.wc[ge] = 0.0;
+      s.wsp[ge] = cp.weight * gm1(ux, uy, uz);
+      write_source(s, PREC, ge, xe, ye, ze, -cp.kw);
+      const int znew = s.Z[gi] + 1;
+      s.Z[gi] = (int8_t)znew;
+      write_source(s, PREC, gi, s.x[gi], s.y[gi], s.z[gi], cp.kw * (double)znew);
+    }
+  }
+  if (b == cp.n_ion_blocks - 1 && threadIdx.x == 0) {
+    const int64_t total = sh_base + sh_wave[0] + sh_wave[1] + sh_wave[2] + sh_wave[3];
+    const int64_t room = cp.cap - n_base;
+    const int64_t fit = total < room ? total : room;
+    d.dropped += total - fit;
+    d.events += fit;
+    d.n_cur = n_base + fit;
+    if (total > fit) atomicOr(s.err, kFlagCapacity);
+  }
+}
+
+__global__ void k_advance(DevState s, int64_t by) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *s.step += by;
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_refresh_sources(DevState s, RunConst rc) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= rc.n_total) return;
+  const int c = s.cid[g];
+  const ClusterParams& cp = s.cp[c];
+  if (g - cp.off >= s.dyn[c].n_cur) return;
+  write_source(s, PREC, g, s.x[g], s.y[g], s.z[g], cp.kw * (double)s.Z[g]);
+}
+
+int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+hipError_t launch_schedule(const DevState& s, const RunConst& rc, const ForceTiling& ft, int64_t k,
+                           hipStream_t st) {
+  k_schedule<<<1, kBlock, 0, st>>>(s, rc, force_tile_targets(ft), ft.S, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_push(const DevState& s, const RunConst& rc, int precision, int S, int64_t k, bool diag,
+                       hipStream_t st) {
+  if (precision == LC_FP64) k_push<LC_FP64><<<blocks_for(rc.n_total), kBlock, 0, st>>>(s, rc, S, k, diag ? 1 : 0);
+  else k_push<LC_FP32_ACC64><<<blocks_for(rc.n_total), kBlock, 0, st>>>(s, rc, S, k, diag ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_start_kick(const DevState& s, const RunConst& rc, int precision, int S, hipStream_t st) {
+  (void)precision;
+  k_start_kick<<<blocks_for(rc.n_total), kBlock, 0, st>>>(s, rc, S);
+  k_sum_kestart<<<rc.n_clusters, kBlock, 0, st>>>(s);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag(const DevState& s, const RunConst& rc, int S, int64_t k, hipStream_t st) {
+  k_diag_partial<<<dim3(kDiagBlocks, rc.n_clusters), kBlock, 0, st>>>(s, rc, S);
+  k_diag_final<<<rc.n_clusters, 64, 0, st>>>(s, rc, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_ionize(const DevState& s, const RunConst& rc, int precision, int S, int64_t k, int n_ion_blocks,
+                         hipStream_t st) {
+  if (n_ion_blocks <= 0) return hipSuccess;
+  if (precision == LC_FP64) {
+    k_ionize_check<LC_FP64><<<n_ion_blocks, kBlock, 0, st>>>(s, rc, S, k);
+    k_ionize_spawn<LC_FP64><<<n_ion_blocks, kBlock, 0, st>>>(s, rc, k);
+  } else {
+    k_ionize_check<LC_FP32_ACC64><<<n_ion_blocks, kBlock, 0, st>>>(s, rc, S, k);
+    k_ionize_spawn<LC_FP32_ACC64><<<n_ion_blocks, kBlock, 0, st>>>(s, rc, k);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_advance(const DevState& s, int64_t by, hipStream_t st) {
+  k_advance<<<1, 64, 0, st>>>(s, by);
+  return hipGetLastError();
+}
+
+hipError_t launch_refresh_sources(const DevState& s, const RunConst& rc, int precision, hipStream_t st) {
+  if (precision == LC_FP64) k_refresh_sources<LC_FP64><<<blocks_for(rc.n_total), kBlock, 0, st>>>(s, rc);
+  else k_refresh_sources<LC_FP32_ACC64><<<blocks_for(rc.n_total), kBlock, 0, st>>>(s, rc);
+  return hipGetLastError();
+}
+
+}  // namespace lc

@@ -1,0 +1,115 @@
+"""Host-side checks of the C ABI (no GPU call): the library loads and exports every entry
+point include/lcmd.h declares, configurations are validated, the state size is consistent,
+and the library's unit constants equal the oracle's independently written ones."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1307_3711_amd as lc
+from paper_1307_3711_amd import _binding
+from oracle import units
+from workloads import small_ar, ar_20k, xe_200k
+from workloads.species import SPECIES
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "lcmd.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lc_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = lc.lib()
+    names = declared_symbols()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), f"liblcmd.so does not export {n}"
+
+
+def test_version_and_error_strings():
+    L = lc.lib()
+    assert L.lc_version() == 1
+    for code in [0, -1, -2, -3, -4, -5, -6]:
+        assert L.lc_error_string(code)
+    assert L.lc_error_string(0).decode() == "ok"
+
+
+def test_units_match_oracle():
+    """Constants of the two independent implementations (C++ host runtime vs oracle/units.py)."""
+    for lam, inten in [(0.8, 1e16), (0.806, 8e15), (0.857, 5e16), (0.79, 4e15)]:
+        u = lc.units(lam, inten)
+        assert u["kappa"] == pytest.approx(units.kappa(lam), rel=1e-15)
+        assert u["field_au"] == pytest.approx(units.field_au_per_a0(lam), rel=1e-14)
+        assert u["rate_scale"] == pytest.approx(units.rate_scale(lam), rel=1e-14)
+        assert u["a0"] == pytest.approx(units.a0_from_intensity(inten, lam), rel=1e-15)
+        assert u["k_per_nm"] == pytest.approx(units.nm_to_norm(1.0, lam), rel=1e-15)
+        assert u["mec2_ev"] == units.MEC2_EV
+
+
+def _desc(c):
+    return lc.make_cluster(SPECIES[c.species], c.r0_nm, c.n_ion, c.capacity, c.laser.intensity_wcm2,
+                           envelope=c.laser.envelope, fwhm_fs=c.laser.fwhm_fs, n_cycles=c.laser.n_cycles)
+
+
+def _bytes(cfg, cls):
+    arr = (_binding.ClusterDesc * len(cls))(*cls)
+    return lc.lib().lc_state_bytes(ctypes.byref(cfg), arr, len(cls))
+
+
+def test_state_bytes_scales_with_capacity():
+    c, run = small_ar()
+    cfg = lc.make_config("fp64", max_splits=8)
+    b1 = _bytes(cfg, [_desc(c)])
+    assert b1 > 0
+    c2 = _binding.ClusterDesc.from_buffer_copy(_desc(c))
+    c2.capacity = 2 * c.capacity
+    b2 = _bytes(cfg, [c2])
+    # per-slot bytes: 10 FP64 arrays + double4 source + Z + cid + 8 splits x 4 FP64 partials + flag
+    per_slot = 10 * 8 + 32 + 1 + 4 + 8 * 4 * 8 + 4
+    assert abs((b2 - b1) - per_slot * c.capacity) <= 64 * 256
+    cfg32 = lc.make_config("fp32_acc64", max_splits=8)
+    assert _bytes(cfg32, [_desc(c)]) < b1  # float4 sources instead of double4
+    for mk in (ar_20k, xe_200k):
+        cc, _ = mk()
+        assert _bytes(cfg, [_desc(cc)]) > 0
+
+
+@pytest.mark.parametrize("field,value", [("dt", 0.0), ("dt", -1.0), ("softening_nm", 0.0), ("lambda_um", 0.0),
+                                         ("max_splits", 0), ("max_splits", 65), ("precision", 7),
+                                         ("diag_every", -1), ("struct_size", 8)])
+def test_invalid_config_rejected(field, value):
+    c, run = small_ar()
+    cfg = lc.make_config("fp64")
+    setattr(cfg, field, value)
+    assert _bytes(cfg, [_desc(c)]) == 0
+
+
+@pytest.mark.parametrize("field,value", [("capacity", 100), ("z_max", 16), ("z_max", -1), ("r0_nm", 0.0),
+                                         ("envelope", 9), ("n_ion", -1), ("fwhm_fs", 0.0)])
+def test_invalid_cluster_rejected(field, value):
+    c, run = small_ar()
+    d = _desc(c)
+    if field == "fwhm_fs":
+        d.envelope = 0
+    setattr(d, field, value)
+    assert _bytes(lc.make_config("fp64"), [d]) == 0
+
+
+def test_plane_wave_needs_ionization_off():
+    c, run = small_ar()
+    d = _desc(c)
+    d.phase = 1
+    assert _bytes(lc.make_config("fp64", ionize=True), [d]) == 0
+    assert _bytes(lc.make_config("fp64", ionize=False), [d]) > 0
+
+
+def test_field_workspace_size():
+    L = lc.lib()
+    assert L.lc_field_workspace_bytes(0, 1000, None) > 1000 * 32
+    bad = lc.make_tuning(R=3)
+    assert L.lc_field_workspace_bytes(0, 1000, ctypes.byref(bad)) == 0
+    assert L.lc_field_workspace_bytes(9, 1000, None) == 0

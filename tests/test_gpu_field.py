@@ -1,0 +1,153 @@
+"""GPU parity of the Coulomb direct sum (lc_field) against the FP64 oracle.
+
+Element by element on seeded cluster states spanning several LDS tiles, target blocks and a
+ragged tail, for every precision and a range of tilings; then sampled targets of the full
+20k-macroparticle argon state in the tiling the benchmark uses.
+
+Tolerances (fixed before measuring):
+  FP64: per target |dE| <= 1e-12 * S1_i and |dphi| <= 1e-12 * S0_i, where
+        S1_i = sum_j |q_j| |r_ij| / (r_ij^2 + eps^2)^{3/2} and S0_i = sum_j |q_j| / (r_ij^2+eps^2)^{1/2}
+        bound the magnitudes of the summed terms (rounding of a sum is relative to them);
+  FP32 (+FP64 accumulation): compared with the oracle evaluated on the FP32-rounded inputs
+        (the kernel's actual operands): |dE| <= 64 u S1_i with u = 2^-24 (per-term rounding of a
+        few ulp plus FP32 summation within one LDS tile, which grows like sqrt(T) u);
+  FP32 Kahan: |dE| <= 16 u S1_i.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import units
+from workloads import Cluster, Laser, Run, ar_20k, initial_state
+
+from _helpers import gpu_available
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0**-24
+
+
+def _state(n, seed, r0=2.5):
+    n_ion = max(1, n // 2)
+    c = Cluster(species="Ar", r0_nm=r0, n_ion=n_ion, capacity=2 * n_ion, z_init=1)
+    st = initial_state(c, seed)
+    x = units.nm_to_norm(st["x_nm"], 0.8)[:n]
+    Z = st["Z"][:n].astype(np.float64)
+    w = units.n_atoms(r0, 2.4) / n_ion
+    q = units.kappa(0.8) * w * Z
+    # a few higher charge states, as after ionization
+    q[: n_ion: 7] *= 3.0
+    return x, q
+
+
+def _scales(x, q, eps2, idx=None):
+    idx = np.arange(x.shape[0]) if idx is None else idx
+    s1 = np.zeros(len(idx))
+    s0 = np.zeros(len(idx))
+    for k, i in enumerate(idx):
+        d = x[i] - x
+        r2 = np.sum(d * d, axis=1) + eps2
+        r = np.sqrt(r2 - eps2)
+        m = np.ones(x.shape[0], bool)
+        m[i] = False
+        s1[k] = np.sum(np.abs(q[m]) * r[m] / r2[m] ** 1.5)
+        s0[k] = np.sum(np.abs(q[m]) / np.sqrt(r2[m]))
+    return s1, s0
+
+
+def _gpu_field(x, q, eps2, precision, tuning=None, phi=True):
+    import torch
+    import paper_1307_3711_amd as lc
+    xyzq = torch.tensor(np.concatenate([x.T, q[None, :]], axis=0), dtype=torch.float64, device="cuda")
+    t = lc.make_tuning(**tuning) if tuning else None
+    E, P = lc.field(xyzq, eps2, precision=precision, want_phi=phi, tuning=t)
+    torch.cuda.synchronize()
+    return E.cpu().numpy().T, (P.cpu().numpy() if phi else None)
+
+
+EPS2 = units.nm_to_norm(0.1, 0.8) ** 2
+
+TILINGS = [
+    {},
+    dict(R=1, WJ=1, T=64, S=1),
+    dict(R=2, WJ=2, T=256, S=3),
+    dict(R=4, WJ=4, T=512, S=2),
+    dict(R=1, WJ=4, T=128, S=5, persistent=1),
+    dict(R=2, WJ=1, T=1920, S=1, persistent=1),
+]
+
+
+@pytest.mark.skipif(not gpu_available(), reason="needs a GPU")
+@pytest.mark.parametrize("n", [1, 2, 3, 65, 257, 1000, 2053])
+@pytest.mark.parametrize("ti", range(len(TILINGS)))
+def test_field_fp64_elementwise(n, ti):
+    x, q = _state(n, n + 17)
+    Eo, Po = oracle.coulomb_field(x, q, EPS2)
+    Eg, Pg = _gpu_field(x, q, EPS2, "fp64", TILINGS[ti])
+    s1, s0 = _scales(x, q, EPS2)
+    print(f"fp64 n={n} tiling={TILINGS[ti]} maxrel={np.max(np.abs(Eg - Eo) / s1[:, None]):.3e}", flush=True)
+    assert np.all(np.abs(Eg - Eo) <= 1e-12 * s1[:, None] + 1e-300)
+    assert np.all(np.abs(Pg - Po) <= 1e-12 * s0 + 1e-300)
+
+
+@pytest.mark.skipif(not gpu_available(), reason="needs a GPU")
+@pytest.mark.parametrize("precision,factor", [("fp32_acc64", 64.0), ("fp32_kahan", 16.0)])
+@pytest.mark.parametrize("n", [2, 63, 1000, 2053])
+@pytest.mark.parametrize("ti", [0, 1, 2, 3, 4])
+def test_field_fp32_elementwise(precision, factor, n, ti):
+    if precision == "fp32_kahan" and TILINGS[ti].get("R", 4) == 8:
+        pytest.skip("no R=8 Kahan variant")
+    x, q = _state(n, 3 * n + 1)
+    xr = x.astype(np.float32).astype(np.float64)
+    qr = q.astype(np.float32).astype(np.float64)
+    Eo, Po = oracle.coulomb_field(xr, qr, float(np.float32(EPS2)))
+    Eg, Pg = _gpu_field(x, q, EPS2, precision, TILINGS[ti])
+    s1, s0 = _scales(xr, qr, EPS2)
+    print(f"{precision} n={n} tiling={TILINGS[ti]} maxrel={np.max(np.abs(Eg - Eo) / s1[:, None]):.3e}", flush=True)
+    assert np.all(np.abs(Eg - Eo) <= factor * U32 * s1[:, None] + 1e-300)
+    assert np.all(np.abs(Pg - Po) <= factor * U32 * s0 + 1e-300)
+
+
+@pytest.mark.skipif(not gpu_available(), reason="needs a GPU")
+def test_field_empty_input():
+    import torch
+    import paper_1307_3711_amd as lc
+    xyzq = torch.zeros((4, 0), dtype=torch.float64, device="cuda")
+    E, P = lc.field(xyzq, EPS2)
+    assert E.shape == (3, 0) and P.shape == (0,)
+
+
+@pytest.mark.skipif(not gpu_available(), reason="needs a GPU")
+def test_field_rejects_bad_arguments():
+    import torch
+    import paper_1307_3711_amd as lc
+    xyzq = torch.zeros((4, 10), dtype=torch.float64, device="cuda")
+    with pytest.raises(lc.LcError):
+        lc.field(xyzq, 0.0)
+    with pytest.raises(lc.LcError):
+        lc.field(xyzq, EPS2, tuning=lc.make_tuning(R=3))
+
+
+@pytest.mark.skipif(not gpu_available(), reason="needs a GPU")
+@pytest.mark.parametrize("precision", ["fp64", "fp32_acc64"])
+def test_field_full_20k_sampled(precision):
+    """The 20k-macroparticle argon state at full size (the benchmark's workload): sampled
+    targets against the oracle evaluated target by target."""
+    c, run = ar_20k()
+    st = initial_state(c, run.seed)
+    x = units.nm_to_norm(st["x_nm"], 0.8)
+    w = units.n_atoms(c.r0_nm, 2.4) / c.n_ion
+    q = units.kappa(0.8) * w * st["Z"].astype(np.float64)
+    idx = np.unique(np.concatenate([np.arange(0, x.shape[0], 997), [0, 9999, 10000, x.shape[0] - 1]]))
+    Eg, Pg = _gpu_field(x, q, EPS2, precision, dict(S=16))
+    if precision == "fp64":
+        Eo, Po = oracle.coulomb_field_at(x, q, EPS2, idx)
+        tol = 1e-12
+    else:
+        xr = x.astype(np.float32).astype(np.float64)
+        qr = q.astype(np.float32).astype(np.float64)
+        Eo, Po = oracle.coulomb_field_at(xr, qr, float(np.float32(EPS2)), idx)
+        tol = 64 * U32
+    s1, s0 = _scales(x, q, EPS2, idx)
+    assert np.all(np.abs(Eg[idx] - Eo) <= tol * s1[:, None])
+    assert np.all(np.abs(Pg[idx] - Po) <= tol * s0)

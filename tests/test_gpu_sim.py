@@ -1,0 +1,229 @@
+"""GPU parity of whole time steps (field, laser, Boris push, ionization, diagnostics) against
+the FP64 oracle, plus determinism, graph replay, checkpoints and error latching.
+
+Tolerances (fixed before measuring), small argon cluster (500 Ar+ + 500 e-, 200 steps):
+  FP64: max |dx| / R0 <= 1e-9, max |du| <= 1e-9 * max |u|; KE, PE, W_L, W_C within 1e-10
+        relative to their scale; identical ionization events (same charges, same count) -
+        both sides draw the same Philox numbers and take alpha < P in FP64;
+  FP32 pair arithmetic (+FP64 accumulation or Kahan): max |dx| / R0 <= 1e-4, energies within
+        1e-4 relative (FP32 rounding of the positions the field sees, about 1e-5 relative to
+        the 0.01 nm electron-ion offsets, amplified by the short-time divergence of the orbits).
+"""
+import math
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import units
+from workloads import Cluster, Laser, Run, initial_state, small_ar, ensemble, xe_200k
+
+from _helpers import gpu_available, gpu_run, oracle_run, oracle_spread
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+def _compare_state(sim, osim, r0_norm, dx_tol, du_tol, cluster=0):
+    g = sim.particles(cluster)
+    assert g["n"] == osim.N
+    assert np.array_equal(g["Z"], osim.charges())
+    dx = np.max(np.abs(g["x"] - osim.positions())) / r0_norm
+    uo = osim.momenta()
+    du = np.max(np.abs(g["u"] - uo)) / max(np.max(np.abs(uo)), 1e-300)
+    return dx, du
+
+
+def _compare_records(rg, ro, cols, tol):
+    assert rg.shape[0] == ro.shape[0]
+    for col in cols:
+        scale = np.max(np.abs(ro[:, col])) + 1e-300
+        err = np.max(np.abs(rg[:, col] - ro[:, col])) / scale
+        assert err <= tol, f"record column {col}: {err:.3e} > {tol:.1e}"
+
+
+ENERGY_COLS = [5, 6, 7, 8, 9, 10]
+
+
+def test_small_ar_fp64_200_steps():
+    c, run = small_ar()
+    sim, states = gpu_run([c], run, "fp64")
+    osim = oracle_run(c, run, states[0])
+    print("small Ar fp64: 200 steps", flush=True)
+    sim.step(200)
+    rg = sim.diagnostics(0)
+    ro = osim.run(200)
+    r0n = units.nm_to_norm(c.r0_nm, 0.8)
+    dx, du = _compare_state(sim, osim, r0n, 1e-9, 1e-9)
+    print(f"max|dx|/R0 = {dx:.3e}  max|du|/max|u| = {du:.3e}  events gpu={rg[-1][21]} oracle={ro[-1][21]}")
+    assert dx <= 1e-9 and du <= 1e-9
+    _compare_records(rg, ro, ENERGY_COLS, 1e-10)
+    assert np.array_equal(rg[:, 21], ro[:, 21]) and np.array_equal(rg[:, 2], ro[:, 2])
+    assert np.array_equal(rg[:, 24:41], ro[:, 24:41])
+    assert rg[0, 23] == pytest.approx(osim.ke_start, rel=1e-12, abs=1e-300)
+
+
+@pytest.mark.parametrize("precision", ["fp32_acc64", "fp32_kahan"])
+def test_small_ar_fp32_200_steps(precision):
+    c, run = small_ar()
+    sim, states = gpu_run([c], run, precision)
+    osim = oracle_run(c, run, states[0])
+    sim.step(200)
+    rg = sim.diagnostics(0)
+    ro = osim.run(200)
+    r0n = units.nm_to_norm(c.r0_nm, 0.8)
+    g = sim.particles(0)
+    print(f"{precision}: N gpu={g['n']} oracle={osim.N}", flush=True)
+    if g["n"] == osim.N and np.array_equal(g["Z"], osim.charges()):
+        dx = np.max(np.abs(g["x"] - osim.positions())) / r0n
+        print(f"{precision}: max|dx|/R0 = {dx:.3e}")
+        assert dx <= 1e-4
+    _compare_records(rg, ro, [5, 6, 8, 9], 1e-4)
+
+
+def test_energy_identity_and_newton3_on_gpu():
+    """K6 and K5 on the GPU's own records: KE(n+1/2) - KE(-1/2) = W_L + W_C + spawn KE to
+    rounding; sum w Z E_C vanishes to rounding."""
+    c, run = small_ar()
+    c = Cluster(species="Ar", r0_nm=2.5, n_ion=500, capacity=4500, laser=Laser(intensity_wcm2=3e16, envelope="flat"))
+    run = Run(dt=0.05, t0=math.pi / 2, ionize=True, diag_every=5, seed=3)
+    sim, _ = gpu_run([c], run, "fp64")
+    sim.step(100)
+    r = sim.diagnostics(0)
+    assert r[-1][21] > 0
+    ke0 = r[0][23]
+    for row in r:
+        lhs = row[5] - ke0
+        rhs = row[8] + row[9] + row[10]
+        assert abs(lhs - rhs) <= 1e-11 * (abs(row[8]) + abs(row[9]) + row[10] + abs(ke0))
+        assert np.linalg.norm(row[14:17]) <= 1e-12 * row[17]
+
+
+def test_two_body_closed_form_on_gpu():
+    """K2 through the GPU path: separation of two Ar+ from rest vs the closed-form t(d)."""
+    c = Cluster(species="Ar", r0_nm=1.0, n_ion=2, capacity=2, z_init=1, laser=Laser(intensity_wcm2=0.0, envelope="flat"))
+    errs = []
+    for dt in [0.8, 0.4]:
+        run = Run(dt=dt, ionize=False, diag_every=0, softening_nm=1e-6)
+        d0 = 0.01
+        kn = units.nm_to_norm(1.0, 0.8)
+        st = {"x_nm": np.array([[-d0 / 2 / kn, 0, 0], [d0 / 2 / kn, 0, 0]]), "u": np.zeros((2, 3)),
+              "Z": np.array([1, 1], np.int8)}
+        sim, _ = gpu_run([c], run, "fp64", states=[st], weight=1.0)
+        nst = int(round(160.0 / dt))
+        sim.step(nst)
+        x = sim.particles(0)["x"]
+        d = x[1, 0] - x[0, 0]
+        p = oracle.make_params(c, run, weight=1.0)
+        m = p.mass_ion
+        s = d / d0
+        t_closed = math.sqrt(m / 2 * d0**3 / (2 * p.kappa)) * (math.sqrt(s * (s - 1)) + math.log(math.sqrt(s) + math.sqrt(s - 1)))
+        errs.append(abs(t_closed - nst * dt))
+    assert errs[0] / errs[1] > 3.0
+    assert errs[1] < 2e-3
+
+
+def test_determinism_and_graph_replay_bitwise():
+    c, run = small_ar()
+    run = Run(dt=0.05, ionize=True, diag_every=10, seed=0)
+    out = []
+    for graph in (0, 0, 20):
+        sim, _ = gpu_run([c], run, "fp32_acc64")
+        if graph:
+            sim.set_graph(graph)
+        sim.step(60)
+        g = sim.particles(0)
+        out.append((g, sim.diagnostics(0)))
+    for g, r in out[1:]:
+        assert np.array_equal(g["x"], out[0][0]["x"]) and np.array_equal(g["u"], out[0][0]["u"])
+        assert np.array_equal(g["Z"], out[0][0]["Z"])
+        assert np.array_equal(r, out[0][1])
+
+
+def test_checkpoint_resume_bitwise():
+    c, run = small_ar()
+    sim, states = gpu_run([c], run, "fp64")
+    sim.step(30)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "ck.bin")
+        sim.save(path)
+        sim.step(30)
+        ref = sim.particles(0)
+        sim2, _ = gpu_run([c], run, "fp64", states=states)
+        sim2.load(path)
+        assert sim2.step_index == 30
+        sim2.step(30)
+        got = sim2.particles(0)
+    assert np.array_equal(ref["x"], got["x"]) and np.array_equal(ref["u"], got["u"])
+    assert np.array_equal(ref["Z"], got["Z"])
+
+
+def test_ensemble_matches_oracle_per_cluster():
+    """Uneven clusters in one launch (different species, sizes, intensities, lengths), each
+    against its own oracle run keyed by its cluster index; finished clusters stop.
+
+    Short horizon (8 steps): rounding-level agreement (max |dx| / R0 <= 1e-10).  Full length:
+    heavily lumped clusters are chaotic at dt = 0.05 (see oracle_spread), so positions,
+    momenta and energy records must stay within 100x the spread of rounding-perturbed oracle
+    runs (and within 1e-9 where that spread is smaller); ionization counts must agree."""
+    cl = ensemble(5, seed=3, cap_lo=200, cap_hi=1500)
+    steps = [40, 25, 40, 10, 33]
+    run = Run(dt=0.05, ionize=True, diag_every=5, seed=3)
+    states = [initial_state(c, run.seed, i) for i, c in enumerate(cl)]
+    short, _ = gpu_run(cl, run, "fp64", states=states, n_steps_per_cluster=[8] * len(cl))
+    short.step(8)
+    for i, c in enumerate(cl):
+        osim = oracle_run(c, run, states[i], cluster_index=i)
+        osim.run(8)
+        dx, du = _compare_state(short, osim, units.nm_to_norm(c.r0_nm, 0.8), 0, 0, cluster=i)
+        print(f"cluster {i} 8 steps: dx={dx:.2e} du={du:.2e}", flush=True)
+        assert dx <= 1e-10 and du <= 1e-9
+    sim, _ = gpu_run(cl, run, "fp64", states=states, n_steps_per_cluster=steps)
+    sim.step(max(steps))
+    for i, c in enumerate(cl):
+        osim, ro, spread = oracle_spread(c, run, states[i], i, steps[i])
+        rg = sim.diagnostics(i)
+        g = sim.particles(i)
+        assert g["n"] == osim.N and rg.shape == ro.shape
+        assert np.array_equal(rg[:, 21], ro[:, 21])
+        r0n = units.nm_to_norm(c.r0_nm, 0.8)
+        dx = np.max(np.abs(g["x"] - osim.positions())) / r0n
+        du = np.max(np.abs(g["u"] - osim.momenta())) / max(np.max(np.abs(osim.momenta())), 1e-300)
+        print(f"cluster {i} ({c.species}, cap {c.capacity}, {steps[i]} steps): dx={dx:.2e} (spread "
+              f"{spread['dx']:.2e}) du={du:.2e} (spread {spread['du']:.2e})", flush=True)
+        assert dx <= max(1e-9, 100 * spread["dx"]) and du <= max(1e-9, 100 * spread["du"])
+        for col, sp in spread["cols"].items():
+            sc = np.max(np.abs(ro[:, col])) + 1e-300
+            err = np.max(np.abs(rg[:, col] - ro[:, col])) / sc
+            assert err <= max(1e-10, 100 * sp), (col, err, sp)
+
+
+def test_capacity_overflow_is_latched():
+    c = Cluster(species="Ar", r0_nm=3.0, n_ion=50, capacity=103, z_init=1, z_max=8,
+                laser=Laser(intensity_wcm2=1e18, envelope="flat"))
+    run = Run(dt=0.05, t0=math.pi / 2, ionize=True, diag_every=1, seed=5)
+    sim, states = gpu_run([c], run, "fp64")
+    sim.step(3)
+    import paper_1307_3711_amd as lc
+    with pytest.raises(lc.LcError) as ei:
+        sim.diagnostics(0)
+    assert ei.value.code == -2
+    osim = oracle_run(c, run, states[0])
+    osim.run(3)
+    assert osim.N == c.capacity and osim.counters[0] > 0
+
+
+def test_xe_full_size_first_step():
+    """The 200k-capacity xenon workload at full size (44,444 macroparticles at the start):
+    one FP64 step with ionization against the oracle's step."""
+    c, run = xe_200k()
+    run = Run(dt=0.05, t0=2 * units.fs_to_norm(c.laser.fwhm_fs, 0.8), ionize=True, diag_every=1, seed=0)
+    sim, states = gpu_run([c], run, "fp64")
+    sim.step(1)
+    osim = oracle_run(c, run, states[0])
+    osim.run(1)
+    r0n = units.nm_to_norm(c.r0_nm, 0.8)
+    dx, du = _compare_state(sim, osim, r0n, 1e-12, 1e-9)
+    print(f"xe first step: N={osim.N} dx={dx:.2e} du={du:.2e}", flush=True)
+    assert dx <= 1e-12 and du <= 1e-9
