@@ -29,7 +29,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def make_sim(precision, c, run, st, graph):
+def make_sim(precision, c, run, st, graph, tiling=None):
     import paper_1307_3711_amd as lc
     from workloads.species import SPECIES
     cfg = lc.make_config(precision, ionize=run.ionize, dt=run.dt, softening_nm=run.softening_nm,
@@ -40,10 +40,31 @@ def make_sim(precision, c, run, st, graph):
     sim = lc.Simulation(cfg, [desc])
     sim.init_from_host(0, st["x_nm"], st["u"], st["Z"])
     sim.start()
-    tuned = sim.autotune()
+    if tiling:
+        sim.set_tuning(**tiling)
+        tuned = sim.tuning()
+    else:
+        tuned = sim.autotune()
     if graph:
         sim.set_graph(graph)
     return sim, tuned
+
+
+def counter_traffic(tuned, n):
+    """HBM bytes per Coulomb-kernel launch from the committed rocprofv3 counter runs, or None
+    when the kernel source or the tiling has changed since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_force_f32_ar20k_counters.json")
+    try:
+        rec = json.load(open(path))
+        src = open(os.path.join(ROOT, "paper_1307_3711_amd", "csrc", "force.hip"), "rb").read()
+    except OSError:
+        return None
+    if hashlib.sha256(src).hexdigest() != rec["force_hip_sha256"] or rec["n_particles"] != n:
+        return None
+    if any(tuned.get(k) != v for k, v in rec["tiling"].items()):
+        return None
+    return rec["traffic_bytes_per_launch"]
 
 
 def timed_steps(sim, steps):
@@ -83,7 +104,23 @@ def main():
     ap.add_argument("--graph", type=int, default=100)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tiling", default="", help="R,WJ,T,S,persistent: skip the autotuner")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy a 1 GiB buffer 3 times (HBM counter calibration for rocprofv3)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": src.numel() * 4, "copies": 3}))
+        return
+    tiling = None
+    if args.tiling:
+        R, WJ, T, S, P = [int(v) for v in args.tiling.split(",")]
+        tiling = dict(R=R, WJ=WJ, T=T, S=S, persistent=P)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
@@ -100,7 +137,7 @@ def main():
     pairs = float(n) * float(n)
 
     log(f"bench: {n} macroparticles, fp32_acc64, autotune")
-    sim, tuned = make_sim("fp32_acc64", c, run, st, args.graph)
+    sim, tuned = make_sim("fp32_acc64", c, run, st, args.graph, tiling)
     log(f"bench: tiling {tuned}; warmup {args.warmup}")
     sim.step(args.warmup)
     sim.stream.synchronize()
@@ -123,7 +160,7 @@ def main():
                    "n_particles": n, "pairs_per_step": pairs, "tiling": tuned, "graph_steps": args.graph},
         "cluster_steps_per_s": round(args.steps / wall, 2),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                     "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": counter_traffic(tuned, n),
                      "kernel": "k_force_f32", "avg_launch_ms": round(avg_force_s * 1e3, 5),
                      "launches": force_n, "flops_per_pair": FLOPS_PER_PAIR},
         "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 5) for k, v in prof.items() if v[1]},
