@@ -95,8 +95,160 @@ def cpu_baseline(c, run, st, n, target_s=15.0):
                       f"(FP64, {dt:.1f} s)"}
 
 
+def ensemble_inputs(n_clusters, seed, steps_scale=1.0):
+    """Descriptions and initial states of one seeded ensemble of uneven Ar/Xe clusters."""
+    import paper_1307_3711_amd as lc
+    from workloads import ensemble, initial_state
+    from workloads.species import SPECIES
+    cl = ensemble(n_clusters, seed=seed)
+    descs, states = [], []
+    for i, c in enumerate(cl):
+        d = lc.make_cluster(SPECIES[c.species], c.r0_nm, c.n_ion, c.capacity, c.laser.intensity_wcm2,
+                            envelope=c.laser.envelope, fwhm_fs=c.laser.fwhm_fs, z_max=c.z_max,
+                            electron_offset_nm=c.electron_offset_nm, n_steps=max(1, int(c.n_steps * steps_scale)))
+        descs.append(d)
+        states.append(initial_state(c, seed, i))
+    return cl, descs, states
+
+
+def bench_ensemble(args):
+    """256 uneven clusters (Ar/Xe, 1k-16k capacity, 2-10 nm, 1e15-1e17 W/cm^2, 20-100 fs),
+    each run to t_end = 4 FWHM (or --steps), FP32+FP64acc vs the FP64 path on the same work."""
+    import numpy as np
+    from paper_1307_3711_amd.ensemble import run_ensemble
+    cl, descs, states = ensemble_inputs(args.clusters, args.seed)
+    max_steps = args.steps if args.steps_given else None
+    log(f"ensemble: {len(cl)} clusters, capacity {sum(c.capacity for c in cl)}, "
+        f"up to {max(c.n_steps for c in cl)} steps")
+    r32 = run_ensemble(descs, states, "fp32_acc64", max_steps=max_steps, graph_steps=args.graph // 2 or 50,
+                       progress=lambda d, t: log(f"  fp32 step {d}/{t}"))
+    out = {"metric": "cluster-steps/s (FP32 pair math + FP64 accumulation), 256-cluster ensemble",
+           "value": round(r32["cluster_steps"] / r32["wall_s"], 2), "unit": "cluster-steps/s", "n_gpus": 1,
+           "steps": r32["steps"], "warmup": 0, "ms_per_step": round(r32["wall_s"] / r32["steps"] * 1e3, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32+fp64acc",
+           "data": "synthetic",
+           "config": {"workload": f"{len(cl)} Ar/Xe clusters, capacity log-uniform 1k-16k, R0 2-10 nm, "
+                                  "1e15-1e17 W/cm2, FWHM 20-100 fs, t_end = 4 FWHM, ionization on",
+                      "seed": args.seed, "tiling": r32["tiling"], "total_capacity": int(sum(c.capacity for c in cl))},
+           "gpairs_per_s": round(r32["pairs"] / r32["wall_s"] / 1e9, 2), "pairs": r32["pairs"],
+           "wall_s": round(r32["wall_s"], 3)}
+    if not args.no_fp64:
+        r64 = run_ensemble(descs, states, "fp64", max_steps=max_steps, graph_steps=args.graph // 2 or 50,
+                           progress=lambda d, t: log(f"  fp64 step {d}/{t}"))
+        a32, a64 = r32["last"][:, 19], r64["last"][:, 19]
+        z32, z64 = r32["last"][:, 18], r64["last"][:, 18]
+        rel_a = np.abs(a32 - a64) / np.maximum(np.abs(a64), 1e-30)
+        out["fp64"] = {"value": round(r64["cluster_steps"] / r64["wall_s"], 2), "unit": "cluster-steps/s",
+                       "gpairs_per_s": round(r64["pairs"] / r64["wall_s"] / 1e9, 2), "wall_s": round(r64["wall_s"], 3)}
+        out["error_vs_fp64"] = {"absorbed_eV_per_atom_rel_median": float(np.median(rel_a)),
+                                "absorbed_eV_per_atom_rel_p90": float(np.quantile(rel_a, 0.9)),
+                                "mean_charge_abs_median": float(np.median(np.abs(z32 - z64))),
+                                "mean_charge_abs_max": float(np.max(np.abs(z32 - z64)))}
+    print(json.dumps(out), flush=True)
+
+
+def _features_of(cl):
+    from paper_1307_3711_amd.ensemble import features
+    from workloads.species import SPECIES
+    import numpy as np
+    r0 = np.array([c.r0_nm for c in cl])
+    na = np.array([(c.r0_nm * 10.0 / SPECIES[c.species]["rw_angstrom"]) ** 3 for c in cl])
+    inten = np.array([c.laser.intensity_wcm2 for c in cl])
+    fwhm = np.array([c.laser.fwhm_fs for c in cl])
+    return features(r0, na, inten, fwhm)
+
+
+def bench_surrogate(args):
+    """Train the 4-64-64-2 surrogate on ensemble MD runs, time 1M-point inference, and judge it
+    on held-out clusters re-run by the MD (three extra seeds give the MD's own spread)."""
+    import numpy as np
+    import torch
+    import paper_1307_3711_amd as lc
+    from paper_1307_3711_amd.ensemble import run_ensemble, targets
+    from workloads import initial_state, surrogate_inputs
+    from workloads.species import SPECIES
+    from workloads.surrogate import init_params, row_order
+
+    Xl, Yl = [], []
+    md_wall = md_runs = md_cs = 0
+    for b in range(args.batches):
+        cl, descs, states = ensemble_inputs(256, b)
+        r = run_ensemble(descs, states, "fp32_acc64", seed=b, progress=lambda d, t: log(f"  batch {b}: {d}/{t}"))
+        md_wall += r["wall_s"]
+        md_runs += len(cl)
+        md_cs += r["cluster_steps"]
+        Xl.append(_features_of(cl))
+        Yl.append(targets(r["last"]))
+        log(f"surrogate data: batch {b} done in {r['wall_s']:.1f} s")
+    X = np.concatenate(Xl)
+    Y = np.concatenate(Yl)
+    n = X.shape[0]
+    perm = np.random.Generator(np.random.Philox(key=[0, 77])).permutation(n)
+    n_tr = int(0.9 * n)
+    tr, va = perm[:n_tr], perm[n_tr:]
+    Xtr, Ytr = torch.from_numpy(X[tr]).cuda(), torch.from_numpy(Y[tr]).cuda()
+    net = lc.Surrogate(init_params(0))
+    net.fit_scaler(Xtr, Ytr)
+    batch = 256
+    rows = torch.from_numpy(row_order(n_tr, batch, args.train_steps, 1)).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = net.train(Xtr, Ytr, rows, batch, args.train_steps, args.lr)
+    net.stream.synchronize()
+    train_s = time.perf_counter() - t0
+    pv = net.infer(torch.from_numpy(X[va]).cuda()).cpu().numpy()
+    val_rmse = np.sqrt(np.mean((pv - Y[va]) ** 2, axis=0))
+
+    # inference throughput on 1M query points
+    q = surrogate_inputs(1_000_000, seed=100)
+    na = (q[:, 0] * 10.0 / q[:, 1]) ** 3
+    from paper_1307_3711_amd.ensemble import features
+    Xq = torch.from_numpy(features(q[:, 0], na, q[:, 2], q[:, 3])).cuda()
+    net.infer(Xq)
+    net.stream.synchronize()
+    t0 = time.perf_counter()
+    reps = 20
+    for _ in range(reps):
+        Yq = net.infer(Xq)
+    net.stream.synchronize()
+    inf_s = (time.perf_counter() - t0) / reps
+
+    # held-out clusters (ensemble seed 200) re-run by the MD with 4 seeds
+    cl, descs, _ = ensemble_inputs(64, 200)
+    ph = net.infer(torch.from_numpy(_features_of(cl)).cuda()).cpu().numpy()
+    md = []
+    for sd in (200, 201, 202, 203):
+        states = [initial_state(c, sd, i) for i, c in enumerate(cl)]
+        r = run_ensemble(descs, states, "fp32_acc64", seed=sd)
+        md.append(targets(r["last"]))
+    md = np.array(md)
+    rmse_sur = np.sqrt(np.mean((ph - md[0]) ** 2, axis=0))
+    rmse_md = np.sqrt(np.mean((md[1:] - md[0][None]) ** 2, axis=(0, 1)))
+    md_runs_per_s = md_runs / md_wall
+    out = {"metric": "surrogate points/s (BF16 MFMA 4-64-64-2) vs MD cluster runs/s", "value": round(1e6 / inf_s, 1),
+           "unit": "points/s", "n_gpus": 1, "steps": args.train_steps, "warmup": 0,
+           "ms_per_step": round(train_s / max(args.train_steps, 1) * 1e3, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (fp32 accumulate)", "data": "synthetic",
+           "config": {"workload": f"{md_runs} ensemble MD runs ({args.batches} x 256 clusters), 90/10 split, "
+                                  "batch 256, Adam; 1M-point inference; 64 held-out clusters re-run by MD",
+                      "lr": args.lr},
+           "md_runs_per_s": round(md_runs_per_s, 3), "md_cluster_steps_per_s": round(md_cs / md_wall, 1),
+           "speedup_vs_md": round((1e6 / inf_s) / md_runs_per_s, 1), "train_s": round(train_s, 3),
+           "final_train_loss": float(losses[-50:].mean().cpu()),
+           "val_rmse": {"log_absorbed_eV": float(val_rmse[0]), "mean_charge": float(val_rmse[1])},
+           "heldout_rmse_vs_md": {"log_absorbed_eV": float(rmse_sur[0]), "mean_charge": float(rmse_sur[1])},
+           "md_seed_spread_rmse": {"log_absorbed_eV": float(rmse_md[0]), "mean_charge": float(rmse_md[1])}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--batches", type=int, default=16, help="surrogate: 256-cluster ensembles of training data")
+    ap.add_argument("--train-steps", type=int, default=6000)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--workload", default="ar20k", choices=["ar20k", "ensemble", "surrogate"])
+    ap.add_argument("--clusters", type=int, default=256)
+    ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--warmup", type=int, default=100)
@@ -108,6 +260,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB buffer 3 times (HBM counter calibration for rocprofv3)")
     args = ap.parse_args()
+    args.steps_given = any(a.startswith("--steps") for a in sys.argv[1:])
     if args.copy_probe:
         import torch
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -125,6 +278,11 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "ensemble":
+        return bench_ensemble(args)
+    if args.workload == "surrogate":
+        return bench_surrogate(args)
 
     import numpy as np
     import torch

@@ -177,6 +177,11 @@ int lc_read_particles(lc_sim* sim, int32_t cluster, double* x, double* u, int8_t
 /* Current time-step index (host mirror of the device counter). */
 int64_t lc_step_index(const lc_sim* sim);
 
+/* Work counters of one cluster: out[0] steps taken (a cluster stops at its n_steps),
+ * out[1] live macroparticles, out[2] pair interactions evaluated (sum over its steps of
+ * N^2, self pairs included), out[3] ionization events.  Synchronizes the stream. */
+int lc_cluster_counters(lc_sim* sim, int32_t cluster, double out[4]);
+
 /* Set or read the Coulomb kernel tiling used by this handle. */
 int lc_set_tuning(lc_sim* sim, const lc_tuning* t);
 int lc_get_tuning(const lc_sim* sim, lc_tuning* t);
@@ -214,6 +219,53 @@ size_t lc_field_workspace_bytes(int32_t precision, int64_t n, const lc_tuning* t
  * LC_E_INVALID for n < 0, eps2 <= 0, a too small workspace or an unknown tiling. */
 int lc_field(int32_t precision, int64_t n, const double* d_xyzq, double eps2, double* d_E,
              double* d_phi, void* d_work, size_t work_bytes, const lc_tuning* t, void* hip_stream);
+
+/* ---------------------------------------------------------------- surrogate network */
+/* A small network 4-64-64-2 (SiLU hidden units) that maps standardized features of a
+ * cluster run (log R0, log N_atoms from Eq.(1), log peak intensity, log pulse FWHM) to
+ * standardized (log absorbed energy per atom, mean ion charge).  It is trained on ensemble
+ * runs of the model above and answers in place of a run.  FP32 master weights and Adam
+ * moments; BF16 weights, inputs, hidden activations and hidden-2 gradient in the products;
+ * FP32 accumulation on the BF16 matrix cores.
+ *
+ * Parameter order (4,610 floats): W1 (64 x 4 row-major), b1 (64), W2 (64 x 64, W2[n][k] maps
+ * hidden-1 unit k to hidden-2 unit n), b2 (64), W3 (2 x 64), b3 (2).
+ * Device pointers below are caller-owned; d_state must hold lc_mlp_state_bytes() bytes
+ * (256-B aligned).  Rows of d_X are 4 floats, rows of d_Y 2 floats. */
+size_t lc_mlp_state_bytes(void);
+int lc_mlp_n_params(void);
+
+/* Upload FP32 master weights from host memory; zero the Adam moments and step count and
+ * reset the scaler to identity.  Synchronizes the stream. */
+int lc_mlp_set_params(void* d_state, const float* host_params, void* hip_stream);
+
+/* Copy the master weights (4,610 floats) and the scaler (x mean[4], x std[4], y mean[2],
+ * y std[2]) to host memory (either pointer may be NULL).  Synchronizes the stream. */
+int lc_mlp_get_params(const void* d_state, float* host_params, float* host_scaler, void* hip_stream);
+
+/* Population mean and standard deviation of every input and target column over n rows
+ * (FP64 sums in row order), stored as the scaler.  Asynchronous. */
+int lc_mlp_fit_scaler(void* d_state, const float* d_X, const float* d_Y, int64_t n, void* hip_stream);
+
+/* steps Adam steps (lr, beta1 0.9, beta2 0.999, eps 1e-8) on minibatches of `batch` rows
+ * (32..256, a multiple of 32): step k uses rows d_rows[k*batch .. (k+1)*batch) of d_X/d_Y
+ * (d_rows: steps*batch int32 in [0, n)).  Loss (1/(2B)) sum (y - t)^2 of each step goes to
+ * d_loss[k] (may be NULL).  One workgroup runs all steps in a fixed order (bitwise
+ * reproducible).  Asynchronous; an out-of-range row is replaced by row 0 and reported by
+ * lc_mlp_status. */
+int lc_mlp_train(void* d_state, const float* d_X, const float* d_Y, int64_t n, const int32_t* d_rows,
+                 int32_t batch, int32_t steps, float lr, float* d_loss, void* hip_stream);
+
+/* Gradient of the loss over one minibatch (rows d_rows[0..batch)) without updating the
+ * weights: d_grad receives 4,610 floats in parameter order, d_loss one float. */
+int lc_mlp_grad(void* d_state, const float* d_X, const float* d_Y, int64_t n, const int32_t* d_rows,
+                int32_t batch, float* d_grad, float* d_loss, void* hip_stream);
+
+/* Predict n rows: raw features in (standardized inside), de-standardized outputs out. */
+int lc_mlp_infer(const void* d_state, const float* d_X, float* d_Y, int64_t n, void* hip_stream);
+
+/* LC_E_INVALID if a training call met an out-of-range row, else LC_OK.  Synchronizes. */
+int lc_mlp_status(const void* d_state, void* hip_stream);
 
 /* ---------------------------------------------------------------- constants and errors */
 

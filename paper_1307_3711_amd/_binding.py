@@ -103,6 +103,7 @@ def lib():
         "lc_read_diagnostics": ([vp, ctypes.c_int32, dp, ctypes.c_int32, i32p], ctypes.c_int),
         "lc_read_particles": ([vp, ctypes.c_int32, dp, dp, i8p, dp, dp, ctypes.c_int64, i64p], ctypes.c_int),
         "lc_step_index": ([vp], ctypes.c_int64),
+        "lc_cluster_counters": ([vp, ctypes.c_int32, dp], ctypes.c_int),
         "lc_set_tuning": ([vp, tp], ctypes.c_int),
         "lc_get_tuning": ([vp, tp], ctypes.c_int),
         "lc_autotune": ([vp, ctypes.c_char_p, tp], ctypes.c_int),
@@ -110,6 +111,16 @@ def lib():
         "lc_load_state": ([vp, ctypes.c_char_p], ctypes.c_int),
         "lc_destroy": ([vp], None),
         "lc_profile_steps": ([vp, ctypes.c_int64, dp, i64p], ctypes.c_int),
+        "lc_mlp_state_bytes": ([], ctypes.c_size_t),
+        "lc_mlp_n_params": ([], ctypes.c_int),
+        "lc_mlp_set_params": ([vp, vp, vp], ctypes.c_int),
+        "lc_mlp_get_params": ([vp, vp, vp, vp], ctypes.c_int),
+        "lc_mlp_fit_scaler": ([vp, vp, vp, ctypes.c_int64, vp], ctypes.c_int),
+        "lc_mlp_train": ([vp, vp, vp, ctypes.c_int64, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, vp, vp],
+                         ctypes.c_int),
+        "lc_mlp_grad": ([vp, vp, vp, ctypes.c_int64, vp, ctypes.c_int32, vp, vp, vp], ctypes.c_int),
+        "lc_mlp_infer": ([vp, vp, vp, ctypes.c_int64, vp], ctypes.c_int),
+        "lc_mlp_status": ([vp, vp], ctypes.c_int),
         "lc_field_workspace_bytes": ([ctypes.c_int32, ctypes.c_int64, tp], ctypes.c_size_t),
         "lc_field": ([ctypes.c_int32, ctypes.c_int64, vp, ctypes.c_double, vp, vp, vp, ctypes.c_size_t, tp, vp],
                      ctypes.c_int),
@@ -249,6 +260,12 @@ class Simulation:
         k = n.value
         return {"x": x[:k], "u": u[:k], "Z": Z[:k], "wl": wl[:k], "wc": wc[:k], "n": k}
 
+    def counters(self, cluster=0):
+        """(steps taken, live macroparticles, pair interactions evaluated, ionization events)."""
+        out = (ctypes.c_double * 4)()
+        _check(lib().lc_cluster_counters(self.h, cluster, out), self.h)
+        return {"steps": int(out[0]), "n": int(out[1]), "pairs": out[2], "events": int(out[3])}
+
     def tuning(self):
         t = Tuning()
         _check(lib().lc_get_tuning(self.h, ctypes.byref(t)), self.h)
@@ -301,3 +318,89 @@ def field(xyzq, eps2, precision="fp64", want_phi=True, tuning=None):
                       int(wb), tp, ctypes.c_void_p(st.cuda_stream))
     _check(code)
     return E, phi
+
+
+class Surrogate:
+    """The 4-64-64-2 surrogate network on the GPU (lc_mlp_*).
+
+    Its state (master weights, Adam moments, scaler, scratch) lives in one torch uint8 tensor;
+    inputs and outputs are CUDA float32 tensors of shape (n, 4) and (n, 2).
+    """
+
+    def __init__(self, params, device="cuda", stream=None):
+        L = lib()
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        with torch.cuda.stream(self.stream):
+            self.state = torch.empty(int(L.lc_mlp_state_bytes()), dtype=torch.uint8, device=self.device)
+        self.set_params(params)
+
+    def _st(self):
+        return ctypes.c_void_p(self.stream.cuda_stream)
+
+    def _ptr(self, t):
+        return ctypes.c_void_p(t.data_ptr())
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, np.float32)
+        if p.size != lib().lc_mlp_n_params():
+            raise ValueError("wrong number of parameters")
+        _check(lib().lc_mlp_set_params(self._ptr(self.state), p.ctypes.data_as(ctypes.c_void_p), self._st()))
+
+    def params(self):
+        p = np.zeros(lib().lc_mlp_n_params(), np.float32)
+        sc = np.zeros(12, np.float32)
+        _check(lib().lc_mlp_get_params(self._ptr(self.state), p.ctypes.data_as(ctypes.c_void_p),
+                                       sc.ctypes.data_as(ctypes.c_void_p), self._st()))
+        return p, {"x_mu": sc[0:4], "x_sd": sc[4:8], "y_mu": sc[8:10], "y_sd": sc[10:12]}
+
+    @staticmethod
+    def _check_xy(X, Y=None):
+        if X.dtype != torch.float32 or not X.is_cuda or X.dim() != 2 or X.shape[1] != 4 or not X.is_contiguous():
+            raise ValueError("X must be a contiguous (n, 4) float32 CUDA tensor")
+        if Y is not None and (Y.dtype != torch.float32 or not Y.is_cuda or Y.shape != (X.shape[0], 2)
+                              or not Y.is_contiguous()):
+            raise ValueError("Y must be a contiguous (n, 2) float32 CUDA tensor")
+
+    def _sync_inputs(self):
+        # inputs were produced on torch's current stream; order the library's stream after it
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def fit_scaler(self, X, Y):
+        self._check_xy(X, Y)
+        self._sync_inputs()
+        _check(lib().lc_mlp_fit_scaler(self._ptr(self.state), self._ptr(X), self._ptr(Y), X.shape[0], self._st()))
+
+    def train(self, X, Y, rows, batch, steps, lr):
+        self._check_xy(X, Y)
+        if rows.dtype != torch.int32 or not rows.is_cuda or rows.numel() < steps * batch:
+            raise ValueError("rows must be an int32 CUDA tensor of at least steps*batch entries")
+        self._sync_inputs()
+        with torch.cuda.stream(self.stream):
+            loss = torch.empty(max(steps, 1), dtype=torch.float32, device=self.device)
+        _check(lib().lc_mlp_train(self._ptr(self.state), self._ptr(X), self._ptr(Y), X.shape[0], self._ptr(rows),
+                                  batch, steps, float(lr), self._ptr(loss), self._st()))
+        _check(lib().lc_mlp_status(self._ptr(self.state), self._st()))
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return loss[:steps]
+
+    def grad(self, X, Y, rows, batch):
+        self._check_xy(X, Y)
+        self._sync_inputs()
+        with torch.cuda.stream(self.stream):
+            g = torch.empty(lib().lc_mlp_n_params(), dtype=torch.float32, device=self.device)
+            loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        _check(lib().lc_mlp_grad(self._ptr(self.state), self._ptr(X), self._ptr(Y), X.shape[0], self._ptr(rows),
+                                 batch, self._ptr(g), self._ptr(loss), self._st()))
+        self.stream.synchronize()
+        return g, loss
+
+    def infer(self, X):
+        self._check_xy(X)
+        self._sync_inputs()
+        with torch.cuda.stream(self.stream):
+            Y = torch.empty((X.shape[0], 2), dtype=torch.float32, device=self.device)
+        _check(lib().lc_mlp_infer(self._ptr(self.state), self._ptr(X), self._ptr(Y), X.shape[0], self._st()))
+        # hand the result to the caller's stream: its next use waits for the kernel
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return Y

@@ -235,7 +235,7 @@ hipError_t enqueue_steps(lc_sim* s, int count, int64_t first_step) {
   const int grid = force_grid(s, ft);
   for (int k = 0; k < count; ++k) {
     const bool diag = s->cfg.diag_every > 0 && ((first_step + k) % s->cfg.diag_every) == 0;
-    hipError_t e = launch_schedule(s->s, s->rc, ft, k, s->stream);
+    hipError_t e = launch_schedule(s->s, s->rc, ft, k, s->stream, true);
     if (e != hipSuccess) return e;
     e = launch_force(s->s, s->rc, s->cfg.precision, ft, diag, grid, s->stream);
     if (e != hipSuccess) return e;
@@ -554,6 +554,20 @@ int lc_step(lc_sim* s, int64_t n_steps) {
 
 int64_t lc_step_index(const lc_sim* s) { return s ? s->step : -1; }
 
+int lc_cluster_counters(lc_sim* s, int32_t cluster, double out[4]) {
+  if (!s || !out) return LC_E_INVALID;
+  if (cluster < 0 || cluster >= s->C) return fail(s, LC_E_INVALID, "cluster index out of range");
+  hipError_t e = hipStreamSynchronize(s->stream);
+  ClusterDyn d;
+  if (e == hipSuccess) e = hipMemcpy(&d, s->s.dyn + cluster, sizeof(ClusterDyn), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(s, e, "lc_cluster_counters");
+  out[0] = (double)d.steps_done;
+  out[1] = (double)d.n_cur;
+  out[2] = d.pairs;
+  out[3] = (double)d.events;
+  return LC_OK;
+}
+
 int lc_read_diagnostics(lc_sim* s, int32_t cluster, double* records, int32_t max_records, int32_t* n_out) {
   if (!s || !n_out || max_records < 0) return LC_E_INVALID;
   if (cluster < 0 || cluster >= s->C) return fail(s, LC_E_INVALID, "cluster index out of range");
@@ -850,7 +864,7 @@ extern "C" int lc_profile_steps(lc_sim* s, int64_t n_steps, double* out_ms, int6
     for (int64_t k = 0; k < m && e == hipSuccess; ++k) {
       const bool diag = s->cfg.diag_every > 0 && (s->step % s->cfg.diag_every) == 0;
       hipEvent_t* E = &ev[8 * k];
-      e = launch_schedule(s->s, s->rc, ft, 0, s->stream);
+      e = launch_schedule(s->s, s->rc, ft, 0, s->stream, true);
       if (e == hipSuccess) e = hipEventRecord(E[0], s->stream);
       if (e == hipSuccess) e = launch_force(s->s, s->rc, s->cfg.precision, ft, diag, grid, s->stream);
       if (e == hipSuccess) e = hipEventRecord(E[1], s->stream);

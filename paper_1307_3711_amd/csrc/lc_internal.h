@@ -69,6 +69,8 @@ struct ClusterDyn {
   int32_t n_tiles;      // tiles of this cluster this step
   int32_t i_blocks;     // target blocks this step
   int32_t active;       // 1 while step < n_steps
+  double pairs;         // sum over the steps taken of n_cur^2 (pair interactions evaluated)
+  int64_t steps_done;   // steps this cluster has taken
 };
 
 // Run-wide constants passed by value to every kernel.
@@ -131,7 +133,7 @@ struct ForceTiling {
 hipError_t launch_force(const DevState& s, const RunConst& rc, int precision, const ForceTiling& ft,
                         bool want_phi, int grid_blocks, hipStream_t st);
 hipError_t launch_schedule(const DevState& s, const RunConst& rc, const ForceTiling& ft, int64_t k,
-                           hipStream_t st);
+                           hipStream_t st, bool count_step = false);
 hipError_t launch_push(const DevState& s, const RunConst& rc, int precision, int S, int64_t k, bool diag,
                        hipStream_t st);
 hipError_t launch_start_kick(const DevState& s, const RunConst& rc, int precision, int S, hipStream_t st);

@@ -95,7 +95,8 @@ __device__ inline void laser_at(const ClusterParams& cp, const ClusterDyn& d, do
 // ----------------------------------------------------------------------------- schedule (S6)
 // One block: per cluster, active flag, laser value at t^n, target blocks and tiles of this
 // step; exclusive scan of tiles over clusters in `order` (largest first).
-__global__ __launch_bounds__(kBlock) void k_schedule(DevState s, RunConst rc, int TI, int S, int64_t k) {
+__global__ __launch_bounds__(kBlock) void k_schedule(DevState s, RunConst rc, int TI, int S, int64_t k,
+                                                     int count_step) {
   __shared__ int32_t sh_scan[kBlock];
   __shared__ int32_t sh_carry;
   const int tid = threadIdx.x;
@@ -120,6 +121,10 @@ __global__ __launch_bounds__(kBlock) void k_schedule(DevState s, RunConst rc, in
       d.active = active;
       d.i_blocks = ib;
       d.n_tiles = tiles;
+      if (count_step && active) {
+        d.pairs += (double)ncur * (double)ncur;
+        d.steps_done += 1;
+      }
     }
     sh_scan[tid] = tiles;
     __syncthreads();
@@ -491,8 +496,8 @@ int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 }  // namespace
 
 hipError_t launch_schedule(const DevState& s, const RunConst& rc, const ForceTiling& ft, int64_t k,
-                           hipStream_t st) {
-  k_schedule<<<1, kBlock, 0, st>>>(s, rc, force_tile_targets(ft), ft.S, k);
+                           hipStream_t st, bool count_step) {
+  k_schedule<<<1, kBlock, 0, st>>>(s, rc, force_tile_targets(ft), ft.S, k, count_step ? 1 : 0);
   return hipGetLastError();
 }
 
