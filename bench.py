@@ -147,6 +147,48 @@ def bench_ensemble(args):
     print(json.dumps(out), flush=True)
 
 
+PUSH_BYTES = 173     # per live particle: read x,u (48) Z (1) cluster id (4) W_L,W_C (16) field (24);
+                     # write x,u (48) W_L,W_C (16) float4 source (16)
+ION_BYTES = 9        # per ion: read Z (1), write + read the ionization flag (8)
+
+
+def bench_particles(args):
+    """HBM probe of the particle-parallel kernels on >= 4M live macroparticles: 1024 Ar
+    clusters of 2048 Ar+ + 2048 e- (capacity 8192 each), FP32 sources, one source split."""
+    import numpy as np
+    import paper_1307_3711_amd as lc
+    from workloads import Cluster, Laser, initial_state
+    from workloads.species import SPECIES
+    nc = args.clusters if args.clusters != 256 else 1024
+    c = Cluster(species="Ar", r0_nm=6.0, n_ion=2048, capacity=8192, z_init=1, z_max=8,
+                laser=Laser(intensity_wcm2=1e15, envelope="flat"))
+    cfg = lc.make_config("fp32_acc64", ionize=True, diag_every=0, max_records=1, max_splits=1, seed=1, t0=1.3)
+    d = lc.make_cluster(SPECIES["Ar"], c.r0_nm, c.n_ion, c.capacity, c.laser.intensity_wcm2, envelope="flat")
+    sim = lc.Simulation(cfg, [d] * nc)
+    st = initial_state(c, 1, 0)
+    for i in range(nc):
+        sim.init_from_host(i, st["x_nm"], st["u"], st["Z"])
+    sim.set_tuning(S=1)
+    sim.start()
+    n_live = nc * st["x_nm"].shape[0]
+    t = sim.time_particle_kernels(5)
+    t = sim.time_particle_kernels(args.reps)
+    push_gbs = n_live * PUSH_BYTES / (t["push_ms"] * 1e-3) / 1e9
+    ion_gbs = nc * c.n_ion * ION_BYTES / (t["ionize_ms"] * 1e-3) / 1e9
+    out = {"metric": "HBM GB/s of the push and ionization kernels (>= 4M live macroparticles)",
+           "value": round(push_gbs, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.reps, "warmup": 5,
+           "ms_per_step": round(t["push_ms"], 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{nc} Ar clusters x (2048 Ar+ + 2048 e-), capacity 8192, 1e15 W/cm2 flat",
+                      "live_particles": n_live, "ions": nc * c.n_ion},
+           "roofline": {"bound": "hbm", "achieved": round(push_gbs, 1), "peak": 8000.0, "unit": "GB/s",
+                        "frac": round(push_gbs / 8000.0, 4), "traffic": None, "kernel": "k_push",
+                        "bytes_per_particle": PUSH_BYTES},
+           "ionize": {"ms": round(t["ionize_ms"], 5), "GB_per_s": round(ion_gbs, 1), "bytes_per_ion": ION_BYTES,
+                      "frac_of_hbm_peak": round(ion_gbs / 8000.0, 4)}}
+    print(json.dumps(out), flush=True)
+
+
 def _features_of(cl):
     from paper_1307_3711_amd.ensemble import features
     from workloads.species import SPECIES
@@ -246,7 +288,8 @@ def main():
     ap.add_argument("--batches", type=int, default=16, help="surrogate: 256-cluster ensembles of training data")
     ap.add_argument("--train-steps", type=int, default=6000)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--workload", default="ar20k", choices=["ar20k", "ensemble", "surrogate"])
+    ap.add_argument("--workload", default="ar20k", choices=["ar20k", "ensemble", "surrogate", "particles"])
+    ap.add_argument("--reps", type=int, default=50)
     ap.add_argument("--clusters", type=int, default=256)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--gpus", type=int, default=1)
@@ -283,6 +326,8 @@ def main():
         return bench_ensemble(args)
     if args.workload == "surrogate":
         return bench_surrogate(args)
+    if args.workload == "particles":
+        return bench_particles(args)
 
     import numpy as np
     import torch

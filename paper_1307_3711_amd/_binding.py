@@ -104,6 +104,7 @@ def lib():
         "lc_read_particles": ([vp, ctypes.c_int32, dp, dp, i8p, dp, dp, ctypes.c_int64, i64p], ctypes.c_int),
         "lc_step_index": ([vp], ctypes.c_int64),
         "lc_cluster_counters": ([vp, ctypes.c_int32, dp], ctypes.c_int),
+        "lc_time_particle_kernels": ([vp, ctypes.c_int32, dp], ctypes.c_int),
         "lc_set_tuning": ([vp, tp], ctypes.c_int),
         "lc_get_tuning": ([vp, tp], ctypes.c_int),
         "lc_autotune": ([vp, ctypes.c_char_p, tp], ctypes.c_int),
@@ -259,6 +260,12 @@ class Simulation:
                                        wc.ctypes.data_as(dp), cap, ctypes.byref(n)), self.h)
         k = n.value
         return {"x": x[:k], "u": u[:k], "Z": Z[:k], "wl": wl[:k], "wc": wc[:k], "n": k}
+
+    def time_particle_kernels(self, reps=20):
+        """Average ms of the push kernel and of the ionization kernels (lc_time_particle_kernels)."""
+        out = (ctypes.c_double * 2)()
+        _check(lib().lc_time_particle_kernels(self.h, int(reps), out), self.h)
+        return {"push_ms": out[0], "ionize_ms": out[1]}
 
     def counters(self, cluster=0):
         """(steps taken, live macroparticles, pair interactions evaluated, ionization events)."""

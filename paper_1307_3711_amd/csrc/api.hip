@@ -233,24 +233,26 @@ hipError_t enqueue_steps(lc_sim* s, int count, int64_t first_step) {
   ForceTiling ft = s->ft;
   ft.S = s->S_eff;
   const int grid = force_grid(s, ft);
+  // The tables of the first step were built by the previous step's closing schedule (or by
+  // lc_start / a tiling change); every step ends with the schedule of the next one.
   for (int k = 0; k < count; ++k) {
     const bool diag = s->cfg.diag_every > 0 && ((first_step + k) % s->cfg.diag_every) == 0;
-    hipError_t e = launch_schedule(s->s, s->rc, ft, k, s->stream, true);
+    hipError_t e = launch_force(s->s, s->rc, s->cfg.precision, ft, diag, grid, s->stream);
     if (e != hipSuccess) return e;
-    e = launch_force(s->s, s->rc, s->cfg.precision, ft, diag, grid, s->stream);
-    if (e != hipSuccess) return e;
-    e = launch_push(s->s, s->rc, s->cfg.precision, ft.S, k, diag, s->stream);
+    e = launch_push(s->s, s->rc, s->cfg.precision, ft.S, 0, diag, s->stream);
     if (e != hipSuccess) return e;
     if (diag) {
-      e = launch_diag(s->s, s->rc, ft.S, k, s->stream);
+      e = launch_diag(s->s, s->rc, ft.S, 0, s->stream);
       if (e != hipSuccess) return e;
     }
     if (s->cfg.ionize) {
-      e = launch_ionize(s->s, s->rc, s->cfg.precision, ft.S, k, s->L.n_ion_blocks, s->stream);
+      e = launch_ionize(s->s, s->rc, s->cfg.precision, ft.S, 0, s->L.n_ion_blocks, s->stream);
       if (e != hipSuccess) return e;
     }
+    e = launch_schedule(s->s, s->rc, ft, true, s->stream);
+    if (e != hipSuccess) return e;
   }
-  return launch_advance(s->s, count, s->stream);
+  return hipSuccess;
 }
 
 void drop_graph(lc_sim* s) {
@@ -498,7 +500,7 @@ int lc_start(lc_sim* s) {
   ForceTiling ft = s->ft;
   ft.S = s->S_eff;
   hipError_t e = launch_refresh_sources(s->s, s->rc, s->cfg.precision, s->stream);
-  if (e == hipSuccess) e = launch_schedule(s->s, s->rc, ft, 0, s->stream);
+  if (e == hipSuccess) e = launch_schedule(s->s, s->rc, ft, false, s->stream);
   if (e == hipSuccess) e = launch_force(s->s, s->rc, s->cfg.precision, ft, false, force_grid(s, ft), s->stream);
   if (e == hipSuccess) e = launch_start_kick(s->s, s->rc, s->cfg.precision, ft.S, s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "lc_start");
@@ -553,6 +555,33 @@ int lc_step(lc_sim* s, int64_t n_steps) {
 }
 
 int64_t lc_step_index(const lc_sim* s) { return s ? s->step : -1; }
+
+int lc_time_particle_kernels(lc_sim* s, int32_t reps, double out_ms[2]) {
+  if (!s || !out_ms || reps < 1 || reps > 10000) return LC_E_INVALID;
+  if (!s->started) return fail(s, LC_E_STATE, "lc_time_particle_kernels before lc_start");
+  ForceTiling ft = s->ft;
+  ft.S = s->S_eff;
+  hipEvent_t ev[4];
+  for (auto& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) return fail(s, LC_E_HIP, "hipEventCreate");
+  hipError_t e = launch_schedule(s->s, s->rc, ft, false, s->stream);
+  if (e == hipSuccess) e = hipEventRecord(ev[0], s->stream);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_push(s->s, s->rc, s->cfg.precision, ft.S, 0, false, s->stream);
+  if (e == hipSuccess) e = hipEventRecord(ev[1], s->stream);
+  if (e == hipSuccess) e = hipEventRecord(ev[2], s->stream);
+  for (int r = 0; r < reps && e == hipSuccess && s->cfg.ionize; ++r)
+    e = launch_ionize(s->s, s->rc, s->cfg.precision, ft.S, 0, s->L.n_ion_blocks, s->stream);
+  if (e == hipSuccess) e = hipEventRecord(ev[3], s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  float a = 0.f, b = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&a, ev[0], ev[1]);
+  if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[2], ev[3]);
+  for (auto& x : ev) (void)hipEventDestroy(x);
+  if (e != hipSuccess) return hip_fail(s, e, "lc_time_particle_kernels");
+  out_ms[0] = a / reps;
+  out_ms[1] = s->cfg.ionize ? b / reps : 0.0;
+  return LC_OK;
+}
 
 int lc_cluster_counters(lc_sim* s, int32_t cluster, double out[4]) {
   if (!s || !out) return LC_E_INVALID;
@@ -645,6 +674,12 @@ int lc_set_tuning(lc_sim* s, const lc_tuning* t) {
   }
   s->S_eff = S_new;
   drop_graph(s);
+  if (s->started) {
+    ForceTiling cur = ft;
+    cur.S = S_new;
+    hipError_t e = launch_schedule(s->s, s->rc, cur, false, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "lc_set_tuning");
+  }
   return LC_OK;
 }
 
@@ -709,6 +744,10 @@ int lc_load_state(lc_sim* s, const char* path) {
   for (auto& v : s->inited) v = 1;
   s->started = true;
   drop_graph(s);
+  ForceTiling cur = s->ft;
+  cur.S = s->S_eff;
+  e = launch_schedule(s->s, s->rc, cur, false, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "lc_load_state");
   return LC_OK;
 }
 
@@ -728,7 +767,7 @@ __global__ void k_fold_partials(double* part, int64_t stride, int S) {
 
 int field_snapshot(lc_sim* s, const ForceTiling& ft, std::vector<double>& out) {
   const int64_t NT = s->L.n_total;
-  hipError_t e = launch_schedule(s->s, s->rc, ft, 0, s->stream);
+  hipError_t e = launch_schedule(s->s, s->rc, ft, false, s->stream);
   if (e == hipSuccess) e = launch_force(s->s, s->rc, s->cfg.precision, ft, false, force_grid(s, ft), s->stream);
   if (e == hipSuccess) {
     k_fold_partials<<<(int)((NT + kBlock - 1) / kBlock), kBlock, 0, s->stream>>>(s->s.part, NT, ft.S);
@@ -799,11 +838,11 @@ extern "C" int lc_autotune(lc_sim* s, const char* cache_json, lc_tuning* chosen)
             for (int c = 0; c < s->C; ++c) nmax = std::max(nmax, s->n_host[c]);
             if ((int64_t)S * 64 > std::max<int64_t>(nmax, 64)) continue;
             const int reps = 3;
-            hipError_t e = launch_schedule(s->s, s->rc, ft, 0, s->stream);
+            hipError_t e = launch_schedule(s->s, s->rc, ft, false, s->stream);
             if (e == hipSuccess) e = launch_force(s->s, s->rc, prec, ft, false, force_grid(s, ft), s->stream);  // warm
             if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
             for (int r = 0; r < reps && e == hipSuccess; ++r) {
-              e = launch_schedule(s->s, s->rc, ft, 0, s->stream);
+              e = launch_schedule(s->s, s->rc, ft, false, s->stream);
               if (e == hipSuccess) e = launch_force(s->s, s->rc, prec, ft, false, force_grid(s, ft), s->stream);
             }
             if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
@@ -828,6 +867,10 @@ extern "C" int lc_autotune(lc_sim* s, const char* cache_json, lc_tuning* chosen)
   s->ft = best;
   s->S_eff = best.S;
   drop_graph(s);
+  {
+    hipError_t e = launch_schedule(s->s, s->rc, best, false, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "lc_autotune");
+  }
   if (chosen) lc_get_tuning(s, chosen);
   if (cache_json) {
     FILE* f = std::fopen(cache_json, "a");
@@ -864,8 +907,7 @@ extern "C" int lc_profile_steps(lc_sim* s, int64_t n_steps, double* out_ms, int6
     for (int64_t k = 0; k < m && e == hipSuccess; ++k) {
       const bool diag = s->cfg.diag_every > 0 && (s->step % s->cfg.diag_every) == 0;
       hipEvent_t* E = &ev[8 * k];
-      e = launch_schedule(s->s, s->rc, ft, 0, s->stream, true);
-      if (e == hipSuccess) e = hipEventRecord(E[0], s->stream);
+      e = hipEventRecord(E[0], s->stream);
       if (e == hipSuccess) e = launch_force(s->s, s->rc, s->cfg.precision, ft, diag, grid, s->stream);
       if (e == hipSuccess) e = hipEventRecord(E[1], s->stream);
       used[4 * k + 0] = 1;
@@ -885,7 +927,7 @@ extern "C" int lc_profile_steps(lc_sim* s, int64_t n_steps, double* out_ms, int6
         if (e == hipSuccess) e = hipEventRecord(E[7], s->stream);
         used[4 * k + 3] = 1;
       }
-      if (e == hipSuccess) e = launch_advance(s->s, 1, s->stream);
+      if (e == hipSuccess) e = launch_schedule(s->s, s->rc, ft, true, s->stream);
       s->step += 1;
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);

@@ -18,11 +18,11 @@
 //     the persistent variant pulls tiles from a device counter instead of blockIdx.
 //
 // Precision variants:
-//   LC_FP64        : FP64 pair terms; 1/sqrt from v_rsq_f64 refined by two Newton-Raphson
-//                    steps y <- y (3 - r2 y^2)/2 (quadratic convergence from the ~2^-23
-//                    hardware estimate to FP64 rounding).
+//   LC_FP64        : FP64 pair terms; 1/sqrt from v_rsq_f64 refined by the second-order
+//                    series of (1 - e)^{-1/2} (one FMA-based residual, cubic convergence).
 //   LC_FP32_ACC64  : FP32 pair terms with v_rsq_f32, FP32 sums within one LDS tile, FP64
-//                    accumulation across tiles.
+//                    accumulation across tiles; tiles of equal-charge sources (the electron
+//                    block, frozen or equal ion charges) use a loop with the charge factored out.
 //   LC_FP32_KAHAN  : as above with Kahan-compensated FP32 sums within the tile.
 #include "lc_internal.h"
 
@@ -30,7 +30,7 @@ namespace lc {
 
 namespace {
 
-constexpr int kU = 4;  // inner-loop unroll; LDS tiles are padded to a multiple of it
+constexpr int kU = 8;  // inner-loop unroll; LDS tiles are padded to a multiple of it (times WJ)
 
 struct TileMap {
   const int32_t* tile_start;   // [n_clusters + 1] prefix over clusters in `order`
@@ -68,14 +68,63 @@ __device__ inline void decode_tile(const TileMap& m, int t, int S, int& c, int& 
 
 __device__ inline float rsq32(float x) { return __builtin_amdgcn_rsqf(x); }
 
+// 1/sqrt(x) to FP64 rounding: with y0 from v_rsq_f64 and e = 1 - x y0^2 (computed with an
+// FMA), 1/sqrt(x) = y0 (1 - e)^{-1/2} = y0 (1 + e/2 + 3e^2/8 + O(e^3)); the hardware estimate
+// leaves |e| below about 2^-22, so the truncated series is exact to far below an FP64 ulp.
 __device__ inline double rsq64(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  double h = x * y;
-  double e = __builtin_fma(-h, y, 1.0);
-  y = __builtin_fma(0.5 * y, e, y);
-  h = x * y;
-  e = __builtin_fma(-h, y, 1.0);
-  return __builtin_fma(0.5 * y, e, y);
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = __builtin_fma(-x * y, y, 1.0);
+  const double p = __builtin_fma(0.375, e, 0.5);
+  return __builtin_fma(y * e, p, y);
+}
+
+// ----------------------------------------------------------------------------- FP32 pair loop
+// Sources [kb, kb + per) of the LDS tile against the lane's R targets.  UNIFORM: every source
+// has the same charge q0 and the caller multiplies the sums by it (q r^-3 costs one multiply
+// less per pair).  PHI: also the potential, with the self pair masked out by index.
+template <int R, bool PHI, bool KAHAN, bool UNIFORM>
+__device__ inline void pair_loop(const float4* lds, int kb, int per, int64_t jt, const int64_t* ii, const float* xi,
+                                 const float* yi, const float* zi, float eps2f, float* fx, float* fy, float* fz,
+                                 float* fp) {
+  float cx[R], cy[R], cz[R], cpc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) { fx[r] = fy[r] = fz[r] = fp[r] = 0.f; cx[r] = cy[r] = cz[r] = cpc[r] = 0.f; }
+  for (int k = kb; k < kb + per; k += kU) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const float4 sj = lds[k + u];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const float dx = xi[r] - sj.x;
+        const float dy = yi[r] - sj.y;
+        const float dz = zi[r] - sj.z;
+        float r2 = __builtin_fmaf(dx, dx, eps2f);
+        r2 = __builtin_fmaf(dy, dy, r2);
+        r2 = __builtin_fmaf(dz, dz, r2);
+        const float inv = rsq32(r2);
+        float qinv = UNIFORM ? inv : sj.w * inv;
+        const float sc = qinv * (inv * inv);
+        if (KAHAN) {
+          float y, tt;
+          y = __builtin_fmaf(sc, dx, -cx[r]); tt = fx[r] + y; cx[r] = (tt - fx[r]) - y; fx[r] = tt;
+          y = __builtin_fmaf(sc, dy, -cy[r]); tt = fy[r] + y; cy[r] = (tt - fy[r]) - y; fy[r] = tt;
+          y = __builtin_fmaf(sc, dz, -cz[r]); tt = fz[r] + y; cz[r] = (tt - fz[r]) - y; fz[r] = tt;
+        } else {
+          fx[r] = __builtin_fmaf(sc, dx, fx[r]);
+          fy[r] = __builtin_fmaf(sc, dy, fy[r]);
+          fz[r] = __builtin_fmaf(sc, dz, fz[r]);
+        }
+        if (PHI) {
+          if (jt + k + u == ii[r]) qinv = 0.f;  // exclude the self pair from the potential
+          if (KAHAN) {
+            float y = qinv - cpc[r]; float tt = fp[r] + y; cpc[r] = (tt - fp[r]) - y; fp[r] = tt;
+          } else {
+            fp[r] += qinv;
+          }
+        }
+      }
+    }
+  }
 }
 
 // ----------------------------------------------------------------------------- FP32 body
@@ -113,58 +162,35 @@ __device__ void tile_f32(const ForceArgs<float4>& a, int t, float4* lds) {
   for (int64_t jt = j0; jt < j1; jt += a.T) {
     const int cnt = (int)((j1 - jt < a.T) ? (j1 - jt) : a.T);
     const int cntp = (cnt + kU * WJ - 1) / (kU * WJ) * (kU * WJ);
+    // Padding entries sit at 1e30: r^2 overflows to +inf, v_rsq_f32(+inf) = +0, so they add
+    // exactly zero on both inner loops.  A tile whose sources all carry the same charge takes
+    // the uniform loop, which factors the charge out of the pair term.
+    const float q0 = a.src[off + jt].w;
+    int same = 1;
     __syncthreads();
-    for (int k = tid; k < cntp; k += kBlock)
-      lds[k] = (k < cnt) ? a.src[off + jt + k] : make_float4(0.f, 0.f, 0.f, 0.f);
-    __syncthreads();
+    for (int k = tid; k < cntp; k += kBlock) {
+      float4 v = make_float4(1e30f, 1e30f, 1e30f, 0.f);
+      if (k < cnt) {
+        v = a.src[off + jt + k];
+        same &= (v.w == q0);
+      }
+      lds[k] = v;
+    }
+    const int uniform = __syncthreads_and(same);
     const int per = cntp / WJ;
     const int kb = jw * per;
     float fx[R], fy[R], fz[R], fp[R];
-    float cx[R], cy[R], cz[R], cpc[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) { fx[r] = fy[r] = fz[r] = fp[r] = 0.f; cx[r] = cy[r] = cz[r] = cpc[r] = 0.f; }
-    for (int k = kb; k < kb + per; k += kU) {
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const float4 sj = lds[k + u];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const float dx = xi[r] - sj.x;
-          const float dy = yi[r] - sj.y;
-          const float dz = zi[r] - sj.z;
-          float r2 = __builtin_fmaf(dx, dx, eps2f);
-          r2 = __builtin_fmaf(dy, dy, r2);
-          r2 = __builtin_fmaf(dz, dz, r2);
-          const float inv = rsq32(r2);
-          float qinv = sj.w * inv;
-          const float sc = qinv * (inv * inv);
-          if (KAHAN) {
-            float y, tt;
-            y = __builtin_fmaf(sc, dx, -cx[r]); tt = fx[r] + y; cx[r] = (tt - fx[r]) - y; fx[r] = tt;
-            y = __builtin_fmaf(sc, dy, -cy[r]); tt = fy[r] + y; cy[r] = (tt - fy[r]) - y; fy[r] = tt;
-            y = __builtin_fmaf(sc, dz, -cz[r]); tt = fz[r] + y; cz[r] = (tt - fz[r]) - y; fz[r] = tt;
-          } else {
-            fx[r] = __builtin_fmaf(sc, dx, fx[r]);
-            fy[r] = __builtin_fmaf(sc, dy, fy[r]);
-            fz[r] = __builtin_fmaf(sc, dz, fz[r]);
-          }
-          if (PHI) {
-            if (jt + k + u == ii[r]) qinv = 0.f;  // exclude the self pair from the potential
-            if (KAHAN) {
-              float y = qinv - cpc[r]; float tt = fp[r] + y; cpc[r] = (tt - fp[r]) - y; fp[r] = tt;
-            } else {
-              fp[r] += qinv;
-            }
-          }
-        }
-      }
-    }
+    if (uniform)
+      pair_loop<R, PHI, KAHAN, true>(lds, kb, per, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp);
+    else
+      pair_loop<R, PHI, KAHAN, false>(lds, kb, per, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp);
+    const double qs = uniform ? (double)q0 : 1.0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      ex[r] += (double)fx[r];
-      ey[r] += (double)fy[r];
-      ez[r] += (double)fz[r];
-      if (PHI) ep[r] += (double)fp[r];
+      ex[r] += (double)fx[r] * qs;
+      ey[r] += (double)fy[r] * qs;
+      ez[r] += (double)fz[r] * qs;
+      if (PHI) ep[r] += (double)fp[r] * qs;
     }
   }
 

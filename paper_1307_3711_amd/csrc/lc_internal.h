@@ -70,6 +70,7 @@ struct ClusterDyn {
   int32_t i_blocks;     // target blocks this step
   int32_t active;       // 1 while step < n_steps
   double pairs;         // sum over the steps taken of n_cur^2 (pair interactions evaluated)
+  int64_t n_sched;      // particle count the current step's tiles were built for
   int64_t steps_done;   // steps this cluster has taken
 };
 
@@ -132,15 +133,14 @@ struct ForceTiling {
 // Host launchers (defined in force.hip / step.hip).
 hipError_t launch_force(const DevState& s, const RunConst& rc, int precision, const ForceTiling& ft,
                         bool want_phi, int grid_blocks, hipStream_t st);
-hipError_t launch_schedule(const DevState& s, const RunConst& rc, const ForceTiling& ft, int64_t k,
-                           hipStream_t st, bool count_step = false);
+hipError_t launch_schedule(const DevState& s, const RunConst& rc, const ForceTiling& ft, bool advance,
+                           hipStream_t st);
 hipError_t launch_push(const DevState& s, const RunConst& rc, int precision, int S, int64_t k, bool diag,
                        hipStream_t st);
 hipError_t launch_start_kick(const DevState& s, const RunConst& rc, int precision, int S, hipStream_t st);
 hipError_t launch_diag(const DevState& s, const RunConst& rc, int S, int64_t k, hipStream_t st);
 hipError_t launch_ionize(const DevState& s, const RunConst& rc, int precision, int S, int64_t k,
                          int n_ion_blocks, hipStream_t st);
-hipError_t launch_advance(const DevState& s, int64_t by, hipStream_t st);
 hipError_t launch_refresh_sources(const DevState& s, const RunConst& rc, int precision, hipStream_t st);
 
 // Standalone field (lc_field).

@@ -93,14 +93,16 @@ __device__ inline void laser_at(const ClusterParams& cp, const ClusterDyn& d, do
 }
 
 // ----------------------------------------------------------------------------- schedule (S6)
-// One block: per cluster, active flag, laser value at t^n, target blocks and tiles of this
-// step; exclusive scan of tiles over clusters in `order` (largest first).
-__global__ __launch_bounds__(kBlock) void k_schedule(DevState s, RunConst rc, int TI, int S, int64_t k,
-                                                     int count_step) {
+// One block: per cluster, active flag, laser value at t^n, target blocks and tiles of step n;
+// exclusive scan of tiles over clusters in `order` (largest first).  advance = 1 ends a step:
+// it counts the step just taken (n_sched^2 pair interactions of every cluster that was
+// active) and moves the device step index on; advance = 0 rebuilds the tables of the current
+// step (after the tiling changed).
+__global__ __launch_bounds__(kBlock) void k_schedule(DevState s, RunConst rc, int TI, int S, int advance) {
   __shared__ int32_t sh_scan[kBlock];
   __shared__ int32_t sh_carry;
   const int tid = threadIdx.x;
-  const int64_t n = *s.step + k;
+  const int64_t n = *s.step + advance;
   const double t = rc.t0 + (double)n * rc.dt;
   if (tid == 0) sh_carry = 0;
   __syncthreads();
@@ -111,8 +113,13 @@ __global__ __launch_bounds__(kBlock) void k_schedule(DevState s, RunConst rc, in
       const int c = s.order[p];
       const ClusterParams& cp = s.cp[c];
       ClusterDyn& d = s.dyn[c];
+      if (advance && d.active) {
+        d.pairs += (double)d.n_sched * (double)d.n_sched;
+        d.steps_done += 1;
+      }
       const int active = (n < cp.n_steps) ? 1 : 0;
       const int64_t ncur = d.n_cur;
+      d.n_sched = ncur;
       const int ib = active ? (int)((ncur + TI - 1) / TI) : 0;
       tiles = ib * S;
       const double env = envelope(cp, t);
@@ -121,10 +128,6 @@ __global__ __launch_bounds__(kBlock) void k_schedule(DevState s, RunConst rc, in
       d.active = active;
       d.i_blocks = ib;
       d.n_tiles = tiles;
-      if (count_step && active) {
-        d.pairs += (double)ncur * (double)ncur;
-        d.steps_done += 1;
-      }
     }
     sh_scan[tid] = tiles;
     __syncthreads();
@@ -148,6 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_schedule(DevState s, RunConst rc, in
     s.tile_start[rc.n_clusters] = sh_carry;
     *s.tile_total = sh_carry;
     *s.queue = 0;
+    if (advance) *s.step = n;  // every thread read the old index before the loop's barriers
   }
 }
 
@@ -477,10 +481,6 @@ __global__ __launch_bounds__(kBlock) void k_ionize_spawn(DevState s, RunConst rc
   }
 }
 
-__global__ void k_advance(DevState s, int64_t by) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *s.step += by;
-}
-
 template <int PREC>
 __global__ __launch_bounds__(kBlock) void k_refresh_sources(DevState s, RunConst rc) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -495,9 +495,9 @@ int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
 
-hipError_t launch_schedule(const DevState& s, const RunConst& rc, const ForceTiling& ft, int64_t k,
-                           hipStream_t st, bool count_step) {
-  k_schedule<<<1, kBlock, 0, st>>>(s, rc, force_tile_targets(ft), ft.S, k, count_step ? 1 : 0);
+hipError_t launch_schedule(const DevState& s, const RunConst& rc, const ForceTiling& ft, bool advance,
+                           hipStream_t st) {
+  k_schedule<<<1, kBlock, 0, st>>>(s, rc, force_tile_targets(ft), ft.S, advance ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -531,11 +531,6 @@ hipError_t launch_ionize(const DevState& s, const RunConst& rc, int precision, i
     k_ionize_check<LC_FP32_ACC64><<<n_ion_blocks, kBlock, 0, st>>>(s, rc, S, k);
     k_ionize_spawn<LC_FP32_ACC64><<<n_ion_blocks, kBlock, 0, st>>>(s, rc, k);
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_advance(const DevState& s, int64_t by, hipStream_t st) {
-  k_advance<<<1, 64, 0, st>>>(s, by);
   return hipGetLastError();
 }
 
