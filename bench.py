@@ -189,6 +189,83 @@ def bench_particles(args):
     print(json.dumps(out), flush=True)
 
 
+def _xe_run(precision, c, run, st, steps, tiling=None):
+    import numpy as np
+    import torch
+    import paper_1307_3711_amd as lc
+    from workloads.species import SPECIES
+    de = 100
+    cfg = lc.make_config(precision, ionize=True, dt=run.dt, softening_nm=run.softening_nm, diag_every=de,
+                         max_records=steps // de + 2, max_splits=16, seed=run.seed)
+    d = lc.make_cluster(SPECIES[c.species], c.r0_nm, c.n_ion, c.capacity, c.laser.intensity_wcm2,
+                        envelope=c.laser.envelope, fwhm_fs=c.laser.fwhm_fs, z_max=c.z_max,
+                        electron_offset_nm=c.electron_offset_nm)
+    sim = lc.Simulation(cfg, [d])
+    sim.init_from_host(0, st["x_nm"], st["u"], st["Z"])
+    sim.start()
+    tuned = sim.autotune() if tiling is None else (sim.set_tuning(**tiling) or sim.tuning())
+    sim.set_graph(de)
+    sim.stream.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        k = min(1000, steps - done)
+        sim.step(k)
+        done += k
+        sim.stream.synchronize()
+        log(f"  {precision}: step {done}/{steps}, N = {sim.counters(0)['n']}")
+    wall = time.perf_counter() - t0
+    rec = sim.diagnostics(0)
+    cnt = sim.counters(0)
+    sim.close()
+    return {"wall": wall, "rec": rec, "counters": cnt, "tiling": tuned}
+
+
+def bench_xe(args):
+    """Xe, R0 = 20 nm, capacity 200k macroparticles (22,222 Xe+ + 22,222 e- at the start, room
+    for Xe8+), 5e16 W/cm^2, 100 fs FWHM Gaussian, ionization on, 10k steps: long-pulse
+    throughput of the FP32+FP64acc path and its energy bookkeeping, with the FP64 path on the
+    first --fp64-steps steps for the error statement."""
+    import numpy as np
+    from workloads import initial_state, xe_200k
+    c, run = xe_200k()
+    st = initial_state(c, run.seed)
+    steps = args.steps if args.steps_given else c.n_steps
+    r32 = _xe_run("fp32_acc64", c, run, st, steps)
+    rec = r32["rec"]
+    # discrete energy identity (exact up to rounding) and total-energy bookkeeping
+    ident = np.abs(rec[:, 5] - rec[:, 23] - (rec[:, 8] + rec[:, 9] + rec[:, 10]))
+    ident_rel = float(np.max(ident / (np.abs(rec[:, 8]) + np.abs(rec[:, 9]) + rec[:, 10] + np.abs(rec[:, 23]))))
+    out = {"metric": "G pair-interactions/s (FP32 pair math + FP64 accumulation), Xe long pulse",
+           "value": round(r32["counters"]["pairs"] / r32["wall"] / 1e9, 2), "unit": "Gpair/s", "n_gpus": 1,
+           "steps": steps, "warmup": 0, "ms_per_step": round(r32["wall"] / steps * 1e3, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "fp32+fp64acc", "data": "synthetic",
+           "config": {"workload": "Xe cluster R0=20nm, capacity 200k (22,222 Xe+ + 22,222 e- at start), 5e16 W/cm2, "
+                                  "100 fs Gaussian, ionization to Xe8+, dt=0.05", "tiling": r32["tiling"]},
+           "cluster_steps_per_s": round(steps / r32["wall"], 2), "pairs": r32["counters"]["pairs"],
+           "final_macroparticles": r32["counters"]["n"], "ionization_events": r32["counters"]["events"],
+           "mean_charge_end": float(rec[-1, 18]), "absorbed_eV_per_atom_end": float(rec[-1, 19]),
+           "energy_identity_max_rel_residual": ident_rel,
+           "records": {"t": rec[:, 0].tolist(), "N": rec[:, 2].tolist(), "mean_Z": rec[:, 18].tolist(),
+                       "absorbed_eV_per_atom": rec[:, 19].tolist()}}
+    if not args.no_fp64:
+        n64 = min(args.fp64_steps, steps)
+        r64 = _xe_run("fp64", c, run, st, n64)
+        k = r64["rec"].shape[0]
+        a, b = rec[:k], r64["rec"]
+
+        def rel(col):
+            return float(np.max(np.abs(a[:, col] - b[:, col])) / max(np.max(np.abs(b[:, col])), 1e-300))
+
+        out["fp64"] = {"steps": n64, "gpairs_per_s": round(r64["counters"]["pairs"] / r64["wall"] / 1e9, 2),
+                       "ms_per_step": round(r64["wall"] / n64 * 1e3, 4)}
+        out["error_vs_fp64"] = {"over_steps": n64, "rel_KE": rel(5), "rel_PE": rel(7), "rel_W_laser": rel(8),
+                                "events_fp32": float(a[-1, 21]), "events_fp64": float(b[-1, 21]),
+                                "max_abs_mean_charge": float(np.max(np.abs(a[:, 18] - b[:, 18])))}
+    print(json.dumps(out), flush=True)
+
+
 def _features_of(cl):
     from paper_1307_3711_amd.ensemble import features
     from workloads.species import SPECIES
@@ -224,6 +301,8 @@ def bench_surrogate(args):
         log(f"surrogate data: batch {b} done in {r['wall_s']:.1f} s")
     X = np.concatenate(Xl)
     Y = np.concatenate(Yl)
+    if args.save_data:
+        np.savez(args.save_data, X=X, Y=Y)
     n = X.shape[0]
     perm = np.random.Generator(np.random.Philox(key=[0, 77])).permutation(n)
     n_tr = int(0.9 * n)
@@ -235,7 +314,11 @@ def bench_surrogate(args):
     rows = torch.from_numpy(row_order(n_tr, batch, args.train_steps, 1)).cuda()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    losses = net.train(Xtr, Ytr, rows, batch, args.train_steps, args.lr)
+    # piecewise-constant learning rate: lr, lr/3, lr/10, lr/30 over four equal phases (Adam
+    # moments and step count carry across the calls)
+    q = args.train_steps // 4
+    losses = torch.cat([net.train(Xtr, Ytr, rows[k * q * batch:], batch, q, args.lr * f)
+                        for k, f in enumerate((1.0, 1 / 3, 0.1, 1 / 30))])
     net.stream.synchronize()
     train_s = time.perf_counter() - t0
     pv = net.infer(torch.from_numpy(X[va]).cuda()).cpu().numpy()
@@ -266,6 +349,10 @@ def bench_surrogate(args):
     md = np.array(md)
     rmse_sur = np.sqrt(np.mean((ph - md[0]) ** 2, axis=0))
     rmse_md = np.sqrt(np.mean((md[1:] - md[0][None]) ** 2, axis=(0, 1)))
+    med_sur = np.median(np.abs(ph - md[0]), axis=0)
+    med_md = np.median(np.abs(md[1:] - md[0][None]), axis=(0, 1))
+    # the method without the network: predicting the training mean
+    rmse_mean = np.sqrt(np.mean((Y[tr].mean(axis=0)[None] - md[0]) ** 2, axis=0))
     md_runs_per_s = md_runs / md_wall
     out = {"metric": "surrogate points/s (BF16 MFMA 4-64-64-2) vs MD cluster runs/s", "value": round(1e6 / inf_s, 1),
            "unit": "points/s", "n_gpus": 1, "steps": args.train_steps, "warmup": 0,
@@ -279,7 +366,10 @@ def bench_surrogate(args):
            "final_train_loss": float(losses[-50:].mean().cpu()),
            "val_rmse": {"log_absorbed_eV": float(val_rmse[0]), "mean_charge": float(val_rmse[1])},
            "heldout_rmse_vs_md": {"log_absorbed_eV": float(rmse_sur[0]), "mean_charge": float(rmse_sur[1])},
-           "md_seed_spread_rmse": {"log_absorbed_eV": float(rmse_md[0]), "mean_charge": float(rmse_md[1])}}
+           "md_seed_spread_rmse": {"log_absorbed_eV": float(rmse_md[0]), "mean_charge": float(rmse_md[1])},
+           "heldout_median_abs_err": {"log_absorbed_eV": float(med_sur[0]), "mean_charge": float(med_sur[1])},
+           "md_seed_spread_median_abs": {"log_absorbed_eV": float(med_md[0]), "mean_charge": float(med_md[1])},
+           "train_mean_predictor_rmse": {"log_absorbed_eV": float(rmse_mean[0]), "mean_charge": float(rmse_mean[1])}}
     print(json.dumps(out), flush=True)
 
 
@@ -287,8 +377,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--batches", type=int, default=16, help="surrogate: 256-cluster ensembles of training data")
     ap.add_argument("--train-steps", type=int, default=6000)
-    ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--workload", default="ar20k", choices=["ar20k", "ensemble", "surrogate", "particles"])
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--save-data", default="", help="surrogate: write the MD training set (npz) here")
+    ap.add_argument("--fp64-steps", type=int, default=2000, help="xe200k: steps of the FP64 comparison run")
+    ap.add_argument("--workload", default="ar20k", choices=["ar20k", "ensemble", "surrogate", "particles", "xe200k"])
     ap.add_argument("--reps", type=int, default=50)
     ap.add_argument("--clusters", type=int, default=256)
     ap.add_argument("--seed", type=int, default=0)
@@ -315,8 +407,8 @@ def main():
         return
     tiling = None
     if args.tiling:
-        R, WJ, T, S, P = [int(v) for v in args.tiling.split(",")]
-        tiling = dict(R=R, WJ=WJ, T=T, S=S, persistent=P)
+        v = [int(x) for x in args.tiling.split(",")] + [0]
+        tiling = dict(R=v[0], WJ=v[1], T=v[2], S=v[3], persistent=v[4], scalar=v[5])
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
@@ -328,6 +420,8 @@ def main():
         return bench_surrogate(args)
     if args.workload == "particles":
         return bench_particles(args)
+    if args.workload == "xe200k":
+        return bench_xe(args)
 
     import numpy as np
     import torch

@@ -121,7 +121,9 @@ typedef struct {
   int32_t tile_sources;       /* T: sources staged in LDS per step (256..4096)          */
   int32_t j_splits;           /* S: source range split over S blocks (partials in HBM)  */
   int32_t persistent;         /* 1: persistent grid pulling tiles from a device queue   */
-  int32_t reserved[3];
+  int32_t scalar_sources;     /* FP32 modes: 1 reads source records through the scalar  */
+                              /*   unit into SGPR operands instead of staging LDS tiles  */
+  int32_t reserved[2];
 } lc_tuning;
 
 typedef struct lc_sim lc_sim;

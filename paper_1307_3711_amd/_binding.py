@@ -60,17 +60,18 @@ class Tuning(ctypes.Structure):
     _fields_ = [
         ("targets_per_lane", ctypes.c_int32), ("waves_per_target", ctypes.c_int32),
         ("tile_sources", ctypes.c_int32), ("j_splits", ctypes.c_int32), ("persistent", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("scalar_sources", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2),
     ]
 
     def as_dict(self):
         return {"R": self.targets_per_lane, "WJ": self.waves_per_target, "T": self.tile_sources,
-                "S": self.j_splits, "persistent": self.persistent}
+                "S": self.j_splits, "persistent": self.persistent, "scalar": self.scalar_sources}
 
 
-def make_tuning(R=0, WJ=0, T=0, S=0, persistent=0):
+def make_tuning(R=0, WJ=0, T=0, S=0, persistent=0, scalar=0):
     t = Tuning()
     t.targets_per_lane, t.waves_per_target, t.tile_sources, t.j_splits, t.persistent = R, WJ, T, S, persistent
+    t.scalar_sources = scalar
     return t
 
 
@@ -278,8 +279,8 @@ class Simulation:
         _check(lib().lc_get_tuning(self.h, ctypes.byref(t)), self.h)
         return t.as_dict()
 
-    def set_tuning(self, R=0, WJ=0, T=0, S=0, persistent=0):
-        _check(lib().lc_set_tuning(self.h, ctypes.byref(make_tuning(R, WJ, T, S, persistent))), self.h)
+    def set_tuning(self, R=0, WJ=0, T=0, S=0, persistent=0, scalar=0):
+        _check(lib().lc_set_tuning(self.h, ctypes.byref(make_tuning(R, WJ, T, S, persistent, scalar))), self.h)
 
     def autotune(self, cache_json=None):
         t = Tuning()

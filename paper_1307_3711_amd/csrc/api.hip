@@ -140,6 +140,7 @@ ForceTiling default_tiling(int precision) {
   ft.T = 1024;
   ft.S = 0;  // automatic
   ft.persistent = 0;
+  ft.scalar_src = 0;
   return ft;
 }
 
@@ -662,6 +663,7 @@ int lc_set_tuning(lc_sim* s, const lc_tuning* t) {
   if (t->tile_sources) ft.T = t->tile_sources;
   ft.S = t->j_splits;
   ft.persistent = t->persistent ? 1 : 0;
+  ft.scalar_src = t->scalar_sources ? 1 : 0;
   ForceTiling chk = ft;
   if (chk.S == 0) chk.S = 1;
   if (!force_tiling_valid(s->cfg.precision, chk) || ft.S > s->cfg.max_splits || ft.S < 0)
@@ -691,6 +693,7 @@ int lc_get_tuning(const lc_sim* s, lc_tuning* t) {
   t->tile_sources = s->ft.T;
   t->j_splits = s->S_eff;
   t->persistent = s->ft.persistent;
+  t->scalar_sources = s->ft.scalar_src;
   return LC_OK;
 }
 
@@ -830,8 +833,11 @@ extern "C" int lc_autotune(lc_sim* s, const char* cache_json, lc_tuning* chosen)
     for (int WJ : WJs)
       for (int T : Ts)
         for (int S : Ss)
-          for (int pers = 0; pers < 2; ++pers) {
-            ForceTiling ft{R, WJ, T, S, pers};
+          for (int mode = 0; mode < 4; ++mode) {
+            const int pers = mode & 1, scal = mode >> 1;
+            if (scal && prec == LC_FP64) continue;
+            if (scal && T != 1024) continue;  // T only sets the uniform-charge segment length there
+            ForceTiling ft{R, WJ, T, S, pers, scal};
             if (S > s->cfg.max_splits || !force_tiling_valid(prec, ft)) continue;
             // skip split counts that leave most blocks without sources
             int64_t nmax = 0;
@@ -879,9 +885,14 @@ extern "C" int lc_autotune(lc_sim* s, const char* cache_json, lc_tuning* chosen)
       for (int c = 0; c < s->C; ++c) ntot += s->n_host[c];
       std::fprintf(f,
                    "{\"precision\": %d, \"clusters\": %d, \"particles\": %lld, \"R\": %d, \"WJ\": %d, \"T\": %d, "
-                   "\"S\": %d, \"persistent\": %d, \"ms\": %.6f, \"rel_err_vs_default\": %.3e, \"candidates\": %zu}\n",
-                   prec, s->C, (long long)ntot, best.R, best.WJ, best.T, best.S, best.persistent, best_ms, best_err,
-                   cands.size());
+                   "\"S\": %d, \"persistent\": %d, \"scalar_sources\": %d, \"ms\": %.6f, "
+                   "\"rel_err_vs_default\": %.3e, \"candidates\": %zu, \"fastest\": [",
+                   prec, s->C, (long long)ntot, best.R, best.WJ, best.T, best.S, best.persistent, best.scalar_src,
+                   best_ms, best_err, cands.size());
+      for (size_t k = 0; k < cands.size() && k < 12; ++k)
+        std::fprintf(f, "%s[%d, %d, %d, %d, %d, %d, %.6f]", k ? ", " : "", cands[k].ft.R, cands[k].ft.WJ,
+                     cands[k].ft.T, cands[k].ft.S, cands[k].ft.persistent, cands[k].ft.scalar_src, cands[k].ms);
+      std::fprintf(f, "]}\n");
       std::fclose(f);
     }
   }
@@ -955,6 +966,7 @@ size_t lc_field_workspace_bytes(int32_t precision, int64_t n, const lc_tuning* t
     if (t->waves_per_target) ft.WJ = t->waves_per_target;
     if (t->tile_sources) ft.T = t->tile_sources;
     if (t->j_splits) ft.S = t->j_splits;
+    ft.scalar_src = t->scalar_sources ? 1 : 0;
   }
   if (!force_tiling_valid(precision, ft)) return 0;
   return field_workspace_bytes(precision, n, ft);
@@ -973,6 +985,7 @@ int lc_field(int32_t precision, int64_t n, const double* d_xyzq, double eps2, do
     if (t->tile_sources) ft.T = t->tile_sources;
     if (t->j_splits) ft.S = t->j_splits;
     ft.persistent = t->persistent ? 1 : 0;
+    ft.scalar_src = t->scalar_sources ? 1 : 0;
   }
   if (!force_tiling_valid(precision, ft)) return LC_E_INVALID;
   if (((uintptr_t)d_work & 255) != 0) return LC_E_INVALID;

@@ -82,17 +82,17 @@ __device__ inline double rsq64(double x) {
 // Sources [kb, kb + per) of the LDS tile against the lane's R targets.  UNIFORM: every source
 // has the same charge q0 and the caller multiplies the sums by it (q r^-3 costs one multiply
 // less per pair).  PHI: also the potential, with the self pair masked out by index.
-template <int R, bool PHI, bool KAHAN, bool UNIFORM>
-__device__ inline void pair_loop(const float4* lds, int kb, int per, int64_t jt, const int64_t* ii, const float* xi,
+// src is an LDS tile, or a global source array read with wave-uniform indices (the compiler
+// then issues scalar loads and the pair arithmetic takes SGPR operands).  The sums and the
+// Kahan compensations (cx..cpc) accumulate onto the caller's registers.
+template <int R, bool PHI, bool KAHAN, bool UNIFORM, int U, typename P>
+__device__ inline void pair_loop(P src, int kb, int per, int64_t jt, const int64_t* ii, const float* xi,
                                  const float* yi, const float* zi, float eps2f, float* fx, float* fy, float* fz,
-                                 float* fp) {
-  float cx[R], cy[R], cz[R], cpc[R];
+                                 float* fp, float* cx, float* cy, float* cz, float* cpc) {
+  for (int k = kb; k < kb + per; k += U) {
 #pragma unroll
-  for (int r = 0; r < R; ++r) { fx[r] = fy[r] = fz[r] = fp[r] = 0.f; cx[r] = cy[r] = cz[r] = cpc[r] = 0.f; }
-  for (int k = kb; k < kb + per; k += kU) {
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const float4 sj = lds[k + u];
+    for (int u = 0; u < U; ++u) {
+      const float4 sj = src[k + u];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const float dx = xi[r] - sj.x;
@@ -128,8 +128,8 @@ __device__ inline void pair_loop(const float4* lds, int kb, int per, int64_t jt,
 }
 
 // ----------------------------------------------------------------------------- FP32 body
-template <int R, int WJ, bool PHI, bool KAHAN>
-__device__ void tile_f32(const ForceArgs<float4>& a, int t, float4* lds) {
+template <int R, int WJ, bool PHI, bool KAHAN, bool SCALAR>
+__device__ void tile_f32(const ForceArgs<float4>& a, const float4* __restrict__ gsrc, int t, float4* lds) {
   int c, ib, s;
   decode_tile(a.map, t, a.S, c, ib, s);
   const ClusterParams& cp = a.map.cp[c];
@@ -138,7 +138,7 @@ __device__ void tile_f32(const ForceArgs<float4>& a, int t, float4* lds) {
   constexpr int TG = 4 / WJ;
   constexpr int TI = TG * 64 * R;
   const int tid = threadIdx.x;
-  const int w = tid >> 6, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;  // wave index, uniform
   const int g = w / WJ, jw = w % WJ;
   const int64_t i0 = (int64_t)ib * TI + (int64_t)g * 64 * R;
 
@@ -159,6 +159,45 @@ __device__ void tile_f32(const ForceArgs<float4>& a, int t, float4* lds) {
   for (int r = 0; r < R; ++r) { ex[r] = ey[r] = ez[r] = ep[r] = 0.0; }
   const float eps2f = (float)a.eps2;
 
+  if constexpr (SCALAR) {
+    // Sources straight from global memory with wave-uniform indices: scalar loads, SGPR
+    // operands, no LDS traffic and no block barriers in the loop.  The WJ waves sharing these
+    // targets take consecutive sub-ranges of the split; each wave walks its sub-range in
+    // segments of T sources, with a per-segment uniform-charge check (wave vote).
+    const int64_t sub = (j1 - j0 + WJ - 1) / WJ;
+    const int64_t w0 = j0 + (int64_t)jw * sub;
+    const int64_t w1 = (w0 + sub < j1) ? (w0 + sub) : j1;
+    const float4* __restrict__ base = gsrc + off;
+    for (int64_t jt = w0; jt < w1; jt += a.T) {
+      const int cnt = (int)((w1 - jt < a.T) ? (w1 - jt) : a.T);
+      const float q0 = base[jt].w;
+      int same = 1;
+      for (int k = lane; k < cnt; k += 64) same &= (base[jt + k].w == q0);
+      const int uniform = __all(same);
+      const int main = cnt & ~(kU - 1);
+      float fx[R], fy[R], fz[R], fp[R], cx[R], cy[R], cz[R], cpc[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) { fx[r] = fy[r] = fz[r] = fp[r] = 0.f; cx[r] = cy[r] = cz[r] = cpc[r] = 0.f; }
+      const float4* __restrict__ seg = base + jt;
+      if (uniform) {
+        pair_loop<R, PHI, KAHAN, true, kU>(seg, 0, main, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy, cz, cpc);
+        pair_loop<R, PHI, KAHAN, true, 1>(seg, main, cnt - main, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy, cz,
+                                          cpc);
+      } else {
+        pair_loop<R, PHI, KAHAN, false, kU>(seg, 0, main, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy, cz, cpc);
+        pair_loop<R, PHI, KAHAN, false, 1>(seg, main, cnt - main, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy, cz,
+                                           cpc);
+      }
+      const double qs = uniform ? (double)q0 : 1.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        ex[r] += (double)fx[r] * qs;
+        ey[r] += (double)fy[r] * qs;
+        ez[r] += (double)fz[r] * qs;
+        if (PHI) ep[r] += (double)fp[r] * qs;
+      }
+    }
+  } else
   for (int64_t jt = j0; jt < j1; jt += a.T) {
     const int cnt = (int)((j1 - jt < a.T) ? (j1 - jt) : a.T);
     const int cntp = (cnt + kU * WJ - 1) / (kU * WJ) * (kU * WJ);
@@ -179,11 +218,13 @@ __device__ void tile_f32(const ForceArgs<float4>& a, int t, float4* lds) {
     const int uniform = __syncthreads_and(same);
     const int per = cntp / WJ;
     const int kb = jw * per;
-    float fx[R], fy[R], fz[R], fp[R];
+    float fx[R], fy[R], fz[R], fp[R], cx[R], cy[R], cz[R], cpc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) { fx[r] = fy[r] = fz[r] = fp[r] = 0.f; cx[r] = cy[r] = cz[r] = cpc[r] = 0.f; }
     if (uniform)
-      pair_loop<R, PHI, KAHAN, true>(lds, kb, per, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp);
+      pair_loop<R, PHI, KAHAN, true, kU>(lds, kb, per, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy, cz, cpc);
     else
-      pair_loop<R, PHI, KAHAN, false>(lds, kb, per, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp);
+      pair_loop<R, PHI, KAHAN, false, kU>(lds, kb, per, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy, cz, cpc);
     const double qs = uniform ? (double)q0 : 1.0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -249,7 +290,7 @@ __device__ void tile_f64(const ForceArgs<double4>& a, int t, double4* lds) {
   constexpr int TG = 4 / WJ;
   constexpr int TI = TG * 64 * R;
   const int tid = threadIdx.x;
-  const int w = tid >> 6, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;  // wave index, uniform
   const int g = w / WJ, jw = w % WJ;
   const int64_t i0 = (int64_t)ib * TI + (int64_t)g * 64 * R;
 
@@ -348,12 +389,12 @@ __device__ void tile_f64(const ForceArgs<double4>& a, int t, double4* lds) {
 }
 
 // ----------------------------------------------------------------------------- kernels
-template <int R, int WJ, bool PHI, bool KAHAN>
-__global__ __launch_bounds__(kBlock) void k_force_f32(ForceArgs<float4> a) {
+template <int R, int WJ, bool PHI, bool KAHAN, bool SCALAR>
+__global__ __launch_bounds__(kBlock) void k_force_f32(ForceArgs<float4> a, const float4* __restrict__ gsrc) {
   extern __shared__ float4 lds32[];
   const int total = *a.map.tile_total;
   if (!a.persistent) {
-    if ((int)blockIdx.x < total) tile_f32<R, WJ, PHI, KAHAN>(a, blockIdx.x, lds32);
+    if ((int)blockIdx.x < total) tile_f32<R, WJ, PHI, KAHAN, SCALAR>(a, gsrc, blockIdx.x, lds32);
     return;
   }
   __shared__ int sh_t;
@@ -363,7 +404,7 @@ __global__ __launch_bounds__(kBlock) void k_force_f32(ForceArgs<float4> a) {
     __syncthreads();
     const int t = sh_t;
     if (t >= total) break;
-    tile_f32<R, WJ, PHI, KAHAN>(a, t, lds32);
+    tile_f32<R, WJ, PHI, KAHAN, SCALAR>(a, gsrc, t, lds32);
   }
 }
 
@@ -388,20 +429,28 @@ __global__ __launch_bounds__(kBlock) void k_force_f64(ForceArgs<double4> a) {
 
 size_t force_lds_bytes(int precision, const ForceTiling& ft, bool phi) {
   const size_t src = (precision == LC_FP64) ? sizeof(double4) : sizeof(float4);
-  size_t tile = (size_t)(ft.T + kU * ft.WJ) * src;
+  size_t tile = (ft.scalar_src && precision != LC_FP64) ? 0 : (size_t)(ft.T + kU * ft.WJ) * src;
   size_t red = (ft.WJ > 1) ? (size_t)(phi ? 4 : 3) * ft.R * kBlock * sizeof(double) : 0;
   return tile > red ? tile : red;
 }
 
 template <int R, int WJ>
-hipError_t dispatch_f32(const ForceArgs<float4>& a, bool phi, int kahan, int grid, size_t lds,
+hipError_t dispatch_f32(const ForceArgs<float4>& a, bool phi, int kahan, int scalar, int grid, size_t lds,
                         hipStream_t st) {
-  if (kahan) {
-    if (phi) k_force_f32<R, WJ, true, true><<<grid, kBlock, lds, st>>>(a);
-    else k_force_f32<R, WJ, false, true><<<grid, kBlock, lds, st>>>(a);
+  if (scalar) {
+    if (kahan) {
+      if (phi) k_force_f32<R, WJ, true, true, true><<<grid, kBlock, lds, st>>>(a, a.src);
+      else k_force_f32<R, WJ, false, true, true><<<grid, kBlock, lds, st>>>(a, a.src);
+    } else {
+      if (phi) k_force_f32<R, WJ, true, false, true><<<grid, kBlock, lds, st>>>(a, a.src);
+      else k_force_f32<R, WJ, false, false, true><<<grid, kBlock, lds, st>>>(a, a.src);
+    }
+  } else if (kahan) {
+    if (phi) k_force_f32<R, WJ, true, true, false><<<grid, kBlock, lds, st>>>(a, a.src);
+    else k_force_f32<R, WJ, false, true, false><<<grid, kBlock, lds, st>>>(a, a.src);
   } else {
-    if (phi) k_force_f32<R, WJ, true, false><<<grid, kBlock, lds, st>>>(a);
-    else k_force_f32<R, WJ, false, false><<<grid, kBlock, lds, st>>>(a);
+    if (phi) k_force_f32<R, WJ, true, false, false><<<grid, kBlock, lds, st>>>(a, a.src);
+    else k_force_f32<R, WJ, false, false, false><<<grid, kBlock, lds, st>>>(a, a.src);
   }
   return hipGetLastError();
 }
@@ -436,12 +485,12 @@ hipError_t launch_generic(int precision, const ForceTiling& ft, const TileMap& m
   ForceArgs<float4> a{(const float4*)src, part, stride, eps2, ft.T, ft.S, ft.persistent, map};
   const int kahan = (precision == LC_FP32_KAHAN);
   switch (ft.R) {
-    case 1: LC_WJ_SWITCH(1, dispatch_f32, a, phi, kahan, grid, lds, st)
-    case 2: LC_WJ_SWITCH(2, dispatch_f32, a, phi, kahan, grid, lds, st)
-    case 4: LC_WJ_SWITCH(4, dispatch_f32, a, phi, kahan, grid, lds, st)
+    case 1: LC_WJ_SWITCH(1, dispatch_f32, a, phi, kahan, ft.scalar_src, grid, lds, st)
+    case 2: LC_WJ_SWITCH(2, dispatch_f32, a, phi, kahan, ft.scalar_src, grid, lds, st)
+    case 4: LC_WJ_SWITCH(4, dispatch_f32, a, phi, kahan, ft.scalar_src, grid, lds, st)
     case 8:
       if (ft.WJ != 1) return hipErrorInvalidValue;
-      return dispatch_f32<8, 1>(a, phi, kahan, grid, lds, st);
+      return dispatch_f32<8, 1>(a, phi, kahan, ft.scalar_src, grid, lds, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -527,6 +576,7 @@ bool force_tiling_valid(int precision, const ForceTiling& ft) {
   bool r_ok = ft.R == 1 || ft.R == 2 || ft.R == 4 || (ft.R == 8 && precision != LC_FP64 && ft.WJ == 1);
   bool wj_ok = ft.WJ == 1 || ft.WJ == 2 || ft.WJ == 4;
   bool t_ok = ft.T >= 64 && ft.T <= 4096 && (ft.T % 64) == 0;
+  if (ft.scalar_src && precision == LC_FP64) return false;  // scalar source path is FP32 only
   bool s_ok = ft.S >= 1 && ft.S <= 64;
   if (!(r_ok && wj_ok && t_ok && s_ok)) return false;
   return force_lds_bytes(precision, ft, true) <= 64 * 1024;

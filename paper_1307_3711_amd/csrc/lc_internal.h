@@ -128,6 +128,7 @@ struct ForceTiling {
   int T;
   int S;
   int persistent;
+  int scalar_src;   // FP32: sources as SGPR operands (scalar loads) instead of LDS tiles
 };
 
 // Host launchers (defined in force.hip / step.hip).

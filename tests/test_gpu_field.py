@@ -74,12 +74,14 @@ TILINGS = [
     dict(R=4, WJ=4, T=512, S=2),
     dict(R=1, WJ=4, T=128, S=5, persistent=1),
     dict(R=2, WJ=1, T=1920, S=1, persistent=1),
+    dict(R=1, WJ=4, T=1024, S=7, scalar=1),
+    dict(R=2, WJ=2, T=256, S=3, persistent=1, scalar=1),
 ]
 
 
 @pytest.mark.skipif(not gpu_available(), reason="needs a GPU")
 @pytest.mark.parametrize("n", [1, 2, 3, 65, 257, 1000, 2053])
-@pytest.mark.parametrize("ti", range(len(TILINGS)))
+@pytest.mark.parametrize("ti", [0, 1, 2, 3, 4, 5])
 def test_field_fp64_elementwise(n, ti):
     x, q = _state(n, n + 17)
     Eo, Po = oracle.coulomb_field(x, q, EPS2)
@@ -93,7 +95,7 @@ def test_field_fp64_elementwise(n, ti):
 @pytest.mark.skipif(not gpu_available(), reason="needs a GPU")
 @pytest.mark.parametrize("precision,factor", [("fp32_acc64", 64.0), ("fp32_kahan", 16.0)])
 @pytest.mark.parametrize("n", [2, 63, 1000, 2053])
-@pytest.mark.parametrize("ti", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("ti", [0, 1, 2, 3, 4, 6, 7])
 def test_field_fp32_elementwise(precision, factor, n, ti):
     if precision == "fp32_kahan" and TILINGS[ti].get("R", 4) == 8:
         pytest.skip("no R=8 Kahan variant")

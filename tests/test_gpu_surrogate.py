@@ -1,0 +1,64 @@
+"""What the surrogate network gains over the method without it, on a small ensemble.
+
+MD runs of uneven clusters (the ensemble path) produce training data; the network is trained
+on the GPU by the library's own kernels and then judged on held-out clusters re-run by the MD:
+it must predict the mean ion charge better than the best constant (the training mean, which is
+all one has without a model or a new MD run) and answer many orders of magnitude faster than
+the MD produces a run.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from _helpers import gpu_available
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+def _runs(n, seed, scale=0.2):
+    import paper_1307_3711_amd as lc
+    from paper_1307_3711_amd.ensemble import features, run_ensemble, targets
+    from workloads import ensemble, initial_state
+    from workloads.species import SPECIES
+    cl = ensemble(n, seed=seed, cap_lo=300, cap_hi=900)
+    descs = [lc.make_cluster(SPECIES[c.species], c.r0_nm, c.n_ion, c.capacity, c.laser.intensity_wcm2,
+                             envelope=c.laser.envelope, fwhm_fs=c.laser.fwhm_fs, z_max=c.z_max,
+                             n_steps=max(1, int(c.n_steps * scale))) for c in cl]
+    states = [initial_state(c, seed, i) for i, c in enumerate(cl)]
+    r = run_ensemble(descs, states, "fp32_acc64", seed=seed, autotune=False)
+    na = np.array([(c.r0_nm * 10.0 / SPECIES[c.species]["rw_angstrom"]) ** 3 for c in cl])
+    X = features(np.array([c.r0_nm for c in cl]), na, np.array([c.laser.intensity_wcm2 for c in cl]),
+                 np.array([c.laser.fwhm_fs for c in cl]))
+    return X, targets(r["last"]), r["wall_s"]
+
+
+def test_surrogate_beats_constant_and_md_speed():
+    import torch
+    import paper_1307_3711_amd as lc
+    from workloads.surrogate import init_params, row_order
+    X, Y, md_wall = _runs(160, 5)
+    Xh, Yh, _ = _runs(40, 6)
+    net = lc.Surrogate(init_params(3))
+    Xd, Yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    net.fit_scaler(Xd, Yd)
+    steps, batch = 3000, 32
+    rows = torch.from_numpy(row_order(X.shape[0], batch, steps, 4)).cuda()
+    q = steps // 3
+    for k, lr in enumerate((3e-3, 1e-3, 3e-4)):
+        net.train(Xd, Yd, rows[k * q * batch:], batch, q, lr)
+    pred = net.infer(torch.from_numpy(Xh).cuda()).cpu().numpy()
+    rmse_net = np.sqrt(np.mean((pred[:, 1] - Yh[:, 1]) ** 2))
+    rmse_const = np.sqrt(np.mean((Y[:, 1].mean() - Yh[:, 1]) ** 2))
+    print(f"mean charge on held-out clusters: network RMSE {rmse_net:.3f}, constant {rmse_const:.3f}", flush=True)
+    assert rmse_net < 0.7 * rmse_const
+    Xq = torch.from_numpy(np.repeat(Xh, 4096, axis=0)).cuda()
+    net.infer(Xq)
+    net.stream.synchronize()
+    t0 = time.perf_counter()
+    net.infer(Xq)
+    net.stream.synchronize()
+    per_point = (time.perf_counter() - t0) / Xq.shape[0]
+    per_run = md_wall / X.shape[0]
+    print(f"surrogate {per_point * 1e9:.2f} ns/point vs MD {per_run * 1e3:.2f} ms/run", flush=True)
+    assert per_run / per_point > 1e5
