@@ -131,17 +131,19 @@ def test_field_rejects_bad_arguments():
 
 
 @pytest.mark.skipif(not gpu_available(), reason="needs a GPU")
-@pytest.mark.parametrize("precision", ["fp64", "fp32_acc64"])
-def test_field_full_20k_sampled(precision):
-    """The 20k-macroparticle argon state at full size (the benchmark's workload): sampled
-    targets against the oracle evaluated target by target."""
+@pytest.mark.parametrize("precision,tiling", [("fp64", dict(S=16)), ("fp32_acc64", dict(S=16)),
+                                              ("fp32_acc64", dict(R=1, WJ=4, T=1024, S=16, scalar=1))])
+def test_field_full_20k_sampled(precision, tiling):
+    """The 20k-macroparticle argon state at full size (the benchmark's workload, including the
+    scalar-source tiling the autotuner picks for it): sampled targets against the oracle
+    evaluated target by target."""
     c, run = ar_20k()
     st = initial_state(c, run.seed)
     x = units.nm_to_norm(st["x_nm"], 0.8)
     w = units.n_atoms(c.r0_nm, 2.4) / c.n_ion
     q = units.kappa(0.8) * w * st["Z"].astype(np.float64)
     idx = np.unique(np.concatenate([np.arange(0, x.shape[0], 997), [0, 9999, 10000, x.shape[0] - 1]]))
-    Eg, Pg = _gpu_field(x, q, EPS2, precision, dict(S=16))
+    Eg, Pg = _gpu_field(x, q, EPS2, precision, tiling)
     if precision == "fp64":
         Eo, Po = oracle.coulomb_field_at(x, q, EPS2, idx)
         tol = 1e-12

@@ -16,7 +16,7 @@ from _helpers import gpu_available
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
 
 
-def _runs(n, seed, scale=0.2):
+def _runs(n, seed, scale=1.0):
     import paper_1307_3711_amd as lc
     from paper_1307_3711_amd.ensemble import features, run_ensemble, targets
     from workloads import ensemble, initial_state
