@@ -32,8 +32,11 @@ def log(msg):
 def make_sim(precision, c, run, st, graph, tiling=None):
     import paper_1307_3711_amd as lc
     from workloads.species import SPECIES
+    # room for the pair-once kernel (blocks of 128 slots and up) where the precision allows it
+    mpb = lc.pair_blocks_for([c.capacity], 128) if precision == "fp32_acc64" else 0
     cfg = lc.make_config(precision, ionize=run.ionize, dt=run.dt, softening_nm=run.softening_nm,
-                         diag_every=run.diag_every, max_records=256, max_splits=64, seed=run.seed)
+                         diag_every=run.diag_every, max_records=256, max_splits=64, seed=run.seed,
+                         max_pair_blocks=mpb)
     desc = lc.make_cluster(SPECIES[c.species], c.r0_nm, c.n_ion, c.capacity, c.laser.intensity_wcm2,
                            envelope=c.laser.envelope, fwhm_fs=c.laser.fwhm_fs, z_max=c.z_max,
                            electron_offset_nm=c.electron_offset_nm)
@@ -195,8 +198,9 @@ def _xe_run(precision, c, run, st, steps, tiling=None):
     import paper_1307_3711_amd as lc
     from workloads.species import SPECIES
     de = 100
+    mpb = lc.pair_blocks_for([c.capacity], 256) if precision == "fp32_acc64" else 0
     cfg = lc.make_config(precision, ionize=True, dt=run.dt, softening_nm=run.softening_nm, diag_every=de,
-                         max_records=steps // de + 2, max_splits=16, seed=run.seed)
+                         max_records=steps // de + 2, max_splits=16, seed=run.seed, max_pair_blocks=mpb)
     d = lc.make_cluster(SPECIES[c.species], c.r0_nm, c.n_ion, c.capacity, c.laser.intensity_wcm2,
                         envelope=c.laser.envelope, fwhm_fs=c.laser.fwhm_fs, z_max=c.z_max,
                         electron_offset_nm=c.electron_offset_nm)
@@ -391,7 +395,7 @@ def main():
     ap.add_argument("--graph", type=int, default=100)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tiling", default="", help="R,WJ,T,S,persistent: skip the autotuner")
+    ap.add_argument("--tiling", default="", help="R,WJ,T,S,persistent[,scalar[,newton3]]: skip the autotuner")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB buffer 3 times (HBM counter calibration for rocprofv3)")
     args = ap.parse_args()
@@ -407,8 +411,8 @@ def main():
         return
     tiling = None
     if args.tiling:
-        v = [int(x) for x in args.tiling.split(",")] + [0]
-        tiling = dict(R=v[0], WJ=v[1], T=v[2], S=v[3], persistent=v[4], scalar=v[5])
+        v = [int(x) for x in args.tiling.split(",")] + [0, 0]
+        tiling = dict(R=v[0], WJ=v[1], T=v[2], S=v[3], persistent=v[4], scalar=v[5], newton3=v[6])
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)

@@ -88,7 +88,9 @@ typedef struct {
   int32_t diag_every;     /* one diagnostic record every k steps (0: none)              */
   int32_t max_records;    /* records kept per cluster (ring buffer)                     */
   int32_t max_splits;     /* largest source split the tuner may use (1..64)             */
-  int32_t reserved;
+  int32_t max_pair_blocks;/* M >= 0: room for the pair-once kernel (lc_tuning.newton3) on  */
+                          /*   clusters of up to M blocks; costs 12 M bytes per slot      */
+                          /*   (slots rounded up to 512 per cluster); 0: not available    */
   uint64_t seed;          /* Philox key word 0 (word 1 is the cluster index)            */
 } lc_config;
 
@@ -123,7 +125,14 @@ typedef struct {
   int32_t persistent;         /* 1: persistent grid pulling tiles from a device queue   */
   int32_t scalar_sources;     /* FP32 modes: 1 reads source records through the scalar  */
                               /*   unit into SGPR operands instead of staging LDS tiles  */
-  int32_t reserved[2];
+  int32_t newton3;            /* LC_FP32_ACC64: 1 evaluates each unordered pair once and  */
+                              /*   applies it to both particles (Newton's third law) on   */
+                              /*   steps without a diagnostic record; blocks of           */
+                              /*   B = (4/WJ) 64 R slots, (R, WJ) in {(1,1), (2,1), (1,2), */
+                              /*   (2,2), (4,2), (4,4)}; needs ceil(capacity / B) <=      */
+                              /*   max_pair_blocks for every cluster.  Diagnostic steps   */
+                              /*   (which need the potential) use the other fields.       */
+  int32_t reserved;
 } lc_tuning;
 
 typedef struct lc_sim lc_sim;
@@ -176,6 +185,15 @@ int lc_read_diagnostics(lc_sim* sim, int32_t cluster, double* records, int32_t m
 int lc_read_particles(lc_sim* sim, int32_t cluster, double* x, double* u, int8_t* Z, double* wl,
                       double* wc, int64_t cap, int64_t* n_out);
 
+/* Coulomb field of one cluster's current positions (Sec. II force from every other charged
+ * macroparticle of the cluster), from a field pass with the handle's tiling (the pair-once
+ * kernel if the tiling selects it): E (n x 3 host doubles, field units a0), cap bounds the
+ * rows written, *n_out receives the live count.  The pass overwrites the field partials of
+ * the last step, which the next step recomputes before use; a cluster that has retired
+ * (n_steps reached) is not part of the pass and its rows are not meaningful.  Synchronizes
+ * the stream. */
+int lc_read_field(lc_sim* sim, int32_t cluster, double* E, int64_t cap, int64_t* n_out);
+
 /* Current time-step index (host mirror of the device counter). */
 int64_t lc_step_index(const lc_sim* sim);
 
@@ -224,6 +242,7 @@ size_t lc_field_workspace_bytes(int32_t precision, int64_t n, const lc_tuning* t
  * d_xyzq: device, 4 n doubles laid out x[n], y[n], z[n], q[n] (q in field units).
  * d_E: device, 3 n doubles out, laid out Ex[n], Ey[n], Ez[n].  d_work: caller-owned device
  * workspace of at least lc_field_workspace_bytes().  Asynchronous on hip_stream.
+ * A tiling with newton3 = 1 computes E only (d_phi must be NULL).
  * LC_E_INVALID for n < 0, eps2 <= 0, a too small workspace or an unknown tiling. */
 int lc_field(int32_t precision, int64_t n, const double* d_xyzq, double eps2, double* d_E,
              double* d_phi, void* d_work, size_t work_bytes, const lc_tuning* t, void* hip_stream);

@@ -40,7 +40,7 @@ class Config(ctypes.Structure):
         ("struct_size", ctypes.c_uint32), ("precision", ctypes.c_int32), ("ionize", ctypes.c_int32),
         ("ofi_field", ctypes.c_int32), ("lambda_um", ctypes.c_double), ("dt", ctypes.c_double),
         ("t0", ctypes.c_double), ("softening_nm", ctypes.c_double), ("diag_every", ctypes.c_int32),
-        ("max_records", ctypes.c_int32), ("max_splits", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("max_records", ctypes.c_int32), ("max_splits", ctypes.c_int32), ("max_pair_blocks", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
     ]
 
@@ -60,19 +60,27 @@ class Tuning(ctypes.Structure):
     _fields_ = [
         ("targets_per_lane", ctypes.c_int32), ("waves_per_target", ctypes.c_int32),
         ("tile_sources", ctypes.c_int32), ("j_splits", ctypes.c_int32), ("persistent", ctypes.c_int32),
-        ("scalar_sources", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2),
+        ("scalar_sources", ctypes.c_int32), ("newton3", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self):
         return {"R": self.targets_per_lane, "WJ": self.waves_per_target, "T": self.tile_sources,
-                "S": self.j_splits, "persistent": self.persistent, "scalar": self.scalar_sources}
+                "S": self.j_splits, "persistent": self.persistent, "scalar": self.scalar_sources,
+                "newton3": self.newton3}
 
 
-def make_tuning(R=0, WJ=0, T=0, S=0, persistent=0, scalar=0):
+def make_tuning(R=0, WJ=0, T=0, S=0, persistent=0, scalar=0, newton3=0):
     t = Tuning()
     t.targets_per_lane, t.waves_per_target, t.tile_sources, t.j_splits, t.persistent = R, WJ, T, S, persistent
     t.scalar_sources = scalar
+    t.newton3 = newton3
     return t
+
+
+def pair_blocks_for(capacities, block=128):
+    """Rows per block the pair-once kernel needs for clusters of these capacities with blocks of
+    at least `block` slots (pass as max_pair_blocks)."""
+    return max(-(-int(c) // block) for c in capacities)
 
 
 _lib = None
@@ -103,6 +111,7 @@ def lib():
         "lc_set_graph": ([vp, ctypes.c_int32], ctypes.c_int),
         "lc_read_diagnostics": ([vp, ctypes.c_int32, dp, ctypes.c_int32, i32p], ctypes.c_int),
         "lc_read_particles": ([vp, ctypes.c_int32, dp, dp, i8p, dp, dp, ctypes.c_int64, i64p], ctypes.c_int),
+        "lc_read_field": ([vp, ctypes.c_int32, dp, ctypes.c_int64, i64p], ctypes.c_int),
         "lc_step_index": ([vp], ctypes.c_int64),
         "lc_cluster_counters": ([vp, ctypes.c_int32, dp], ctypes.c_int),
         "lc_time_particle_kernels": ([vp, ctypes.c_int32, dp], ctypes.c_int),
@@ -151,7 +160,7 @@ def units(lambda_um, intensity_wcm2=0.0):
 
 
 def make_config(precision="fp64", ionize=True, ofi_field="laser_only", lambda_um=0.8, dt=0.05, t0=0.0,
-                softening_nm=0.1, diag_every=10, max_records=1024, max_splits=32, seed=0):
+                softening_nm=0.1, diag_every=10, max_records=1024, max_splits=32, seed=0, max_pair_blocks=0):
     c = Config()
     c.struct_size = ctypes.sizeof(Config)
     c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -159,6 +168,7 @@ def make_config(precision="fp64", ionize=True, ofi_field="laser_only", lambda_um
     c.ofi_field = OFI[ofi_field]
     c.lambda_um, c.dt, c.t0, c.softening_nm = lambda_um, dt, t0, softening_nm
     c.diag_every, c.max_records, c.max_splits, c.seed = diag_every, max_records, max_splits, seed
+    c.max_pair_blocks = max_pair_blocks
     return c
 
 
@@ -262,6 +272,16 @@ class Simulation:
         k = n.value
         return {"x": x[:k], "u": u[:k], "Z": Z[:k], "wl": wl[:k], "wc": wc[:k], "n": k}
 
+    def field(self, cluster=0):
+        """Coulomb field (n x 3, field units) of a cluster's current positions, from a field pass
+        with the current tiling (lc_read_field)."""
+        cap = self.capacity[cluster]
+        E = np.zeros((cap, 3))
+        n = ctypes.c_int64()
+        _check(lib().lc_read_field(self.h, cluster, E.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), cap,
+                                   ctypes.byref(n)), self.h)
+        return E[:n.value]
+
     def time_particle_kernels(self, reps=20):
         """Average ms of the push kernel and of the ionization kernels (lc_time_particle_kernels)."""
         out = (ctypes.c_double * 2)()
@@ -279,8 +299,9 @@ class Simulation:
         _check(lib().lc_get_tuning(self.h, ctypes.byref(t)), self.h)
         return t.as_dict()
 
-    def set_tuning(self, R=0, WJ=0, T=0, S=0, persistent=0, scalar=0):
-        _check(lib().lc_set_tuning(self.h, ctypes.byref(make_tuning(R, WJ, T, S, persistent, scalar))), self.h)
+    def set_tuning(self, R=0, WJ=0, T=0, S=0, persistent=0, scalar=0, newton3=0):
+        _check(lib().lc_set_tuning(self.h, ctypes.byref(make_tuning(R, WJ, T, S, persistent, scalar, newton3))),
+               self.h)
 
     def autotune(self, cache_json=None):
         t = Tuning()

@@ -53,8 +53,13 @@ double a0_of(double intensity, double lambda_um) { return std::sqrt(intensity * 
 
 size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// Pair-once partial rows: cluster c gets 3 M n3_round(cap_c) floats, enough for nb <= M blocks
+// of any pair-once block size (128, 256 or 512 slots, all dividing 512).
+constexpr int kMaxPairBlocks = 32768;
+int64_t n3_round(int64_t cap) { return (cap + 511) / 512 * 512; }
+
 struct Layout {
-  size_t x, y, z, ux, uy, uz, wl, wc, wsp, kebar, pos4, posq, Z, cid, part, flag, ib_count, ib_cluster;
+  size_t x, y, z, ux, uy, uz, wl, wc, wsp, kebar, pos4, posq, Z, cid, part, n3part, flag, ib_count, ib_cluster;
   size_t cp, dyn, order, tile_start, tile_total, queue, err, step, diag_part, records, total;
   int64_t n_total;
   int n_ion_blocks;
@@ -71,6 +76,8 @@ bool valid_config(const lc_config* cfg, std::string* why) {
   if (cfg->diag_every < 0) { *why = "diag_every must be >= 0"; return false; }
   if (cfg->diag_every > 0 && cfg->max_records < 1) { *why = "max_records must be >= 1"; return false; }
   if (cfg->max_splits < 1 || cfg->max_splits > 64) { *why = "max_splits must be in [1, 64]"; return false; }
+  if (cfg->max_pair_blocks < 0 || cfg->max_pair_blocks > kMaxPairBlocks) { *why = "max_pair_blocks out of range"; return false; }
+  if (cfg->max_pair_blocks > 0 && cfg->precision != LC_FP32_ACC64) { *why = "the pair-once kernel needs LC_FP32_ACC64"; return false; }
   if (cfg->ionize != 0 && cfg->ionize != 1) { *why = "ionize must be 0 or 1"; return false; }
   if (cfg->ofi_field != LC_LASER_ONLY && cfg->ofi_field != LC_LOCAL) { *why = "unknown ofi_field"; return false; }
   return true;
@@ -115,6 +122,9 @@ Layout make_layout(const lc_config* cfg, const lc_cluster* cl, int C) {
   L.Z = take((size_t)NT);
   L.cid = take(sizeof(int32_t) * (size_t)NT);
   L.part = take(sizeof(double) * (size_t)cfg->max_splits * kComp * (size_t)NT);
+  int64_t n3_slots = 0;
+  for (int c = 0; c < C; ++c) n3_slots += n3_round(cl[c].capacity);
+  L.n3part = take(sizeof(float) * 3 * (size_t)cfg->max_pair_blocks * (size_t)n3_slots);
   L.flag = take(sizeof(int32_t) * (size_t)NT);
   L.ib_count = take(sizeof(int32_t) * (size_t)std::max(ib, 1));
   L.ib_cluster = take(sizeof(int32_t) * (size_t)std::max(ib, 1));
@@ -141,6 +151,7 @@ ForceTiling default_tiling(int precision) {
   ft.S = 0;  // automatic
   ft.persistent = 0;
   ft.scalar_src = 0;
+  ft.newton3 = 0;
   return ft;
 }
 
@@ -209,6 +220,34 @@ int hip_fail(lc_sim* s, hipError_t e, const char* where) {
   return fail(s, LC_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
 }
 
+bool is_diag_step(const lc_sim* s, int64_t step) {
+  return s->cfg.diag_every > 0 && (step % s->cfg.diag_every) == 0;
+}
+
+// The field pass of a step takes the pair-once kernel iff the tiling asks for it and the step
+// does not need the potential.
+bool n3_pass(const lc_sim* s, const ForceTiling& ft, bool want_phi) { (void)s; return ft.newton3 && !want_phi; }
+
+FieldLayout field_layout(const ForceTiling& ft, bool n3) {
+  FieldLayout fl;
+  fl.S = n3 ? 1 : ft.S;  // the pair-once pass folds its rows into split 0
+  return fl;
+}
+
+// A pair-once tiling fits when every cluster's capacity spans at most max_pair_blocks blocks.
+bool n3_fits(const lc_sim* s, const ForceTiling& ft) {
+  if (!ft.newton3) return true;
+  if (s->cfg.max_pair_blocks <= 0 || s->cfg.precision != LC_FP32_ACC64) return false;
+  const int64_t B = n3_block_size(ft);
+  int64_t tiles = 0;
+  for (int c = 0; c < s->C; ++c) {
+    const int64_t nb = (s->cl[c].capacity + B - 1) / B;
+    if (nb > s->cfg.max_pair_blocks) return false;
+    tiles += nb * (nb + 1) / 2;
+  }
+  return tiles <= std::numeric_limits<int32_t>::max();
+}
+
 int choose_splits(const lc_sim* s, const ForceTiling& ft) {
   if (ft.S > 0) return std::min(ft.S, s->cfg.max_splits);
   const int TI = force_tile_targets(ft);
@@ -219,38 +258,41 @@ int choose_splits(const lc_sim* s, const ForceTiling& ft) {
   return S;
 }
 
-int force_grid(const lc_sim* s, const ForceTiling& ft) {
-  const int TI = force_tile_targets(ft);
+int force_grid(const lc_sim* s, const ForceTiling& ft, bool n3) {
   if (ft.persistent) return device_cus() * 4;
+  const int TI = n3 ? n3_block_size(ft) : force_tile_targets(ft);
   int64_t tiles = 0;
   for (int c = 0; c < s->C; ++c) {
     const int64_t n = s->cfg.ionize ? s->cl[c].capacity : s->n_host[c];
-    tiles += (std::max<int64_t>(n, 1) + TI - 1) / TI;
+    const int64_t nb = (std::max<int64_t>(n, 1) + TI - 1) / TI;
+    tiles += n3 ? nb * (nb + 1) / 2 : nb * ft.S;
   }
-  return (int)std::min<int64_t>(tiles * ft.S, std::numeric_limits<int32_t>::max());
+  return (int)std::min<int64_t>(tiles, std::numeric_limits<int32_t>::max());
 }
 
 hipError_t enqueue_steps(lc_sim* s, int count, int64_t first_step) {
   ForceTiling ft = s->ft;
   ft.S = s->S_eff;
-  const int grid = force_grid(s, ft);
   // The tables of the first step were built by the previous step's closing schedule (or by
   // lc_start / a tiling change); every step ends with the schedule of the next one.
   for (int k = 0; k < count; ++k) {
-    const bool diag = s->cfg.diag_every > 0 && ((first_step + k) % s->cfg.diag_every) == 0;
-    hipError_t e = launch_force(s->s, s->rc, s->cfg.precision, ft, diag, grid, s->stream);
+    const bool diag = is_diag_step(s, first_step + k);
+    const bool n3 = n3_pass(s, ft, diag);
+    const FieldLayout fl = field_layout(ft, n3);
+    hipError_t e = launch_force(s->s, s->rc, s->cfg.precision, ft, diag, force_grid(s, ft, n3), s->stream);
     if (e != hipSuccess) return e;
-    e = launch_push(s->s, s->rc, s->cfg.precision, ft.S, 0, diag, s->stream);
+    e = launch_push(s->s, s->rc, s->cfg.precision, fl, 0, diag, s->stream);
     if (e != hipSuccess) return e;
     if (diag) {
-      e = launch_diag(s->s, s->rc, ft.S, 0, s->stream);
+      e = launch_diag(s->s, s->rc, fl, 0, s->stream);
       if (e != hipSuccess) return e;
     }
     if (s->cfg.ionize) {
-      e = launch_ionize(s->s, s->rc, s->cfg.precision, ft.S, 0, s->L.n_ion_blocks, s->stream);
+      e = launch_ionize(s->s, s->rc, s->cfg.precision, fl, 0, s->L.n_ion_blocks, s->stream);
       if (e != hipSuccess) return e;
     }
-    e = launch_schedule(s->s, s->rc, ft, true, s->stream);
+    const bool n3_next = n3_pass(s, ft, is_diag_step(s, first_step + k + 1));
+    e = launch_schedule(s->s, s->rc, ft, n3_next, true, s->stream);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -344,6 +386,7 @@ int lc_create(lc_sim** out, const lc_config* cfg, const lc_cluster* clusters, in
   d.kebar = (double*)(b + L.kebar);
   d.pos4 = (float4*)(b + L.pos4); d.posq = (double4*)(b + L.posq);
   d.Z = (int8_t*)(b + L.Z); d.cid = (int32_t*)(b + L.cid); d.part = (double*)(b + L.part);
+  d.n3part = (float*)(b + L.n3part);
   d.flag = (int32_t*)(b + L.flag); d.ib_count = (int32_t*)(b + L.ib_count);
   d.ib_cluster = (int32_t*)(b + L.ib_cluster);
   d.cp = (ClusterParams*)(b + L.cp); d.dyn = (ClusterDyn*)(b + L.dyn);
@@ -363,19 +406,21 @@ int lc_create(lc_sim** out, const lc_config* cfg, const lc_cluster* clusters, in
   rc.ofi_local = cfg->ofi_field == LC_LOCAL;
   rc.diag_every = cfg->diag_every;
   rc.max_records = cfg->diag_every > 0 ? cfg->max_records : 1;
-  rc.pad = 0;
+  rc.n3_rows = cfg->max_pair_blocks;
   rc.n_total = L.n_total;
   rc.mec2_ev = kMec2Ev;
 
   // Per-cluster tables.
   std::vector<ClusterParams> cps(n_clusters);
   std::vector<int32_t> cid(L.n_total), ibc(std::max(L.n_ion_blocks, 1), 0);
-  int64_t off = 0;
+  int64_t off = 0, n3_off = 0;
   int ib0 = 0;
   for (int c = 0; c < n_clusters; ++c) {
     const lc_cluster& k = clusters[c];
     ClusterParams p{};
     p.off = off;
+    p.n3_off = n3_off;
+    n3_off += 3 * (int64_t)cfg->max_pair_blocks * n3_round(k.capacity);
     p.cap = k.capacity;
     p.n_ion = k.n_ion;
     p.n_steps = k.n_steps > 0 ? k.n_steps : std::numeric_limits<int64_t>::max();
@@ -500,10 +545,13 @@ int lc_start(lc_sim* s) {
   s->S_eff = choose_splits(s, s->ft);
   ForceTiling ft = s->ft;
   ft.S = s->S_eff;
+  const bool n3 = n3_pass(s, ft, false);
   hipError_t e = launch_refresh_sources(s->s, s->rc, s->cfg.precision, s->stream);
-  if (e == hipSuccess) e = launch_schedule(s->s, s->rc, ft, false, s->stream);
-  if (e == hipSuccess) e = launch_force(s->s, s->rc, s->cfg.precision, ft, false, force_grid(s, ft), s->stream);
-  if (e == hipSuccess) e = launch_start_kick(s->s, s->rc, s->cfg.precision, ft.S, s->stream);
+  if (e == hipSuccess) e = launch_schedule(s->s, s->rc, ft, n3, false, s->stream);
+  if (e == hipSuccess) e = launch_force(s->s, s->rc, s->cfg.precision, ft, false, force_grid(s, ft, n3), s->stream);
+  if (e == hipSuccess) e = launch_start_kick(s->s, s->rc, s->cfg.precision, field_layout(ft, n3), s->stream);
+  // tables of step 0
+  if (e == hipSuccess) e = launch_schedule(s->s, s->rc, ft, n3_pass(s, ft, is_diag_step(s, 0)), false, s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "lc_start");
   s->started = true;
   return LC_OK;
@@ -565,13 +613,16 @@ int lc_time_particle_kernels(lc_sim* s, int32_t reps, double out_ms[2]) {
   hipEvent_t ev[4];
   for (auto& e : ev)
     if (hipEventCreate(&e) != hipSuccess) return fail(s, LC_E_HIP, "hipEventCreate");
-  hipError_t e = launch_schedule(s->s, s->rc, ft, false, s->stream);
+  // times the kernels on the partials of the last field pass, in the layout of the current step
+  const bool n3 = n3_pass(s, ft, is_diag_step(s, s->step));
+  const FieldLayout fl = field_layout(ft, n3);
+  hipError_t e = launch_schedule(s->s, s->rc, ft, n3, false, s->stream);
   if (e == hipSuccess) e = hipEventRecord(ev[0], s->stream);
-  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_push(s->s, s->rc, s->cfg.precision, ft.S, 0, false, s->stream);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_push(s->s, s->rc, s->cfg.precision, fl, 0, false, s->stream);
   if (e == hipSuccess) e = hipEventRecord(ev[1], s->stream);
   if (e == hipSuccess) e = hipEventRecord(ev[2], s->stream);
   for (int r = 0; r < reps && e == hipSuccess && s->cfg.ionize; ++r)
-    e = launch_ionize(s->s, s->rc, s->cfg.precision, ft.S, 0, s->L.n_ion_blocks, s->stream);
+    e = launch_ionize(s->s, s->rc, s->cfg.precision, fl, 0, s->L.n_ion_blocks, s->stream);
   if (e == hipSuccess) e = hipEventRecord(ev[3], s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   float a = 0.f, b = 0.f;
@@ -664,10 +715,12 @@ int lc_set_tuning(lc_sim* s, const lc_tuning* t) {
   ft.S = t->j_splits;
   ft.persistent = t->persistent ? 1 : 0;
   ft.scalar_src = t->scalar_sources ? 1 : 0;
+  ft.newton3 = t->newton3 ? 1 : 0;
   ForceTiling chk = ft;
   if (chk.S == 0) chk.S = 1;
   if (!force_tiling_valid(s->cfg.precision, chk) || ft.S > s->cfg.max_splits || ft.S < 0)
     return fail(s, LC_E_INVALID, "invalid tiling");
+  if (!n3_fits(s, ft)) return fail(s, LC_E_INVALID, "pair-once tiling needs ceil(capacity / B) <= max_pair_blocks");
   s->ft = ft;
   const int S_new = choose_splits(s, ft);
   if (s->started && S_new != s->S_eff) {
@@ -679,7 +732,7 @@ int lc_set_tuning(lc_sim* s, const lc_tuning* t) {
   if (s->started) {
     ForceTiling cur = ft;
     cur.S = S_new;
-    hipError_t e = launch_schedule(s->s, s->rc, cur, false, s->stream);
+    hipError_t e = launch_schedule(s->s, s->rc, cur, n3_pass(s, cur, is_diag_step(s, s->step)), false, s->stream);
     if (e != hipSuccess) return hip_fail(s, e, "lc_set_tuning");
   }
   return LC_OK;
@@ -694,6 +747,7 @@ int lc_get_tuning(const lc_sim* s, lc_tuning* t) {
   t->j_splits = s->S_eff;
   t->persistent = s->ft.persistent;
   t->scalar_sources = s->ft.scalar_src;
+  t->newton3 = s->ft.newton3;
   return LC_OK;
 }
 
@@ -749,7 +803,7 @@ int lc_load_state(lc_sim* s, const char* path) {
   drop_graph(s);
   ForceTiling cur = s->ft;
   cur.S = s->S_eff;
-  e = launch_schedule(s->s, s->rc, cur, false, s->stream);
+  e = launch_schedule(s->s, s->rc, cur, n3_pass(s, cur, is_diag_step(s, s->step)), false, s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "lc_load_state");
   return LC_OK;
 }
@@ -757,23 +811,25 @@ int lc_load_state(lc_sim* s, const char* path) {
 // ----------------------------------------------------------------------------- autotuner
 namespace {
 
-__global__ void k_fold_partials(double* part, int64_t stride, int S) {
-  // field of every slot summed over splits in split order into split 0 (components 0..2)
+// Field of every live slot from the last pass, summed in the push's order, into split 0
+// (components 0..2) of the split partials; slots beyond a cluster's count get zero.
+__global__ void k_fold_partials(DevState s, RunConst rc, FieldLayout fl) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= stride) return;
-  for (int c = 0; c < 3; ++c) {
-    double v = 0.0;
-    for (int s = 0; s < S; ++s) v += part[((int64_t)s * kComp + c) * stride + g];
-    part[(int64_t)c * stride + g] = v;
-  }
+  if (g >= rc.n_total) return;
+  const int c = s.cid[g];
+  double e[3] = {0.0, 0.0, 0.0};
+  if (g - s.cp[c].off < s.dyn[c].n_sched) field_sum(s, rc, fl, g, e[0], e[1], e[2]);
+  for (int k = 0; k < 3; ++k) s.part[(int64_t)k * rc.n_total + g] = e[k];
 }
 
 int field_snapshot(lc_sim* s, const ForceTiling& ft, std::vector<double>& out) {
   const int64_t NT = s->L.n_total;
-  hipError_t e = launch_schedule(s->s, s->rc, ft, false, s->stream);
-  if (e == hipSuccess) e = launch_force(s->s, s->rc, s->cfg.precision, ft, false, force_grid(s, ft), s->stream);
+  const bool n3 = n3_pass(s, ft, false);
+  hipError_t e = launch_schedule(s->s, s->rc, ft, n3, false, s->stream);
+  if (e == hipSuccess) e = launch_force(s->s, s->rc, s->cfg.precision, ft, false, force_grid(s, ft, n3), s->stream);
   if (e == hipSuccess) {
-    k_fold_partials<<<(int)((NT + kBlock - 1) / kBlock), kBlock, 0, s->stream>>>(s->s.part, NT, ft.S);
+    // all reads of split 0 happen in the same thread before its writes
+    k_fold_partials<<<(int)((NT + kBlock - 1) / kBlock), kBlock, 0, s->stream>>>(s->s, s->rc, field_layout(ft, n3));
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -781,6 +837,44 @@ int field_snapshot(lc_sim* s, const ForceTiling& ft, std::vector<double>& out) {
   if (e == hipSuccess) e = hipMemcpy(out.data(), s->s.part, sizeof(double) * 3 * NT, hipMemcpyDeviceToHost);
   return e == hipSuccess ? LC_OK : hip_fail(s, e, "autotune snapshot");
 }
+
+}  // namespace
+
+extern "C" int lc_read_field(lc_sim* s, int32_t cluster, double* E, int64_t cap, int64_t* n_out) {
+  if (!s || !n_out || cap < 0 || (cap > 0 && !E)) return LC_E_INVALID;
+  if (cluster < 0 || cluster >= s->C) return fail(s, LC_E_INVALID, "cluster index out of range");
+  if (!s->started) return fail(s, LC_E_STATE, "lc_read_field before lc_start");
+  hipError_t e = hipStreamSynchronize(s->stream);
+  ClusterDyn d;
+  if (e == hipSuccess) e = hipMemcpy(&d, s->s.dyn + cluster, sizeof(ClusterDyn), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(s, e, "lc_read_field");
+  if (s->cfg.ionize)
+    for (int c = 0; c < s->C; ++c) {
+      ClusterDyn dc;
+      e = hipMemcpy(&dc, s->s.dyn + c, sizeof(ClusterDyn), hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return hip_fail(s, e, "lc_read_field");
+      s->n_host[c] = dc.n_cur;
+    }
+  ForceTiling ft = s->ft;
+  ft.S = s->S_eff;
+  std::vector<double> all;
+  int rc = field_snapshot(s, ft, all);
+  if (rc != LC_OK) return rc;
+  // the current step's tables again (the snapshot built those of a pass without potential)
+  e = launch_schedule(s->s, s->rc, ft, n3_pass(s, ft, is_diag_step(s, s->step)), false, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "lc_read_field");
+  int64_t off = 0;
+  for (int c = 0; c < cluster; ++c) off += s->cl[c].capacity;
+  const int64_t NT = s->L.n_total;
+  const int64_t n = std::min<int64_t>(d.n_cur, cap);
+  for (int64_t i = 0; i < n; ++i)
+    for (int k = 0; k < 3; ++k) E[3 * i + k] = all[k * NT + off + i];
+  *n_out = d.n_cur;
+  return latched_error(s);
+}
+
+namespace {
 
 double rel_diff(const std::vector<double>& a, const std::vector<double>& b, const lc_sim* s) {
   // normwise relative difference over live slots
@@ -829,27 +923,30 @@ extern "C" int lc_autotune(lc_sim* s, const char* cache_json, lc_tuning* chosen)
   const int Ss[] = {1, 2, 4, 8, 16, 32, 64};
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(s, LC_E_HIP, "events");
+  int64_t nmax = 0;
+  for (int c = 0; c < s->C; ++c) nmax = std::max(nmax, s->n_host[c]);
   for (int R : Rs)
     for (int WJ : WJs)
       for (int T : Ts)
         for (int S : Ss)
-          for (int mode = 0; mode < 4; ++mode) {
-            const int pers = mode & 1, scal = mode >> 1;
+          for (int mode = 0; mode < 8; ++mode) {
+            const int pers = mode & 1, scal = (mode >> 1) & 1, n3 = mode >> 2;
             if (scal && prec == LC_FP64) continue;
             if (scal && T != 1024) continue;  // T only sets the uniform-charge segment length there
-            ForceTiling ft{R, WJ, T, S, pers, scal};
-            if (S > s->cfg.max_splits || !force_tiling_valid(prec, ft)) continue;
+            // pair-once candidates: S and T only serve the diagnostic steps; time one of each
+            if (n3 && (!scal || T != 1024 || S != std::min(16, s->cfg.max_splits))) continue;
+            ForceTiling ft{R, WJ, T, S, pers, scal, n3};
+            if (S > s->cfg.max_splits || !force_tiling_valid(prec, ft) || !n3_fits(s, ft)) continue;
             // skip split counts that leave most blocks without sources
-            int64_t nmax = 0;
-            for (int c = 0; c < s->C; ++c) nmax = std::max(nmax, s->n_host[c]);
-            if ((int64_t)S * 64 > std::max<int64_t>(nmax, 64)) continue;
+            if (!n3 && (int64_t)S * 64 > std::max<int64_t>(nmax, 64)) continue;
             const int reps = 3;
-            hipError_t e = launch_schedule(s->s, s->rc, ft, false, s->stream);
-            if (e == hipSuccess) e = launch_force(s->s, s->rc, prec, ft, false, force_grid(s, ft), s->stream);  // warm
+            const int grid = force_grid(s, ft, n3 != 0);
+            hipError_t e = launch_schedule(s->s, s->rc, ft, n3 != 0, false, s->stream);
+            if (e == hipSuccess) e = launch_force(s->s, s->rc, prec, ft, false, grid, s->stream);  // warm
             if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
             for (int r = 0; r < reps && e == hipSuccess; ++r) {
-              e = launch_schedule(s->s, s->rc, ft, false, s->stream);
-              if (e == hipSuccess) e = launch_force(s->s, s->rc, prec, ft, false, force_grid(s, ft), s->stream);
+              e = launch_schedule(s->s, s->rc, ft, n3 != 0, false, s->stream);
+              if (e == hipSuccess) e = launch_force(s->s, s->rc, prec, ft, false, grid, s->stream);
             }
             if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -874,7 +971,7 @@ extern "C" int lc_autotune(lc_sim* s, const char* cache_json, lc_tuning* chosen)
   s->S_eff = best.S;
   drop_graph(s);
   {
-    hipError_t e = launch_schedule(s->s, s->rc, best, false, s->stream);
+    hipError_t e = launch_schedule(s->s, s->rc, best, n3_pass(s, best, is_diag_step(s, s->step)), false, s->stream);
     if (e != hipSuccess) return hip_fail(s, e, "lc_autotune");
   }
   if (chosen) lc_get_tuning(s, chosen);
@@ -885,13 +982,14 @@ extern "C" int lc_autotune(lc_sim* s, const char* cache_json, lc_tuning* chosen)
       for (int c = 0; c < s->C; ++c) ntot += s->n_host[c];
       std::fprintf(f,
                    "{\"precision\": %d, \"clusters\": %d, \"particles\": %lld, \"R\": %d, \"WJ\": %d, \"T\": %d, "
-                   "\"S\": %d, \"persistent\": %d, \"scalar_sources\": %d, \"ms\": %.6f, "
+                   "\"S\": %d, \"persistent\": %d, \"scalar_sources\": %d, \"newton3\": %d, \"ms\": %.6f, "
                    "\"rel_err_vs_default\": %.3e, \"candidates\": %zu, \"fastest\": [",
                    prec, s->C, (long long)ntot, best.R, best.WJ, best.T, best.S, best.persistent, best.scalar_src,
-                   best_ms, best_err, cands.size());
+                   best.newton3, best_ms, best_err, cands.size());
       for (size_t k = 0; k < cands.size() && k < 12; ++k)
-        std::fprintf(f, "%s[%d, %d, %d, %d, %d, %d, %.6f]", k ? ", " : "", cands[k].ft.R, cands[k].ft.WJ,
-                     cands[k].ft.T, cands[k].ft.S, cands[k].ft.persistent, cands[k].ft.scalar_src, cands[k].ms);
+        std::fprintf(f, "%s[%d, %d, %d, %d, %d, %d, %d, %.6f]", k ? ", " : "", cands[k].ft.R, cands[k].ft.WJ,
+                     cands[k].ft.T, cands[k].ft.S, cands[k].ft.persistent, cands[k].ft.scalar_src,
+                     cands[k].ft.newton3, cands[k].ms);
       std::fprintf(f, "]}\n");
       std::fclose(f);
     }
@@ -906,7 +1004,6 @@ extern "C" int lc_profile_steps(lc_sim* s, int64_t n_steps, double* out_ms, int6
   for (int k = 0; k < 4; ++k) { out_ms[k] = 0.0; out_launches[k] = 0; }
   ForceTiling ft = s->ft;
   ft.S = s->S_eff;
-  const int grid = force_grid(s, ft);
   const int64_t chunk = 256;  // steps per event batch
   std::vector<hipEvent_t> ev(8 * chunk);
   for (auto& e : ev)
@@ -916,29 +1013,31 @@ extern "C" int lc_profile_steps(lc_sim* s, int64_t n_steps, double* out_ms, int6
     const int64_t m = std::min(chunk, n_steps - done);
     std::vector<int> used(4 * m, 0);
     for (int64_t k = 0; k < m && e == hipSuccess; ++k) {
-      const bool diag = s->cfg.diag_every > 0 && (s->step % s->cfg.diag_every) == 0;
+      const bool diag = is_diag_step(s, s->step);
+      const bool n3 = n3_pass(s, ft, diag);
+      const FieldLayout fl = field_layout(ft, n3);
       hipEvent_t* E = &ev[8 * k];
       e = hipEventRecord(E[0], s->stream);
-      if (e == hipSuccess) e = launch_force(s->s, s->rc, s->cfg.precision, ft, diag, grid, s->stream);
+      if (e == hipSuccess) e = launch_force(s->s, s->rc, s->cfg.precision, ft, diag, force_grid(s, ft, n3), s->stream);
       if (e == hipSuccess) e = hipEventRecord(E[1], s->stream);
       used[4 * k + 0] = 1;
       if (e == hipSuccess) e = hipEventRecord(E[2], s->stream);
-      if (e == hipSuccess) e = launch_push(s->s, s->rc, s->cfg.precision, ft.S, 0, diag, s->stream);
+      if (e == hipSuccess) e = launch_push(s->s, s->rc, s->cfg.precision, fl, 0, diag, s->stream);
       if (e == hipSuccess) e = hipEventRecord(E[3], s->stream);
       used[4 * k + 1] = 1;
       if (diag && e == hipSuccess) {
         e = hipEventRecord(E[4], s->stream);
-        if (e == hipSuccess) e = launch_diag(s->s, s->rc, ft.S, 0, s->stream);
+        if (e == hipSuccess) e = launch_diag(s->s, s->rc, fl, 0, s->stream);
         if (e == hipSuccess) e = hipEventRecord(E[5], s->stream);
         used[4 * k + 2] = 1;
       }
       if (s->cfg.ionize && e == hipSuccess) {
         e = hipEventRecord(E[6], s->stream);
-        if (e == hipSuccess) e = launch_ionize(s->s, s->rc, s->cfg.precision, ft.S, 0, s->L.n_ion_blocks, s->stream);
+        if (e == hipSuccess) e = launch_ionize(s->s, s->rc, s->cfg.precision, fl, 0, s->L.n_ion_blocks, s->stream);
         if (e == hipSuccess) e = hipEventRecord(E[7], s->stream);
         used[4 * k + 3] = 1;
       }
-      if (e == hipSuccess) e = launch_schedule(s->s, s->rc, ft, true, s->stream);
+      if (e == hipSuccess) e = launch_schedule(s->s, s->rc, ft, n3_pass(s, ft, is_diag_step(s, s->step + 1)), true, s->stream);
       s->step += 1;
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -967,6 +1066,7 @@ size_t lc_field_workspace_bytes(int32_t precision, int64_t n, const lc_tuning* t
     if (t->tile_sources) ft.T = t->tile_sources;
     if (t->j_splits) ft.S = t->j_splits;
     ft.scalar_src = t->scalar_sources ? 1 : 0;
+    ft.newton3 = t->newton3 ? 1 : 0;
   }
   if (!force_tiling_valid(precision, ft)) return 0;
   return field_workspace_bytes(precision, n, ft);
@@ -986,8 +1086,10 @@ int lc_field(int32_t precision, int64_t n, const double* d_xyzq, double eps2, do
     if (t->j_splits) ft.S = t->j_splits;
     ft.persistent = t->persistent ? 1 : 0;
     ft.scalar_src = t->scalar_sources ? 1 : 0;
+    ft.newton3 = t->newton3 ? 1 : 0;
   }
   if (!force_tiling_valid(precision, ft)) return LC_E_INVALID;
+  if (ft.newton3 && d_phi) return LC_E_INVALID;
   if (((uintptr_t)d_work & 255) != 0) return LC_E_INVALID;
   if (work_bytes < field_workspace_bytes(precision, n, ft)) return LC_E_INVALID;
   hipError_t e = launch_field_standalone(precision, n, d_xyzq, eps2, d_E, d_phi, d_work, ft, (hipStream_t)hip_stream);

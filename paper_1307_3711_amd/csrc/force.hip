@@ -24,6 +24,8 @@
 //                    accumulation across tiles; tiles of equal-charge sources (the electron
 //                    block, frozen or equal ion charges) use a loop with the charge factored out.
 //   LC_FP32_KAHAN  : as above with Kahan-compensated FP32 sums within the tile.
+#include <limits>
+
 #include "lc_internal.h"
 
 namespace lc {
@@ -388,7 +390,329 @@ __device__ void tile_f64(const ForceArgs<double4>& a, int t, double4* lds) {
   }
 }
 
+// ----------------------------------------------------------------------------- FP32, pairs once
+// Newton's third law: the pair term of (i, j) is the pair term of (j, i) with the sign of the
+// separation flipped and the partner's charge, so one evaluation can serve both particles.
+// A cluster's slots are cut into blocks of B = (4/WJ) * 64 * R.  The tile (I, J), I < J, takes
+// every pair (i in block I, j in block J) once and produces E_i's part from block J and E_j's
+// part from block I; the diagonal tile (I, I) takes all pairs of its block one-sided (the self
+// pair adds exactly zero).  Inside a block of 256 threads, 4/WJ target groups hold 64 R targets
+// each (R per lane) and the WJ waves of a group split the B sources.  A wave walks its sources
+// in chunks of 64, staged twice in a row in its own LDS slice: at rotation k lane l meets
+// source (l + k) mod 64 at index l + k, an immediate offset.  The reaction sums of the chunk's
+// sources travel with the rotation in registers: lane l holds the running sum of source
+// (l + k) mod 64, adds its terms, and hands it to lane l - 1 (DPP wave rotate by one lane), so
+// after 64 rotations lane l holds source l's sum, accumulated in a fixed order (deterministic).
+// Tiles of equal-charge sources or equal-charge targets factor the charge out of the pair term.
+//
+// Partial fields are FP32 rows, one per (block K, partner block m) of a cluster:
+//   row (K, m), component d, local slot l:  n3part[n3_off + ((K M + m) 3 + d) B + l]
+// written by exactly one tile.  M (rows per block) is fixed at creation; nb = ceil(n / B).
+// k_fold_n3 then sums a slot's rows m = 0 .. nb - 1 in FP64, in a fixed order, into split 0
+// of the FP64 partials, which the push reads as a one-split field.
+struct N3Args {
+  const float4* src;   // source records, global slot indexed
+  float* part;         // pair-once rows
+  int M;               // rows per block
+  double eps2;
+  int persistent;
+  TileMap map;
+};
+
+__device__ inline void decode_pair_tile(const TileMap& m, int t, int& c, int& I, int& J) {
+  int lo = 0, hi = m.n_clusters - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (m.tile_start[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  c = m.order[lo];
+  const int64_t local = t - m.tile_start[lo];
+  // tiles of a cluster in J-major order: local = J (J + 1) / 2 + I, 0 <= I <= J
+  int64_t j = (int64_t)((sqrt(8.0 * (double)local + 1.0) - 1.0) * 0.5);
+  while (j * (j + 1) / 2 > local) --j;
+  while ((j + 1) * (j + 2) / 2 <= local) ++j;
+  J = (int)j;
+  I = (int)(local - j * (j + 1) / 2);
+}
+
+// x from lane (l + 1) mod 64 for every lane l (DPP wave_rol:1).
+__device__ inline float wave_rol1(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x134, 0xf, 0xf, false));
+}
+
+// Orders the LDS traffic of one wave around a point where lanes read what other lanes wrote.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One chunk of 64 sources (sb: the chunk twice) against the lane's R targets.  US: all
+// sources of the chunk carry one charge (factored out by the caller); UT: likewise for the
+// targets of the wave.  JSIDE: also the reaction sums sum_r q_r s_r (r_i - r_j) of the
+// chunk's sources, returned in (ax, ay, az) of lane l for source l.
+template <int R, bool US, bool UT, bool JSIDE>
+__device__ inline void n3_chunk(const float4* sb, int lane, const float* xi, const float* yi, const float* zi,
+                                const float* qi, float eps2f, float* fx, float* fy, float* fz, float& ax, float& ay,
+                                float& az) {
+  constexpr int U = (R >= 8) ? 1 : 8 / R;
+  float rx = 0.f, ry = 0.f, rz = 0.f;  // running sums of source (lane + k) mod 64
+  for (int k0 = 0; k0 < 64; k0 += U) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u;
+      const float4 sj = sb[lane + k];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const float dx = xi[r] - sj.x;
+        const float dy = yi[r] - sj.y;
+        const float dz = zi[r] - sj.z;
+        float r2 = __builtin_fmaf(dx, dx, eps2f);
+        r2 = __builtin_fmaf(dy, dy, r2);
+        r2 = __builtin_fmaf(dz, dz, r2);
+        const float inv = rsq32(r2);
+        const float r3 = inv * (inv * inv);
+        const float si = US ? r3 : sj.w * r3;
+        fx[r] = __builtin_fmaf(si, dx, fx[r]);
+        fy[r] = __builtin_fmaf(si, dy, fy[r]);
+        fz[r] = __builtin_fmaf(si, dz, fz[r]);
+        if (JSIDE) {
+          const float sr = UT ? r3 : qi[r] * r3;
+          rx = __builtin_fmaf(sr, dx, rx);
+          ry = __builtin_fmaf(sr, dy, ry);
+          rz = __builtin_fmaf(sr, dz, rz);
+        }
+      }
+      if (JSIDE) {
+        rx = wave_rol1(rx);
+        ry = wave_rol1(ry);
+        rz = wave_rol1(rz);
+      }
+    }
+  }
+  ax = rx;
+  ay = ry;
+  az = rz;
+}
+
+constexpr int kN3Fixed = 4 * 128 * 4;  // floats: per-wave chunk copies
+
+__host__ __device__ constexpr int n3_block(int R, int WJ) { return (4 / WJ) * 64 * R; }
+
+template <int R, int WJ>
+__device__ void tile_n3(const N3Args& a, int t, float* lds) {
+  constexpr int TG = 4 / WJ, TGT = 64 * R, B = TG * TGT, PW = B / WJ, NCH = PW / 64;
+  static_assert(PW % 64 == 0, "each wave takes whole chunks of 64 sources");
+  int c, I, J;
+  decode_pair_tile(a.map, t, c, I, J);
+  const ClusterParams& cp = a.map.cp[c];
+  const int64_t n = a.map.dyn[c].n_cur;
+  const float4* __restrict__ src = a.src + cp.off;
+  float* rows = a.part + cp.n3_off;
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int g = w / WJ, jw = w % WJ;
+  const bool jside = (I != J);
+  // rows exist only for blocks holding live slots (I <= J < nb <= M for a table built for n)
+  const bool live = (int64_t)J * B < n && I <= J && J < a.M;
+  float4* sb = reinterpret_cast<float4*>(lds) + w * 128;
+  float* jres = lds + kN3Fixed;       // [TG][3][B] reaction sums of the block's sources
+  float* ired = jres + TG * 3 * B;    // [WJ - 1][3][B] target sums of waves jw > 0
+
+  const int64_t i0 = (int64_t)I * B + (int64_t)g * TGT;
+  const bool tvalid = live && i0 < n;  // wave-uniform
+  const float qT = tvalid ? src[i0].w : 0.f;
+  float xi[R], yi[R], zi[R], qi[R];
+  int same_t = 1;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t ii = i0 + r * 64 + lane;
+    if (ii < n) {
+      const float4 p = src[ii];
+      xi[r] = p.x; yi[r] = p.y; zi[r] = p.z; qi[r] = p.w;
+      same_t &= (p.w == qT);
+    } else {
+      // far away: r^2 overflows to +inf, v_rsq_f32(+inf) = +0, both sides add exactly zero
+      xi[r] = yi[r] = zi[r] = 1e30f;
+      qi[r] = qT;
+    }
+  }
+  const bool ut = __all(same_t);
+  const float eps2f = (float)a.eps2;
+  float ex[R], ey[R], ez[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) ex[r] = ey[r] = ez[r] = 0.f;
+
+  if (tvalid) {
+    for (int ch = 0; ch < NCH; ++ch) {
+      const int64_t jb = (int64_t)J * B + jw * PW + ch * 64;
+      if (jb >= n) break;
+      const int64_t jj = jb + lane;
+      const float4 sv = (jj < n) ? src[jj] : make_float4(1e30f, 1e30f, 1e30f, 0.f);
+      const float qs0 = src[jb].w;
+      const bool us = __all(jj >= n || sv.w == qs0);
+      sb[lane] = sv;
+      sb[lane + 64] = sv;
+      wave_lds_sync();
+      float cx[R], cy[R], cz[R], ax, ay, az;
+#pragma unroll
+      for (int r = 0; r < R; ++r) cx[r] = cy[r] = cz[r] = 0.f;
+      if (jside) {
+        if (us) {
+          if (ut) n3_chunk<R, true, true, true>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az);
+          else n3_chunk<R, true, false, true>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az);
+        } else {
+          if (ut) n3_chunk<R, false, true, true>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az);
+          else n3_chunk<R, false, false, true>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az);
+        }
+      } else {
+        if (us) n3_chunk<R, true, true, false>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az);
+        else n3_chunk<R, false, true, false>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az);
+      }
+      wave_lds_sync();
+      const float fs = us ? qs0 : 1.f;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        ex[r] = __builtin_fmaf(fs, cx[r], ex[r]);
+        ey[r] = __builtin_fmaf(fs, cy[r], ey[r]);
+        ez[r] = __builtin_fmaf(fs, cz[r], ez[r]);
+      }
+      if (jside) {
+        // E_j = sum_i q_i (r_j - r_i) s_ij = -(reaction sum), charge factored when uniform
+        const float js = ut ? -qT : -1.f;
+        const int jl = jw * PW + ch * 64 + lane;
+        jres[(g * 3 + 0) * B + jl] = js * ax;
+        jres[(g * 3 + 1) * B + jl] = js * ay;
+        jres[(g * 3 + 2) * B + jl] = js * az;
+      }
+      wave_lds_sync();  // every lane's reads of sb are done before the next chunk restages it
+    }
+  }
+  __syncthreads();
+
+  // Target side: the WJ waves of a group add up in a fixed order; row (I, J).
+  if (WJ > 1) {
+    if (jw > 0 && tvalid) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int l = g * TGT + r * 64 + lane;
+        ired[((jw - 1) * 3 + 0) * B + l] = ex[r];
+        ired[((jw - 1) * 3 + 1) * B + l] = ey[r];
+        ired[((jw - 1) * 3 + 2) * B + l] = ez[r];
+      }
+    }
+    __syncthreads();
+    if (jw == 0 && tvalid) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int l = g * TGT + r * 64 + lane;
+        for (int q = 0; q < WJ - 1; ++q) {
+          ex[r] += ired[(q * 3 + 0) * B + l];
+          ey[r] += ired[(q * 3 + 1) * B + l];
+          ez[r] += ired[(q * 3 + 2) * B + l];
+        }
+      }
+    }
+  }
+  if (jw == 0 && tvalid) {
+    float* row = rows + (int64_t)((int64_t)I * a.M + J) * 3 * B;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int l = g * TGT + r * 64 + lane;
+      if ((int64_t)I * B + l < n) {
+        row[l] = ex[r];
+        row[B + l] = ey[r];
+        row[2 * B + l] = ez[r];
+      }
+    }
+  }
+  // Source side: the target groups add up in a fixed order; row (J, I).
+  if (jside && live) {
+    float* row = rows + (int64_t)((int64_t)J * a.M + I) * 3 * B;
+    for (int jl = tid; jl < B; jl += kBlock) {
+      if ((int64_t)J * B + jl >= n) break;
+      float sx = 0.f, sy = 0.f, sz = 0.f;
+      for (int q = 0; q < TG; ++q) {
+        if ((int64_t)I * B + (int64_t)q * TGT >= n) break;
+        sx += jres[(q * 3 + 0) * B + jl];
+        sy += jres[(q * 3 + 1) * B + jl];
+        sz += jres[(q * 3 + 2) * B + jl];
+      }
+      row[jl] = sx;
+      row[B + jl] = sy;
+      row[2 * B + jl] = sz;
+    }
+  }
+}
+
+// Row sums of the pair-once pass: a block of 8 waves takes 64 consecutive global slots; wave w
+// adds rows m = w, w + 8, ... (coalesced across the lanes), and wave 0 combines the 8 partial
+// sums in order.  Writes E into components 0..2 of split 0 for live slots of active clusters.
+constexpr int kFoldWaves = 8;
+
+__global__ __launch_bounds__(64 * kFoldWaves) void k_fold_n3(DevState s, RunConst rc, int B) {
+  __shared__ double red[kFoldWaves - 1][3][64];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t g = (int64_t)blockIdx.x * 64 + lane;
+  double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+  bool live = false;
+  if (g < rc.n_total) {
+    const int c = s.cid[g];
+    const ClusterParams& cp = s.cp[c];
+    const ClusterDyn& d = s.dyn[c];
+    const int64_t l = g - cp.off;
+    live = d.active && l < d.n_sched;
+    if (live) {
+      const int64_t K = l / B;
+      const int64_t nb = (d.n_sched + B - 1) / B;
+      const float* r = s.n3part + cp.n3_off + (K * rc.n3_rows + w) * 3 * (int64_t)B + (l - K * B);
+      const int64_t step = (int64_t)kFoldWaves * 3 * B;
+      for (int64_t m = w; m < nb; m += kFoldWaves, r += step) {
+        e0 += (double)r[0];
+        e1 += (double)r[B];
+        e2 += (double)r[2 * B];
+      }
+    }
+  }
+  if (w > 0) {
+    red[w - 1][0][lane] = e0;
+    red[w - 1][1][lane] = e1;
+    red[w - 1][2][lane] = e2;
+  }
+  __syncthreads();
+  if (w == 0 && live) {
+    for (int q = 0; q < kFoldWaves - 1; ++q) {
+      e0 += red[q][0][lane];
+      e1 += red[q][1][lane];
+      e2 += red[q][2][lane];
+    }
+    s.part[g] = e0;
+    s.part[rc.n_total + g] = e1;
+    s.part[2 * rc.n_total + g] = e2;
+  }
+}
+
 // ----------------------------------------------------------------------------- kernels
+template <int R, int WJ>
+__global__ __launch_bounds__(kBlock) void k_force_n3(N3Args a) {
+  extern __shared__ float lds_n3[];
+  const int total = *a.map.tile_total;
+  if (!a.persistent) {
+    if ((int)blockIdx.x < total) tile_n3<R, WJ>(a, blockIdx.x, lds_n3);
+    return;
+  }
+  __shared__ int sh_t;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) sh_t = atomicAdd(a.map.queue, 1);
+    __syncthreads();
+    const int t = sh_t;
+    if (t >= total) break;
+    tile_n3<R, WJ>(a, t, lds_n3);
+  }
+}
+
 template <int R, int WJ, bool PHI, bool KAHAN, bool SCALAR>
 __global__ __launch_bounds__(kBlock) void k_force_f32(ForceArgs<float4> a, const float4* __restrict__ gsrc) {
   extern __shared__ float4 lds32[];
@@ -462,6 +786,31 @@ hipError_t dispatch_f64(const ForceArgs<double4>& a, bool phi, int grid, size_t 
   return hipGetLastError();
 }
 
+// Pair-once shapes: whole 64-source chunks per wave, blocks of 128..512 slots, and every shape
+// also valid for the regular kernels (which take the steps that need the potential).
+bool n3_shape_ok(int R, int WJ) {
+  return (WJ == 1 && (R == 1 || R == 2)) || (WJ == 2 && (R == 1 || R == 2 || R == 4)) || (WJ == 4 && R == 4);
+}
+
+size_t n3_lds_bytes(const ForceTiling& ft) {
+  const size_t B = (size_t)n3_block(ft.R, ft.WJ);
+  return sizeof(float) * ((size_t)kN3Fixed + (size_t)(4 / ft.WJ) * 3 * B + (size_t)(ft.WJ - 1) * 3 * B);
+}
+
+hipError_t launch_n3(const ForceTiling& ft, const N3Args& a, int grid, hipStream_t st) {
+  const size_t lds = n3_lds_bytes(ft);
+  switch (ft.WJ * 16 + ft.R) {
+    case 16 + 1: k_force_n3<1, 1><<<grid, kBlock, lds, st>>>(a); break;
+    case 16 + 2: k_force_n3<2, 1><<<grid, kBlock, lds, st>>>(a); break;
+    case 32 + 1: k_force_n3<1, 2><<<grid, kBlock, lds, st>>>(a); break;
+    case 32 + 2: k_force_n3<2, 2><<<grid, kBlock, lds, st>>>(a); break;
+    case 32 + 4: k_force_n3<4, 2><<<grid, kBlock, lds, st>>>(a); break;
+    case 64 + 4: k_force_n3<4, 4><<<grid, kBlock, lds, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 #define LC_WJ_SWITCH(R, FN, ...)                                   \
   switch (ft.WJ) {                                                  \
     case 1: return FN<R, 1>(__VA_ARGS__);                           \
@@ -503,7 +852,7 @@ struct FieldWs {
   ClusterDyn* dyn;
   int32_t* ints;
   void* src;
-  double* part;
+  double* part;      // split partials (regular kernels) or pair-once rows (newton3), as floats
 };
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -519,16 +868,17 @@ FieldWs carve_field_ws(void* work, int precision, int64_t n, const ForceTiling& 
   return w;
 }
 
-__global__ void k_field_setup(FieldWs w, int64_t n, int tiles_per_split_blocks, int S) {
+__global__ void k_field_setup(FieldWs w, int64_t n, int i_blocks, int tiles) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     ClusterParams cp = {};
     cp.off = 0;
     cp.cap = n;
+    cp.n3_off = 0;
     *w.cp = cp;
     ClusterDyn d = {};
     d.n_cur = n;
-    d.i_blocks = tiles_per_split_blocks;
-    d.n_tiles = tiles_per_split_blocks * S;
+    d.i_blocks = i_blocks;
+    d.n_tiles = tiles;
     d.active = 1;
     *w.dyn = d;
     w.ints[0] = 0;
@@ -568,15 +918,41 @@ __global__ void k_sum_partials(const double* part, int64_t n, int S, double* E, 
   if (phi) phi[i] = p;
 }
 
+// Field of the standalone call from pair-once rows (M = nb rows per block).
+__global__ void k_sum_n3(const float* rows, int64_t n, int B, double* E) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t K = i / B, l = i - K * B;
+  const int64_t nb = (n + B - 1) / B;
+  const float* r = rows + K * nb * 3 * B + l;
+  double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+  for (int64_t m = 0; m < nb; ++m, r += 3 * (int64_t)B) {
+    e0 += (double)r[0];
+    e1 += (double)r[B];
+    e2 += (double)r[2 * B];
+  }
+  E[i] = e0;
+  E[n + i] = e1;
+  E[2 * n + i] = e2;
+}
+
 }  // namespace
 
 int force_tile_targets(const ForceTiling& ft) { return (4 / ft.WJ) * 64 * ft.R; }
+
+int n3_block_size(const ForceTiling& ft) { return n3_block(ft.R, ft.WJ); }
+
+int64_t n3_tiles(int64_t n, int B) {
+  const int64_t nb = (n + B - 1) / B;
+  return nb * (nb + 1) / 2;
+}
 
 bool force_tiling_valid(int precision, const ForceTiling& ft) {
   bool r_ok = ft.R == 1 || ft.R == 2 || ft.R == 4 || (ft.R == 8 && precision != LC_FP64 && ft.WJ == 1);
   bool wj_ok = ft.WJ == 1 || ft.WJ == 2 || ft.WJ == 4;
   bool t_ok = ft.T >= 64 && ft.T <= 4096 && (ft.T % 64) == 0;
   if (ft.scalar_src && precision == LC_FP64) return false;  // scalar source path is FP32 only
+  if (ft.newton3 && (precision != LC_FP32_ACC64 || !n3_shape_ok(ft.R, ft.WJ))) return false;
   bool s_ok = ft.S >= 1 && ft.S <= 64;
   if (!(r_ok && wj_ok && t_ok && s_ok)) return false;
   return force_lds_bytes(precision, ft, true) <= 64 * 1024;
@@ -585,6 +961,14 @@ bool force_tiling_valid(int precision, const ForceTiling& ft) {
 hipError_t launch_force(const DevState& s, const RunConst& rc, int precision, const ForceTiling& ft,
                         bool want_phi, int grid_blocks, hipStream_t st) {
   TileMap map{s.tile_start, s.order, s.cp, s.dyn, s.tile_total, s.queue, rc.n_clusters};
+  if (ft.newton3 && !want_phi) {
+    if (precision != LC_FP32_ACC64 || rc.n3_rows <= 0) return hipErrorInvalidValue;
+    N3Args a{s.pos4, s.n3part, rc.n3_rows, rc.eps2, ft.persistent, map};
+    hipError_t e = launch_n3(ft, a, grid_blocks, st);
+    if (e != hipSuccess) return e;
+    k_fold_n3<<<(int)((rc.n_total + 63) / 64), 64 * kFoldWaves, 0, st>>>(s, rc, n3_block(ft.R, ft.WJ));
+    return hipGetLastError();
+  }
   const void* src = (precision == LC_FP64) ? (const void*)s.posq : (const void*)s.pos4;
   return launch_generic(precision, ft, map, src, s.part, rc.n_total, rc.eps2, want_phi, grid_blocks, st);
 }
@@ -592,7 +976,13 @@ hipError_t launch_force(const DevState& s, const RunConst& rc, int precision, co
 size_t field_workspace_bytes(int precision, int64_t n, const ForceTiling& ft) {
   size_t b = align256(sizeof(ClusterParams)) + align256(sizeof(ClusterDyn)) + 256;
   b += align256((size_t)n * (precision == LC_FP64 ? sizeof(double4) : sizeof(float4)));
-  b += align256((size_t)ft.S * kComp * (size_t)n * sizeof(double));
+  if (ft.newton3) {
+    const size_t B = (size_t)n3_block(ft.R, ft.WJ);
+    const size_t nb = ((size_t)n + B - 1) / B;
+    b += align256(nb * nb * 3 * B * sizeof(float));
+  } else {
+    b += align256((size_t)ft.S * kComp * (size_t)n * sizeof(double));
+  }
   return b;
 }
 
@@ -600,22 +990,32 @@ hipError_t launch_field_standalone(int precision, int64_t n, const double* xyzq,
                                    double* phi, void* work, const ForceTiling& ft, hipStream_t st) {
   if (n == 0) return hipSuccess;
   FieldWs w = carve_field_ws(work, precision, n, ft);
-  const int TI = force_tile_targets(ft);
+  const int TI = ft.newton3 ? n3_block(ft.R, ft.WJ) : force_tile_targets(ft);
   const int ib = (int)((n + TI - 1) / TI);
-  k_field_setup<<<1, 64, 0, st>>>(w, n, ib, ft.S);
+  const int64_t tiles = ft.newton3 ? (int64_t)ib * (ib + 1) / 2 : (int64_t)ib * ft.S;
+  if (tiles > std::numeric_limits<int32_t>::max()) return hipErrorInvalidValue;
+  k_field_setup<<<1, 64, 0, st>>>(w, n, ib, (int)tiles);
   const int pb = (int)((n + kBlock - 1) / kBlock);
   if (precision == LC_FP64) k_pack_sources<double4><<<pb, kBlock, 0, st>>>(xyzq, n, (double4*)w.src);
   else k_pack_sources<float4><<<pb, kBlock, 0, st>>>(xyzq, n, (float4*)w.src);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   TileMap map{w.ints, w.ints + 2, w.cp, w.dyn, w.ints + 3, w.ints + 4, 1};
-  int grid = ib * ft.S;
+  int grid = (int)tiles;
   if (ft.persistent) {
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     int pg = cus * 8;
     grid = grid < pg ? grid : pg;
+  }
+  if (ft.newton3) {
+    if (phi) return hipErrorInvalidValue;
+    N3Args a{(const float4*)w.src, (float*)w.part, ib, eps2, ft.persistent, map};
+    e = launch_n3(ft, a, grid, st);
+    if (e != hipSuccess) return e;
+    k_sum_n3<<<pb, kBlock, 0, st>>>((const float*)w.part, n, TI, E);
+    return hipGetLastError();
   }
   e = launch_generic(precision, ft, map, w.src, w.part, n, eps2, phi != nullptr, grid, st);
   if (e != hipSuccess) return e;

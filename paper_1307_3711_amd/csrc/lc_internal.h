@@ -53,6 +53,7 @@ struct ClusterParams {
   int32_t ion_block0;   // first entry of this cluster in the ion-block table
   int32_t n_ion_blocks;
   int32_t pad;
+  int64_t n3_off;       // first float of this cluster's pair-once partial rows (see force.hip)
 };
 
 // Per-cluster dynamic state, written by the kernels.
@@ -85,7 +86,7 @@ struct RunConst {
   int32_t ofi_local;
   int32_t diag_every;
   int32_t max_records;
-  int32_t pad;
+  int32_t n3_rows;      // M: partial rows per target block of the pair-once kernel (0: none)
   int64_t n_total;      // total slots (sum of capacities)
   double mec2_ev;       // electron rest energy (eV) for the absorbed-energy column
 };
@@ -107,6 +108,7 @@ struct DevState {
   int8_t* Z;
   int32_t* cid;         // cluster of each slot
   double* part;         // field partials [split][comp][slot]
+  float* n3part;        // pair-once partial rows (FP32), per cluster from cp.n3_off
   int32_t* flag;        // ionization flags [slot of ion]
   int32_t* ib_count;    // spawns per ion block
   int32_t* ib_cluster;  // cluster of each ion block
@@ -129,18 +131,43 @@ struct ForceTiling {
   int S;
   int persistent;
   int scalar_src;   // FP32: sources as SGPR operands (scalar loads) instead of LDS tiles
+  int newton3;      // FP32 + FP64 accumulation: each unordered pair once on steps without phi
 };
 
+// How the field partials of a step are laid out for the kernels that read them: S FP64 split
+// partials [split][comp][slot] (a pair-once pass leaves its field in split 0: S = 1).
+struct FieldLayout {
+  int S;
+};
+
+
+// Coulomb field of global slot g from the partials of the last field pass, summed over the
+// splits in split order (FP64).
+__device__ inline void field_sum(const DevState& s, const RunConst& rc, const FieldLayout& fl, int64_t g,
+                                 double& ex, double& ey, double& ez) {
+  ex = 0.0; ey = 0.0; ez = 0.0;
+  for (int k = 0; k < fl.S; ++k) {
+    const double* b = s.part + (int64_t)k * kComp * rc.n_total + g;
+    ex += b[0];
+    ey += b[rc.n_total];
+    ez += b[2 * rc.n_total];
+  }
+}
+
 // Host launchers (defined in force.hip / step.hip).
+// A pass without the potential takes the pair-once kernel when ft.newton3 is set.
 hipError_t launch_force(const DevState& s, const RunConst& rc, int precision, const ForceTiling& ft,
                         bool want_phi, int grid_blocks, hipStream_t st);
-hipError_t launch_schedule(const DevState& s, const RunConst& rc, const ForceTiling& ft, bool advance,
+// n3: build the pair-once tile tables (blocks of n3_block_size(ft)) instead of target blocks
+// times splits.
+hipError_t launch_schedule(const DevState& s, const RunConst& rc, const ForceTiling& ft, bool n3, bool advance,
                            hipStream_t st);
-hipError_t launch_push(const DevState& s, const RunConst& rc, int precision, int S, int64_t k, bool diag,
-                       hipStream_t st);
-hipError_t launch_start_kick(const DevState& s, const RunConst& rc, int precision, int S, hipStream_t st);
-hipError_t launch_diag(const DevState& s, const RunConst& rc, int S, int64_t k, hipStream_t st);
-hipError_t launch_ionize(const DevState& s, const RunConst& rc, int precision, int S, int64_t k,
+hipError_t launch_push(const DevState& s, const RunConst& rc, int precision, const FieldLayout& fl, int64_t k,
+                       bool diag, hipStream_t st);
+hipError_t launch_start_kick(const DevState& s, const RunConst& rc, int precision, const FieldLayout& fl,
+                             hipStream_t st);
+hipError_t launch_diag(const DevState& s, const RunConst& rc, const FieldLayout& fl, int64_t k, hipStream_t st);
+hipError_t launch_ionize(const DevState& s, const RunConst& rc, int precision, const FieldLayout& fl, int64_t k,
                          int n_ion_blocks, hipStream_t st);
 hipError_t launch_refresh_sources(const DevState& s, const RunConst& rc, int precision, hipStream_t st);
 
@@ -150,6 +177,8 @@ hipError_t launch_field_standalone(int precision, int64_t n, const double* xyzq,
 size_t field_workspace_bytes(int precision, int64_t n, const ForceTiling& ft);
 
 int force_tile_targets(const ForceTiling& ft);
+int n3_block_size(const ForceTiling& ft);
+int64_t n3_tiles(int64_t n, int B);
 bool force_tiling_valid(int precision, const ForceTiling& ft);
 
 }  // namespace lc

@@ -77,17 +77,6 @@ __device__ inline void write_source(const DevState& s, int precision, int64_t g,
   else s.pos4[g] = make_float4((float)x, (float)y, (float)z, (float)q);
 }
 
-__device__ inline void field_sum(const DevState& s, const RunConst& rc, int S, int64_t g, double& ex,
-                                 double& ey, double& ez) {
-  ex = 0.0; ey = 0.0; ez = 0.0;
-  for (int k = 0; k < S; ++k) {
-    const double* b = s.part + (int64_t)k * kComp * rc.n_total + g;
-    ex += b[0];
-    ey += b[rc.n_total];
-    ez += b[2 * rc.n_total];
-  }
-}
-
 __device__ inline void laser_at(const ClusterParams& cp, const ClusterDyn& d, double t, double z, double& a) {
   a = (cp.phase == LC_DIPOLE) ? d.laser_e : d.env * sin(t - z);
 }
@@ -97,8 +86,10 @@ __device__ inline void laser_at(const ClusterParams& cp, const ClusterDyn& d, do
 // exclusive scan of tiles over clusters in `order` (largest first).  advance = 1 ends a step:
 // it counts the step just taken (n_sched^2 pair interactions of every cluster that was
 // active) and moves the device step index on; advance = 0 rebuilds the tables of the current
-// step (after the tiling changed).
-__global__ __launch_bounds__(kBlock) void k_schedule(DevState s, RunConst rc, int TI, int S, int advance) {
+// step (after the tiling changed).  n3: tiles of the pair-once kernel, nb (nb + 1) / 2 per
+// cluster for nb blocks of TI slots; otherwise target blocks of TI times S source splits.
+__global__ __launch_bounds__(kBlock) void k_schedule(DevState s, RunConst rc, int TI, int S, int n3,
+                                                     int advance) {
   __shared__ int32_t sh_scan[kBlock];
   __shared__ int32_t sh_carry;
   const int tid = threadIdx.x;
@@ -121,7 +112,7 @@ __global__ __launch_bounds__(kBlock) void k_schedule(DevState s, RunConst rc, in
       const int64_t ncur = d.n_cur;
       d.n_sched = ncur;
       const int ib = active ? (int)((ncur + TI - 1) / TI) : 0;
-      tiles = ib * S;
+      tiles = n3 ? (int32_t)((int64_t)ib * (ib + 1) / 2) : ib * S;
       const double env = envelope(cp, t);
       d.env = env;
       d.laser_e = env * sin(t);
@@ -160,7 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_schedule(DevState s, RunConst rc, in
 // with the exact discrete work split W_L / W_C, optional KE(n) for the diagnostics, and the
 // refresh of the source record the next field pass reads.
 template <int PREC>
-__global__ __launch_bounds__(kBlock) void k_push(DevState s, RunConst rc, int S, int64_t k, int diag) {
+__global__ __launch_bounds__(kBlock) void k_push(DevState s, RunConst rc, FieldLayout fl, int64_t k, int diag) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (g >= rc.n_total) return;
   const int c = s.cid[g];
@@ -172,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_push(DevState s, RunConst rc, int S,
   const double t = rc.t0 + (double)n * rc.dt;
 
   double ecx, ecy, ecz;
-  field_sum(s, rc, S, g, ecx, ecy, ecz);
+  field_sum(s, rc, fl, g, ecx, ecy, ecz);
   double x = s.x[g], y = s.y[g], z = s.z[g];
   double a;
   laser_at(cp, d, t, z, a);
@@ -222,7 +213,7 @@ __global__ __launch_bounds__(kBlock) void k_push(DevState s, RunConst rc, int S,
 // ----------------------------------------------------------------------------- start
 // Backward half kick with the full Lorentz force at t0: u^{-1/2} = u^0 - (Z/M)(dt/2)(E + v x B);
 // kebar receives w M (gamma^{-1/2} - 1) for the start energy.
-__global__ __launch_bounds__(kBlock) void k_start_kick(DevState s, RunConst rc, int S) {
+__global__ __launch_bounds__(kBlock) void k_start_kick(DevState s, RunConst rc, FieldLayout fl) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (g >= rc.n_total) return;
   const int c = s.cid[g];
@@ -230,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_start_kick(DevState s, RunConst rc, 
   const ClusterDyn& d = s.dyn[c];
   if (g - cp.off >= d.n_cur) return;
   double ecx, ecy, ecz;
-  field_sum(s, rc, S, g, ecx, ecy, ecz);
+  field_sum(s, rc, fl, g, ecx, ecy, ecz);
   double a;
   laser_at(cp, d, rc.t0, s.z[g], a);
   const int zc = s.Z[g];
@@ -281,7 +272,7 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_diag_partial(DevState s, RunConst rc, int S) {
+__global__ __launch_bounds__(kBlock) void k_diag_partial(DevState s, RunConst rc, FieldLayout fl) {
   __shared__ double sh[4][kQ];
   const int c = blockIdx.y;
   const ClusterParams& cp = s.cp[c];
@@ -297,9 +288,9 @@ __global__ __launch_bounds__(kBlock) void k_diag_partial(DevState s, RunConst rc
     const double w = cp.weight;
     const double ux = s.ux[g], uy = s.uy[g], uz = s.uz[g];
     double ex, ey, ez;
-    field_sum(s, rc, S, g, ex, ey, ez);
+    field_sum(s, rc, fl, g, ex, ey, ez);
     double phi = 0.0;
-    for (int k = 0; k < S; ++k) phi += s.part[((int64_t)k * kComp + 3) * rc.n_total + g];
+    for (int k = 0; k < fl.S; ++k) phi += s.part[((int64_t)k * kComp + 3) * rc.n_total + g];
     q[0] += w * M * gm1(ux, uy, uz);
     q[1] += s.kebar[g];
     q[2] += 0.5 * w * (double)zc * phi;
@@ -379,7 +370,7 @@ __global__ __launch_bounds__(64) void k_diag_final(DevState s, RunConst rc, int6
 // Flag every ion whose uniform draw alpha in (0,1] falls below P = 1 - exp(-nu dt), nu the
 // ADK rate at the driving field; count flags per ion block.
 template <int PREC>
-__global__ __launch_bounds__(kBlock) void k_ionize_check(DevState s, RunConst rc, int S, int64_t k) {
+__global__ __launch_bounds__(kBlock) void k_ionize_check(DevState s, RunConst rc, FieldLayout fl, int64_t k) {
   const int ibk = blockIdx.x;
   const int c = s.ib_cluster[ibk];
   const ClusterParams& cp = s.cp[c];
@@ -396,7 +387,7 @@ __global__ __launch_bounds__(kBlock) void k_ionize_check(DevState s, RunConst rc
       double F;
       if (rc.ofi_local) {
         double ex, ey, ez;
-        field_sum(s, rc, S, g, ex, ey, ez);
+        field_sum(s, rc, fl, g, ex, ey, ez);
         ex += d.laser_e;
         F = sqrt(ex * ex + ey * ey + ez * ez);
       } else {
@@ -495,40 +486,42 @@ int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
 
-hipError_t launch_schedule(const DevState& s, const RunConst& rc, const ForceTiling& ft, bool advance,
+hipError_t launch_schedule(const DevState& s, const RunConst& rc, const ForceTiling& ft, bool n3, bool advance,
                            hipStream_t st) {
-  k_schedule<<<1, kBlock, 0, st>>>(s, rc, force_tile_targets(ft), ft.S, advance ? 1 : 0);
+  const int TI = n3 ? n3_block_size(ft) : force_tile_targets(ft);
+  k_schedule<<<1, kBlock, 0, st>>>(s, rc, TI, ft.S, n3 ? 1 : 0, advance ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_push(const DevState& s, const RunConst& rc, int precision, int S, int64_t k, bool diag,
-                       hipStream_t st) {
-  if (precision == LC_FP64) k_push<LC_FP64><<<blocks_for(rc.n_total), kBlock, 0, st>>>(s, rc, S, k, diag ? 1 : 0);
-  else k_push<LC_FP32_ACC64><<<blocks_for(rc.n_total), kBlock, 0, st>>>(s, rc, S, k, diag ? 1 : 0);
+hipError_t launch_push(const DevState& s, const RunConst& rc, int precision, const FieldLayout& fl, int64_t k,
+                       bool diag, hipStream_t st) {
+  if (precision == LC_FP64) k_push<LC_FP64><<<blocks_for(rc.n_total), kBlock, 0, st>>>(s, rc, fl, k, diag ? 1 : 0);
+  else k_push<LC_FP32_ACC64><<<blocks_for(rc.n_total), kBlock, 0, st>>>(s, rc, fl, k, diag ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_start_kick(const DevState& s, const RunConst& rc, int precision, int S, hipStream_t st) {
+hipError_t launch_start_kick(const DevState& s, const RunConst& rc, int precision, const FieldLayout& fl,
+                             hipStream_t st) {
   (void)precision;
-  k_start_kick<<<blocks_for(rc.n_total), kBlock, 0, st>>>(s, rc, S);
+  k_start_kick<<<blocks_for(rc.n_total), kBlock, 0, st>>>(s, rc, fl);
   k_sum_kestart<<<rc.n_clusters, kBlock, 0, st>>>(s);
   return hipGetLastError();
 }
 
-hipError_t launch_diag(const DevState& s, const RunConst& rc, int S, int64_t k, hipStream_t st) {
-  k_diag_partial<<<dim3(kDiagBlocks, rc.n_clusters), kBlock, 0, st>>>(s, rc, S);
+hipError_t launch_diag(const DevState& s, const RunConst& rc, const FieldLayout& fl, int64_t k, hipStream_t st) {
+  k_diag_partial<<<dim3(kDiagBlocks, rc.n_clusters), kBlock, 0, st>>>(s, rc, fl);
   k_diag_final<<<rc.n_clusters, 64, 0, st>>>(s, rc, k);
   return hipGetLastError();
 }
 
-hipError_t launch_ionize(const DevState& s, const RunConst& rc, int precision, int S, int64_t k, int n_ion_blocks,
-                         hipStream_t st) {
+hipError_t launch_ionize(const DevState& s, const RunConst& rc, int precision, const FieldLayout& fl, int64_t k,
+                         int n_ion_blocks, hipStream_t st) {
   if (n_ion_blocks <= 0) return hipSuccess;
   if (precision == LC_FP64) {
-    k_ionize_check<LC_FP64><<<n_ion_blocks, kBlock, 0, st>>>(s, rc, S, k);
+    k_ionize_check<LC_FP64><<<n_ion_blocks, kBlock, 0, st>>>(s, rc, fl, k);
     k_ionize_spawn<LC_FP64><<<n_ion_blocks, kBlock, 0, st>>>(s, rc, k);
   } else {
-    k_ionize_check<LC_FP32_ACC64><<<n_ion_blocks, kBlock, 0, st>>>(s, rc, S, k);
+    k_ionize_check<LC_FP32_ACC64><<<n_ion_blocks, kBlock, 0, st>>>(s, rc, fl, k);
     k_ionize_spawn<LC_FP32_ACC64><<<n_ion_blocks, kBlock, 0, st>>>(s, rc, k);
   }
   return hipGetLastError();

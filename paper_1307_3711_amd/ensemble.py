@@ -10,7 +10,7 @@ import time
 import numpy as np
 import torch
 
-from ._binding import R_ABS_EV, R_MEANZ, Simulation, make_config
+from ._binding import R_ABS_EV, R_MEANZ, Simulation, make_config, pair_blocks_for
 
 
 def run_ensemble(descs, states, precision="fp32_acc64", dt=0.05, softening_nm=0.1, seed=0, diag_every=50,
@@ -18,8 +18,10 @@ def run_ensemble(descs, states, precision="fp32_acc64", dt=0.05, softening_nm=0.
     """Integrate every cluster until it retires.  descs: lc_cluster descriptions with n_steps
     set; states: initial particle arrays (x_nm, u, Z) per cluster.  Returns a dict with the
     last diagnostic record of each cluster, per-cluster counters and the timed wall clock."""
+    # room for the pair-once kernel (blocks of 128 slots and up) where the precision allows it
+    mpb = pair_blocks_for([d.capacity for d in descs], 128) if precision == "fp32_acc64" else 0
     cfg = make_config(precision, ionize=True, dt=dt, softening_nm=softening_nm, diag_every=diag_every,
-                      max_records=4, max_splits=8, seed=seed)
+                      max_records=4, max_splits=8, seed=seed, max_pair_blocks=mpb)
     sim = Simulation(cfg, descs)
     for i, st in enumerate(states):
         sim.init_from_host(i, st["x_nm"], st["u"], st["Z"])

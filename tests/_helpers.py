@@ -27,13 +27,14 @@ def descs(clusters, weight=None):
 
 
 def gpu_run(clusters, run, precision="fp64", states=None, max_records=4096, weight=None, n_steps_per_cluster=None,
-            max_splits=32, tuning=None):
-    """Create, initialise and start a GPU simulation of the given clusters."""
+            max_splits=32, tuning=None, max_pair_blocks=0):
+    """Create, initialise and start a GPU simulation of the given clusters (a tuning is set
+    before the start, so the start's field pass already uses it)."""
     import paper_1307_3711_amd as lc
     lam = clusters[0].laser.lambda_um
     cfg = lc.make_config(precision, ionize=run.ionize, ofi_field=run.ofi_field, lambda_um=lam, dt=run.dt, t0=run.t0,
                          softening_nm=run.softening_nm, diag_every=run.diag_every, max_records=max_records,
-                         max_splits=max_splits, seed=run.seed)
+                         max_splits=max_splits, seed=run.seed, max_pair_blocks=max_pair_blocks)
     ds = descs(clusters, weight)
     if n_steps_per_cluster is not None:
         for d, n in zip(ds, n_steps_per_cluster):
@@ -54,6 +55,19 @@ def oracle_run(cluster, run, state, cluster_index=0, weight=None):
     sim = oracle.Sim.from_workload(cluster, run, state, cluster_index, **kw)
     sim.start()
     return sim
+
+
+def field_scale(x, q, eps2):
+    """S1_i = sum_{j != i} |q_j| |r_ij| / (r_ij^2 + eps^2)^{3/2}: the magnitude of the terms a
+    field sum adds, against which its rounding is measured."""
+    s1 = np.zeros(x.shape[0])
+    for i in range(x.shape[0]):
+        d = x[i] - x
+        r2 = np.sum(d * d, axis=1)
+        t = np.abs(q) * np.sqrt(r2) / (r2 + eps2) ** 1.5
+        t[i] = 0.0
+        s1[i] = np.sum(t)
+    return s1
 
 
 def norm_positions(state, lam=0.8):

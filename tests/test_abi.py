@@ -113,3 +113,34 @@ def test_field_workspace_size():
     bad = lc.make_tuning(R=3)
     assert L.lc_field_workspace_bytes(0, 1000, ctypes.byref(bad)) == 0
     assert L.lc_field_workspace_bytes(9, 1000, None) == 0
+
+
+def test_pair_once_rows_in_state_bytes():
+    """max_pair_blocks M adds 3 M FP32 rows per slot, slots rounded up to 512 per cluster."""
+    c, run = small_ar()
+    d = _desc(c)
+    base = _bytes(lc.make_config("fp32_acc64", max_splits=8), [d])
+    with_rows = _bytes(lc.make_config("fp32_acc64", max_splits=8, max_pair_blocks=10), [d])
+    slots = -(-c.capacity // 512) * 512
+    assert abs((with_rows - base) - 12 * 10 * slots) <= 256
+    assert _bytes(lc.make_config("fp64", max_pair_blocks=10), [d]) == 0        # FP32 + FP64 accumulation only
+    assert _bytes(lc.make_config("fp32_kahan", max_pair_blocks=10), [d]) == 0
+    assert _bytes(lc.make_config("fp32_acc64", max_pair_blocks=-1), [d]) == 0
+    assert _bytes(lc.make_config("fp32_acc64", max_pair_blocks=40000), [d]) == 0
+
+
+@pytest.mark.parametrize("R,WJ,ok", [(1, 1, True), (2, 1, True), (1, 2, True), (2, 2, True), (4, 2, True),
+                                     (4, 4, True), (4, 1, False), (1, 4, False), (2, 4, False), (8, 1, False)])
+def test_pair_once_field_workspace(R, WJ, ok):
+    L = lc.lib()
+    n = 1000
+    t = lc.make_tuning(R=R, WJ=WJ, newton3=1)
+    wb = L.lc_field_workspace_bytes(1, n, ctypes.byref(t))
+    if not ok:
+        assert wb == 0
+        return
+    B = (4 // WJ) * 64 * R
+    nb = -(-n // B)
+    assert wb >= nb * nb * 3 * B * 4 + n * 16
+    assert L.lc_field_workspace_bytes(0, n, ctypes.byref(t)) == 0   # not for FP64
+    assert L.lc_field_workspace_bytes(2, n, ctypes.byref(t)) == 0   # not for Kahan

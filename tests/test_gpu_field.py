@@ -110,6 +110,46 @@ def test_field_fp32_elementwise(precision, factor, n, ti):
     assert np.all(np.abs(Pg - Po) <= factor * U32 * s0 + 1e-300)
 
 
+N3_TILINGS = [
+    dict(R=1, WJ=1, newton3=1),
+    dict(R=2, WJ=1, newton3=1),
+    dict(R=1, WJ=2, newton3=1),
+    dict(R=2, WJ=2, newton3=1, persistent=1),
+    dict(R=4, WJ=2, newton3=1),
+    dict(R=4, WJ=4, newton3=1),
+    dict(R=4, WJ=4, newton3=1, persistent=1),
+]
+
+
+@pytest.mark.skipif(not gpu_available(), reason="needs a GPU")
+@pytest.mark.parametrize("n", [1, 2, 63, 129, 1000, 2053])
+@pytest.mark.parametrize("ti", range(len(N3_TILINGS)))
+def test_field_pair_once_elementwise(n, ti):
+    """Each unordered pair evaluated once and applied to both particles: same tolerance as the
+    one-sided FP32 kernel (64 u S1 against the oracle on the FP32-rounded inputs).  The state
+    has non-uniform ion charges and uniform electrons, so blocks and chunks of every charge
+    pattern occur, and n spans one block, several blocks and ragged tails."""
+    x, q = _state(n, 5 * n + 3)
+    xr = x.astype(np.float32).astype(np.float64)
+    qr = q.astype(np.float32).astype(np.float64)
+    Eo, _ = oracle.coulomb_field(xr, qr, float(np.float32(EPS2)))
+    Eg, _ = _gpu_field(x, q, EPS2, "fp32_acc64", N3_TILINGS[ti], phi=False)
+    s1, _ = _scales(xr, qr, EPS2)
+    print(f"pair-once n={n} tiling={N3_TILINGS[ti]} maxrel={np.max(np.abs(Eg - Eo) / s1[:, None]):.3e}", flush=True)
+    assert np.all(np.abs(Eg - Eo) <= 64.0 * U32 * s1[:, None] + 1e-300)
+
+
+@pytest.mark.skipif(not gpu_available(), reason="needs a GPU")
+def test_field_pair_once_rejects_potential():
+    import torch
+    import paper_1307_3711_amd as lc
+    xyzq = torch.zeros((4, 10), dtype=torch.float64, device="cuda")
+    with pytest.raises(lc.LcError):
+        lc.field(xyzq, EPS2, precision="fp32_acc64", want_phi=True, tuning=lc.make_tuning(R=4, WJ=4, newton3=1))
+    with pytest.raises(lc.LcError):
+        lc.field(xyzq, EPS2, precision="fp64", want_phi=False, tuning=lc.make_tuning(R=4, WJ=4, newton3=1))
+
+
 @pytest.mark.skipif(not gpu_available(), reason="needs a GPU")
 def test_field_empty_input():
     import torch
@@ -132,7 +172,9 @@ def test_field_rejects_bad_arguments():
 
 @pytest.mark.skipif(not gpu_available(), reason="needs a GPU")
 @pytest.mark.parametrize("precision,tiling", [("fp64", dict(S=16)), ("fp32_acc64", dict(S=16)),
-                                              ("fp32_acc64", dict(R=1, WJ=4, T=1024, S=16, scalar=1))])
+                                              ("fp32_acc64", dict(R=1, WJ=4, T=1024, S=16, scalar=1)),
+                                              ("fp32_acc64", dict(R=4, WJ=4, newton3=1)),
+                                              ("fp32_acc64", dict(R=2, WJ=2, newton3=1, persistent=1))])
 def test_field_full_20k_sampled(precision, tiling):
     """The 20k-macroparticle argon state at full size (the benchmark's workload, including the
     scalar-source tiling the autotuner picks for it): sampled targets against the oracle
@@ -143,7 +185,8 @@ def test_field_full_20k_sampled(precision, tiling):
     w = units.n_atoms(c.r0_nm, 2.4) / c.n_ion
     q = units.kappa(0.8) * w * st["Z"].astype(np.float64)
     idx = np.unique(np.concatenate([np.arange(0, x.shape[0], 997), [0, 9999, 10000, x.shape[0] - 1]]))
-    Eg, Pg = _gpu_field(x, q, EPS2, precision, tiling)
+    phi = not tiling.get("newton3", 0)
+    Eg, Pg = _gpu_field(x, q, EPS2, precision, tiling, phi=phi)
     if precision == "fp64":
         Eo, Po = oracle.coulomb_field_at(x, q, EPS2, idx)
         tol = 1e-12
@@ -154,4 +197,5 @@ def test_field_full_20k_sampled(precision, tiling):
         tol = 64 * U32
     s1, s0 = _scales(x, q, EPS2, idx)
     assert np.all(np.abs(Eg[idx] - Eo) <= tol * s1[:, None])
-    assert np.all(np.abs(Pg[idx] - Po) <= tol * s0)
+    if phi:
+        assert np.all(np.abs(Pg[idx] - Po) <= tol * s0)

@@ -20,7 +20,7 @@ import oracle
 from oracle import units
 from workloads import Cluster, Laser, Run, initial_state, small_ar, ensemble, xe_200k
 
-from _helpers import gpu_available, gpu_run, oracle_run, oracle_spread
+from _helpers import field_scale, gpu_available, gpu_run, oracle_run, oracle_spread
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
 
@@ -64,10 +64,21 @@ def test_small_ar_fp64_200_steps():
     assert rg[0, 23] == pytest.approx(osim.ke_start, rel=1e-12, abs=1e-300)
 
 
-@pytest.mark.parametrize("precision", ["fp32_acc64", "fp32_kahan"])
-def test_small_ar_fp32_200_steps(precision):
+# Pair-once tilings (each unordered pair evaluated once for both particles on steps without
+# a diagnostic record); the diagnostic steps take the one-sided kernels with the other fields.
+N3 = dict(R=4, WJ=4, T=1024, S=8, scalar=1, newton3=1)
+N3_TILINGS = [N3, dict(R=1, WJ=2, S=4, persistent=1, newton3=1), dict(R=2, WJ=1, S=2, newton3=1)]
+
+
+@pytest.mark.parametrize("precision,tiling", [("fp32_acc64", None), ("fp32_kahan", None), ("fp32_acc64", N3_TILINGS[0]),
+                                              ("fp32_acc64", N3_TILINGS[1]), ("fp32_acc64", N3_TILINGS[2])])
+def test_small_ar_fp32_200_steps(precision, tiling):
+    import paper_1307_3711_amd as lc
     c, run = small_ar()
-    sim, states = gpu_run([c], run, precision)
+    mpb = lc.pair_blocks_for([c.capacity]) if tiling else 0
+    sim, states = gpu_run([c], run, precision, tuning=tiling, max_pair_blocks=mpb)
+    if tiling:
+        assert sim.tuning()["newton3"] == 1
     osim = oracle_run(c, run, states[0])
     sim.step(200)
     rg = sim.diagnostics(0)
@@ -124,12 +135,15 @@ def test_two_body_closed_form_on_gpu():
     assert errs[1] < 2e-3
 
 
-def test_determinism_and_graph_replay_bitwise():
+@pytest.mark.parametrize("tiling", [None, N3])
+def test_determinism_and_graph_replay_bitwise(tiling):
+    import paper_1307_3711_amd as lc
     c, run = small_ar()
     run = Run(dt=0.05, ionize=True, diag_every=10, seed=0)
+    mpb = lc.pair_blocks_for([c.capacity]) if tiling else 0
     out = []
     for graph in (0, 0, 20):
-        sim, _ = gpu_run([c], run, "fp32_acc64")
+        sim, _ = gpu_run([c], run, "fp32_acc64", tuning=tiling, max_pair_blocks=mpb)
         if graph:
             sim.set_graph(graph)
         sim.step(60)
@@ -197,6 +211,54 @@ def test_ensemble_matches_oracle_per_cluster():
             sc = np.max(np.abs(ro[:, col])) + 1e-300
             err = np.max(np.abs(rg[:, col] - ro[:, col])) / sc
             assert err <= max(1e-10, 100 * sp), (col, err, sp)
+
+
+@pytest.mark.parametrize("tiling", N3_TILINGS + [dict(R=4, WJ=2, newton3=1), dict(R=1, WJ=1, newton3=1, persistent=1)])
+def test_ensemble_field_pair_once_matches_oracle(tiling):
+    """Pair-once field passes over an ensemble of uneven clusters (one launch, per-cluster
+    row tables): after some steps with ionization (counts changed, spawned electrons
+    appended), each cluster's field against the oracle on the FP32-rounded positions and
+    charges, element by element, to 64 u S1 (as the one-sided FP32 kernel)."""
+    import paper_1307_3711_amd as lc
+    from workloads.species import SPECIES
+    cl = ensemble(5, seed=3, cap_lo=200, cap_hi=1500)
+    run = Run(dt=0.05, ionize=True, diag_every=5, seed=3)
+    states = [initial_state(c, run.seed, i) for i, c in enumerate(cl)]
+    mpb = lc.pair_blocks_for([c.capacity for c in cl])
+    sim, _ = gpu_run(cl, run, "fp32_acc64", states=states, tuning=tiling, max_pair_blocks=mpb)
+    sim.step(7)
+    eps2 = float(np.float32(units.nm_to_norm(run.softening_nm, 0.8) ** 2))
+    u32 = 2.0**-24
+    for i, c in enumerate(cl):
+        g = sim.particles(i)
+        E = sim.field(i)
+        w = units.n_atoms(c.r0_nm, SPECIES[c.species]["rw_angstrom"]) / c.n_ion
+        q = units.kappa(0.8) * w * g["Z"].astype(np.float64)
+        xr = g["x"].astype(np.float32).astype(np.float64)
+        qr = q.astype(np.float32).astype(np.float64)
+        Eo, _ = oracle.coulomb_field(xr, qr, eps2)
+        s1 = field_scale(xr, qr, eps2)
+        rel = np.max(np.abs(E - Eo) / (s1[:, None] + 1e-300))
+        print(f"cluster {i} ({c.species}, n {g['n']}): pair-once field maxrel {rel:.2e}", flush=True)
+        assert E.shape == Eo.shape
+        assert np.all(np.abs(E - Eo) <= 64 * u32 * s1[:, None] + 1e-300)
+
+
+def test_pair_once_needs_room():
+    """A pair-once tiling is refused when a cluster spans more blocks than max_pair_blocks,
+    or when the handle has no pair-once rows at all; the tiling in force stays unchanged."""
+    import paper_1307_3711_amd as lc
+    c, run = small_ar()                                  # capacity 4500
+    sim, _ = gpu_run([c], run, "fp32_acc64", max_pair_blocks=9)
+    with pytest.raises(lc.LcError):
+        sim.set_tuning(R=4, WJ=4, newton3=1)             # blocks of 256: 18 > 9
+    assert sim.tuning()["newton3"] == 0
+    sim.set_tuning(R=2, WJ=1, newton3=1)                 # blocks of 512: 9
+    assert sim.tuning()["newton3"] == 1
+    sim.step(3)
+    sim0, _ = gpu_run([c], run, "fp32_acc64")
+    with pytest.raises(lc.LcError):
+        sim0.set_tuning(R=2, WJ=1, newton3=1)
 
 
 def test_capacity_overflow_is_latched():
