@@ -259,7 +259,7 @@ int choose_splits(const lc_sim* s, const ForceTiling& ft) {
 }
 
 int force_grid(const lc_sim* s, const ForceTiling& ft, bool n3) {
-  if (ft.persistent) return device_cus() * 4;
+  if (ft.persistent && !n3) return device_cus() * 4;
   const int TI = n3 ? n3_block_size(ft) : force_tile_targets(ft);
   int64_t tiles = 0;
   for (int c = 0; c < s->C; ++c) {
@@ -267,6 +267,7 @@ int force_grid(const lc_sim* s, const ForceTiling& ft, bool n3) {
     const int64_t nb = (std::max<int64_t>(n, 1) + TI - 1) / TI;
     tiles += n3 ? nb * (nb + 1) / 2 : nb * ft.S;
   }
+  if (ft.persistent) return n3_persistent_grid(ft, tiles, device_cus());
   return (int)std::min<int64_t>(tiles, std::numeric_limits<int32_t>::max());
 }
 
@@ -721,6 +722,7 @@ int lc_set_tuning(lc_sim* s, const lc_tuning* t) {
   if (!force_tiling_valid(s->cfg.precision, chk) || ft.S > s->cfg.max_splits || ft.S < 0)
     return fail(s, LC_E_INVALID, "invalid tiling");
   if (!n3_fits(s, ft)) return fail(s, LC_E_INVALID, "pair-once tiling needs ceil(capacity / B) <= max_pair_blocks");
+  if (ft.newton3 && ft.persistent) (void)force_grid(s, ft, true);  // occupancy query outside any capture
   s->ft = ft;
   const int S_new = choose_splits(s, ft);
   if (s->started && S_new != s->S_eff) {

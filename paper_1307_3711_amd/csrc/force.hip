@@ -437,7 +437,8 @@ __device__ inline void decode_pair_tile(const TileMap& m, int t, int& c, int& I,
 
 // x from lane (l + 1) mod 64 for every lane l (DPP wave_rol:1).
 __device__ inline float wave_rol1(float x) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x134, 0xf, 0xf, false));
+  // every lane of the wave has a source lane, so no "old" value is needed
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x134, 0xf, 0xf, false));
 }
 
 // Orders the LDS traffic of one wave around a point where lanes read what other lanes wrote.
@@ -446,6 +447,11 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+
+// Per-wave LDS slice: the chunk twice (128 entries) plus room for the prefetch of the rotation
+// after the last one (up to 8 entries, read and discarded).
+constexpr int kN3Slice = 136;
+constexpr int kN3Fixed = 4 * kN3Slice * 4;  // floats: the four waves' slices
 
 // One chunk of 64 sources (sb: the chunk twice) against the lane's R targets.  US: all
 // sources of the chunk carry one charge (factored out by the caller); UT: likewise for the
@@ -456,12 +462,20 @@ __device__ inline void n3_chunk(const float4* sb, int lane, const float* xi, con
                                 const float* qi, float eps2f, float* fx, float* fy, float* fz, float& ax, float& ay,
                                 float& az) {
   constexpr int U = (R >= 8) ? 1 : 8 / R;
+  static_assert(128 + U <= kN3Slice, "prefetch stays inside the wave's slice");
   float rx = 0.f, ry = 0.f, rz = 0.f;  // running sums of source (lane + k) mod 64
+  // software pipeline: the sources of the next U rotations are read while these are used
+  // (the slice has kN3Slice >= 128 + U entries, so the read after the last rotation stays in it)
+  float4 cur[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) cur[u] = sb[lane + u];
   for (int k0 = 0; k0 < 64; k0 += U) {
+    float4 nxt[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) nxt[u] = sb[lane + k0 + U + u];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int k = k0 + u;
-      const float4 sj = sb[lane + k];
+      const float4 sj = cur[u];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const float dx = xi[r] - sj.x;
@@ -489,13 +503,14 @@ __device__ inline void n3_chunk(const float4* sb, int lane, const float* xi, con
         rz = wave_rol1(rz);
       }
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u) cur[u] = nxt[u];
   }
   ax = rx;
   ay = ry;
   az = rz;
 }
 
-constexpr int kN3Fixed = 4 * 128 * 4;  // floats: per-wave chunk copies
 
 __host__ __device__ constexpr int n3_block(int R, int WJ) { return (4 / WJ) * 64 * R; }
 
@@ -515,7 +530,7 @@ __device__ void tile_n3(const N3Args& a, int t, float* lds) {
   const bool jside = (I != J);
   // rows exist only for blocks holding live slots (I <= J < nb <= M for a table built for n)
   const bool live = (int64_t)J * B < n && I <= J && J < a.M;
-  float4* sb = reinterpret_cast<float4*>(lds) + w * 128;
+  float4* sb = reinterpret_cast<float4*>(lds) + w * kN3Slice;
   float* jres = lds + kN3Fixed;       // [TG][3][B] reaction sums of the block's sources
   float* ired = jres + TG * 3 * B;    // [WJ - 1][3][B] target sums of waves jw > 0
 
@@ -797,6 +812,27 @@ size_t n3_lds_bytes(const ForceTiling& ft) {
   return sizeof(float) * ((size_t)kN3Fixed + (size_t)(4 / ft.WJ) * 3 * B + (size_t)(ft.WJ - 1) * 3 * B);
 }
 
+// Workgroups of the pair-once kernel one CU holds at once (occupancy), cached per shape.
+int n3_resident_per_cu(const ForceTiling& ft) {
+  static int cache[8][4] = {};
+  int& v = cache[ft.R & 7][ft.WJ & 3];
+  if (v > 0) return v;
+  const size_t lds = n3_lds_bytes(ft);
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (ft.WJ * 16 + ft.R) {
+    case 16 + 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<1, 1>, kBlock, lds); break;
+    case 16 + 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<2, 1>, kBlock, lds); break;
+    case 32 + 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<1, 2>, kBlock, lds); break;
+    case 32 + 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<2, 2>, kBlock, lds); break;
+    case 32 + 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<4, 2>, kBlock, lds); break;
+    case 64 + 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<4, 4>, kBlock, lds); break;
+    default: break;
+  }
+  v = (e == hipSuccess && nb > 0) ? nb : 4;
+  return v;
+}
+
 hipError_t launch_n3(const ForceTiling& ft, const N3Args& a, int grid, hipStream_t st) {
   const size_t lds = n3_lds_bytes(ft);
   switch (ft.WJ * 16 + ft.R) {
@@ -941,6 +977,15 @@ __global__ void k_sum_n3(const float* rows, int64_t n, int B, double* E) {
 int force_tile_targets(const ForceTiling& ft) { return (4 / ft.WJ) * 64 * ft.R; }
 
 int n3_block_size(const ForceTiling& ft) { return n3_block(ft.R, ft.WJ); }
+
+int n3_persistent_grid(const ForceTiling& ft, int64_t tiles, int cus) {
+  // as many workgroups as fit at once, trimmed so that every one of them takes the same
+  // number of tiles (within one) in the same number of rounds
+  const int64_t pmax = std::max<int64_t>(1, (int64_t)cus * n3_resident_per_cu(ft));
+  const int64_t t = std::max<int64_t>(tiles, 1);
+  const int64_t rounds = (t + pmax - 1) / pmax;
+  return (int)((t + rounds - 1) / rounds);
+}
 
 int64_t n3_tiles(int64_t n, int B) {
   const int64_t nb = (n + B - 1) / B;
