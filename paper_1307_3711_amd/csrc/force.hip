@@ -398,8 +398,9 @@ __device__ void tile_f64(const ForceArgs<double4>& a, int t, double4* lds) {
 // part from block I; the diagonal tile (I, I) takes all pairs of its block one-sided (the self
 // pair adds exactly zero).  Inside a block of 256 threads, 4/WJ target groups hold 64 R targets
 // each (R per lane) and the WJ waves of a group split the B sources.  A wave walks its sources
-// in chunks of 64, staged twice in a row in its own LDS slice: at rotation k lane l meets
-// source (l + k) mod 64 at index l + k, an immediate offset.  The reaction sums of the chunk's
+// in chunks of 64, staged twice in a row in its own LDS slice (structure of arrays x, y, z, q,
+// so every read is a unit-stride dword access free of bank conflicts): at rotation k lane l
+// meets source (l + k) mod 64 at index l + k, an immediate offset.  The reaction sums of the chunk's
 // sources travel with the rotation in registers: lane l holds the running sum of source
 // (l + k) mod 64, adds its terms, and hands it to lane l - 1 (DPP wave rotate by one lane), so
 // after 64 rotations lane l holds source l's sum, accumulated in a fixed order (deterministic).
@@ -448,69 +449,91 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Per-wave LDS slice: the chunk twice (128 entries) plus room for the prefetch of the rotation
-// after the last one (up to 8 entries, read and discarded).
+// Per-wave LDS slice: x, y, z, q arrays of the chunk twice (128 entries each) plus room for
+// the prefetch of the rotation after the last one (up to 8 entries, read and discarded).
 constexpr int kN3Slice = 136;
-constexpr int kN3Fixed = 4 * kN3Slice * 4;  // floats: the four waves' slices
+constexpr int kN3Fixed = 4 * 4 * kN3Slice;  // floats: the four waves' slices
 
-// One chunk of 64 sources (sb: the chunk twice) against the lane's R targets.  US: all
-// sources of the chunk carry one charge (factored out by the caller); UT: likewise for the
-// targets of the wave.  JSIDE: also the reaction sums sum_r q_r s_r (r_i - r_j) of the
-// chunk's sources, returned in (ax, ay, az) of lane l for source l.
-template <int R, bool US, bool UT, bool JSIDE>
-__device__ inline void n3_chunk(const float4* sb, int lane, const float* xi, const float* yi, const float* zi,
-                                const float* qi, float eps2f, float* fx, float* fy, float* fz, float& ax, float& ay,
-                                float& az) {
-  constexpr int U = (R >= 8) ? 1 : 8 / R;
-  static_assert(128 + U <= kN3Slice, "prefetch stays inside the wave's slice");
-  float rx = 0.f, ry = 0.f, rz = 0.f;  // running sums of source (lane + k) mod 64
-  // software pipeline: the sources of the next U rotations are read while these are used
-  // (the slice has kN3Slice >= 128 + U entries, so the read after the last rotation stays in it)
-  float4 cur[U];
+// One chunk of 64 sources (sb: x, y, z, q arrays of the chunk twice, kN3Slice apart) against
+// the lane's R targets.  US: all sources of the chunk carry one charge (factored out by the
+// caller); UT: likewise for the targets of the wave.  JSIDE: also the reaction sums
+// sum_r q_r s_r (r_i - r_j) of the chunk's sources, returned in (ax, ay, az) of lane l for
+// source l.
+// U rotations of the chunk from the register buffers (bx, by, bz, bq) holding their sources.
+template <int R, int U, bool US, bool UT, bool JSIDE>
+__device__ inline void n3_steps(const float* bx, const float* by, const float* bz, const float* bq, const float* xi,
+                                const float* yi, const float* zi, const float* qi, float eps2f, float* fx, float* fy,
+                                float* fz, float& rx, float& ry, float& rz) {
 #pragma unroll
-  for (int u = 0; u < U; ++u) cur[u] = sb[lane + u];
-  for (int k0 = 0; k0 < 64; k0 += U) {
-    float4 nxt[U];
+  for (int u = 0; u < U; ++u) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) nxt[u] = sb[lane + k0 + U + u];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const float4 sj = cur[u];
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const float dx = xi[r] - sj.x;
-        const float dy = yi[r] - sj.y;
-        const float dz = zi[r] - sj.z;
-        float r2 = __builtin_fmaf(dx, dx, eps2f);
-        r2 = __builtin_fmaf(dy, dy, r2);
-        r2 = __builtin_fmaf(dz, dz, r2);
-        const float inv = rsq32(r2);
-        const float r3 = inv * (inv * inv);
-        const float si = US ? r3 : sj.w * r3;
-        fx[r] = __builtin_fmaf(si, dx, fx[r]);
-        fy[r] = __builtin_fmaf(si, dy, fy[r]);
-        fz[r] = __builtin_fmaf(si, dz, fz[r]);
-        if (JSIDE) {
-          const float sr = UT ? r3 : qi[r] * r3;
-          rx = __builtin_fmaf(sr, dx, rx);
-          ry = __builtin_fmaf(sr, dy, ry);
-          rz = __builtin_fmaf(sr, dz, rz);
-        }
-      }
+    for (int r = 0; r < R; ++r) {
+      const float dx = xi[r] - bx[u];
+      const float dy = yi[r] - by[u];
+      const float dz = zi[r] - bz[u];
+      float r2 = __builtin_fmaf(dx, dx, eps2f);
+      r2 = __builtin_fmaf(dy, dy, r2);
+      r2 = __builtin_fmaf(dz, dz, r2);
+      const float inv = rsq32(r2);
+      const float r3 = inv * (inv * inv);
+      const float si = US ? r3 : bq[u] * r3;
+      fx[r] = __builtin_fmaf(si, dx, fx[r]);
+      fy[r] = __builtin_fmaf(si, dy, fy[r]);
+      fz[r] = __builtin_fmaf(si, dz, fz[r]);
       if (JSIDE) {
-        rx = wave_rol1(rx);
-        ry = wave_rol1(ry);
-        rz = wave_rol1(rz);
+        const float sr = UT ? r3 : qi[r] * r3;
+        rx = __builtin_fmaf(sr, dx, rx);
+        ry = __builtin_fmaf(sr, dy, ry);
+        rz = __builtin_fmaf(sr, dz, rz);
       }
     }
+    if (JSIDE) {
+      rx = wave_rol1(rx);
+      ry = wave_rol1(ry);
+      rz = wave_rol1(rz);
+    }
+  }
+}
+
+// Sources of rotations [k, k + U) into registers.
+template <int U, bool US>
+__device__ inline void n3_load(const float* sx, int k, float* bx, float* by, float* bz, float* bq) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+  for (int u = 0; u < U; ++u) {
+    bx[u] = sx[k + u];
+    by[u] = sx[kN3Slice + k + u];
+    bz[u] = sx[2 * kN3Slice + k + u];
+    if (!US) bq[u] = sx[3 * kN3Slice + k + u];
+  }
+}
+
+// One chunk of 64 sources (sb: x, y, z, q arrays of the chunk twice, kN3Slice apart) against
+// the lane's R targets.  US: all sources of the chunk carry one charge (factored out by the
+// caller); UT: likewise for the targets of the wave.  JSIDE: also the reaction sums
+// sum_r q_r s_r (r_i - r_j) of the chunk's sources, returned in (ax, ay, az) of lane l for
+// source l.  Software pipelined over two register buffers: the sources of the next U
+// rotations are read while the current U are used (the slice has kN3Slice >= 128 + U
+// entries, so the read after the last rotation stays inside it).
+template <int R, bool US, bool UT, bool JSIDE>
+__device__ inline void n3_chunk(const float* sb, int lane, const float* xi, const float* yi, const float* zi,
+                                const float* qi, float eps2f, float* fx, float* fy, float* fz, float& ax, float& ay,
+                                float& az) {
+  constexpr int U = (R >= 4) ? 2 : 4;  // rotations per register buffer
+  static_assert(128 + U <= kN3Slice && 64 % (2 * U) == 0, "prefetch stays inside the wave's slice");
+  const float* sx = sb + lane;
+  float rx = 0.f, ry = 0.f, rz = 0.f;  // running sums of source (lane + k) mod 64
+  float ax_[U], ay_[U], az_[U], aq_[U], bx_[U], by_[U], bz_[U], bq_[U];
+  n3_load<U, US>(sx, 0, ax_, ay_, az_, aq_);
+  for (int k0 = 0; k0 < 64; k0 += 2 * U) {
+    n3_load<U, US>(sx, k0 + U, bx_, by_, bz_, bq_);
+    n3_steps<R, U, US, UT, JSIDE>(ax_, ay_, az_, aq_, xi, yi, zi, qi, eps2f, fx, fy, fz, rx, ry, rz);
+    n3_load<U, US>(sx, k0 + 2 * U, ax_, ay_, az_, aq_);
+    n3_steps<R, U, US, UT, JSIDE>(bx_, by_, bz_, bq_, xi, yi, zi, qi, eps2f, fx, fy, fz, rx, ry, rz);
   }
   ax = rx;
   ay = ry;
   az = rz;
 }
-
 
 __host__ __device__ constexpr int n3_block(int R, int WJ) { return (4 / WJ) * 64 * R; }
 
@@ -530,7 +553,7 @@ __device__ void tile_n3(const N3Args& a, int t, float* lds) {
   const bool jside = (I != J);
   // rows exist only for blocks holding live slots (I <= J < nb <= M for a table built for n)
   const bool live = (int64_t)J * B < n && I <= J && J < a.M;
-  float4* sb = reinterpret_cast<float4*>(lds) + w * kN3Slice;
+  float* sb = lds + w * 4 * kN3Slice;  // x, y, z, q arrays of the wave's chunk
   float* jres = lds + kN3Fixed;       // [TG][3][B] reaction sums of the block's sources
   float* ired = jres + TG * 3 * B;    // [WJ - 1][3][B] target sums of waves jw > 0
 
@@ -566,8 +589,14 @@ __device__ void tile_n3(const N3Args& a, int t, float* lds) {
       const float4 sv = (jj < n) ? src[jj] : make_float4(1e30f, 1e30f, 1e30f, 0.f);
       const float qs0 = src[jb].w;
       const bool us = __all(jj >= n || sv.w == qs0);
-      sb[lane] = sv;
-      sb[lane + 64] = sv;
+      sb[lane] = sv.x;
+      sb[lane + 64] = sv.x;
+      sb[kN3Slice + lane] = sv.y;
+      sb[kN3Slice + lane + 64] = sv.y;
+      sb[2 * kN3Slice + lane] = sv.z;
+      sb[2 * kN3Slice + lane + 64] = sv.z;
+      sb[3 * kN3Slice + lane] = sv.w;
+      sb[3 * kN3Slice + lane + 64] = sv.w;
       wave_lds_sync();
       float cx[R], cy[R], cz[R], ax, ay, az;
 #pragma unroll
@@ -710,7 +739,7 @@ __global__ __launch_bounds__(64 * kFoldWaves) void k_fold_n3(DevState s, RunCons
 
 // ----------------------------------------------------------------------------- kernels
 template <int R, int WJ>
-__global__ __launch_bounds__(kBlock) void k_force_n3(N3Args a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_force_n3(N3Args a) {
   extern __shared__ float lds_n3[];
   const int total = *a.map.tile_total;
   if (!a.persistent) {
