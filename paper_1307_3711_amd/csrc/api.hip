@@ -280,9 +280,10 @@ hipError_t enqueue_steps(lc_sim* s, int count, int64_t first_step) {
     const bool diag = is_diag_step(s, first_step + k);
     const bool n3 = n3_pass(s, ft, diag);
     const FieldLayout fl = field_layout(ft, n3);
-    hipError_t e = launch_force(s->s, s->rc, s->cfg.precision, ft, diag, force_grid(s, ft, n3), s->stream);
+    hipError_t e = launch_force(s->s, s->rc, s->cfg.precision, ft, diag, force_grid(s, ft, n3), s->stream, false);
     if (e != hipSuccess) return e;
-    e = launch_push(s->s, s->rc, s->cfg.precision, fl, 0, diag, s->stream);
+    e = n3 ? launch_fold_push(s->s, s->rc, s->cfg.precision, n3_block_size(ft), 0, diag, s->stream)
+           : launch_push(s->s, s->rc, s->cfg.precision, fl, 0, diag, s->stream);
     if (e != hipSuccess) return e;
     if (diag) {
       e = launch_diag(s->s, s->rc, fl, 0, s->stream);
@@ -1020,11 +1021,14 @@ extern "C" int lc_profile_steps(lc_sim* s, int64_t n_steps, double* out_ms, int6
       const FieldLayout fl = field_layout(ft, n3);
       hipEvent_t* E = &ev[8 * k];
       e = hipEventRecord(E[0], s->stream);
-      if (e == hipSuccess) e = launch_force(s->s, s->rc, s->cfg.precision, ft, diag, force_grid(s, ft, n3), s->stream);
+      if (e == hipSuccess)
+        e = launch_force(s->s, s->rc, s->cfg.precision, ft, diag, force_grid(s, ft, n3), s->stream, false);
       if (e == hipSuccess) e = hipEventRecord(E[1], s->stream);
       used[4 * k + 0] = 1;
       if (e == hipSuccess) e = hipEventRecord(E[2], s->stream);
-      if (e == hipSuccess) e = launch_push(s->s, s->rc, s->cfg.precision, fl, 0, diag, s->stream);
+      if (e == hipSuccess)
+        e = n3 ? launch_fold_push(s->s, s->rc, s->cfg.precision, n3_block_size(ft), 0, diag, s->stream)
+               : launch_push(s->s, s->rc, s->cfg.precision, fl, 0, diag, s->stream);
       if (e == hipSuccess) e = hipEventRecord(E[3], s->stream);
       used[4 * k + 1] = 1;
       if (diag && e == hipSuccess) {

@@ -689,11 +689,10 @@ __device__ void tile_n3(const N3Args& a, int t, float* lds) {
   }
 }
 
-// Row sums of the pair-once pass: a block of 8 waves takes 64 consecutive global slots; wave w
-// adds rows m = w, w + 8, ... (coalesced across the lanes), and wave 0 combines the 8 partial
-// sums in order.  Writes E into components 0..2 of split 0 for live slots of active clusters.
-constexpr int kFoldWaves = 8;
-
+// Row sums of the pair-once pass: a block of kFoldWaves waves takes 64 consecutive global
+// slots; wave w adds rows m = w, w + 8, ... (coalesced across the lanes), and wave 0 combines
+// the partial sums in order.  Writes E into components 0..2 of split 0 for live slots of
+// active clusters.
 __global__ __launch_bounds__(64 * kFoldWaves) void k_fold_n3(DevState s, RunConst rc, int B) {
   __shared__ double red[kFoldWaves - 1][3][64];
   const int lane = threadIdx.x & 63;
@@ -703,21 +702,8 @@ __global__ __launch_bounds__(64 * kFoldWaves) void k_fold_n3(DevState s, RunCons
   bool live = false;
   if (g < rc.n_total) {
     const int c = s.cid[g];
-    const ClusterParams& cp = s.cp[c];
-    const ClusterDyn& d = s.dyn[c];
-    const int64_t l = g - cp.off;
-    live = d.active && l < d.n_sched;
-    if (live) {
-      const int64_t K = l / B;
-      const int64_t nb = (d.n_sched + B - 1) / B;
-      const float* r = s.n3part + cp.n3_off + (K * rc.n3_rows + w) * 3 * (int64_t)B + (l - K * B);
-      const int64_t step = (int64_t)kFoldWaves * 3 * B;
-      for (int64_t m = w; m < nb; m += kFoldWaves, r += step) {
-        e0 += (double)r[0];
-        e1 += (double)r[B];
-        e2 += (double)r[2 * B];
-      }
-    }
+    live = s.dyn[c].active && g - s.cp[c].off < s.dyn[c].n_sched;
+    if (live) n3_row_partial(s, rc, B, g, w, kFoldWaves, e0, e1, e2);
   }
   if (w > 0) {
     red[w - 1][0][lane] = e0;
@@ -1033,13 +1019,13 @@ bool force_tiling_valid(int precision, const ForceTiling& ft) {
 }
 
 hipError_t launch_force(const DevState& s, const RunConst& rc, int precision, const ForceTiling& ft,
-                        bool want_phi, int grid_blocks, hipStream_t st) {
+                        bool want_phi, int grid_blocks, hipStream_t st, bool fold_n3) {
   TileMap map{s.tile_start, s.order, s.cp, s.dyn, s.tile_total, s.queue, rc.n_clusters};
   if (ft.newton3 && !want_phi) {
     if (precision != LC_FP32_ACC64 || rc.n3_rows <= 0) return hipErrorInvalidValue;
     N3Args a{s.pos4, s.n3part, rc.n3_rows, rc.eps2, ft.persistent, map};
     hipError_t e = launch_n3(ft, a, grid_blocks, st);
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || !fold_n3) return e;
     k_fold_n3<<<(int)((rc.n_total + 63) / 64), 64 * kFoldWaves, 0, st>>>(s, rc, n3_block(ft.R, ft.WJ));
     return hipGetLastError();
   }

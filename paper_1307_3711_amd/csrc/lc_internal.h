@@ -154,16 +154,44 @@ __device__ inline void field_sum(const DevState& s, const RunConst& rc, const Fi
   }
 }
 
+// Pair-once rows (written by the pair-once Coulomb kernel, layout in force.hip): the partial
+// sums of global slot g over the rows m = w, w + ways, w + 2 ways, ... < nb of its block, in
+// that order (FP64).  Blocks of `ways` waves over 64 consecutive slots read them coalesced.
+constexpr int kFoldWaves = 8;
+
+__device__ inline void n3_row_partial(const DevState& s, const RunConst& rc, int B, int64_t g, int w, int ways,
+                                      double& e0, double& e1, double& e2) {
+  e0 = 0.0; e1 = 0.0; e2 = 0.0;
+  const int c = s.cid[g];
+  const ClusterParams& cp = s.cp[c];
+  const ClusterDyn& d = s.dyn[c];
+  const int64_t l = g - cp.off;
+  const int64_t K = l / B;
+  const int64_t nb = (d.n_sched + B - 1) / B;
+  const float* r = s.n3part + cp.n3_off + (K * rc.n3_rows + w) * 3 * (int64_t)B + (l - K * B);
+  const int64_t step = (int64_t)ways * 3 * B;
+  for (int64_t m = w; m < nb; m += ways, r += step) {
+    e0 += (double)r[0];
+    e1 += (double)r[B];
+    e2 += (double)r[2 * B];
+  }
+}
+
 // Host launchers (defined in force.hip / step.hip).
 // A pass without the potential takes the pair-once kernel when ft.newton3 is set.
+// fold_n3 = false leaves the rows unsummed for launch_fold_push.
 hipError_t launch_force(const DevState& s, const RunConst& rc, int precision, const ForceTiling& ft,
-                        bool want_phi, int grid_blocks, hipStream_t st);
+                        bool want_phi, int grid_blocks, hipStream_t st, bool fold_n3 = true);
 // n3: build the pair-once tile tables (blocks of n3_block_size(ft)) instead of target blocks
 // times splits.
 hipError_t launch_schedule(const DevState& s, const RunConst& rc, const ForceTiling& ft, bool n3, bool advance,
                            hipStream_t st);
 hipError_t launch_push(const DevState& s, const RunConst& rc, int precision, const FieldLayout& fl, int64_t k,
                        bool diag, hipStream_t st);
+// Push after a pair-once pass whose rows were not folded: the fold and the push in one kernel
+// (the field is also left in split 0 for the ionization check).
+hipError_t launch_fold_push(const DevState& s, const RunConst& rc, int precision, int B, int64_t k, bool diag,
+                            hipStream_t st);
 hipError_t launch_start_kick(const DevState& s, const RunConst& rc, int precision, const FieldLayout& fl,
                              hipStream_t st);
 hipError_t launch_diag(const DevState& s, const RunConst& rc, const FieldLayout& fl, int64_t k, hipStream_t st);

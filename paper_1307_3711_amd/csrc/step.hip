@@ -147,23 +147,16 @@ __global__ __launch_bounds__(kBlock) void k_schedule(DevState s, RunConst rc, in
 }
 
 // ----------------------------------------------------------------------------- push (S3)
-// Relativistic Boris step of every live particle: u^{n-1/2} -> u^{n+1/2}, x^n -> x^{n+1},
-// with the exact discrete work split W_L / W_C, optional KE(n) for the diagnostics, and the
-// refresh of the source record the next field pass reads.
+// Relativistic Boris step of live particle g (cluster c) at step index n in the Coulomb field
+// (ecx, ecy, ecz): u^{n-1/2} -> u^{n+1/2}, x^n -> x^{n+1}, with the exact discrete work split
+// W_L / W_C, optional KE(n) for the diagnostics, and the refresh of the source record the next
+// field pass reads.
 template <int PREC>
-__global__ __launch_bounds__(kBlock) void k_push(DevState s, RunConst rc, FieldLayout fl, int64_t k, int diag) {
-  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (g >= rc.n_total) return;
-  const int c = s.cid[g];
+__device__ inline void push_one(const DevState& s, const RunConst& rc, int64_t g, int c, int64_t n, int diag,
+                                double ecx, double ecy, double ecz) {
   const ClusterParams& cp = s.cp[c];
   const ClusterDyn& d = s.dyn[c];
-  if (!d.active) return;
-  if (g - cp.off >= d.n_cur) return;
-  const int64_t n = *s.step + k;
   const double t = rc.t0 + (double)n * rc.dt;
-
-  double ecx, ecy, ecz;
-  field_sum(s, rc, fl, g, ecx, ecy, ecz);
   double x = s.x[g], y = s.y[g], z = s.z[g];
   double a;
   laser_at(cp, d, t, z, a);
@@ -208,6 +201,55 @@ __global__ __launch_bounds__(kBlock) void k_push(DevState s, RunConst rc, FieldL
   write_source(s, PREC, g, x, y, z, cp.kw * (double)zc);
   if (!(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(unx) && isfinite(uny) && isfinite(unz)))
     atomicOr(s.err, kFlagNonfinite);
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_push(DevState s, RunConst rc, FieldLayout fl, int64_t k, int diag) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= rc.n_total) return;
+  const int c = s.cid[g];
+  const ClusterDyn& d = s.dyn[c];
+  if (!d.active) return;
+  if (g - s.cp[c].off >= d.n_cur) return;
+  double ecx, ecy, ecz;
+  field_sum(s, rc, fl, g, ecx, ecy, ecz);
+  push_one<PREC>(s, rc, g, c, *s.step + k, diag, ecx, ecy, ecz);
+}
+
+// Fold of the pair-once rows and push in one kernel: kFoldWaves waves over 64 consecutive
+// slots add their share of the rows, wave 0 combines them in order, keeps the field in split 0
+// (read by the ionization check) and pushes.
+template <int PREC>
+__global__ __launch_bounds__(64 * kFoldWaves) void k_fold_push(DevState s, RunConst rc, int B, int64_t k, int diag) {
+  __shared__ double red[kFoldWaves - 1][3][64];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t g = (int64_t)blockIdx.x * 64 + lane;
+  double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+  bool live = false;
+  int c = 0;
+  if (g < rc.n_total) {
+    c = s.cid[g];
+    live = s.dyn[c].active && g - s.cp[c].off < s.dyn[c].n_cur;
+    if (live) n3_row_partial(s, rc, B, g, w, kFoldWaves, e0, e1, e2);
+  }
+  if (w > 0) {
+    red[w - 1][0][lane] = e0;
+    red[w - 1][1][lane] = e1;
+    red[w - 1][2][lane] = e2;
+  }
+  __syncthreads();
+  if (w == 0 && live) {
+    for (int q = 0; q < kFoldWaves - 1; ++q) {
+      e0 += red[q][0][lane];
+      e1 += red[q][1][lane];
+      e2 += red[q][2][lane];
+    }
+    s.part[g] = e0;
+    s.part[rc.n_total + g] = e1;
+    s.part[2 * rc.n_total + g] = e2;
+    push_one<PREC>(s, rc, g, c, *s.step + k, diag, e0, e1, e2);
+  }
 }
 
 // ----------------------------------------------------------------------------- start
@@ -497,6 +539,14 @@ hipError_t launch_push(const DevState& s, const RunConst& rc, int precision, con
                        bool diag, hipStream_t st) {
   if (precision == LC_FP64) k_push<LC_FP64><<<blocks_for(rc.n_total), kBlock, 0, st>>>(s, rc, fl, k, diag ? 1 : 0);
   else k_push<LC_FP32_ACC64><<<blocks_for(rc.n_total), kBlock, 0, st>>>(s, rc, fl, k, diag ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_push(const DevState& s, const RunConst& rc, int precision, int B, int64_t k, bool diag,
+                            hipStream_t st) {
+  const int blocks = (int)((rc.n_total + 63) / 64);
+  if (precision == LC_FP64) k_fold_push<LC_FP64><<<blocks, 64 * kFoldWaves, 0, st>>>(s, rc, B, k, diag ? 1 : 0);
+  else k_fold_push<LC_FP32_ACC64><<<blocks, 64 * kFoldWaves, 0, st>>>(s, rc, B, k, diag ? 1 : 0);
   return hipGetLastError();
 }
 
