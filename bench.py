@@ -23,6 +23,7 @@ sys.path.insert(0, ROOT)
 FLOPS_PER_PAIR = 20.0          # N-body convention for one softened pair interaction
 FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector (published)
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector (published)
+VALU_ISSUE_PER_S = 256 * 2.4e9  # wave64 VALU instructions per second: 4 SIMD16 per CU, 4 cycles each
 
 
 def log(msg):
@@ -53,21 +54,34 @@ def make_sim(precision, c, run, st, graph, tiling=None):
     return sim, tuned
 
 
-def counter_traffic(tuned, n):
-    """HBM bytes per Coulomb-kernel launch from the committed rocprofv3 counter runs, or None
-    when the kernel source or the tiling has changed since they were taken."""
+def counter_record(tuned, n):
+    """The committed rocprofv3 counter record (HBM bytes per launch, VALU instructions) of the
+    Coulomb kernel this tiling runs, or None when the kernel source or the tiling has changed
+    since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_force_f32_ar20k_counters.json")
+    path = os.path.join(ROOT, "profiles", "k_force_ar20k_counters.json")
     try:
-        rec = json.load(open(path))
+        recs = json.load(open(path))["records"]
         src = open(os.path.join(ROOT, "paper_1307_3711_amd", "csrc", "force.hip"), "rb").read()
-    except OSError:
+    except (OSError, KeyError, ValueError):
         return None
-    if hashlib.sha256(src).hexdigest() != rec["force_hip_sha256"] or rec["n_particles"] != n:
-        return None
-    if any(tuned.get(k) != v for k, v in rec["tiling"].items()):
-        return None
-    return rec["traffic_bytes_per_launch"]
+    sha = hashlib.sha256(src).hexdigest()
+    for rec in recs:
+        if rec["force_hip_sha256"] != sha or rec["n_particles"] != n:
+            continue
+        if all(tuned.get(k) == v for k, v in rec["tiling"].items()):
+            return rec
+    return None
+
+
+def pair_evaluations(n, tuned):
+    """Pair terms one field pass evaluates: n^2 one-sided; with the pair-once kernel each pair
+    of different blocks once and the pairs inside a block (self pair included) one-sided."""
+    if not tuned.get("newton3"):
+        return float(n) * n
+    B = (4 // tuned["WJ"]) * 64 * tuned["R"]
+    sizes = [min(B, n - i) for i in range(0, n, B)]
+    return (float(n) * n + sum(float(b) * b for b in sizes)) / 2.0
 
 
 def timed_steps(sim, steps):
@@ -153,6 +167,45 @@ def bench_ensemble(args):
 PUSH_BYTES = 173     # per live particle: read x,u (48) Z (1) cluster id (4) W_L,W_C (16) field (24);
                      # write x,u (48) W_L,W_C (16) float4 source (16)
 ION_BYTES = 9        # per ion: read Z (1), write + read the ionization flag (8)
+
+
+def bench_scan(args):
+    """Coulomb-kernel rate against N: argon clusters at the density of the 20k workload
+    (R0 = 8 nm (N / 20000)^(1/3), Ar+ and e- pairs, charges frozen), one-sided scalar-source
+    tiling and pair-once tiling, each timed with HIP events around its field passes."""
+    import paper_1307_3711_amd as lc
+    from workloads import Cluster, Laser, Run, initial_state
+    from workloads.species import SPECIES
+    sizes = [int(v) for v in args.sizes.split(",")]
+    tilings = {"one_sided": dict(R=1, WJ=4, T=1024, S=16, scalar=1),
+               "pair_once": dict(R=4, WJ=4, T=1024, S=16, scalar=1, newton3=1)}
+    res = []
+    for n in sizes:
+        r0 = 8.0 * (n / 20000.0) ** (1.0 / 3.0)
+        c = Cluster(species="Ar", r0_nm=r0, n_ion=n // 2, capacity=n, z_init=1,
+                    laser=Laser(intensity_wcm2=1e16, envelope="flat"))
+        run = Run(dt=0.05, ionize=False, diag_every=0, seed=args.seed)
+        st = initial_state(c, run.seed)
+        row = {"n": n, "r0_nm": round(r0, 3)}
+        for name, til in tilings.items():
+            sim, _ = make_sim("fp32_acc64", c, run, st, 0, til)
+            sim.step(5)
+            prof = sim.profile_steps(args.reps)
+            ms, cnt = prof["field"]
+            t = ms / max(cnt, 1) * 1e-3
+            row[name] = {"us_per_pass": round(t * 1e6, 2), "interactions_per_s": float(n) * n / t}
+            sim.close()
+            log(f"scan n={n} {name}: {t * 1e6:.1f} us, {float(n) * n / t / 1e12:.3f}e12 interactions/s")
+        res.append(row)
+    big = res[-1]["pair_once"]["interactions_per_s"]
+    out = {"metric": "Coulomb pass interactions/s against N (FP32 pair math + FP64 accumulation)",
+           "value": round(big / 1e9, 1), "unit": "Gpair/s", "n_gpus": 1, "steps": args.reps, "warmup": 5,
+           "ms_per_step": res[-1]["pair_once"]["us_per_pass"] / 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "fp32+fp64acc", "data": "synthetic",
+           "config": {"workload": "Ar clusters at the 20k workload's density, sizes " + args.sizes,
+                      "tilings": tilings},
+           "scan": res}
+    print(json.dumps(out), flush=True)
 
 
 def bench_particles(args):
@@ -384,7 +437,10 @@ def main():
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--save-data", default="", help="surrogate: write the MD training set (npz) here")
     ap.add_argument("--fp64-steps", type=int, default=2000, help="xe200k: steps of the FP64 comparison run")
-    ap.add_argument("--workload", default="ar20k", choices=["ar20k", "ensemble", "surrogate", "particles", "xe200k"])
+    ap.add_argument("--workload", default="ar20k", choices=["ar20k", "ensemble", "surrogate", "particles", "xe200k",
+                                                            "scan"])
+    ap.add_argument("--sizes", default="20000,30000,40000,60000,100000",
+                    help="particle counts of the scan workload")
     ap.add_argument("--reps", type=int, default=50)
     ap.add_argument("--clusters", type=int, default=256)
     ap.add_argument("--seed", type=int, default=0)
@@ -424,6 +480,8 @@ def main():
         return bench_surrogate(args)
     if args.workload == "particles":
         return bench_particles(args)
+    if args.workload == "scan":
+        return bench_scan(args)
     if args.workload == "xe200k":
         return bench_xe(args)
 
@@ -451,6 +509,9 @@ def main():
     avg_force_s = force_ms / max(force_n, 1) * 1e-3
     achieved = FLOPS_PER_PAIR * pairs / avg_force_s / 1e12
     value = args.steps * pairs / wall / 1e9
+    crec = counter_record(tuned, n)
+    evals = pair_evaluations(n, tuned)
+    kname = "k_force_n3" if tuned.get("newton3") else "k_force_f32"
     out = {
         "metric": "G pair-interactions/s (FP32 pair math + FP64 accumulation), one Ar cluster",
         "value": round(value, 3), "unit": "Gpair/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -461,9 +522,13 @@ def main():
                    "n_particles": n, "pairs_per_step": pairs, "tiling": tuned, "graph_steps": args.graph},
         "cluster_steps_per_s": round(args.steps / wall, 2),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": counter_traffic(tuned, n),
-                     "kernel": "k_force_f32", "avg_launch_ms": round(avg_force_s * 1e3, 5),
-                     "launches": force_n, "flops_per_pair": FLOPS_PER_PAIR},
+                     "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                     "traffic": crec["traffic_bytes_per_launch"] if crec else None,
+                     "kernel": kname, "avg_launch_ms": round(avg_force_s * 1e3, 5),
+                     "launches": force_n, "flops_per_pair": FLOPS_PER_PAIR,
+                     "pair_interactions_per_launch": pairs, "pair_evaluations_per_launch": evals,
+                     "valu_issue_frac": (round(crec["valu_wave_instructions"] / (crec["avg_duration_ns"] * 1e-9)
+                                               / VALU_ISSUE_PER_S, 4) if crec else None)},
         "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 5) for k, v in prof.items() if v[1]},
     }
     total_steps = args.warmup + args.steps + args.profile_steps

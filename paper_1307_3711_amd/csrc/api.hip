@@ -1014,7 +1014,7 @@ extern "C" int lc_profile_steps(lc_sim* s, int64_t n_steps, double* out_ms, int6
   hipError_t e = hipSuccess;
   for (int64_t done = 0; done < n_steps && e == hipSuccess;) {
     const int64_t m = std::min(chunk, n_steps - done);
-    std::vector<int> used(4 * m, 0);
+    std::vector<int> used(4 * m, 0), fgroup(m, 0);
     for (int64_t k = 0; k < m && e == hipSuccess; ++k) {
       const bool diag = is_diag_step(s, s->step);
       const bool n3 = n3_pass(s, ft, diag);
@@ -1025,6 +1025,9 @@ extern "C" int lc_profile_steps(lc_sim* s, int64_t n_steps, double* out_ms, int6
         e = launch_force(s->s, s->rc, s->cfg.precision, ft, diag, force_grid(s, ft, n3), s->stream, false);
       if (e == hipSuccess) e = hipEventRecord(E[1], s->stream);
       used[4 * k + 0] = 1;
+      // with a pair-once tiling the one-sided pass of a diagnostic step (potential included)
+      // is diagnostic work: it goes to that group, so group 0 times the pair-once kernel alone
+      fgroup[k] = (diag && ft.newton3) ? 2 : 0;
       if (e == hipSuccess) e = hipEventRecord(E[2], s->stream);
       if (e == hipSuccess)
         e = n3 ? launch_fold_push(s->s, s->rc, s->cfg.precision, n3_block_size(ft), 0, diag, s->stream)
@@ -1052,8 +1055,9 @@ extern "C" int lc_profile_steps(lc_sim* s, int64_t n_steps, double* out_ms, int6
         if (!used[4 * k + c]) continue;
         float ms = 0.f;
         e = hipEventElapsedTime(&ms, ev[8 * k + 2 * c], ev[8 * k + 2 * c + 1]);
-        out_ms[c] += ms;
-        out_launches[c] += 1;
+        const int grp = (c == 0) ? fgroup[k] : c;
+        out_ms[grp] += ms;
+        if (c == grp) out_launches[grp] += 1;
       }
     done += m;
   }
