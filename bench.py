@@ -189,7 +189,7 @@ def bench_scan(args):
         row = {"n": n, "r0_nm": round(r0, 3)}
         for name, til in tilings.items():
             sim, _ = make_sim("fp32_acc64", c, run, st, 0, til)
-            sim.step(5)
+            sim.profile_steps(max(20, args.reps))  # warm-up at steady clocks, same launches
             prof = sim.profile_steps(args.reps)
             ms, cnt = prof["field"]
             t = ms / max(cnt, 1) * 1e-3

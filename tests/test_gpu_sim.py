@@ -244,6 +244,35 @@ def test_ensemble_field_pair_once_matches_oracle(tiling):
         assert np.all(np.abs(E - Eo) <= 64 * u32 * s1[:, None] + 1e-300)
 
 
+def test_pair_once_local_ofi_field():
+    """With ionization driven by the local field (|E_C + E_L| at the ion), the ionization check
+    reads the Coulomb field the fused fold-and-push kernel leaves behind on pair-once steps.
+    Against a one-sided FP32 run of the same state: the fields differ only by FP32 rounding,
+    so the ionization decisions (alpha < P in FP64 from identical Philox draws) and the charge
+    states after 12 steps are identical, and positions agree to 1e-5 R0; the oracle (FP64)
+    agrees on the event count within a few events."""
+    import paper_1307_3711_amd as lc
+    c = Cluster(species="Ar", r0_nm=2.5, n_ion=500, capacity=4500, z_max=8,
+                laser=Laser(intensity_wcm2=3e16, envelope="flat"))
+    run = Run(dt=0.05, t0=math.pi / 2, ionize=True, ofi_field="local", diag_every=4, seed=7)
+    mpb = lc.pair_blocks_for([c.capacity])
+    a, states = gpu_run([c], run, "fp32_acc64", tuning=N3, max_pair_blocks=mpb)
+    b, _ = gpu_run([c], run, "fp32_acc64", states=states, tuning=dict(R=1, WJ=4, T=1024, S=8, scalar=1))
+    a.step(12)
+    b.step(12)
+    ga, gb = a.particles(0), b.particles(0)
+    ra, rb = a.diagnostics(0), b.diagnostics(0)
+    print(f"local OFI: events pair-once {ra[-1][21]:.0f}, one-sided {rb[-1][21]:.0f}", flush=True)
+    assert ra[-1][21] > 0
+    assert ga["n"] == gb["n"] and np.array_equal(ga["Z"], gb["Z"])
+    assert np.array_equal(ra[:, 21], rb[:, 21])
+    r0n = units.nm_to_norm(c.r0_nm, 0.8)
+    assert np.max(np.abs(ga["x"] - gb["x"])) / r0n <= 1e-5
+    osim = oracle_run(c, run, states[0])
+    ro = osim.run(12)
+    assert abs(ro[-1][21] - ra[-1][21]) <= max(3, 0.02 * ro[-1][21])
+
+
 def test_pair_once_needs_room():
     """A pair-once tiling is refused when a cluster spans more blocks than max_pair_blocks,
     or when the handle has no pair-once rows at all; the tiling in force stays unchanged."""
