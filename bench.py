@@ -34,7 +34,7 @@ def make_sim(precision, c, run, st, graph, tiling=None):
     import paper_1307_3711_amd as lc
     from workloads.species import SPECIES
     # room for the pair-once kernel (blocks of 128 slots and up) where the precision allows it
-    mpb = lc.pair_blocks_for([c.capacity], 128) if precision == "fp32_acc64" else 0
+    mpb = lc.pair_blocks_for([c.capacity], 128) if precision in ("fp32_acc64", "fp64") else 0
     cfg = lc.make_config(precision, ionize=run.ionize, dt=run.dt, softening_nm=run.softening_nm,
                          diag_every=run.diag_every, max_records=256, max_splits=64, seed=run.seed,
                          max_pair_blocks=mpb)
@@ -251,7 +251,7 @@ def _xe_run(precision, c, run, st, steps, tiling=None):
     import paper_1307_3711_amd as lc
     from workloads.species import SPECIES
     de = 100
-    mpb = lc.pair_blocks_for([c.capacity], 256) if precision == "fp32_acc64" else 0
+    mpb = lc.pair_blocks_for([c.capacity], 256) if precision in ("fp32_acc64", "fp64") else 0
     cfg = lc.make_config(precision, ionize=True, dt=run.dt, softening_nm=run.softening_nm, diag_every=de,
                          max_records=steps // de + 2, max_splits=16, seed=run.seed, max_pair_blocks=mpb)
     d = lc.make_cluster(SPECIES[c.species], c.r0_nm, c.n_ion, c.capacity, c.laser.intensity_wcm2,

@@ -89,8 +89,9 @@ typedef struct {
   int32_t max_records;    /* records kept per cluster (ring buffer)                     */
   int32_t max_splits;     /* largest source split the tuner may use (1..64)             */
   int32_t max_pair_blocks;/* M >= 0: room for the pair-once kernel (lc_tuning.newton3) on  */
-                          /*   clusters of up to M blocks; costs 12 M bytes per slot      */
-                          /*   (slots rounded up to 512 per cluster); 0: not available    */
+                          /*   clusters of up to M blocks; costs 12 M (LC_FP32_ACC64) or  */
+                          /*   24 M (LC_FP64) bytes per slot, slots rounded up to 512 per */
+                          /*   cluster; 0: not available; not for LC_FP32_KAHAN          */
   uint64_t seed;          /* Philox key word 0 (word 1 is the cluster index)            */
 } lc_config;
 
@@ -125,7 +126,8 @@ typedef struct {
   int32_t persistent;         /* 1: persistent grid pulling tiles from a device queue   */
   int32_t scalar_sources;     /* FP32 modes: 1 reads source records through the scalar  */
                               /*   unit into SGPR operands instead of staging LDS tiles  */
-  int32_t newton3;            /* LC_FP32_ACC64: 1 evaluates each unordered pair once and  */
+  int32_t newton3;            /* LC_FP32_ACC64, LC_FP64: 1 evaluates each unordered pair  */
+                              /*   once (in the handle's pair precision) and            */
                               /*   applies it to both particles (Newton's third law) on   */
                               /*   steps without a diagnostic record; blocks of           */
                               /*   B = (4/WJ) 64 R slots, (R, WJ) in {(1,1), (2,1), (1,2), */

@@ -77,7 +77,7 @@ bool valid_config(const lc_config* cfg, std::string* why) {
   if (cfg->diag_every > 0 && cfg->max_records < 1) { *why = "max_records must be >= 1"; return false; }
   if (cfg->max_splits < 1 || cfg->max_splits > 64) { *why = "max_splits must be in [1, 64]"; return false; }
   if (cfg->max_pair_blocks < 0 || cfg->max_pair_blocks > kMaxPairBlocks) { *why = "max_pair_blocks out of range"; return false; }
-  if (cfg->max_pair_blocks > 0 && cfg->precision != LC_FP32_ACC64) { *why = "the pair-once kernel needs LC_FP32_ACC64"; return false; }
+  if (cfg->max_pair_blocks > 0 && cfg->precision == LC_FP32_KAHAN) { *why = "no pair-once kernel for LC_FP32_KAHAN"; return false; }
   if (cfg->ionize != 0 && cfg->ionize != 1) { *why = "ionize must be 0 or 1"; return false; }
   if (cfg->ofi_field != LC_LASER_ONLY && cfg->ofi_field != LC_LOCAL) { *why = "unknown ofi_field"; return false; }
   return true;
@@ -124,7 +124,8 @@ Layout make_layout(const lc_config* cfg, const lc_cluster* cl, int C) {
   L.part = take(sizeof(double) * (size_t)cfg->max_splits * kComp * (size_t)NT);
   int64_t n3_slots = 0;
   for (int c = 0; c < C; ++c) n3_slots += n3_round(cl[c].capacity);
-  L.n3part = take(sizeof(float) * 3 * (size_t)cfg->max_pair_blocks * (size_t)n3_slots);
+  const size_t row_elem = cfg->precision == LC_FP64 ? sizeof(double) : sizeof(float);
+  L.n3part = take(row_elem * 3 * (size_t)cfg->max_pair_blocks * (size_t)n3_slots);
   L.flag = take(sizeof(int32_t) * (size_t)NT);
   L.ib_count = take(sizeof(int32_t) * (size_t)std::max(ib, 1));
   L.ib_cluster = take(sizeof(int32_t) * (size_t)std::max(ib, 1));
@@ -237,7 +238,7 @@ FieldLayout field_layout(const ForceTiling& ft, bool n3) {
 // A pair-once tiling fits when every cluster's capacity spans at most max_pair_blocks blocks.
 bool n3_fits(const lc_sim* s, const ForceTiling& ft) {
   if (!ft.newton3) return true;
-  if (s->cfg.max_pair_blocks <= 0 || s->cfg.precision != LC_FP32_ACC64) return false;
+  if (s->cfg.max_pair_blocks <= 0 || s->cfg.precision == LC_FP32_KAHAN) return false;
   const int64_t B = n3_block_size(ft);
   int64_t tiles = 0;
   for (int c = 0; c < s->C; ++c) {
@@ -267,7 +268,7 @@ int force_grid(const lc_sim* s, const ForceTiling& ft, bool n3) {
     const int64_t nb = (std::max<int64_t>(n, 1) + TI - 1) / TI;
     tiles += n3 ? nb * (nb + 1) / 2 : nb * ft.S;
   }
-  if (ft.persistent) return n3_persistent_grid(ft, tiles, device_cus());
+  if (ft.persistent) return n3_persistent_grid(s->cfg.precision, ft, tiles, device_cus());
   return (int)std::min<int64_t>(tiles, std::numeric_limits<int32_t>::max());
 }
 
@@ -388,7 +389,7 @@ int lc_create(lc_sim** out, const lc_config* cfg, const lc_cluster* clusters, in
   d.kebar = (double*)(b + L.kebar);
   d.pos4 = (float4*)(b + L.pos4); d.posq = (double4*)(b + L.posq);
   d.Z = (int8_t*)(b + L.Z); d.cid = (int32_t*)(b + L.cid); d.part = (double*)(b + L.part);
-  d.n3part = (float*)(b + L.n3part);
+  d.n3part = (void*)(b + L.n3part);
   d.flag = (int32_t*)(b + L.flag); d.ib_count = (int32_t*)(b + L.ib_count);
   d.ib_cluster = (int32_t*)(b + L.ib_cluster);
   d.cp = (ClusterParams*)(b + L.cp); d.dyn = (ClusterDyn*)(b + L.dyn);
@@ -936,8 +937,9 @@ extern "C" int lc_autotune(lc_sim* s, const char* cache_json, lc_tuning* chosen)
             const int pers = mode & 1, scal = (mode >> 1) & 1, n3 = mode >> 2;
             if (scal && prec == LC_FP64) continue;
             if (scal && T != 1024) continue;  // T only sets the uniform-charge segment length there
-            // pair-once candidates: S and T only serve the diagnostic steps; time one of each
-            if (n3 && (!scal || T != 1024 || S != std::min(16, s->cfg.max_splits))) continue;
+            // pair-once candidates: S, T and the source path only serve the diagnostic steps;
+            // time one of each (scalar sources for FP32, LDS tiles for FP64)
+            if (n3 && (scal != (prec != LC_FP64) || T != 1024 || S != std::min(16, s->cfg.max_splits))) continue;
             ForceTiling ft{R, WJ, T, S, pers, scal, n3};
             if (S > s->cfg.max_splits || !force_tiling_valid(prec, ft) || !n3_fits(s, ft)) continue;
             // skip split counts that leave most blocks without sources

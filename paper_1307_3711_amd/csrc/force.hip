@@ -80,6 +80,9 @@ __device__ inline double rsq64(double x) {
   return __builtin_fma(y * e, p, y);
 }
 
+__device__ inline float n3_rsq(float x) { return rsq32(x); }
+__device__ inline double n3_rsq(double x) { return rsq64(x); }
+
 // ----------------------------------------------------------------------------- FP32 pair loop
 // Sources [kb, kb + per) of the LDS tile against the lane's R targets.  UNIFORM: every source
 // has the same charge q0 and the caller multiplies the sums by it (q r^-3 costs one multiply
@@ -390,7 +393,7 @@ __device__ void tile_f64(const ForceArgs<double4>& a, int t, double4* lds) {
   }
 }
 
-// ----------------------------------------------------------------------------- FP32, pairs once
+// ----------------------------------------------------------------------------- pairs once
 // Newton's third law: the pair term of (i, j) is the pair term of (j, i) with the sign of the
 // separation flipped and the partner's charge, so one evaluation can serve both particles.
 // A cluster's slots are cut into blocks of B = (4/WJ) * 64 * R.  The tile (I, J), I < J, takes
@@ -406,19 +409,38 @@ __device__ void tile_f64(const ForceArgs<double4>& a, int t, double4* lds) {
 // after 64 rotations lane l holds source l's sum, accumulated in a fixed order (deterministic).
 // Tiles of equal-charge sources or equal-charge targets factor the charge out of the pair term.
 //
-// Partial fields are FP32 rows, one per (block K, partner block m) of a cluster:
+// Partial fields are rows of the pair type (FP32 rows for LC_FP32_ACC64, FP64 rows for
+// LC_FP64), one per (block K, partner block m) of a cluster:
 //   row (K, m), component d, local slot l:  n3part[n3_off + ((K M + m) 3 + d) B + l]
 // written by exactly one tile.  M (rows per block) is fixed at creation; nb = ceil(n / B).
 // k_fold_n3 then sums a slot's rows m = 0 .. nb - 1 in FP64, in a fixed order, into split 0
 // of the FP64 partials, which the push reads as a one-split field.
+// Pair arithmetic of the pair-once kernel: float (LC_FP32_ACC64) or double (LC_FP64).
+// kFar places padding entries so far away that every term they take part in is exactly zero:
+// FP32 r^2 overflows to +inf and v_rsq_f32(+inf) = +0; FP64 r^2 = 1e300 stays finite (the
+// refined 1/sqrt needs a finite argument) and (1/r)^3 = 1e-450 underflows to zero.
+template <typename T> struct N3Type;
+template <> struct N3Type<float> {
+  using V4 = float4;
+  static constexpr float kFar = 1e30f;
+};
+template <> struct N3Type<double> {
+  using V4 = double4;
+  static constexpr double kFar = 1e150;
+};
+
+template <typename T>
 struct N3Args {
-  const float4* src;   // source records, global slot indexed
-  float* part;         // pair-once rows
-  int M;               // rows per block
+  const typename N3Type<T>::V4* src;  // source records, global slot indexed
+  T* part;                            // pair-once rows
+  int M;                              // rows per block
   double eps2;
   int persistent;
   TileMap map;
 };
+
+__device__ inline float n3_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double n3_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 __device__ inline void decode_pair_tile(const TileMap& m, int t, int& c, int& I, int& J) {
   int lo = 0, hi = m.n_clusters - 1;
@@ -441,6 +463,12 @@ __device__ inline float wave_rol1(float x) {
   // every lane of the wave has a source lane, so no "old" value is needed
   return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x134, 0xf, 0xf, false));
 }
+__device__ inline double wave_rol1(double x) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, 0x134, 0xf, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), 0x134, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
 
 // Orders the LDS traffic of one wave around a point where lanes read what other lanes wrote.
 __device__ inline void wave_lds_sync() {
@@ -452,7 +480,7 @@ __device__ inline void wave_lds_sync() {
 // Per-wave LDS slice: x, y, z, q arrays of the chunk twice (128 entries each) plus room for
 // the prefetch of the rotation after the last one (up to 8 entries, read and discarded).
 constexpr int kN3Slice = 136;
-constexpr int kN3Fixed = 4 * 4 * kN3Slice;  // floats: the four waves' slices
+constexpr int kN3Fixed = 4 * 4 * kN3Slice;  // elements: the four waves' slices
 
 // One chunk of 64 sources (sb: x, y, z, q arrays of the chunk twice, kN3Slice apart) against
 // the lane's R targets.  US: all sources of the chunk carry one charge (factored out by the
@@ -460,31 +488,30 @@ constexpr int kN3Fixed = 4 * 4 * kN3Slice;  // floats: the four waves' slices
 // sum_r q_r s_r (r_i - r_j) of the chunk's sources, returned in (ax, ay, az) of lane l for
 // source l.
 // U rotations of the chunk from the register buffers (bx, by, bz, bq) holding their sources.
-template <int R, int U, bool US, bool UT, bool JSIDE>
-__device__ inline void n3_steps(const float* bx, const float* by, const float* bz, const float* bq, const float* xi,
-                                const float* yi, const float* zi, const float* qi, float eps2f, float* fx, float* fy,
-                                float* fz, float& rx, float& ry, float& rz) {
+template <typename T, int R, int U, bool US, bool UT, bool JSIDE>
+__device__ inline void n3_steps(const T* bx, const T* by, const T* bz, const T* bq, const T* xi, const T* yi,
+                                const T* zi, const T* qi, T eps2f, T* fx, T* fy, T* fz, T& rx, T& ry, T& rz) {
 #pragma unroll
   for (int u = 0; u < U; ++u) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const float dx = xi[r] - bx[u];
-      const float dy = yi[r] - by[u];
-      const float dz = zi[r] - bz[u];
-      float r2 = __builtin_fmaf(dx, dx, eps2f);
-      r2 = __builtin_fmaf(dy, dy, r2);
-      r2 = __builtin_fmaf(dz, dz, r2);
-      const float inv = rsq32(r2);
-      const float r3 = inv * (inv * inv);
-      const float si = US ? r3 : bq[u] * r3;
-      fx[r] = __builtin_fmaf(si, dx, fx[r]);
-      fy[r] = __builtin_fmaf(si, dy, fy[r]);
-      fz[r] = __builtin_fmaf(si, dz, fz[r]);
+      const T dx = xi[r] - bx[u];
+      const T dy = yi[r] - by[u];
+      const T dz = zi[r] - bz[u];
+      T r2 = n3_fma(dx, dx, eps2f);
+      r2 = n3_fma(dy, dy, r2);
+      r2 = n3_fma(dz, dz, r2);
+      const T inv = n3_rsq(r2);
+      const T r3 = inv * (inv * inv);
+      const T si = US ? r3 : bq[u] * r3;
+      fx[r] = n3_fma(si, dx, fx[r]);
+      fy[r] = n3_fma(si, dy, fy[r]);
+      fz[r] = n3_fma(si, dz, fz[r]);
       if (JSIDE) {
-        const float sr = UT ? r3 : qi[r] * r3;
-        rx = __builtin_fmaf(sr, dx, rx);
-        ry = __builtin_fmaf(sr, dy, ry);
-        rz = __builtin_fmaf(sr, dz, rz);
+        const T sr = UT ? r3 : qi[r] * r3;
+        rx = n3_fma(sr, dx, rx);
+        ry = n3_fma(sr, dy, ry);
+        rz = n3_fma(sr, dz, rz);
       }
     }
     if (JSIDE) {
@@ -496,8 +523,8 @@ __device__ inline void n3_steps(const float* bx, const float* by, const float* b
 }
 
 // Sources of rotations [k, k + U) into registers.
-template <int U, bool US>
-__device__ inline void n3_load(const float* sx, int k, float* bx, float* by, float* bz, float* bq) {
+template <typename T, int U, bool US>
+__device__ inline void n3_load(const T* sx, int k, T* bx, T* by, T* bz, T* bq) {
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     bx[u] = sx[k + u];
@@ -514,21 +541,20 @@ __device__ inline void n3_load(const float* sx, int k, float* bx, float* by, flo
 // source l.  Software pipelined over two register buffers: the sources of the next U
 // rotations are read while the current U are used (the slice has kN3Slice >= 128 + U
 // entries, so the read after the last rotation stays inside it).
-template <int R, bool US, bool UT, bool JSIDE>
-__device__ inline void n3_chunk(const float* sb, int lane, const float* xi, const float* yi, const float* zi,
-                                const float* qi, float eps2f, float* fx, float* fy, float* fz, float& ax, float& ay,
-                                float& az) {
-  constexpr int U = (R >= 4) ? 2 : 4;  // rotations per register buffer
+template <typename T, int R, bool US, bool UT, bool JSIDE>
+__device__ inline void n3_chunk(const T* sb, int lane, const T* xi, const T* yi, const T* zi, const T* qi, T eps2f,
+                                T* fx, T* fy, T* fz, T& ax, T& ay, T& az) {
+  constexpr int U = (R >= 4 || sizeof(T) == 8) ? 2 : 4;  // rotations per register buffer
   static_assert(128 + U <= kN3Slice && 64 % (2 * U) == 0, "prefetch stays inside the wave's slice");
-  const float* sx = sb + lane;
-  float rx = 0.f, ry = 0.f, rz = 0.f;  // running sums of source (lane + k) mod 64
-  float ax_[U], ay_[U], az_[U], aq_[U], bx_[U], by_[U], bz_[U], bq_[U];
-  n3_load<U, US>(sx, 0, ax_, ay_, az_, aq_);
+  const T* sx = sb + lane;
+  T rx = 0, ry = 0, rz = 0;  // running sums of source (lane + k) mod 64
+  T ax_[U], ay_[U], az_[U], aq_[U], bx_[U], by_[U], bz_[U], bq_[U];
+  n3_load<T, U, US>(sx, 0, ax_, ay_, az_, aq_);
   for (int k0 = 0; k0 < 64; k0 += 2 * U) {
-    n3_load<U, US>(sx, k0 + U, bx_, by_, bz_, bq_);
-    n3_steps<R, U, US, UT, JSIDE>(ax_, ay_, az_, aq_, xi, yi, zi, qi, eps2f, fx, fy, fz, rx, ry, rz);
-    n3_load<U, US>(sx, k0 + 2 * U, ax_, ay_, az_, aq_);
-    n3_steps<R, U, US, UT, JSIDE>(bx_, by_, bz_, bq_, xi, yi, zi, qi, eps2f, fx, fy, fz, rx, ry, rz);
+    n3_load<T, U, US>(sx, k0 + U, bx_, by_, bz_, bq_);
+    n3_steps<T, R, U, US, UT, JSIDE>(ax_, ay_, az_, aq_, xi, yi, zi, qi, eps2f, fx, fy, fz, rx, ry, rz);
+    n3_load<T, U, US>(sx, k0 + 2 * U, ax_, ay_, az_, aq_);
+    n3_steps<T, R, U, US, UT, JSIDE>(bx_, by_, bz_, bq_, xi, yi, zi, qi, eps2f, fx, fy, fz, rx, ry, rz);
   }
   ax = rx;
   ay = ry;
@@ -537,57 +563,61 @@ __device__ inline void n3_chunk(const float* sb, int lane, const float* xi, cons
 
 __host__ __device__ constexpr int n3_block(int R, int WJ) { return (4 / WJ) * 64 * R; }
 
-template <int R, int WJ>
-__device__ void tile_n3(const N3Args& a, int t, float* lds) {
+template <typename T, int R, int WJ>
+__device__ void tile_n3(const N3Args<T>& a, int t, T* lds) {
+  using V4 = typename N3Type<T>::V4;
+  constexpr T kFar = N3Type<T>::kFar;
   constexpr int TG = 4 / WJ, TGT = 64 * R, B = TG * TGT, PW = B / WJ, NCH = PW / 64;
   static_assert(PW % 64 == 0, "each wave takes whole chunks of 64 sources");
   int c, I, J;
   decode_pair_tile(a.map, t, c, I, J);
   const ClusterParams& cp = a.map.cp[c];
   const int64_t n = a.map.dyn[c].n_cur;
-  const float4* __restrict__ src = a.src + cp.off;
-  float* rows = a.part + cp.n3_off;
+  const V4* __restrict__ src = a.src + cp.off;
+  T* rows = a.part + cp.n3_off;
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int g = w / WJ, jw = w % WJ;
   const bool jside = (I != J);
   // rows exist only for blocks holding live slots (I <= J < nb <= M for a table built for n)
   const bool live = (int64_t)J * B < n && I <= J && J < a.M;
-  float* sb = lds + w * 4 * kN3Slice;  // x, y, z, q arrays of the wave's chunk
-  float* jres = lds + kN3Fixed;       // [TG][3][B] reaction sums of the block's sources
-  float* ired = jres + TG * 3 * B;    // [WJ - 1][3][B] target sums of waves jw > 0
+  T* sb = lds + w * 4 * kN3Slice;  // x, y, z, q arrays of the wave's chunk
+  T* jres = lds + kN3Fixed;       // [TG][3][B] reaction sums of the block's sources
+  T* ired = jres + TG * 3 * B;    // [WJ - 1][3][B] target sums of waves jw > 0
 
   const int64_t i0 = (int64_t)I * B + (int64_t)g * TGT;
   const bool tvalid = live && i0 < n;  // wave-uniform
-  const float qT = tvalid ? src[i0].w : 0.f;
-  float xi[R], yi[R], zi[R], qi[R];
+  const T qT = tvalid ? src[i0].w : T(0);
+  T xi[R], yi[R], zi[R], qi[R];
   int same_t = 1;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int64_t ii = i0 + r * 64 + lane;
     if (ii < n) {
-      const float4 p = src[ii];
+      const V4 p = src[ii];
       xi[r] = p.x; yi[r] = p.y; zi[r] = p.z; qi[r] = p.w;
       same_t &= (p.w == qT);
     } else {
-      // far away: r^2 overflows to +inf, v_rsq_f32(+inf) = +0, both sides add exactly zero
-      xi[r] = yi[r] = zi[r] = 1e30f;
+      // far away: both sides add exactly zero (see N3Type)
+      xi[r] = yi[r] = zi[r] = kFar;
       qi[r] = qT;
     }
   }
   const bool ut = __all(same_t);
-  const float eps2f = (float)a.eps2;
-  float ex[R], ey[R], ez[R];
+  const T eps2f = (T)a.eps2;
+  T ex[R], ey[R], ez[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) ex[r] = ey[r] = ez[r] = 0.f;
+  for (int r = 0; r < R; ++r) ex[r] = ey[r] = ez[r] = 0;
 
   if (tvalid) {
     for (int ch = 0; ch < NCH; ++ch) {
       const int64_t jb = (int64_t)J * B + jw * PW + ch * 64;
       if (jb >= n) break;
       const int64_t jj = jb + lane;
-      const float4 sv = (jj < n) ? src[jj] : make_float4(1e30f, 1e30f, 1e30f, 0.f);
-      const float qs0 = src[jb].w;
+      V4 sv;
+      if (jj < n) sv = src[jj];
+      else { sv.x = kFar; sv.y = kFar; sv.z = kFar; sv.w = 0; }
+      const T qs0 = src[jb].w;
       const bool us = __all(jj >= n || sv.w == qs0);
       sb[lane] = sv.x;
       sb[lane + 64] = sv.x;
@@ -598,32 +628,32 @@ __device__ void tile_n3(const N3Args& a, int t, float* lds) {
       sb[3 * kN3Slice + lane] = sv.w;
       sb[3 * kN3Slice + lane + 64] = sv.w;
       wave_lds_sync();
-      float cx[R], cy[R], cz[R], ax, ay, az;
+      T cx[R], cy[R], cz[R], ax, ay, az;
 #pragma unroll
-      for (int r = 0; r < R; ++r) cx[r] = cy[r] = cz[r] = 0.f;
+      for (int r = 0; r < R; ++r) cx[r] = cy[r] = cz[r] = 0;
       if (jside) {
         if (us) {
-          if (ut) n3_chunk<R, true, true, true>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az);
-          else n3_chunk<R, true, false, true>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az);
+          if (ut) n3_chunk<T, R, true, true, true>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az);
+          else n3_chunk<T, R, true, false, true>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az);
         } else {
-          if (ut) n3_chunk<R, false, true, true>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az);
-          else n3_chunk<R, false, false, true>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az);
+          if (ut) n3_chunk<T, R, false, true, true>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az);
+          else n3_chunk<T, R, false, false, true>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az);
         }
       } else {
-        if (us) n3_chunk<R, true, true, false>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az);
-        else n3_chunk<R, false, true, false>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az);
+        if (us) n3_chunk<T, R, true, true, false>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az);
+        else n3_chunk<T, R, false, true, false>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az);
       }
       wave_lds_sync();
-      const float fs = us ? qs0 : 1.f;
+      const T fs = us ? qs0 : T(1);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        ex[r] = __builtin_fmaf(fs, cx[r], ex[r]);
-        ey[r] = __builtin_fmaf(fs, cy[r], ey[r]);
-        ez[r] = __builtin_fmaf(fs, cz[r], ez[r]);
+        ex[r] = n3_fma(fs, cx[r], ex[r]);
+        ey[r] = n3_fma(fs, cy[r], ey[r]);
+        ez[r] = n3_fma(fs, cz[r], ez[r]);
       }
       if (jside) {
         // E_j = sum_i q_i (r_j - r_i) s_ij = -(reaction sum), charge factored when uniform
-        const float js = ut ? -qT : -1.f;
+        const T js = ut ? -qT : T(-1);
         const int jl = jw * PW + ch * 64 + lane;
         jres[(g * 3 + 0) * B + jl] = js * ax;
         jres[(g * 3 + 1) * B + jl] = js * ay;
@@ -659,7 +689,7 @@ __device__ void tile_n3(const N3Args& a, int t, float* lds) {
     }
   }
   if (jw == 0 && tvalid) {
-    float* row = rows + (int64_t)((int64_t)I * a.M + J) * 3 * B;
+    T* row = rows + (int64_t)((int64_t)I * a.M + J) * 3 * B;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int l = g * TGT + r * 64 + lane;
@@ -672,10 +702,10 @@ __device__ void tile_n3(const N3Args& a, int t, float* lds) {
   }
   // Source side: the target groups add up in a fixed order; row (J, I).
   if (jside && live) {
-    float* row = rows + (int64_t)((int64_t)J * a.M + I) * 3 * B;
+    T* row = rows + (int64_t)((int64_t)J * a.M + I) * 3 * B;
     for (int jl = tid; jl < B; jl += kBlock) {
       if ((int64_t)J * B + jl >= n) break;
-      float sx = 0.f, sy = 0.f, sz = 0.f;
+      T sx = 0, sy = 0, sz = 0;
       for (int q = 0; q < TG; ++q) {
         if ((int64_t)I * B + (int64_t)q * TGT >= n) break;
         sx += jres[(q * 3 + 0) * B + jl];
@@ -693,6 +723,7 @@ __device__ void tile_n3(const N3Args& a, int t, float* lds) {
 // slots; wave w adds rows m = w, w + 8, ... (coalesced across the lanes), and wave 0 combines
 // the partial sums in order.  Writes E into components 0..2 of split 0 for live slots of
 // active clusters.
+template <typename Tr>
 __global__ __launch_bounds__(64 * kFoldWaves) void k_fold_n3(DevState s, RunConst rc, int B) {
   __shared__ double red[kFoldWaves - 1][3][64];
   const int lane = threadIdx.x & 63;
@@ -703,7 +734,7 @@ __global__ __launch_bounds__(64 * kFoldWaves) void k_fold_n3(DevState s, RunCons
   if (g < rc.n_total) {
     const int c = s.cid[g];
     live = s.dyn[c].active && g - s.cp[c].off < s.dyn[c].n_sched;
-    if (live) n3_row_partial(s, rc, B, g, w, kFoldWaves, e0, e1, e2);
+    if (live) n3_row_partial<Tr>(s, rc, B, g, w, kFoldWaves, e0, e1, e2);
   }
   if (w > 0) {
     red[w - 1][0][lane] = e0;
@@ -724,12 +755,16 @@ __global__ __launch_bounds__(64 * kFoldWaves) void k_fold_n3(DevState s, RunCons
 }
 
 // ----------------------------------------------------------------------------- kernels
-template <int R, int WJ>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_force_n3(N3Args a) {
-  extern __shared__ float lds_n3[];
+// Occupancy the register allocation aims at: 5 waves per SIMD for FP32 pairs (85 VGPRs at
+// R = 4, no spills), 3 for FP64 pairs (twice the registers per value).
+template <typename T, int R, int WJ>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 5)))
+void k_force_n3(N3Args<T> a) {
+  extern __shared__ __align__(16) unsigned char lds_n3_raw[];
+  T* lds_n3 = reinterpret_cast<T*>(lds_n3_raw);
   const int total = *a.map.tile_total;
   if (!a.persistent) {
-    if ((int)blockIdx.x < total) tile_n3<R, WJ>(a, blockIdx.x, lds_n3);
+    if ((int)blockIdx.x < total) tile_n3<T, R, WJ>(a, blockIdx.x, lds_n3);
     return;
   }
   __shared__ int sh_t;
@@ -739,7 +774,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     __syncthreads();
     const int t = sh_t;
     if (t >= total) break;
-    tile_n3<R, WJ>(a, t, lds_n3);
+    tile_n3<T, R, WJ>(a, t, lds_n3);
   }
 }
 
@@ -822,41 +857,49 @@ bool n3_shape_ok(int R, int WJ) {
   return (WJ == 1 && (R == 1 || R == 2)) || (WJ == 2 && (R == 1 || R == 2 || R == 4)) || (WJ == 4 && R == 4);
 }
 
-size_t n3_lds_bytes(const ForceTiling& ft) {
+size_t n3_lds_bytes(const ForceTiling& ft, size_t elem) {
   const size_t B = (size_t)n3_block(ft.R, ft.WJ);
-  return sizeof(float) * ((size_t)kN3Fixed + (size_t)(4 / ft.WJ) * 3 * B + (size_t)(ft.WJ - 1) * 3 * B);
+  return elem * ((size_t)kN3Fixed + (size_t)(4 / ft.WJ) * 3 * B + (size_t)(ft.WJ - 1) * 3 * B);
 }
 
+size_t n3_elem(int precision) { return precision == LC_FP64 ? sizeof(double) : sizeof(float); }
+
 // Workgroups of the pair-once kernel one CU holds at once (occupancy), cached per shape.
-int n3_resident_per_cu(const ForceTiling& ft) {
-  static int cache[8][4] = {};
-  int& v = cache[ft.R & 7][ft.WJ & 3];
-  if (v > 0) return v;
-  const size_t lds = n3_lds_bytes(ft);
+template <typename T>
+int n3_resident_t(const ForceTiling& ft) {
+  const size_t lds = n3_lds_bytes(ft, sizeof(T));
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (ft.WJ * 16 + ft.R) {
-    case 16 + 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<1, 1>, kBlock, lds); break;
-    case 16 + 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<2, 1>, kBlock, lds); break;
-    case 32 + 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<1, 2>, kBlock, lds); break;
-    case 32 + 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<2, 2>, kBlock, lds); break;
-    case 32 + 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<4, 2>, kBlock, lds); break;
-    case 64 + 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<4, 4>, kBlock, lds); break;
+    case 16 + 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<T, 1, 1>, kBlock, lds); break;
+    case 16 + 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<T, 2, 1>, kBlock, lds); break;
+    case 32 + 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<T, 1, 2>, kBlock, lds); break;
+    case 32 + 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<T, 2, 2>, kBlock, lds); break;
+    case 32 + 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<T, 4, 2>, kBlock, lds); break;
+    case 64 + 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<T, 4, 4>, kBlock, lds); break;
     default: break;
   }
-  v = (e == hipSuccess && nb > 0) ? nb : 4;
+  return (e == hipSuccess && nb > 0) ? nb : 4;
+}
+
+int n3_resident_per_cu(int precision, const ForceTiling& ft) {
+  static int cache[2][8][4] = {};
+  int& v = cache[precision == LC_FP64 ? 1 : 0][ft.R & 7][ft.WJ & 3];
+  if (v > 0) return v;
+  v = (precision == LC_FP64) ? n3_resident_t<double>(ft) : n3_resident_t<float>(ft);
   return v;
 }
 
-hipError_t launch_n3(const ForceTiling& ft, const N3Args& a, int grid, hipStream_t st) {
-  const size_t lds = n3_lds_bytes(ft);
+template <typename T>
+hipError_t launch_n3(const ForceTiling& ft, const N3Args<T>& a, int grid, hipStream_t st) {
+  const size_t lds = n3_lds_bytes(ft, sizeof(T));
   switch (ft.WJ * 16 + ft.R) {
-    case 16 + 1: k_force_n3<1, 1><<<grid, kBlock, lds, st>>>(a); break;
-    case 16 + 2: k_force_n3<2, 1><<<grid, kBlock, lds, st>>>(a); break;
-    case 32 + 1: k_force_n3<1, 2><<<grid, kBlock, lds, st>>>(a); break;
-    case 32 + 2: k_force_n3<2, 2><<<grid, kBlock, lds, st>>>(a); break;
-    case 32 + 4: k_force_n3<4, 2><<<grid, kBlock, lds, st>>>(a); break;
-    case 64 + 4: k_force_n3<4, 4><<<grid, kBlock, lds, st>>>(a); break;
+    case 16 + 1: k_force_n3<T, 1, 1><<<grid, kBlock, lds, st>>>(a); break;
+    case 16 + 2: k_force_n3<T, 2, 1><<<grid, kBlock, lds, st>>>(a); break;
+    case 32 + 1: k_force_n3<T, 1, 2><<<grid, kBlock, lds, st>>>(a); break;
+    case 32 + 2: k_force_n3<T, 2, 2><<<grid, kBlock, lds, st>>>(a); break;
+    case 32 + 4: k_force_n3<T, 4, 2><<<grid, kBlock, lds, st>>>(a); break;
+    case 64 + 4: k_force_n3<T, 4, 4><<<grid, kBlock, lds, st>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -970,12 +1013,13 @@ __global__ void k_sum_partials(const double* part, int64_t n, int S, double* E, 
 }
 
 // Field of the standalone call from pair-once rows (M = nb rows per block).
-__global__ void k_sum_n3(const float* rows, int64_t n, int B, double* E) {
+template <typename Tr>
+__global__ void k_sum_n3(const Tr* rows, int64_t n, int B, double* E) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t K = i / B, l = i - K * B;
   const int64_t nb = (n + B - 1) / B;
-  const float* r = rows + K * nb * 3 * B + l;
+  const Tr* r = rows + K * nb * 3 * B + l;
   double e0 = 0.0, e1 = 0.0, e2 = 0.0;
   for (int64_t m = 0; m < nb; ++m, r += 3 * (int64_t)B) {
     e0 += (double)r[0];
@@ -993,10 +1037,10 @@ int force_tile_targets(const ForceTiling& ft) { return (4 / ft.WJ) * 64 * ft.R; 
 
 int n3_block_size(const ForceTiling& ft) { return n3_block(ft.R, ft.WJ); }
 
-int n3_persistent_grid(const ForceTiling& ft, int64_t tiles, int cus) {
+int n3_persistent_grid(int precision, const ForceTiling& ft, int64_t tiles, int cus) {
   // as many workgroups as fit at once, trimmed so that every one of them takes the same
   // number of tiles (within one) in the same number of rounds
-  const int64_t pmax = std::max<int64_t>(1, (int64_t)cus * n3_resident_per_cu(ft));
+  const int64_t pmax = std::max<int64_t>(1, (int64_t)cus * n3_resident_per_cu(precision, ft));
   const int64_t t = std::max<int64_t>(tiles, 1);
   const int64_t rounds = (t + pmax - 1) / pmax;
   return (int)((t + rounds - 1) / rounds);
@@ -1012,7 +1056,7 @@ bool force_tiling_valid(int precision, const ForceTiling& ft) {
   bool wj_ok = ft.WJ == 1 || ft.WJ == 2 || ft.WJ == 4;
   bool t_ok = ft.T >= 64 && ft.T <= 4096 && (ft.T % 64) == 0;
   if (ft.scalar_src && precision == LC_FP64) return false;  // scalar source path is FP32 only
-  if (ft.newton3 && (precision != LC_FP32_ACC64 || !n3_shape_ok(ft.R, ft.WJ))) return false;
+  if (ft.newton3 && (precision == LC_FP32_KAHAN || !n3_shape_ok(ft.R, ft.WJ))) return false;
   bool s_ok = ft.S >= 1 && ft.S <= 64;
   if (!(r_ok && wj_ok && t_ok && s_ok)) return false;
   return force_lds_bytes(precision, ft, true) <= 64 * 1024;
@@ -1022,11 +1066,20 @@ hipError_t launch_force(const DevState& s, const RunConst& rc, int precision, co
                         bool want_phi, int grid_blocks, hipStream_t st, bool fold_n3) {
   TileMap map{s.tile_start, s.order, s.cp, s.dyn, s.tile_total, s.queue, rc.n_clusters};
   if (ft.newton3 && !want_phi) {
-    if (precision != LC_FP32_ACC64 || rc.n3_rows <= 0) return hipErrorInvalidValue;
-    N3Args a{s.pos4, s.n3part, rc.n3_rows, rc.eps2, ft.persistent, map};
-    hipError_t e = launch_n3(ft, a, grid_blocks, st);
-    if (e != hipSuccess || !fold_n3) return e;
-    k_fold_n3<<<(int)((rc.n_total + 63) / 64), 64 * kFoldWaves, 0, st>>>(s, rc, n3_block(ft.R, ft.WJ));
+    if (precision == LC_FP32_KAHAN || rc.n3_rows <= 0) return hipErrorInvalidValue;
+    hipError_t e;
+    const int fb = (int)((rc.n_total + 63) / 64);
+    if (precision == LC_FP64) {
+      N3Args<double> a{s.posq, (double*)s.n3part, rc.n3_rows, rc.eps2, ft.persistent, map};
+      e = launch_n3(ft, a, grid_blocks, st);
+      if (e != hipSuccess || !fold_n3) return e;
+      k_fold_n3<double><<<fb, 64 * kFoldWaves, 0, st>>>(s, rc, n3_block(ft.R, ft.WJ));
+    } else {
+      N3Args<float> a{s.pos4, (float*)s.n3part, rc.n3_rows, rc.eps2, ft.persistent, map};
+      e = launch_n3(ft, a, grid_blocks, st);
+      if (e != hipSuccess || !fold_n3) return e;
+      k_fold_n3<float><<<fb, 64 * kFoldWaves, 0, st>>>(s, rc, n3_block(ft.R, ft.WJ));
+    }
     return hipGetLastError();
   }
   const void* src = (precision == LC_FP64) ? (const void*)s.posq : (const void*)s.pos4;
@@ -1039,7 +1092,7 @@ size_t field_workspace_bytes(int precision, int64_t n, const ForceTiling& ft) {
   if (ft.newton3) {
     const size_t B = (size_t)n3_block(ft.R, ft.WJ);
     const size_t nb = ((size_t)n + B - 1) / B;
-    b += align256(nb * nb * 3 * B * sizeof(float));
+    b += align256(nb * nb * 3 * B * n3_elem(precision));
   } else {
     b += align256((size_t)ft.S * kComp * (size_t)n * sizeof(double));
   }
@@ -1071,10 +1124,17 @@ hipError_t launch_field_standalone(int precision, int64_t n, const double* xyzq,
   }
   if (ft.newton3) {
     if (phi) return hipErrorInvalidValue;
-    N3Args a{(const float4*)w.src, (float*)w.part, ib, eps2, ft.persistent, map};
-    e = launch_n3(ft, a, grid, st);
-    if (e != hipSuccess) return e;
-    k_sum_n3<<<pb, kBlock, 0, st>>>((const float*)w.part, n, TI, E);
+    if (precision == LC_FP64) {
+      N3Args<double> a{(const double4*)w.src, (double*)w.part, ib, eps2, ft.persistent, map};
+      e = launch_n3(ft, a, grid, st);
+      if (e != hipSuccess) return e;
+      k_sum_n3<double><<<pb, kBlock, 0, st>>>((const double*)w.part, n, TI, E);
+    } else {
+      N3Args<float> a{(const float4*)w.src, (float*)w.part, ib, eps2, ft.persistent, map};
+      e = launch_n3(ft, a, grid, st);
+      if (e != hipSuccess) return e;
+      k_sum_n3<float><<<pb, kBlock, 0, st>>>((const float*)w.part, n, TI, E);
+    }
     return hipGetLastError();
   }
   e = launch_generic(precision, ft, map, w.src, w.part, n, eps2, phi != nullptr, grid, st);

@@ -108,7 +108,7 @@ struct DevState {
   int8_t* Z;
   int32_t* cid;         // cluster of each slot
   double* part;         // field partials [split][comp][slot]
-  float* n3part;        // pair-once partial rows (FP32), per cluster from cp.n3_off
+  void* n3part;         // pair-once partial rows (float or double: the pair type), per cluster from cp.n3_off
   int32_t* flag;        // ionization flags [slot of ion]
   int32_t* ib_count;    // spawns per ion block
   int32_t* ib_cluster;  // cluster of each ion block
@@ -159,6 +159,7 @@ __device__ inline void field_sum(const DevState& s, const RunConst& rc, const Fi
 // that order (FP64).  Blocks of `ways` waves over 64 consecutive slots read them coalesced.
 constexpr int kFoldWaves = 8;
 
+template <typename Tr>
 __device__ inline void n3_row_partial(const DevState& s, const RunConst& rc, int B, int64_t g, int w, int ways,
                                       double& e0, double& e1, double& e2) {
   e0 = 0.0; e1 = 0.0; e2 = 0.0;
@@ -168,7 +169,7 @@ __device__ inline void n3_row_partial(const DevState& s, const RunConst& rc, int
   const int64_t l = g - cp.off;
   const int64_t K = l / B;
   const int64_t nb = (d.n_sched + B - 1) / B;
-  const float* r = s.n3part + cp.n3_off + (K * rc.n3_rows + w) * 3 * (int64_t)B + (l - K * B);
+  const Tr* r = (const Tr*)s.n3part + cp.n3_off + (K * rc.n3_rows + w) * 3 * (int64_t)B + (l - K * B);
   const int64_t step = (int64_t)ways * 3 * B;
   for (int64_t m = w; m < nb; m += ways, r += step) {
     e0 += (double)r[0];
@@ -206,7 +207,7 @@ size_t field_workspace_bytes(int precision, int64_t n, const ForceTiling& ft);
 
 int force_tile_targets(const ForceTiling& ft);
 int n3_block_size(const ForceTiling& ft);
-int n3_persistent_grid(const ForceTiling& ft, int64_t tiles, int cus);
+int n3_persistent_grid(int precision, const ForceTiling& ft, int64_t tiles, int cus);
 int64_t n3_tiles(int64_t n, int B);
 bool force_tiling_valid(int precision, const ForceTiling& ft);
 

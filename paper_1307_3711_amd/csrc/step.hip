@@ -231,7 +231,10 @@ __global__ __launch_bounds__(64 * kFoldWaves) void k_fold_push(DevState s, RunCo
   if (g < rc.n_total) {
     c = s.cid[g];
     live = s.dyn[c].active && g - s.cp[c].off < s.dyn[c].n_cur;
-    if (live) n3_row_partial(s, rc, B, g, w, kFoldWaves, e0, e1, e2);
+    if (live) {
+      if (PREC == LC_FP64) n3_row_partial<double>(s, rc, B, g, w, kFoldWaves, e0, e1, e2);
+      else n3_row_partial<float>(s, rc, B, g, w, kFoldWaves, e0, e1, e2);
+    }
   }
   if (w > 0) {
     red[w - 1][0][lane] = e0;

@@ -19,7 +19,7 @@ def run_ensemble(descs, states, precision="fp32_acc64", dt=0.05, softening_nm=0.
     set; states: initial particle arrays (x_nm, u, Z) per cluster.  Returns a dict with the
     last diagnostic record of each cluster, per-cluster counters and the timed wall clock."""
     # room for the pair-once kernel (blocks of 128 slots and up) where the precision allows it
-    mpb = pair_blocks_for([d.capacity for d in descs], 128) if precision == "fp32_acc64" else 0
+    mpb = pair_blocks_for([d.capacity for d in descs], 128) if precision in ("fp32_acc64", "fp64") else 0
     cfg = make_config(precision, ionize=True, dt=dt, softening_nm=softening_nm, diag_every=diag_every,
                       max_records=4, max_splits=8, seed=seed, max_pair_blocks=mpb)
     sim = Simulation(cfg, descs)

@@ -123,8 +123,10 @@ def test_pair_once_rows_in_state_bytes():
     with_rows = _bytes(lc.make_config("fp32_acc64", max_splits=8, max_pair_blocks=10), [d])
     slots = -(-c.capacity // 512) * 512
     assert abs((with_rows - base) - 12 * 10 * slots) <= 256
-    assert _bytes(lc.make_config("fp64", max_pair_blocks=10), [d]) == 0        # FP32 + FP64 accumulation only
-    assert _bytes(lc.make_config("fp32_kahan", max_pair_blocks=10), [d]) == 0
+    base64 = _bytes(lc.make_config("fp64", max_splits=8), [d])
+    rows64 = _bytes(lc.make_config("fp64", max_splits=8, max_pair_blocks=10), [d])
+    assert abs((rows64 - base64) - 24 * 10 * slots) <= 256                     # FP64 rows
+    assert _bytes(lc.make_config("fp32_kahan", max_pair_blocks=10), [d]) == 0   # no Kahan variant
     assert _bytes(lc.make_config("fp32_acc64", max_pair_blocks=-1), [d]) == 0
     assert _bytes(lc.make_config("fp32_acc64", max_pair_blocks=40000), [d]) == 0
 
@@ -142,5 +144,5 @@ def test_pair_once_field_workspace(R, WJ, ok):
     B = (4 // WJ) * 64 * R
     nb = -(-n // B)
     assert wb >= nb * nb * 3 * B * 4 + n * 16
-    assert L.lc_field_workspace_bytes(0, n, ctypes.byref(t)) == 0   # not for FP64
+    assert L.lc_field_workspace_bytes(0, n, ctypes.byref(t)) >= nb * nb * 3 * B * 8 + n * 32   # FP64 rows
     assert L.lc_field_workspace_bytes(2, n, ctypes.byref(t)) == 0   # not for Kahan

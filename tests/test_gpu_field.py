@@ -140,6 +140,21 @@ def test_field_pair_once_elementwise(n, ti):
 
 
 @pytest.mark.skipif(not gpu_available(), reason="needs a GPU")
+@pytest.mark.parametrize("n", [1, 2, 63, 129, 1000, 2053])
+@pytest.mark.parametrize("ti", [0, 2, 3, 5])
+def test_field_pair_once_fp64_elementwise(n, ti):
+    """FP64 pair-once kernel: each pair once in FP64, FP64 rows: same tolerance as the FP64
+    one-sided kernel (1e-12 S1)."""
+    x, q = _state(n, 7 * n + 5)
+    Eo, _ = oracle.coulomb_field(x, q, EPS2)
+    Eg, _ = _gpu_field(x, q, EPS2, "fp64", N3_TILINGS[ti], phi=False)
+    s1, _ = _scales(x, q, EPS2)
+    print(f"pair-once fp64 n={n} tiling={N3_TILINGS[ti]} maxrel={np.max(np.abs(Eg - Eo) / s1[:, None]):.3e}",
+          flush=True)
+    assert np.all(np.abs(Eg - Eo) <= 1e-12 * s1[:, None] + 1e-300)
+
+
+@pytest.mark.skipif(not gpu_available(), reason="needs a GPU")
 def test_field_pair_once_rejects_potential():
     import torch
     import paper_1307_3711_amd as lc
@@ -147,7 +162,7 @@ def test_field_pair_once_rejects_potential():
     with pytest.raises(lc.LcError):
         lc.field(xyzq, EPS2, precision="fp32_acc64", want_phi=True, tuning=lc.make_tuning(R=4, WJ=4, newton3=1))
     with pytest.raises(lc.LcError):
-        lc.field(xyzq, EPS2, precision="fp64", want_phi=False, tuning=lc.make_tuning(R=4, WJ=4, newton3=1))
+        lc.field(xyzq, EPS2, precision="fp32_kahan", want_phi=False, tuning=lc.make_tuning(R=4, WJ=4, newton3=1))
 
 
 @pytest.mark.skipif(not gpu_available(), reason="needs a GPU")
@@ -174,6 +189,7 @@ def test_field_rejects_bad_arguments():
 @pytest.mark.parametrize("precision,tiling", [("fp64", dict(S=16)), ("fp32_acc64", dict(S=16)),
                                               ("fp32_acc64", dict(R=1, WJ=4, T=1024, S=16, scalar=1)),
                                               ("fp32_acc64", dict(R=4, WJ=4, newton3=1)),
+                                              ("fp64", dict(R=2, WJ=2, newton3=1)),
                                               ("fp32_acc64", dict(R=2, WJ=2, newton3=1, persistent=1))])
 def test_field_full_20k_sampled(precision, tiling):
     """The 20k-macroparticle argon state at full size (the benchmark's workload, including the

@@ -46,9 +46,12 @@ def _compare_records(rg, ro, cols, tol):
 ENERGY_COLS = [5, 6, 7, 8, 9, 10]
 
 
-def test_small_ar_fp64_200_steps():
+@pytest.mark.parametrize("tiling", [None, dict(R=2, WJ=2, newton3=1), dict(R=4, WJ=4, newton3=1)])
+def test_small_ar_fp64_200_steps(tiling):
+    import paper_1307_3711_amd as lc
     c, run = small_ar()
-    sim, states = gpu_run([c], run, "fp64")
+    mpb = lc.pair_blocks_for([c.capacity]) if tiling else 0
+    sim, states = gpu_run([c], run, "fp64", tuning=tiling, max_pair_blocks=mpb)
     osim = oracle_run(c, run, states[0])
     print("small Ar fp64: 200 steps", flush=True)
     sim.step(200)
@@ -213,35 +216,43 @@ def test_ensemble_matches_oracle_per_cluster():
             assert err <= max(1e-10, 100 * sp), (col, err, sp)
 
 
-@pytest.mark.parametrize("tiling", N3_TILINGS + [dict(R=4, WJ=2, newton3=1), dict(R=1, WJ=1, newton3=1, persistent=1)])
-def test_ensemble_field_pair_once_matches_oracle(tiling):
+@pytest.mark.parametrize("precision,tiling", [("fp32_acc64", t) for t in N3_TILINGS + [dict(R=4, WJ=2, newton3=1),
+                                                                                       dict(R=1, WJ=1, newton3=1, persistent=1)]]
+                         + [("fp64", dict(R=2, WJ=2, newton3=1)), ("fp64", dict(R=4, WJ=4, newton3=1, persistent=1))])
+def test_ensemble_field_pair_once_matches_oracle(precision, tiling):
     """Pair-once field passes over an ensemble of uneven clusters (one launch, per-cluster
     row tables): after some steps with ionization (counts changed, spawned electrons
     appended), each cluster's field against the oracle on the FP32-rounded positions and
-    charges, element by element, to 64 u S1 (as the one-sided FP32 kernel)."""
+    charges, element by element, to 64 u S1 (as the one-sided FP32 kernel); FP64 pairs
+    against the oracle on the same positions to 1e-12 S1."""
     import paper_1307_3711_amd as lc
     from workloads.species import SPECIES
     cl = ensemble(5, seed=3, cap_lo=200, cap_hi=1500)
     run = Run(dt=0.05, ionize=True, diag_every=5, seed=3)
     states = [initial_state(c, run.seed, i) for i, c in enumerate(cl)]
     mpb = lc.pair_blocks_for([c.capacity for c in cl])
-    sim, _ = gpu_run(cl, run, "fp32_acc64", states=states, tuning=tiling, max_pair_blocks=mpb)
+    sim, _ = gpu_run(cl, run, precision, states=states, tuning=tiling, max_pair_blocks=mpb)
     sim.step(7)
-    eps2 = float(np.float32(units.nm_to_norm(run.softening_nm, 0.8) ** 2))
-    u32 = 2.0**-24
+    fp64 = precision == "fp64"
+    eps2 = units.nm_to_norm(run.softening_nm, 0.8) ** 2
+    if not fp64:
+        eps2 = float(np.float32(eps2))
+    tol = 1e-12 if fp64 else 64 * 2.0**-24
     for i, c in enumerate(cl):
         g = sim.particles(i)
         E = sim.field(i)
         w = units.n_atoms(c.r0_nm, SPECIES[c.species]["rw_angstrom"]) / c.n_ion
         q = units.kappa(0.8) * w * g["Z"].astype(np.float64)
-        xr = g["x"].astype(np.float32).astype(np.float64)
-        qr = q.astype(np.float32).astype(np.float64)
+        xr, qr = g["x"], q
+        if not fp64:
+            xr = xr.astype(np.float32).astype(np.float64)
+            qr = qr.astype(np.float32).astype(np.float64)
         Eo, _ = oracle.coulomb_field(xr, qr, eps2)
         s1 = field_scale(xr, qr, eps2)
         rel = np.max(np.abs(E - Eo) / (s1[:, None] + 1e-300))
-        print(f"cluster {i} ({c.species}, n {g['n']}): pair-once field maxrel {rel:.2e}", flush=True)
+        print(f"cluster {i} ({c.species}, n {g['n']}): pair-once {precision} field maxrel {rel:.2e}", flush=True)
         assert E.shape == Eo.shape
-        assert np.all(np.abs(E - Eo) <= 64 * u32 * s1[:, None] + 1e-300)
+        assert np.all(np.abs(E - Eo) <= tol * s1[:, None] + 1e-300)
 
 
 def test_pair_once_local_ofi_field():
