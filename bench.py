@@ -79,7 +79,8 @@ def pair_evaluations(n, tuned):
     of different blocks once and the pairs inside a block (self pair included) one-sided."""
     if not tuned.get("newton3"):
         return float(n) * n
-    B = (4 // tuned["WJ"]) * 64 * tuned["R"]
+    R, WJ = tuned["R"], tuned["WJ"]
+    B = 64 * R if (R == WJ and R >= 3) else (4 // WJ) * 64 * R   # square shapes: one target group
     sizes = [min(B, n - i) for i in range(0, n, B)]
     return (float(n) * n + sum(float(b) * b for b in sizes)) / 2.0
 

@@ -129,11 +129,14 @@ typedef struct {
   int32_t newton3;            /* LC_FP32_ACC64, LC_FP64: 1 evaluates each unordered pair  */
                               /*   once (in the handle's pair precision) and            */
                               /*   applies it to both particles (Newton's third law) on   */
-                              /*   steps without a diagnostic record; blocks of           */
-                              /*   B = (4/WJ) 64 R slots, (R, WJ) in {(1,1), (2,1), (1,2), */
-                              /*   (2,2), (4,2), (4,4)}; needs ceil(capacity / B) <=      */
-                              /*   max_pair_blocks for every cluster.  Diagnostic steps   */
-                              /*   (which need the potential) use the other fields.       */
+                              /*   steps without a diagnostic record; (R, WJ) in {(1,1),  */
+                              /*   (2,1), (1,2), (2,2), (4,2)}: blocks of B = (4/WJ) 64 R */
+                              /*   slots, 256 threads; (R, R) for R = 3..6: blocks of     */
+                              /*   B = 64 R slots, 64 R threads.  Needs ceil(capacity/B) */
+                              /*   <= max_pair_blocks for every cluster.  Diagnostic     */
+                              /*   steps (which need the potential) run the one-sided    */
+                              /*   kernel with the other fields, and with R = 1 (FP32) or */
+                              /*   2 (FP64), WJ = 4 when it has no such (R, WJ).          */
   int32_t reserved;
 } lc_tuning;
 

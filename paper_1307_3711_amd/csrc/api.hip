@@ -259,7 +259,18 @@ int choose_splits(const lc_sim* s, const ForceTiling& ft) {
   return S;
 }
 
-int force_grid(const lc_sim* s, const ForceTiling& ft, bool n3) {
+// The tiling a pass runs with: the pair-once shape, or for a pass with the potential the
+// one-sided tiling that stands in for it.
+ForceTiling pass_tiling(const lc_sim* s, const ForceTiling& ft, bool n3) {
+  return (n3 || !ft.newton3) ? ft : regular_tiling(s->cfg.precision, ft);
+}
+
+hipError_t schedule(lc_sim* s, const ForceTiling& ft, bool n3, bool advance) {
+  return launch_schedule(s->s, s->rc, pass_tiling(s, ft, n3), n3, advance, s->stream);
+}
+
+int force_grid(const lc_sim* s, const ForceTiling& ft_in, bool n3) {
+  const ForceTiling ft = pass_tiling(s, ft_in, n3);
   if (ft.persistent && !n3) return device_cus() * 4;
   const int TI = n3 ? n3_block_size(ft) : force_tile_targets(ft);
   int64_t tiles = 0;
@@ -295,7 +306,7 @@ hipError_t enqueue_steps(lc_sim* s, int count, int64_t first_step) {
       if (e != hipSuccess) return e;
     }
     const bool n3_next = n3_pass(s, ft, is_diag_step(s, first_step + k + 1));
-    e = launch_schedule(s->s, s->rc, ft, n3_next, true, s->stream);
+    e = schedule(s, ft, n3_next, true);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -550,11 +561,11 @@ int lc_start(lc_sim* s) {
   ft.S = s->S_eff;
   const bool n3 = n3_pass(s, ft, false);
   hipError_t e = launch_refresh_sources(s->s, s->rc, s->cfg.precision, s->stream);
-  if (e == hipSuccess) e = launch_schedule(s->s, s->rc, ft, n3, false, s->stream);
+  if (e == hipSuccess) e = schedule(s, ft, n3, false);
   if (e == hipSuccess) e = launch_force(s->s, s->rc, s->cfg.precision, ft, false, force_grid(s, ft, n3), s->stream);
   if (e == hipSuccess) e = launch_start_kick(s->s, s->rc, s->cfg.precision, field_layout(ft, n3), s->stream);
   // tables of step 0
-  if (e == hipSuccess) e = launch_schedule(s->s, s->rc, ft, n3_pass(s, ft, is_diag_step(s, 0)), false, s->stream);
+  if (e == hipSuccess) e = schedule(s, ft, n3_pass(s, ft, is_diag_step(s, 0)), false);
   if (e != hipSuccess) return hip_fail(s, e, "lc_start");
   s->started = true;
   return LC_OK;
@@ -619,7 +630,7 @@ int lc_time_particle_kernels(lc_sim* s, int32_t reps, double out_ms[2]) {
   // times the kernels on the partials of the last field pass, in the layout of the current step
   const bool n3 = n3_pass(s, ft, is_diag_step(s, s->step));
   const FieldLayout fl = field_layout(ft, n3);
-  hipError_t e = launch_schedule(s->s, s->rc, ft, n3, false, s->stream);
+  hipError_t e = schedule(s, ft, n3, false);
   if (e == hipSuccess) e = hipEventRecord(ev[0], s->stream);
   for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_push(s->s, s->rc, s->cfg.precision, fl, 0, false, s->stream);
   if (e == hipSuccess) e = hipEventRecord(ev[1], s->stream);
@@ -736,7 +747,7 @@ int lc_set_tuning(lc_sim* s, const lc_tuning* t) {
   if (s->started) {
     ForceTiling cur = ft;
     cur.S = S_new;
-    hipError_t e = launch_schedule(s->s, s->rc, cur, n3_pass(s, cur, is_diag_step(s, s->step)), false, s->stream);
+    hipError_t e = schedule(s, cur, n3_pass(s, cur, is_diag_step(s, s->step)), false);
     if (e != hipSuccess) return hip_fail(s, e, "lc_set_tuning");
   }
   return LC_OK;
@@ -807,7 +818,7 @@ int lc_load_state(lc_sim* s, const char* path) {
   drop_graph(s);
   ForceTiling cur = s->ft;
   cur.S = s->S_eff;
-  e = launch_schedule(s->s, s->rc, cur, n3_pass(s, cur, is_diag_step(s, s->step)), false, s->stream);
+  e = schedule(s, cur, n3_pass(s, cur, is_diag_step(s, s->step)), false);
   if (e != hipSuccess) return hip_fail(s, e, "lc_load_state");
   return LC_OK;
 }
@@ -829,7 +840,7 @@ __global__ void k_fold_partials(DevState s, RunConst rc, FieldLayout fl) {
 int field_snapshot(lc_sim* s, const ForceTiling& ft, std::vector<double>& out) {
   const int64_t NT = s->L.n_total;
   const bool n3 = n3_pass(s, ft, false);
-  hipError_t e = launch_schedule(s->s, s->rc, ft, n3, false, s->stream);
+  hipError_t e = schedule(s, ft, n3, false);
   if (e == hipSuccess) e = launch_force(s->s, s->rc, s->cfg.precision, ft, false, force_grid(s, ft, n3), s->stream);
   if (e == hipSuccess) {
     // all reads of split 0 happen in the same thread before its writes
@@ -865,7 +876,7 @@ extern "C" int lc_read_field(lc_sim* s, int32_t cluster, double* E, int64_t cap,
   int rc = field_snapshot(s, ft, all);
   if (rc != LC_OK) return rc;
   // the current step's tables again (the snapshot built those of a pass without potential)
-  e = launch_schedule(s->s, s->rc, ft, n3_pass(s, ft, is_diag_step(s, s->step)), false, s->stream);
+  e = schedule(s, ft, n3_pass(s, ft, is_diag_step(s, s->step)), false);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "lc_read_field");
   int64_t off = 0;
@@ -921,8 +932,8 @@ extern "C" int lc_autotune(lc_sim* s, const char* cache_json, lc_tuning* chosen)
 
   struct Cand { ForceTiling ft; double ms; };
   std::vector<Cand> cands;
-  const int Rs[] = {1, 2, 4, 8};
-  const int WJs[] = {1, 2, 4};
+  const int Rs[] = {1, 2, 3, 4, 5, 6, 8};   // 3, 5, 6: square pair-once shapes (R = WJ) only
+  const int WJs[] = {1, 2, 3, 4, 5, 6};
   const int Ts[] = {256, 512, 1024, 2048};
   const int Ss[] = {1, 2, 4, 8, 16, 32, 64};
   hipEvent_t e0, e1;
@@ -946,11 +957,11 @@ extern "C" int lc_autotune(lc_sim* s, const char* cache_json, lc_tuning* chosen)
             if (!n3 && (int64_t)S * 64 > std::max<int64_t>(nmax, 64)) continue;
             const int reps = 3;
             const int grid = force_grid(s, ft, n3 != 0);
-            hipError_t e = launch_schedule(s->s, s->rc, ft, n3 != 0, false, s->stream);
+            hipError_t e = schedule(s, ft, n3 != 0, false);
             if (e == hipSuccess) e = launch_force(s->s, s->rc, prec, ft, false, grid, s->stream);  // warm
             if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
             for (int r = 0; r < reps && e == hipSuccess; ++r) {
-              e = launch_schedule(s->s, s->rc, ft, n3 != 0, false, s->stream);
+              e = schedule(s, ft, n3 != 0, false);
               if (e == hipSuccess) e = launch_force(s->s, s->rc, prec, ft, false, grid, s->stream);
             }
             if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
@@ -976,7 +987,7 @@ extern "C" int lc_autotune(lc_sim* s, const char* cache_json, lc_tuning* chosen)
   s->S_eff = best.S;
   drop_graph(s);
   {
-    hipError_t e = launch_schedule(s->s, s->rc, best, n3_pass(s, best, is_diag_step(s, s->step)), false, s->stream);
+    hipError_t e = schedule(s, best, n3_pass(s, best, is_diag_step(s, s->step)), false);
     if (e != hipSuccess) return hip_fail(s, e, "lc_autotune");
   }
   if (chosen) lc_get_tuning(s, chosen);
@@ -1048,7 +1059,7 @@ extern "C" int lc_profile_steps(lc_sim* s, int64_t n_steps, double* out_ms, int6
         if (e == hipSuccess) e = hipEventRecord(E[7], s->stream);
         used[4 * k + 3] = 1;
       }
-      if (e == hipSuccess) e = launch_schedule(s->s, s->rc, ft, n3_pass(s, ft, is_diag_step(s, s->step + 1)), true, s->stream);
+      if (e == hipSuccess) e = schedule(s, ft, n3_pass(s, ft, is_diag_step(s, s->step + 1)), true);
       s->step += 1;
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);

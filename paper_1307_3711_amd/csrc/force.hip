@@ -480,7 +480,7 @@ __device__ inline void wave_lds_sync() {
 // Per-wave LDS slice: x, y, z, q arrays of the chunk twice (128 entries each) plus room for
 // the prefetch of the rotation after the last one (up to 8 entries, read and discarded).
 constexpr int kN3Slice = 136;
-constexpr int kN3Fixed = 4 * 4 * kN3Slice;  // elements: the four waves' slices
+__host__ __device__ constexpr int n3_slices(int waves) { return waves * 4 * kN3Slice; }  // elements
 
 // One chunk of 64 sources (sb: x, y, z, q arrays of the chunk twice, kN3Slice apart) against
 // the lane's R targets.  US: all sources of the chunk carry one charge (factored out by the
@@ -561,13 +561,19 @@ __device__ inline void n3_chunk(const T* sb, int lane, const T* xi, const T* yi,
   az = rz;
 }
 
-__host__ __device__ constexpr int n3_block(int R, int WJ) { return (4 / WJ) * 64 * R; }
+// Shapes: target groups per block are 4/WJ (blocks of 256 threads), except the square shapes
+// R = WJ >= 3, which have one target group of 64 R targets and WJ waves, each wave one 64-source
+// chunk (blocks of 64 R threads, B = 64 R).
+__host__ __device__ constexpr int n3_groups(int R, int WJ) { return (R == WJ && R >= 3) ? 1 : 4 / WJ; }
+__host__ __device__ constexpr int n3_waves(int R, int WJ) { return n3_groups(R, WJ) * WJ; }
+__host__ __device__ constexpr int n3_block(int R, int WJ) { return n3_groups(R, WJ) * 64 * R; }
 
 template <typename T, int R, int WJ>
 __device__ void tile_n3(const N3Args<T>& a, int t, T* lds) {
   using V4 = typename N3Type<T>::V4;
   constexpr T kFar = N3Type<T>::kFar;
-  constexpr int TG = 4 / WJ, TGT = 64 * R, B = TG * TGT, PW = B / WJ, NCH = PW / 64;
+  constexpr int TG = n3_groups(R, WJ), NT = 64 * n3_waves(R, WJ), TGT = 64 * R, B = TG * TGT, PW = B / WJ,
+                NCH = PW / 64;
   static_assert(PW % 64 == 0, "each wave takes whole chunks of 64 sources");
   int c, I, J;
   decode_pair_tile(a.map, t, c, I, J);
@@ -582,7 +588,7 @@ __device__ void tile_n3(const N3Args<T>& a, int t, T* lds) {
   // rows exist only for blocks holding live slots (I <= J < nb <= M for a table built for n)
   const bool live = (int64_t)J * B < n && I <= J && J < a.M;
   T* sb = lds + w * 4 * kN3Slice;  // x, y, z, q arrays of the wave's chunk
-  T* jres = lds + kN3Fixed;       // [TG][3][B] reaction sums of the block's sources
+  T* jres = lds + n3_slices(n3_waves(R, WJ));  // [TG][3][B] reaction sums of the block's sources
   T* ired = jres + TG * 3 * B;    // [WJ - 1][3][B] target sums of waves jw > 0
 
   const int64_t i0 = (int64_t)I * B + (int64_t)g * TGT;
@@ -703,7 +709,7 @@ __device__ void tile_n3(const N3Args<T>& a, int t, T* lds) {
   // Source side: the target groups add up in a fixed order; row (J, I).
   if (jside && live) {
     T* row = rows + (int64_t)((int64_t)J * a.M + I) * 3 * B;
-    for (int jl = tid; jl < B; jl += kBlock) {
+    for (int jl = tid; jl < B; jl += NT) {
       if ((int64_t)J * B + jl >= n) break;
       T sx = 0, sy = 0, sz = 0;
       for (int q = 0; q < TG; ++q) {
@@ -756,9 +762,10 @@ __global__ __launch_bounds__(64 * kFoldWaves) void k_fold_n3(DevState s, RunCons
 
 // ----------------------------------------------------------------------------- kernels
 // Occupancy the register allocation aims at: 5 waves per SIMD for FP32 pairs (85 VGPRs at
-// R = 4, no spills), 3 for FP64 pairs (twice the registers per value).
+// R = 4, no spills; 4 from R = 6), 3 for FP64 pairs (twice the registers per value; 2 from R = 5).
 template <typename T, int R, int WJ>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 5)))
+__global__ __launch_bounds__(64 * n3_waves(R, WJ))
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? (R >= 5 ? 2 : 3) : (R >= 6 ? 4 : 5))))
 void k_force_n3(N3Args<T> a) {
   extern __shared__ __align__(16) unsigned char lds_n3_raw[];
   T* lds_n3 = reinterpret_cast<T*>(lds_n3_raw);
@@ -854,37 +861,42 @@ hipError_t dispatch_f64(const ForceArgs<double4>& a, bool phi, int grid, size_t 
 // Pair-once shapes: whole 64-source chunks per wave, blocks of 128..512 slots, and every shape
 // also valid for the regular kernels (which take the steps that need the potential).
 bool n3_shape_ok(int R, int WJ) {
-  return (WJ == 1 && (R == 1 || R == 2)) || (WJ == 2 && (R == 1 || R == 2 || R == 4)) || (WJ == 4 && R == 4);
+  return (WJ == 1 && (R == 1 || R == 2)) || (WJ == 2 && (R == 1 || R == 2 || R == 4)) ||
+         (R == WJ && R >= 3 && R <= 6);
 }
 
 size_t n3_lds_bytes(const ForceTiling& ft, size_t elem) {
   const size_t B = (size_t)n3_block(ft.R, ft.WJ);
-  return elem * ((size_t)kN3Fixed + (size_t)(4 / ft.WJ) * 3 * B + (size_t)(ft.WJ - 1) * 3 * B);
+  return elem * ((size_t)n3_slices(n3_waves(ft.R, ft.WJ)) + (size_t)n3_groups(ft.R, ft.WJ) * 3 * B +
+                 (size_t)(ft.WJ - 1) * 3 * B);
 }
 
 size_t n3_elem(int precision) { return precision == LC_FP64 ? sizeof(double) : sizeof(float); }
 
 // Workgroups of the pair-once kernel one CU holds at once (occupancy), cached per shape.
+// Pair-once shapes and their kernels: key WJ * 16 + R.
+#define LC_N3_SHAPES(X)                                                                          \
+  X(1, 1) X(2, 1) X(1, 2) X(2, 2) X(4, 2) X(3, 3) X(4, 4) X(5, 5) X(6, 6)
+
 template <typename T>
 int n3_resident_t(const ForceTiling& ft) {
   const size_t lds = n3_lds_bytes(ft, sizeof(T));
+  const int threads = 64 * n3_waves(ft.R, ft.WJ);
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (ft.WJ * 16 + ft.R) {
-    case 16 + 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<T, 1, 1>, kBlock, lds); break;
-    case 16 + 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<T, 2, 1>, kBlock, lds); break;
-    case 32 + 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<T, 1, 2>, kBlock, lds); break;
-    case 32 + 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<T, 2, 2>, kBlock, lds); break;
-    case 32 + 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<T, 4, 2>, kBlock, lds); break;
-    case 64 + 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<T, 4, 4>, kBlock, lds); break;
+#define LC_N3_OCC(R_, WJ_)                                                                         \
+  case WJ_ * 16 + R_: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<T, R_, WJ_>, threads, lds); break;
+    LC_N3_SHAPES(LC_N3_OCC)
+#undef LC_N3_OCC
     default: break;
   }
   return (e == hipSuccess && nb > 0) ? nb : 4;
 }
 
 int n3_resident_per_cu(int precision, const ForceTiling& ft) {
-  static int cache[2][8][4] = {};
-  int& v = cache[precision == LC_FP64 ? 1 : 0][ft.R & 7][ft.WJ & 3];
+  static int cache[2][8][8] = {};
+  int& v = cache[precision == LC_FP64 ? 1 : 0][ft.R & 7][ft.WJ & 7];
   if (v > 0) return v;
   v = (precision == LC_FP64) ? n3_resident_t<double>(ft) : n3_resident_t<float>(ft);
   return v;
@@ -893,13 +905,12 @@ int n3_resident_per_cu(int precision, const ForceTiling& ft) {
 template <typename T>
 hipError_t launch_n3(const ForceTiling& ft, const N3Args<T>& a, int grid, hipStream_t st) {
   const size_t lds = n3_lds_bytes(ft, sizeof(T));
+  const int threads = 64 * n3_waves(ft.R, ft.WJ);
   switch (ft.WJ * 16 + ft.R) {
-    case 16 + 1: k_force_n3<T, 1, 1><<<grid, kBlock, lds, st>>>(a); break;
-    case 16 + 2: k_force_n3<T, 2, 1><<<grid, kBlock, lds, st>>>(a); break;
-    case 32 + 1: k_force_n3<T, 1, 2><<<grid, kBlock, lds, st>>>(a); break;
-    case 32 + 2: k_force_n3<T, 2, 2><<<grid, kBlock, lds, st>>>(a); break;
-    case 32 + 4: k_force_n3<T, 4, 2><<<grid, kBlock, lds, st>>>(a); break;
-    case 64 + 4: k_force_n3<T, 4, 4><<<grid, kBlock, lds, st>>>(a); break;
+#define LC_N3_LAUNCH(R_, WJ_) \
+  case WJ_ * 16 + R_: k_force_n3<T, R_, WJ_><<<grid, threads, lds, st>>>(a); break;
+    LC_N3_SHAPES(LC_N3_LAUNCH)
+#undef LC_N3_LAUNCH
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1051,12 +1062,30 @@ int64_t n3_tiles(int64_t n, int B) {
   return nb * (nb + 1) / 2;
 }
 
+// The one-sided tiling a pair-once tiling's diagnostic steps run with: its own fields when
+// the one-sided kernels have that (R, WJ), else R = 1 (FP32) or 2 (FP64), WJ = 4.
+ForceTiling regular_tiling(int precision, const ForceTiling& ft) {
+  ForceTiling r = ft;
+  r.newton3 = 0;
+  const bool wj_ok = ft.WJ == 1 || ft.WJ == 2 || ft.WJ == 4;
+  const bool r_ok = ft.R == 1 || ft.R == 2 || ft.R == 4 || (ft.R == 8 && precision != LC_FP64 && ft.WJ == 1);
+  if (!(wj_ok && r_ok)) {
+    r.R = (precision == LC_FP64) ? 2 : 1;
+    r.WJ = 4;
+  }
+  return r;
+}
+
 bool force_tiling_valid(int precision, const ForceTiling& ft) {
+  if (ft.newton3) {
+    if (precision == LC_FP32_KAHAN || !n3_shape_ok(ft.R, ft.WJ)) return false;
+    if (n3_lds_bytes(ft, n3_elem(precision)) > 64 * 1024) return false;
+    return force_tiling_valid(precision, regular_tiling(precision, ft));
+  }
   bool r_ok = ft.R == 1 || ft.R == 2 || ft.R == 4 || (ft.R == 8 && precision != LC_FP64 && ft.WJ == 1);
   bool wj_ok = ft.WJ == 1 || ft.WJ == 2 || ft.WJ == 4;
   bool t_ok = ft.T >= 64 && ft.T <= 4096 && (ft.T % 64) == 0;
   if (ft.scalar_src && precision == LC_FP64) return false;  // scalar source path is FP32 only
-  if (ft.newton3 && (precision == LC_FP32_KAHAN || !n3_shape_ok(ft.R, ft.WJ))) return false;
   bool s_ok = ft.S >= 1 && ft.S <= 64;
   if (!(r_ok && wj_ok && t_ok && s_ok)) return false;
   return force_lds_bytes(precision, ft, true) <= 64 * 1024;
@@ -1083,7 +1112,8 @@ hipError_t launch_force(const DevState& s, const RunConst& rc, int precision, co
     return hipGetLastError();
   }
   const void* src = (precision == LC_FP64) ? (const void*)s.posq : (const void*)s.pos4;
-  return launch_generic(precision, ft, map, src, s.part, rc.n_total, rc.eps2, want_phi, grid_blocks, st);
+  const ForceTiling fr = ft.newton3 ? regular_tiling(precision, ft) : ft;
+  return launch_generic(precision, fr, map, src, s.part, rc.n_total, rc.eps2, want_phi, grid_blocks, st);
 }
 
 size_t field_workspace_bytes(int precision, int64_t n, const ForceTiling& ft) {

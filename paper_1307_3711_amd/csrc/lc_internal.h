@@ -207,6 +207,7 @@ size_t field_workspace_bytes(int precision, int64_t n, const ForceTiling& ft);
 
 int force_tile_targets(const ForceTiling& ft);
 int n3_block_size(const ForceTiling& ft);
+ForceTiling regular_tiling(int precision, const ForceTiling& ft);
 int n3_persistent_grid(int precision, const ForceTiling& ft, int64_t tiles, int cus);
 int64_t n3_tiles(int64_t n, int B);
 bool force_tiling_valid(int precision, const ForceTiling& ft);

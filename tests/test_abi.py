@@ -132,7 +132,9 @@ def test_pair_once_rows_in_state_bytes():
 
 
 @pytest.mark.parametrize("R,WJ,ok", [(1, 1, True), (2, 1, True), (1, 2, True), (2, 2, True), (4, 2, True),
-                                     (4, 4, True), (4, 1, False), (1, 4, False), (2, 4, False), (8, 1, False)])
+                                     (3, 3, True), (4, 4, True), (5, 5, True), (6, 6, True), (4, 1, False),
+                                     (1, 4, False), (2, 4, False), (8, 1, False), (3, 1, False), (7, 7, False),
+                                     (8, 8, False)])
 def test_pair_once_field_workspace(R, WJ, ok):
     L = lc.lib()
     n = 1000
@@ -141,8 +143,15 @@ def test_pair_once_field_workspace(R, WJ, ok):
     if not ok:
         assert wb == 0
         return
-    B = (4 // WJ) * 64 * R
+    B = 64 * R if (R == WJ and R >= 3) else (4 // WJ) * 64 * R   # square shapes: one target group
     nb = -(-n // B)
     assert wb >= nb * nb * 3 * B * 4 + n * 16
-    assert L.lc_field_workspace_bytes(0, n, ctypes.byref(t)) >= nb * nb * 3 * B * 8 + n * 32   # FP64 rows
+    square = R == WJ and R >= 3
+    tg, waves = (1, WJ) if square else (4 // WJ, 4)
+    lds64 = 8 * (waves * 4 * 136 + tg * 3 * B + (WJ - 1) * 3 * B)   # FP64 chunk copies + reductions
+    wb64 = L.lc_field_workspace_bytes(0, n, ctypes.byref(t))
+    if lds64 <= 65536:
+        assert wb64 >= nb * nb * 3 * B * 8 + n * 32   # FP64 rows
+    else:
+        assert wb64 == 0                              # shape needs more LDS than a block may take
     assert L.lc_field_workspace_bytes(2, n, ctypes.byref(t)) == 0   # not for Kahan

@@ -118,6 +118,9 @@ N3_TILINGS = [
     dict(R=4, WJ=2, newton3=1),
     dict(R=4, WJ=4, newton3=1),
     dict(R=4, WJ=4, newton3=1, persistent=1),
+    dict(R=3, WJ=3, newton3=1),
+    dict(R=5, WJ=5, newton3=1),
+    dict(R=6, WJ=6, newton3=1, persistent=1),
 ]
 
 
@@ -141,7 +144,7 @@ def test_field_pair_once_elementwise(n, ti):
 
 @pytest.mark.skipif(not gpu_available(), reason="needs a GPU")
 @pytest.mark.parametrize("n", [1, 2, 63, 129, 1000, 2053])
-@pytest.mark.parametrize("ti", [0, 2, 3, 5])
+@pytest.mark.parametrize("ti", [0, 2, 3, 5, 7, 8])
 def test_field_pair_once_fp64_elementwise(n, ti):
     """FP64 pair-once kernel: each pair once in FP64, FP64 rows: same tolerance as the FP64
     one-sided kernel (1e-12 S1)."""
@@ -189,6 +192,7 @@ def test_field_rejects_bad_arguments():
 @pytest.mark.parametrize("precision,tiling", [("fp64", dict(S=16)), ("fp32_acc64", dict(S=16)),
                                               ("fp32_acc64", dict(R=1, WJ=4, T=1024, S=16, scalar=1)),
                                               ("fp32_acc64", dict(R=4, WJ=4, newton3=1)),
+                                              ("fp32_acc64", dict(R=5, WJ=5, newton3=1)),
                                               ("fp64", dict(R=2, WJ=2, newton3=1)),
                                               ("fp32_acc64", dict(R=2, WJ=2, newton3=1, persistent=1))])
 def test_field_full_20k_sampled(precision, tiling):

@@ -46,7 +46,8 @@ def _compare_records(rg, ro, cols, tol):
 ENERGY_COLS = [5, 6, 7, 8, 9, 10]
 
 
-@pytest.mark.parametrize("tiling", [None, dict(R=2, WJ=2, newton3=1), dict(R=4, WJ=4, newton3=1)])
+@pytest.mark.parametrize("tiling", [None, dict(R=2, WJ=2, newton3=1), dict(R=4, WJ=4, newton3=1),
+                                    dict(R=3, WJ=3, newton3=1)])
 def test_small_ar_fp64_200_steps(tiling):
     import paper_1307_3711_amd as lc
     c, run = small_ar()
@@ -70,11 +71,15 @@ def test_small_ar_fp64_200_steps(tiling):
 # Pair-once tilings (each unordered pair evaluated once for both particles on steps without
 # a diagnostic record); the diagnostic steps take the one-sided kernels with the other fields.
 N3 = dict(R=4, WJ=4, T=1024, S=8, scalar=1, newton3=1)
-N3_TILINGS = [N3, dict(R=1, WJ=2, S=4, persistent=1, newton3=1), dict(R=2, WJ=1, S=2, newton3=1)]
+# Square shapes (R = WJ = 5) have no one-sided counterpart: their diagnostic steps run R = 1,
+# WJ = 4 with the tiling's T and S.
+N3_TILINGS = [N3, dict(R=1, WJ=2, S=4, persistent=1, newton3=1), dict(R=2, WJ=1, S=2, newton3=1),
+              dict(R=5, WJ=5, T=1024, S=8, scalar=1, newton3=1)]
 
 
 @pytest.mark.parametrize("precision,tiling", [("fp32_acc64", None), ("fp32_kahan", None), ("fp32_acc64", N3_TILINGS[0]),
-                                              ("fp32_acc64", N3_TILINGS[1]), ("fp32_acc64", N3_TILINGS[2])])
+                                              ("fp32_acc64", N3_TILINGS[1]), ("fp32_acc64", N3_TILINGS[2]),
+                                              ("fp32_acc64", N3_TILINGS[3])])
 def test_small_ar_fp32_200_steps(precision, tiling):
     import paper_1307_3711_amd as lc
     c, run = small_ar()
