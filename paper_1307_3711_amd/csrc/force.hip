@@ -396,14 +396,15 @@ __device__ void tile_f64(const ForceArgs<double4>& a, int t, double4* lds) {
 // ----------------------------------------------------------------------------- pairs once
 // Newton's third law: the pair term of (i, j) is the pair term of (j, i) with the sign of the
 // separation flipped and the partner's charge, so one evaluation can serve both particles.
-// A cluster's slots are cut into blocks of B = (4/WJ) * 64 * R.  The tile (I, J), I < J, takes
-// every pair (i in block I, j in block J) once and produces E_i's part from block J and E_j's
-// part from block I; the diagonal tile (I, I) takes all pairs of its block one-sided (the self
-// pair adds exactly zero).  Inside a block of 256 threads, 4/WJ target groups hold 64 R targets
-// each (R per lane) and the WJ waves of a group split the B sources.  A wave walks its sources
-// in chunks of 64, staged twice in a row in its own LDS slice (structure of arrays x, y, z, q,
-// so every read is a unit-stride dword access free of bank conflicts): at rotation k lane l
-// meets source (l + k) mod 64 at index l + k, an immediate offset.  The reaction sums of the chunk's
+// A cluster's slots are cut into blocks of B slots.  The tile (I, J), I < J, takes every pair
+// (i in block I, j in block J) once and produces E_i's part from block J and E_j's part from
+// block I; the diagonal tile (I, I) takes all pairs of its block one-sided (the self pair adds
+// exactly zero).  A thread block holds TG target groups of 64 R targets (R per lane), and the
+// WJ waves of a group split the B sources: TG = 4/WJ (256 threads, B = (4/WJ) 64 R), or for the
+// square shapes R = WJ >= 3, TG = 1 (64 R threads, B = 64 R).  A wave walks its sources in
+// chunks of 64, staged twice in a row in its own LDS slice (structure of arrays x, y, z, q, so
+// every read is a unit-stride dword access free of bank conflicts): at rotation k lane l meets
+// source (l + k) mod 64 at index l + k, an immediate offset.  The reaction sums of the chunk's
 // sources travel with the rotation in registers: lane l holds the running sum of source
 // (l + k) mod 64, adds its terms, and hands it to lane l - 1 (DPP wave rotate by one lane), so
 // after 64 rotations lane l holds source l's sum, accumulated in a fixed order (deterministic).
@@ -413,8 +414,10 @@ __device__ void tile_f64(const ForceArgs<double4>& a, int t, double4* lds) {
 // LC_FP64), one per (block K, partner block m) of a cluster:
 //   row (K, m), component d, local slot l:  n3part[n3_off + ((K M + m) 3 + d) B + l]
 // written by exactly one tile.  M (rows per block) is fixed at creation; nb = ceil(n / B).
-// k_fold_n3 then sums a slot's rows m = 0 .. nb - 1 in FP64, in a fixed order, into split 0
-// of the FP64 partials, which the push reads as a one-split field.
+// A slot's field is the FP64 sum of its block's rows m = 0 .. nb - 1 in a fixed order, taken
+// by the push kernel of the step (k_fold_push) or by k_fold_n3 into split 0 of the FP64
+// partials (start, field snapshots).
+
 // Pair arithmetic of the pair-once kernel: float (LC_FP32_ACC64) or double (LC_FP64).
 // kFar places padding entries so far away that every term they take part in is exactly zero:
 // FP32 r^2 overflows to +inf and v_rsq_f32(+inf) = +0; FP64 r^2 = 1e300 stays finite (the
