@@ -54,20 +54,31 @@ def make_sim(precision, c, run, st, graph, tiling=None):
     return sim, tuned
 
 
+def kernel_code_digest(path):
+    """sha256 of a source file's code: '//' comments, trailing blanks and empty lines removed,
+    so that a record stays valid across comment edits and is voided by any code change."""
+    import hashlib
+    import re
+    lines = []
+    for line in open(path, encoding="utf-8"):
+        line = re.sub(r"//.*", "", line).rstrip()
+        if line:
+            lines.append(line)
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()
+
+
 def counter_record(tuned, n):
     """The committed rocprofv3 counter record (HBM bytes per launch, VALU instructions) of the
-    Coulomb kernel this tiling runs, or None when the kernel source or the tiling has changed
+    Coulomb kernel this tiling runs, or None when the kernel code or the tiling has changed
     since the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "k_force_ar20k_counters.json")
     try:
         recs = json.load(open(path))["records"]
-        src = open(os.path.join(ROOT, "paper_1307_3711_amd", "csrc", "force.hip"), "rb").read()
+        digest = kernel_code_digest(os.path.join(ROOT, "paper_1307_3711_amd", "csrc", "force.hip"))
     except (OSError, KeyError, ValueError):
         return None
-    sha = hashlib.sha256(src).hexdigest()
     for rec in recs:
-        if rec["force_hip_sha256"] != sha or rec["n_particles"] != n:
+        if rec.get("force_hip_code_sha256") != digest or rec["n_particles"] != n:
             continue
         if all(tuned.get(k) == v for k, v in rec["tiling"].items()):
             return rec
