@@ -269,6 +269,8 @@ hipError_t schedule(lc_sim* s, const ForceTiling& ft, bool n3, bool advance) {
   return launch_schedule(s->s, s->rc, pass_tiling(s, ft, n3), n3, advance, s->stream);
 }
 
+constexpr int kGridPerCu = 32;  // blocks per CU of a non-persistent Coulomb launch at most
+
 int force_grid(const lc_sim* s, const ForceTiling& ft_in, bool n3) {
   const ForceTiling ft = pass_tiling(s, ft_in, n3);
   if (ft.persistent && !n3) return device_cus() * 4;
@@ -280,7 +282,10 @@ int force_grid(const lc_sim* s, const ForceTiling& ft_in, bool n3) {
     tiles += n3 ? nb * (nb + 1) / 2 : nb * ft.S;
   }
   if (ft.persistent) return n3_persistent_grid(s->cfg.precision, ft, tiles, device_cus());
-  return (int)std::min<int64_t>(tiles, std::numeric_limits<int32_t>::max());
+  // With ionization the tile count is bounded by capacities (the live counts are on the
+  // device), which for ensembles can be many times the tiles of a step; blocks beyond
+  // kGridPerCu per CU would mostly find no tile, so the kernels stride over the tiles instead.
+  return (int)std::min<int64_t>(tiles, (int64_t)kGridPerCu * device_cus());
 }
 
 hipError_t enqueue_steps(lc_sim* s, int count, int64_t first_step) {

@@ -774,7 +774,11 @@ void k_force_n3(N3Args<T> a) {
   T* lds_n3 = reinterpret_cast<T*>(lds_n3_raw);
   const int total = *a.map.tile_total;
   if (!a.persistent) {
-    if ((int)blockIdx.x < total) tile_n3<T, R, WJ>(a, blockIdx.x, lds_n3);
+    // one tile per block when the grid covers the tiles, else a block-strided walk over them
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+      if (t != (int)blockIdx.x) __syncthreads();
+      tile_n3<T, R, WJ>(a, t, lds_n3);
+    }
     return;
   }
   __shared__ int sh_t;
@@ -793,7 +797,10 @@ __global__ __launch_bounds__(kBlock) void k_force_f32(ForceArgs<float4> a, const
   extern __shared__ float4 lds32[];
   const int total = *a.map.tile_total;
   if (!a.persistent) {
-    if ((int)blockIdx.x < total) tile_f32<R, WJ, PHI, KAHAN, SCALAR>(a, gsrc, blockIdx.x, lds32);
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+      if (t != (int)blockIdx.x) __syncthreads();
+      tile_f32<R, WJ, PHI, KAHAN, SCALAR>(a, gsrc, t, lds32);
+    }
     return;
   }
   __shared__ int sh_t;
@@ -812,7 +819,10 @@ __global__ __launch_bounds__(kBlock) void k_force_f64(ForceArgs<double4> a) {
   extern __shared__ double4 lds64[];
   const int total = *a.map.tile_total;
   if (!a.persistent) {
-    if ((int)blockIdx.x < total) tile_f64<R, WJ, PHI>(a, blockIdx.x, lds64);
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+      if (t != (int)blockIdx.x) __syncthreads();
+      tile_f64<R, WJ, PHI>(a, t, lds64);
+    }
     return;
   }
   __shared__ int sh_t;
