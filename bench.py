@@ -67,10 +67,10 @@ def kernel_code_digest(path):
     return hashlib.sha256("\n".join(lines).encode()).hexdigest()
 
 
-def counter_record(tuned, n):
+def counter_record(tuned, n, precision="fp32_acc64"):
     """The committed rocprofv3 counter record (HBM bytes per launch, VALU instructions) of the
-    Coulomb kernel this tiling runs, or None when the kernel code or the tiling has changed
-    since the counters were taken."""
+    Coulomb kernel this precision and tiling run, or None when the kernel code or the tiling
+    has changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "k_force_ar20k_counters.json")
     try:
         recs = json.load(open(path))["records"]
@@ -79,6 +79,8 @@ def counter_record(tuned, n):
         return None
     for rec in recs:
         if rec.get("force_hip_code_sha256") != digest or rec["n_particles"] != n:
+            continue
+        if rec.get("precision", "fp32_acc64") != precision:
             continue
         if all(tuned.get(k) == v for k, v in rec["tiling"].items()):
             return rec
@@ -464,6 +466,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tiling", default="", help="R,WJ,T,S,persistent[,scalar[,newton3]]: skip the autotuner")
+    ap.add_argument("--tiling-fp64", default="", help="the same for the FP64 comparison run")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB buffer 3 times (HBM counter calibration for rocprofv3)")
     args = ap.parse_args()
@@ -477,10 +480,14 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": src.numel() * 4, "copies": 3}))
         return
-    tiling = None
-    if args.tiling:
-        v = [int(x) for x in args.tiling.split(",")] + [0, 0]
-        tiling = dict(R=v[0], WJ=v[1], T=v[2], S=v[3], persistent=v[4], scalar=v[5], newton3=v[6])
+    def parse_tiling(text):
+        if not text:
+            return None
+        v = [int(x) for x in text.split(",")] + [0, 0]
+        return dict(R=v[0], WJ=v[1], T=v[2], S=v[3], persistent=v[4], scalar=v[5], newton3=v[6])
+
+    tiling = parse_tiling(args.tiling)
+    tiling64 = parse_tiling(args.tiling_fp64)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
@@ -546,13 +553,15 @@ def main():
     total_steps = args.warmup + args.steps + args.profile_steps
     if not args.no_fp64:
         log("bench: fp64 path on the same steps")
-        sim64, tuned64 = make_sim("fp64", c, run, st, args.graph)
+        sim64, tuned64 = make_sim("fp64", c, run, st, args.graph, tiling64)
         sim64.step(args.warmup)
         wall64 = timed_steps(sim64, args.steps)
         prof64 = sim64.profile_steps(args.profile_steps)
         rec64 = sim64.diagnostics(0)
         f64_ms, f64_n = prof64["field"]
-        ach64 = FLOPS_PER_PAIR * pairs / (f64_ms / max(f64_n, 1) * 1e-3) / 1e12
+        avg64_s = f64_ms / max(f64_n, 1) * 1e-3
+        ach64 = FLOPS_PER_PAIR * pairs / avg64_s / 1e12
+        crec64 = counter_record(tuned64, n, "fp64")
         p32 = sim.particles(0)
         p64 = sim64.particles(0)
         r0n = c.r0_nm * lc.units(0.8)["k_per_nm"]
@@ -564,7 +573,14 @@ def main():
         out["fp64"] = {"value": round(args.steps * pairs / wall64 / 1e9, 3), "unit": "Gpair/s",
                        "ms_per_step": round(wall64 / args.steps * 1e3, 5), "tiling": tuned64,
                        "roofline": {"bound": "alu", "achieved": round(ach64, 3), "peak": FP64_PEAK_TFLOPS,
-                                    "unit": "TFLOP/s", "frac": round(ach64 / FP64_PEAK_TFLOPS, 4)}}
+                                    "unit": "TFLOP/s", "frac": round(ach64 / FP64_PEAK_TFLOPS, 4),
+                                    "traffic": crec64["traffic_bytes_per_launch"] if crec64 else None,
+                                    "kernel": "k_force_n3" if tuned64.get("newton3") else "k_force_f64",
+                                    "avg_launch_ms": round(avg64_s * 1e3, 5), "launches": f64_n,
+                                    "pair_evaluations_per_launch": pair_evaluations(n, tuned64),
+                                    "valu_issue_frac": (round(crec64["valu_wave_instructions"]
+                                                              / (crec64["avg_duration_ns"] * 1e-9)
+                                                              / VALU_ISSUE_PER_S, 4) if crec64 else None)}}
         out["error_vs_fp64"] = {"after_steps": total_steps, "t": float(last64[0]),
                                 "max_dx_over_R0": float(np.max(np.abs(p32["x"] - p64["x"])) / r0n),
                                 "rel_KE": rel(lc.R_KE_HALF), "rel_PE": rel(lc.R_PE),

@@ -171,7 +171,18 @@ __device__ inline void n3_row_partial(const DevState& s, const RunConst& rc, int
   const int64_t nb = (d.n_sched + B - 1) / B;
   const Tr* r = (const Tr*)s.n3part + cp.n3_off + (K * rc.n3_rows + w) * 3 * (int64_t)B + (l - K * B);
   const int64_t step = (int64_t)ways * 3 * B;
-  for (int64_t m = w; m < nb; m += ways, r += step) {
+  // four rows per round keep twelve loads in flight per lane; the sums stay in row order
+  int64_t m = w;
+  for (; m + 3 * ways < nb; m += 4 * ways, r += 4 * step) {
+    const double a0 = (double)r[0], a1 = (double)r[B], a2 = (double)r[2 * B];
+    const double b0 = (double)r[step], b1 = (double)r[step + B], b2 = (double)r[step + 2 * B];
+    const double c0 = (double)r[2 * step], c1 = (double)r[2 * step + B], c2 = (double)r[2 * step + 2 * B];
+    const double d0 = (double)r[3 * step], d1 = (double)r[3 * step + B], d2 = (double)r[3 * step + 2 * B];
+    e0 += a0; e0 += b0; e0 += c0; e0 += d0;
+    e1 += a1; e1 += b1; e1 += c1; e1 += d1;
+    e2 += a2; e2 += b2; e2 += c2; e2 += d2;
+  }
+  for (; m < nb; m += ways, r += step) {
     e0 += (double)r[0];
     e1 += (double)r[B];
     e2 += (double)r[2 * B];

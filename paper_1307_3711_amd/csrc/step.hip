@@ -147,22 +147,38 @@ __global__ __launch_bounds__(kBlock) void k_schedule(DevState s, RunConst rc, in
 }
 
 // ----------------------------------------------------------------------------- push (S3)
+// Per-particle state the push reads (loaded by the caller, which can overlap it with the
+// field's loads).
+struct PState {
+  double x, y, z, ux, uy, uz, wl, wc;
+  int zc;
+};
+
+__device__ inline PState load_pstate(const DevState& s, int64_t g) {
+  PState p;
+  p.x = s.x[g]; p.y = s.y[g]; p.z = s.z[g];
+  p.ux = s.ux[g]; p.uy = s.uy[g]; p.uz = s.uz[g];
+  p.wl = s.wl[g]; p.wc = s.wc[g];
+  p.zc = s.Z[g];
+  return p;
+}
+
 // Relativistic Boris step of live particle g (cluster c) at step index n in the Coulomb field
-// (ecx, ecy, ecz): u^{n-1/2} -> u^{n+1/2}, x^n -> x^{n+1}, with the exact discrete work split
+// (ecx, ecy, ecz) from state p: u^{n-1/2} -> u^{n+1/2}, x^n -> x^{n+1}, with the exact discrete work split
 // W_L / W_C, optional KE(n) for the diagnostics, and the refresh of the source record the next
 // field pass reads.
 template <int PREC>
 __device__ inline void push_one(const DevState& s, const RunConst& rc, int64_t g, int c, int64_t n, int diag,
-                                double ecx, double ecy, double ecz) {
+                                double ecx, double ecy, double ecz, const PState& p) {
   const ClusterParams& cp = s.cp[c];
   const ClusterDyn& d = s.dyn[c];
   const double t = rc.t0 + (double)n * rc.dt;
-  double x = s.x[g], y = s.y[g], z = s.z[g];
+  double x = p.x, y = p.y, z = p.z;
   double a;
   laser_at(cp, d, t, z, a);
-  const int zc = s.Z[g];
+  const int zc = p.zc;
   const double M = (zc < 0) ? 1.0 : cp.mass_ion;
-  const double uox = s.ux[g], uoy = s.uy[g], uoz = s.uz[g];
+  const double uox = p.ux, uoy = p.uy, uoz = p.uz;
   double unx = uox, uny = uoy, unz = uoz;
   const double go = sqrt(1.0 + uox * uox + uoy * uoy + uoz * uoz);
   if (zc != 0) {
@@ -189,8 +205,8 @@ __device__ inline void push_one(const DevState& s, const RunConst& rc, int64_t g
     // M (gamma_new - gamma_old) = Z dt E.(u_old + u_new)/(gamma_old + gamma_new), linear in E
     const double cc = cp.weight * (double)zc * rc.dt / (go + gn);
     const double sx = uox + unx, sy = uoy + uny, sz = uoz + unz;
-    s.wl[g] += cc * (a * sx + 0.0 * sy + 0.0 * sz);
-    s.wc[g] += cc * (ecx * sx + ecy * sy + ecz * sz);
+    s.wl[g] = p.wl + cc * (a * sx + 0.0 * sy + 0.0 * sz);
+    s.wc[g] = p.wc + cc * (ecx * sx + ecy * sy + ecz * sz);
   }
   if (diag) s.kebar[g] = cp.weight * M * 0.5 * (gm1(uox, uoy, uoz) + gm1(unx, uny, unz));
   x += rc.dt * unx / gn;
@@ -213,12 +229,13 @@ __global__ __launch_bounds__(kBlock) void k_push(DevState s, RunConst rc, FieldL
   if (g - s.cp[c].off >= d.n_cur) return;
   double ecx, ecy, ecz;
   field_sum(s, rc, fl, g, ecx, ecy, ecz);
-  push_one<PREC>(s, rc, g, c, *s.step + k, diag, ecx, ecy, ecz);
+  push_one<PREC>(s, rc, g, c, *s.step + k, diag, ecx, ecy, ecz, load_pstate(s, g));
 }
 
 // Fold of the pair-once rows and push in one kernel: kFoldWaves waves over 64 consecutive
 // slots add their share of the rows, wave 0 combines them in order, keeps the field in split 0
-// (read by the ionization check) and pushes.
+// (read by the ionization check) and pushes.  Wave 0 loads the particle state before its rows
+// so both latencies overlap.
 template <int PREC>
 __global__ __launch_bounds__(64 * kFoldWaves) void k_fold_push(DevState s, RunConst rc, int B, int64_t k, int diag) {
   __shared__ double red[kFoldWaves - 1][3][64];
@@ -228,10 +245,12 @@ __global__ __launch_bounds__(64 * kFoldWaves) void k_fold_push(DevState s, RunCo
   double e0 = 0.0, e1 = 0.0, e2 = 0.0;
   bool live = false;
   int c = 0;
+  PState ps;
   if (g < rc.n_total) {
     c = s.cid[g];
     live = s.dyn[c].active && g - s.cp[c].off < s.dyn[c].n_cur;
     if (live) {
+      if (w == 0) ps = load_pstate(s, g);
       if (PREC == LC_FP64) n3_row_partial<double>(s, rc, B, g, w, kFoldWaves, e0, e1, e2);
       else n3_row_partial<float>(s, rc, B, g, w, kFoldWaves, e0, e1, e2);
     }
@@ -251,7 +270,7 @@ __global__ __launch_bounds__(64 * kFoldWaves) void k_fold_push(DevState s, RunCo
     s.part[g] = e0;
     s.part[rc.n_total + g] = e1;
     s.part[2 * rc.n_total + g] = e2;
-    push_one<PREC>(s, rc, g, c, *s.step + k, diag, e0, e1, e2);
+    push_one<PREC>(s, rc, g, c, *s.step + k, diag, e0, e1, e2, ps);
   }
 }
 
