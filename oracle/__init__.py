@@ -25,6 +25,7 @@ _LIB = os.path.join(_HERE, "liblc_oracle.so")
 
 ENVELOPES = {"gauss_field": 0, "gauss_intensity": 1, "sin2": 2, "flat": 3}
 PHASES = {"dipole": 0, "plane_wave": 1}
+POLARIZATIONS = {"linear_x": 0, "circular": 1}
 OFI = {"laser_only": 0, "local": 1}
 MAX_Z = 16
 REC = 48
@@ -61,6 +62,7 @@ class Params(ctypes.Structure):
         ("field_au", ctypes.c_double), ("rate_scale", ctypes.c_double),
         ("delta", ctypes.c_double), ("n_atoms", ctypes.c_double), ("mec2_ev", ctypes.c_double),
         ("seed", ctypes.c_uint64), ("cluster", ctypes.c_uint64), ("n_ion", ctypes.c_int64),
+        ("polarization", ctypes.c_int32), ("pad", ctypes.c_int32),
     ]
 
 
@@ -181,6 +183,7 @@ def make_params(cluster, run, cluster_index=0, weight=None, **override):
     p.a0 = units.a0_from_intensity(cluster.laser.intensity_wcm2, lam)
     p.envelope = ENVELOPES[cluster.laser.envelope]
     p.phase = PHASES[cluster.laser.phase]
+    p.polarization = POLARIZATIONS[cluster.laser.polarization]
     p.tau = units.fs_to_norm(cluster.laser.fwhm_fs, lam)
     p.t_sin2 = 2.0 * np.pi * cluster.laser.n_cycles
     natoms = units.n_atoms(cluster.r0_nm, sp["rw_angstrom"])
@@ -240,7 +243,7 @@ class Sim:
         self.wl = np.zeros(self.cap)
         self.wc = np.zeros(self.cap)
         self.wsp = np.zeros(self.cap)
-        self.work = np.zeros(7 * self.cap)
+        self.work = np.zeros(8 * self.cap)
         self.counters = np.zeros(2)
         self.step_index = 0
         self.ke_start = None

@@ -67,6 +67,7 @@ double or_u01(uint64_t x) { return (double)((x >> 11) + 1ULL) * (1.0 / 900719925
 /* ------------------------------------------------------------------ parameters */
 enum { OR_ENV_GAUSS_FIELD = 0, OR_ENV_GAUSS_INTENSITY = 1, OR_ENV_SIN2 = 2, OR_ENV_FLAT = 3 };
 enum { OR_PHASE_DIPOLE = 0, OR_PHASE_PLANE_WAVE = 1 };
+enum { OR_POL_LINEAR_X = 0, OR_POL_CIRCULAR = 1 };
 enum { OR_OFI_LASER_ONLY = 0, OR_OFI_LOCAL = 1 };
 enum { OR_PURPOSE_ALPHA = 2, OR_PURPOSE_DIRECTION = 3 };
 
@@ -97,6 +98,8 @@ typedef struct {
   uint64_t seed;        /* Philox key word 0                                       */
   uint64_t cluster;     /* Philox key word 1                                       */
   int64_t n_ion;        /* ions occupy indices [0, n_ion)                          */
+  int32_t polarization; /* OR_POL_*                                                */
+  int32_t pad;
 } or_params;
 
 /* ------------------------------------------------------------------ S2: field */
@@ -184,14 +187,23 @@ double or_envelope(const or_params* p, double t) {
   }
 }
 
-/* Eqs.(4)-(9) for linear polarization along x: E = a(t) sin(psi) x^, B = a(t) sin(psi) y^
- * (b0 = a0 in these units).  psi = t in the dipole approximation (the cluster is much
- * smaller than the wavelength); psi = t - z for the plane-wave test mode. */
+/* Eqs.(4)-(9): E = a(t) (sin psi, sin(psi + phi_E), 0), B = a(t) (sin(psi + phi_B), sin psi, 0)
+ * with b0 = a0 in these units.  Linear polarization along x takes the phases that make E_y
+ * and B_x vanish.  Circular polarization takes phi_E = 3 pi/2 and phi_B = pi/2, so that
+ * E_y = -a cos psi and B_x = a cos psi (each component with the full amplitude a(t)).
+ * psi = t in the dipole approximation (the cluster is much smaller than the wavelength);
+ * psi = t - z for the plane-wave test mode. */
 void or_laser(const or_params* p, double t, double z, double E[3], double B[3]) {
   double psi = (p->phase == OR_PHASE_PLANE_WAVE) ? (t - z) : t;
-  double a = or_envelope(p, t) * sin(psi);
+  double env = or_envelope(p, t);
+  double a = env * sin(psi);
   E[0] = a; E[1] = 0.0; E[2] = 0.0;
   B[0] = 0.0; B[1] = a; B[2] = 0.0;
+  if (p->polarization == OR_POL_CIRCULAR) {
+    double c = env * cos(psi);
+    E[1] = -c;
+    B[0] = c;
+  }
 }
 
 /* ------------------------------------------------------------------ S3: Boris */
@@ -308,7 +320,8 @@ typedef struct {
   double* ez;
   double* phi;
   double* kebar;
-  double* elx; /* laser field used at each particle this step (for OFI) */
+  double* elx; /* laser field used at each particle this step (for OFI): x component */
+  double* ely; /* and y component */
 } or_scratch;
 
 static void or_record(const or_params* p, int64_t step, int64_t n, const double* ux, const double* uy,
@@ -372,6 +385,7 @@ static int or_step(const or_params* p, int64_t step, int64_t cap, int64_t* n_io,
     double EL[3], BL[3];
     or_laser(p, t, z[i], EL, BL);
     s->elx[i] = EL[0];
+    s->ely[i] = EL[1];
     double M = or_mass(p, Z[i]);
     double uo[3] = {ux[i], uy[i], uz[i]};
     double un[3] = {uo[0], uo[1], uo[2]};
@@ -414,7 +428,10 @@ static int or_step(const or_params* p, int64_t step, int64_t cap, int64_t* n_io,
       double F;
       if (p->ofi_field == OR_OFI_LOCAL) {
         double fx = s->ex[i] + s->elx[i];
-        F = sqrt(fx * fx + s->ey[i] * s->ey[i] + s->ez[i] * s->ez[i]);
+        double fy = s->ey[i] + s->ely[i];
+        F = sqrt(fx * fx + fy * fy + s->ez[i] * s->ez[i]);
+      } else if (p->polarization == OR_POL_CIRCULAR) {
+        F = sqrt(s->elx[i] * s->elx[i] + s->ely[i] * s->ely[i]);
       } else {
         F = fabs(s->elx[i]);
       }
@@ -454,7 +471,7 @@ static int or_step(const or_params* p, int64_t step, int64_t cap, int64_t* n_io,
   return wrote;
 }
 
-/* Run steps [step0, step0 + nsteps).  work must hold 7*cap doubles.  Records go to rec
+/* Run steps [step0, step0 + nsteps).  work must hold 8*cap doubles.  Records go to rec
  * (OR_REC doubles each, at most max_rec); returns the number written.  counters[0] holds
  * dropped spawns and counters[1] ionization events, both carried across calls. */
 int64_t or_run(const or_params* p, int64_t cap, int64_t* n_io, double* x, double* y, double* z,
@@ -469,6 +486,7 @@ int64_t or_run(const or_params* p, int64_t cap, int64_t* n_io, double* x, double
   s.phi = work + 4 * cap;
   s.kebar = work + 5 * cap;
   s.elx = work + 6 * cap;
+  s.ely = work + 7 * cap;
   int64_t nrec = 0;
   for (int64_t k = 0; k < nsteps; ++k) {
     double* r = (rec && nrec < max_rec) ? rec + nrec * OR_REC : NULL;

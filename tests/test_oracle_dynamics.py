@@ -216,6 +216,64 @@ def test_dipole_free_electron_invariants():
     assert errs[1] < 5e-4
 
 
+def _circular_orbit_error(a, dt, t_run, t0=0.3):
+    """Electron started on the orbit u = a (cos t, sin t, 0) in the circularly polarized dipole
+    field (flat envelope): max error of u at the last half step and of x at the last step
+    against the closed form."""
+    c = Cluster(species="Ar", r0_nm=1.0, n_ion=0, capacity=1,
+                laser=Laser(envelope="flat", polarization="circular"))
+    run = Run(dt=dt, t0=t0, ionize=False, diag_every=0)
+    p = oracle.make_params(c, run, weight=1.0)
+    p.a0 = a
+    u0 = np.array([[a * math.cos(t0), a * math.sin(t0), 0.0]])
+    sim = oracle.Sim(p, 1, np.zeros((1, 3)), u0, np.array([-1], np.int8))
+    sim.start()
+    nst = int(round(t_run / dt))
+    sim.run(nst)
+    t = t0 + nst * dt
+    th = t - dt / 2
+    g = math.sqrt(1.0 + a * a)
+    ue = np.array([a * math.cos(th), a * math.sin(th), 0.0])
+    xe = (a / g) * np.array([math.sin(t) - math.sin(t0), math.cos(t0) - math.cos(t), 0.0])
+    return np.max(np.abs(sim.momenta()[0] - ue)), np.max(np.abs(sim.positions()[0] - xe))
+
+
+@pytest.mark.parametrize("a", [0.3, 1.0, 3.0])
+def test_circular_dipole_orbit_second_order(a):
+    """Circular polarization (Eqs.(4)-(9) with phi_E = 3 pi/2, phi_B = pi/2): for an electron,
+    u = a (cos t, sin t, 0) solves du/dt = -(E + v x B) exactly at any a, since du/dt = -E
+    and v is parallel to B = a (cos t, sin t, 0), so gamma = sqrt(1 + a^2) stays constant and
+    x = (a/gamma)(sin t - sin t0, cos t0 - cos t, 0).  The Boris orbit converges to it at
+    second order in dt."""
+    errs = [_circular_orbit_error(a, dt, 20.0) for dt in (0.1, 0.05, 0.025)]
+    for k in range(2):
+        for m in range(2):
+            assert 3.6 < errs[k][m] / errs[k + 1][m] < 4.4
+    assert errs[2][0] < 2e-4 * max(a, 1.0) and errs[2][1] < 1e-3
+
+
+def test_ionization_survival_law_circular():
+    """Circular polarization with a flat envelope keeps |E_L| = a0 at every phase, so the
+    laser-only ADK rate nu is constant and an ion that may ionize once survives n checks with
+    probability exp(-nu n dt) (binomial count, 4.5 sigma)."""
+    n_ion = 3000
+    c = Cluster(species="Ar", r0_nm=20.0, n_ion=n_ion, capacity=3 * n_ion, z_init=1, z_max=2,
+                laser=Laser(intensity_wcm2=1e15, envelope="flat", polarization="circular"))
+    run = Run(dt=0.05, ionize=True, diag_every=0, seed=22)
+    sim = oracle.Sim.from_workload(c, run, initial_state(c, 22))
+    sim.p.kappa = 0.0
+    sim.start()
+    nsteps = 40
+    sim.run(nsteps)
+    surv = np.mean(sim.charges()[:n_ion] == 1)
+    p = sim.p
+    nu = oracle.adk_rate(p.ip_au[1], 2.0, p.a0 * p.field_au) * p.rate_scale
+    expect = math.exp(-nu * p.dt * nsteps)
+    sigma = math.sqrt(expect * (1 - expect) / n_ion)
+    assert 0.2 < expect < 0.8
+    assert abs(surv - expect) < 4.5 * sigma
+
+
 def _small_cluster(n_ion=100, seed=3, dt=0.05, ionize=False, intensity=1e17, diag_every=1,
                    envelope="flat"):
     c = Cluster(species="Ar", r0_nm=2.0, n_ion=n_ion, capacity=n_ion * 9, z_init=1, z_max=8,

@@ -168,3 +168,20 @@ def test_laser_components_linear():
     E, B = oracle.laser(pp, 1.0, 0.4)
     assert E[0] == pytest.approx(pp.a0 * math.sin(0.6), rel=1e-14)
     assert np.cross(E, B)[2] >= 0.0
+
+
+def test_laser_components_circular():
+    """Eqs.(4)-(9), circular polarization (phi_E = 3 pi/2, phi_B = pi/2): E_x and B_y as in the
+    linear case, E_y = a sin(t + 3 pi/2), B_x = a sin(t + pi/2); |E| = |B| = a(t) at every
+    phase, E . B = 0 and E x B = a^2 z^ (the wave runs along +z)."""
+    lin = oracle.make_params(Cluster(laser=Laser(envelope="flat")), Run())
+    p = oracle.make_params(Cluster(laser=Laser(envelope="flat", polarization="circular")), Run())
+    for t in [0.3, 1.0, 2.5, 4.0, 5.9]:
+        E, B = oracle.laser(p, t)
+        El, Bl = oracle.laser(lin, t)
+        assert E[0] == El[0] and B[1] == Bl[1] and E[2] == 0.0 and B[2] == 0.0
+        assert E[1] == pytest.approx(p.a0 * math.sin(t + 1.5 * math.pi), abs=1e-15 * p.a0)
+        assert B[0] == pytest.approx(p.a0 * math.sin(t + 0.5 * math.pi), abs=1e-15 * p.a0)
+        assert np.linalg.norm(E) == pytest.approx(p.a0, rel=1e-14)
+        assert abs(E @ B) < 1e-15 * p.a0 ** 2
+        assert np.cross(E, B) == pytest.approx([0.0, 0.0, p.a0 ** 2], rel=1e-13, abs=1e-18)

@@ -33,6 +33,7 @@ class Laser:
     fwhm_fs: float = 30.0             # Gaussian envelopes
     n_cycles: float = 10.0            # sin2 envelope: total length in laser periods
     phase: str = "dipole"             # dipole | plane_wave (test mode)
+    polarization: str = "linear_x"    # linear_x | circular (Eqs.(4)-(9))
 
 
 @dataclass(frozen=True)
