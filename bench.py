@@ -233,7 +233,8 @@ def bench_particles(args):
     c = Cluster(species="Ar", r0_nm=6.0, n_ion=2048, capacity=8192, z_init=1, z_max=8,
                 laser=Laser(intensity_wcm2=1e15, envelope="flat"))
     cfg = lc.make_config("fp32_acc64", ionize=True, diag_every=0, max_records=1, max_splits=1, seed=1, t0=1.3)
-    d = lc.make_cluster(SPECIES["Ar"], c.r0_nm, c.n_ion, c.capacity, c.laser.intensity_wcm2, envelope="flat")
+    d = lc.make_cluster(SPECIES["Ar"], c.r0_nm, c.n_ion, c.capacity, c.laser.intensity_wcm2, envelope="flat",
+                        polarization=args.polarization)
     sim = lc.Simulation(cfg, [d] * nc)
     st = initial_state(c, 1, 0)
     for i in range(nc):
@@ -249,7 +250,8 @@ def bench_particles(args):
            "value": round(push_gbs, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.reps, "warmup": 5,
            "ms_per_step": round(t["push_ms"], 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64", "data": "synthetic",
-           "config": {"workload": f"{nc} Ar clusters x (2048 Ar+ + 2048 e-), capacity 8192, 1e15 W/cm2 flat",
+           "config": {"workload": f"{nc} Ar clusters x (2048 Ar+ + 2048 e-), capacity 8192, 1e15 W/cm2 flat, "
+                                  f"{args.polarization} polarization",
                       "live_particles": n_live, "ions": nc * c.n_ion},
            "roofline": {"bound": "hbm", "achieved": round(push_gbs, 1), "peak": 8000.0, "unit": "GB/s",
                         "frac": round(push_gbs / 8000.0, 4), "traffic": None, "kernel": "k_push",
@@ -467,6 +469,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tiling", default="", help="R,WJ,T,S,persistent[,scalar[,newton3]]: skip the autotuner")
     ap.add_argument("--tiling-fp64", default="", help="the same for the FP64 comparison run")
+    ap.add_argument("--polarization", default="linear_x", choices=["linear_x", "circular"],
+                    help="particles workload: laser polarization")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB buffer 3 times (HBM counter calibration for rocprofv3)")
     args = ap.parse_args()

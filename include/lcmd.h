@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define LC_API_VERSION 1
+#define LC_API_VERSION 2
 #define LC_MAX_Z 16       /* size of the per-charge tables (charge states 0..15)        */
 #define LC_REC 48         /* doubles per diagnostic record                              */
 
@@ -69,6 +69,13 @@ typedef enum {
   LC_DIPOLE = 0,          /* field depends on time only (Sec. II dipole approximation)    */
   LC_PLANE_WAVE = 1       /* test mode: phase t - z, wave along +z; ionization must be off */
 } lc_phase;
+
+/* Polarization of the laser field (Eqs.(4)-(9); the magnetic field is z^ x E in both). */
+typedef enum {
+  LC_LINEAR_X = 0,        /* E = a(t) (sin psi, 0, 0), B = a(t) (0, sin psi, 0)             */
+  LC_CIRCULAR = 1         /* phi_E = 3 pi/2, phi_B = pi/2: E = a(t) (sin psi, -cos psi, 0),
+                             B = a(t) (cos psi, sin psi, 0), every component at full a(t)  */
+} lc_polarization;
 
 typedef enum {
   LC_LASER_ONLY = 0,      /* ADK driven by the laser field strength (Sec. II)              */
@@ -111,7 +118,7 @@ typedef struct {
   int64_t capacity;           /* slots for ions + electrons (spawns included)           */
   double weight;              /* real particles per macroparticle; 0: N_atoms / n_ion   */
   int32_t z_max;              /* highest ion charge (<= LC_MAX_Z - 1)                    */
-  int32_t reserved;
+  int32_t polarization;       /* lc_polarization                                        */
   double electron_offset_nm;  /* distance of a spawned electron from its ion            */
   int64_t n_steps;            /* the cluster retires after this many steps (0: never)   */
 } lc_cluster;

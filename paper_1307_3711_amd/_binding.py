@@ -20,6 +20,7 @@ LC_OK, LC_E_INVALID, LC_E_CAPACITY, LC_E_NONFINITE, LC_E_HIP, LC_E_STATE, LC_E_U
 PRECISIONS = {"fp64": 0, "fp32_acc64": 1, "fp32_kahan": 2}
 ENVELOPES = {"gauss_field": 0, "gauss_intensity": 1, "sin2": 2, "flat": 3}
 PHASES = {"dipole": 0, "plane_wave": 1}
+POLARIZATIONS = {"linear_x": 0, "circular": 1}
 OFI = {"laser_only": 0, "local": 1}
 
 # record columns (see include/lcmd.h)
@@ -51,7 +52,7 @@ class ClusterDesc(ctypes.Structure):
         ("ip_ev", ctypes.c_double * LC_MAX_Z), ("intensity_wcm2", ctypes.c_double),
         ("envelope", ctypes.c_int32), ("phase", ctypes.c_int32), ("fwhm_fs", ctypes.c_double),
         ("n_cycles", ctypes.c_double), ("n_ion", ctypes.c_int64), ("capacity", ctypes.c_int64),
-        ("weight", ctypes.c_double), ("z_max", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("weight", ctypes.c_double), ("z_max", ctypes.c_int32), ("polarization", ctypes.c_int32),
         ("electron_offset_nm", ctypes.c_double), ("n_steps", ctypes.c_int64),
     ]
 
@@ -173,7 +174,8 @@ def make_config(precision="fp64", ionize=True, ofi_field="laser_only", lambda_um
 
 
 def make_cluster(species, r0_nm, n_ion, capacity, intensity_wcm2, envelope="gauss_field", fwhm_fs=30.0,
-                 n_cycles=10.0, phase="dipole", weight=0.0, z_max=8, electron_offset_nm=0.01, n_steps=0):
+                 n_cycles=10.0, phase="dipole", weight=0.0, z_max=8, electron_offset_nm=0.01, n_steps=0,
+                 polarization="linear_x"):
     """species: mapping with rw_angstrom, mass_u and ip_ev (charge state k -> k+1, eV)."""
     d = ClusterDesc()
     d.r0_nm, d.rw_angstrom, d.mass_u = r0_nm, species["rw_angstrom"], species["mass_u"]
@@ -182,6 +184,7 @@ def make_cluster(species, r0_nm, n_ion, capacity, intensity_wcm2, envelope="gaus
     d.intensity_wcm2 = intensity_wcm2
     d.envelope = ENVELOPES[envelope]
     d.phase = PHASES[phase]
+    d.polarization = POLARIZATIONS[polarization]
     d.fwhm_fs, d.n_cycles = fwhm_fs, n_cycles
     d.n_ion, d.capacity, d.weight, d.z_max = n_ion, capacity, weight, z_max
     d.electron_offset_nm, d.n_steps = electron_offset_nm, n_steps

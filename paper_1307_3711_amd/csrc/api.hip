@@ -88,6 +88,7 @@ bool valid_cluster(const lc_config* cfg, const lc_cluster& c, std::string* why) 
   if (!(c.intensity_wcm2 >= 0.0)) { *why = "intensity must be >= 0"; return false; }
   if (c.envelope < LC_GAUSS_FIELD || c.envelope > LC_FLAT) { *why = "unknown envelope"; return false; }
   if (c.phase != LC_DIPOLE && c.phase != LC_PLANE_WAVE) { *why = "unknown phase"; return false; }
+  if (c.polarization != LC_LINEAR_X && c.polarization != LC_CIRCULAR) { *why = "unknown polarization"; return false; }
   if (c.phase == LC_PLANE_WAVE && cfg->ionize) { *why = "plane-wave phase is a test mode without ionization"; return false; }
   if ((c.envelope == LC_GAUSS_FIELD || c.envelope == LC_GAUSS_INTENSITY) && !(c.fwhm_fs > 0.0)) { *why = "fwhm_fs must be > 0"; return false; }
   if (c.envelope == LC_SIN2 && !(c.n_cycles > 0.0)) { *why = "n_cycles must be > 0"; return false; }
@@ -469,6 +470,7 @@ int lc_create(lc_sim** out, const lc_config* cfg, const lc_cluster* clusters, in
     }
     p.envelope = k.envelope;
     p.phase = k.phase;
+    p.polarization = k.polarization;
     p.z_max = k.z_max;
     p.ion_block0 = ib0;
     p.n_ion_blocks = (int32_t)((k.n_ion + kBlock - 1) / kBlock);

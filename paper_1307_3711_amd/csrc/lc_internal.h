@@ -52,7 +52,7 @@ struct ClusterParams {
   int32_t z_max;
   int32_t ion_block0;   // first entry of this cluster in the ion-block table
   int32_t n_ion_blocks;
-  int32_t pad;
+  int32_t polarization;  // LC_LINEAR_X or LC_CIRCULAR
   int64_t n3_off;       // first float of this cluster's pair-once partial rows (see force.hip)
 };
 
@@ -64,7 +64,8 @@ struct ClusterDyn {
   int64_t events;       // ionizations (cumulative)
   int64_t rec_count;    // diagnostic records written
   double ke_start;      // sum w M (gamma - 1) at t0 - dt/2
-  double laser_e;       // a(t^n) sin(t^n) of the current step (dipole field value)
+  double laser_e;       // E_x of the dipole field at t^n: a(t^n) sin(t^n)
+  double laser_ey;      // E_y of the dipole field at t^n: -a(t^n) cos(t^n) if circular, else 0
   double env;           // a(t^n)
   int32_t tile0;        // first tile of this cluster in the step's tile enumeration
   int32_t n_tiles;      // tiles of this cluster this step

@@ -77,8 +77,17 @@ __device__ inline void write_source(const DevState& s, int precision, int64_t g,
   else s.pos4[g] = make_float4((float)x, (float)y, (float)z, (float)q);
 }
 
-__device__ inline void laser_at(const ClusterParams& cp, const ClusterDyn& d, double t, double z, double& a) {
-  a = (cp.phase == LC_DIPOLE) ? d.laser_e : d.env * sin(t - z);
+// Laser electric field (ax, ay, 0) at time t and height z (Eqs.(4)-(9)); the magnetic field
+// is z^ x E = (-ay, ax, 0) for both polarizations (b0 = a0).
+__device__ inline void laser_at(const ClusterParams& cp, const ClusterDyn& d, double t, double z, double& ax,
+                                double& ay) {
+  if (cp.phase == LC_DIPOLE) {
+    ax = d.laser_e;
+    ay = d.laser_ey;
+  } else {
+    ax = d.env * sin(t - z);
+    ay = (cp.polarization == LC_CIRCULAR) ? -(d.env * cos(t - z)) : 0.0;
+  }
 }
 
 // ----------------------------------------------------------------------------- schedule (S6)
@@ -116,6 +125,7 @@ __global__ __launch_bounds__(kBlock) void k_schedule(DevState s, RunConst rc, in
       const double env = envelope(cp, t);
       d.env = env;
       d.laser_e = env * sin(t);
+      d.laser_ey = (cp.polarization == LC_CIRCULAR) ? -(env * cos(t)) : 0.0;
       d.active = active;
       d.i_blocks = ib;
       d.n_tiles = tiles;
@@ -174,20 +184,20 @@ __device__ inline void push_one(const DevState& s, const RunConst& rc, int64_t g
   const ClusterDyn& d = s.dyn[c];
   const double t = rc.t0 + (double)n * rc.dt;
   double x = p.x, y = p.y, z = p.z;
-  double a;
-  laser_at(cp, d, t, z, a);
+  double ax, ay;
+  laser_at(cp, d, t, z, ax, ay);
   const int zc = p.zc;
   const double M = (zc < 0) ? 1.0 : cp.mass_ion;
   const double uox = p.ux, uoy = p.uy, uoz = p.uz;
   double unx = uox, uny = uoy, unz = uoz;
   const double go = sqrt(1.0 + uox * uox + uoy * uoy + uoz * uoz);
   if (zc != 0) {
-    // E = E_C + E_L, E_L = (a, 0, 0); B_L = (0, a, 0)
+    // E = E_C + E_L, E_L = (ax, ay, 0); B_L = (-ay, ax, 0)
     const double h = 0.5 * ((double)zc / M) * rc.dt;
-    const double Ex = ecx + a, Ey = ecy, Ez = ecz;
+    const double Ex = ecx + ax, Ey = ecy + ay, Ez = ecz;
     const double umx = uox + h * Ex, umy = uoy + h * Ey, umz = uoz + h * Ez;
     const double gm = sqrt(1.0 + umx * umx + umy * umy + umz * umz);
-    const double tx = h * 0.0 / gm, ty = h * a / gm, tz = h * 0.0 / gm;
+    const double tx = h * -ay / gm, ty = h * ax / gm, tz = h * 0.0 / gm;
     const double t2 = tx * tx + ty * ty + tz * tz;
     const double sx = 2.0 * tx / (1.0 + t2), sy = 2.0 * ty / (1.0 + t2), sz = 2.0 * tz / (1.0 + t2);
     const double upx = umx + (umy * tz - umz * ty);
@@ -205,7 +215,7 @@ __device__ inline void push_one(const DevState& s, const RunConst& rc, int64_t g
     // M (gamma_new - gamma_old) = Z dt E.(u_old + u_new)/(gamma_old + gamma_new), linear in E
     const double cc = cp.weight * (double)zc * rc.dt / (go + gn);
     const double sx = uox + unx, sy = uoy + uny, sz = uoz + unz;
-    s.wl[g] = p.wl + cc * (a * sx + 0.0 * sy + 0.0 * sz);
+    s.wl[g] = p.wl + cc * (ax * sx + ay * sy + 0.0 * sz);
     s.wc[g] = p.wc + cc * (ecx * sx + ecy * sy + ecz * sz);
   }
   if (diag) s.kebar[g] = cp.weight * M * 0.5 * (gm1(uox, uoy, uoz) + gm1(unx, uny, unz));
@@ -286,8 +296,8 @@ __global__ __launch_bounds__(kBlock) void k_start_kick(DevState s, RunConst rc, 
   if (g - cp.off >= d.n_cur) return;
   double ecx, ecy, ecz;
   field_sum(s, rc, fl, g, ecx, ecy, ecz);
-  double a;
-  laser_at(cp, d, rc.t0, s.z[g], a);
+  double ax, ay;
+  laser_at(cp, d, rc.t0, s.z[g], ax, ay);
   const int zc = s.Z[g];
   const double M = (zc < 0) ? 1.0 : cp.mass_ion;
   double ux = s.ux[g], uy = s.uy[g], uz = s.uz[g];
@@ -295,10 +305,10 @@ __global__ __launch_bounds__(kBlock) void k_start_kick(DevState s, RunConst rc, 
     const double h = 0.5 * ((double)zc / M) * rc.dt;
     const double gg = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
     const double vx = ux / gg, vy = uy / gg, vz = uz / gg;
-    // B = (0, a, 0)
-    const double fx = (ecx + a) + (vy * 0.0 - vz * a);
-    const double fy = ecy + (vz * 0.0 - vx * 0.0);
-    const double fz = ecz + (vx * a - vy * 0.0);
+    // E_L = (ax, ay, 0), B = (-ay, ax, 0)
+    const double fx = (ecx + ax) + (vy * 0.0 - vz * ax);
+    const double fy = (ecy + ay) + (vz * -ay - vx * 0.0);
+    const double fz = ecz + (vx * ax - vy * -ay);
     ux -= h * fx;
     uy -= h * fy;
     uz -= h * fz;
@@ -453,7 +463,10 @@ __global__ __launch_bounds__(kBlock) void k_ionize_check(DevState s, RunConst rc
         double ex, ey, ez;
         field_sum(s, rc, fl, g, ex, ey, ez);
         ex += d.laser_e;
+        ey += d.laser_ey;
         F = sqrt(ex * ex + ey * ey + ez * ez);
+      } else if (cp.polarization == LC_CIRCULAR) {
+        F = sqrt(d.laser_e * d.laser_e + d.laser_ey * d.laser_ey);
       } else {
         F = fabs(d.laser_e);
       }

@@ -22,7 +22,8 @@ def descs(clusters, weight=None):
         out.append(lc.make_cluster(SPECIES[c.species], c.r0_nm, c.n_ion, c.capacity, c.laser.intensity_wcm2,
                                    envelope=c.laser.envelope, fwhm_fs=c.laser.fwhm_fs, n_cycles=c.laser.n_cycles,
                                    phase=c.laser.phase, weight=0.0 if weight is None else weight, z_max=c.z_max,
-                                   electron_offset_nm=c.electron_offset_nm, n_steps=0))
+                                   electron_offset_nm=c.electron_offset_nm, n_steps=0,
+                                   polarization=c.laser.polarization))
     return out
 
 

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_version_and_error_strings():
     L = lc.lib()
-    assert L.lc_version() == 1
+    assert L.lc_version() == 2
     for code in [0, -1, -2, -3, -4, -5, -6]:
         assert L.lc_error_string(code)
     assert L.lc_error_string(0).decode() == "ok"
@@ -89,7 +89,8 @@ def test_invalid_config_rejected(field, value):
 
 
 @pytest.mark.parametrize("field,value", [("capacity", 100), ("z_max", 16), ("z_max", -1), ("r0_nm", 0.0),
-                                         ("envelope", 9), ("n_ion", -1), ("fwhm_fs", 0.0)])
+                                         ("envelope", 9), ("n_ion", -1), ("fwhm_fs", 0.0), ("polarization", 2),
+                                         ("polarization", -1)])
 def test_invalid_cluster_rejected(field, value):
     c, run = small_ar()
     d = _desc(c)

@@ -334,3 +334,64 @@ def test_xe_full_size_first_step():
     dx, du = _compare_state(sim, osim, r0n, 1e-12, 1e-9)
     print(f"xe first step: N={osim.N} dx={dx:.2e} du={du:.2e}", flush=True)
     assert dx <= 1e-12 and du <= 1e-9
+
+
+# Circular polarization (Eqs.(4)-(9) with phi_E = 3 pi/2, phi_B = pi/2) on the small argon
+# cluster, same FP64 tolerances as the linear case: laser-only and local ADK field in the
+# dipole approximation (ionization on), and the plane-wave test mode (ionization off).
+CIRC_CASES = [("dipole", "laser_only", None), ("dipole", "local", None),
+              ("dipole", "laser_only", dict(R=4, WJ=4, newton3=1)), ("plane_wave", "laser_only", None)]
+
+
+@pytest.mark.parametrize("phase,ofi,tiling", CIRC_CASES)
+def test_circular_small_ar_fp64(phase, ofi, tiling):
+    import dataclasses
+    import paper_1307_3711_amd as lc
+    c, run = small_ar()
+    c = dataclasses.replace(c, laser=dataclasses.replace(c.laser, polarization="circular", phase=phase))
+    run = dataclasses.replace(run, ofi_field=ofi, ionize=(phase == "dipole"))
+    mpb = lc.pair_blocks_for([c.capacity]) if tiling else 0
+    sim, states = gpu_run([c], run, "fp64", tuning=tiling, max_pair_blocks=mpb)
+    osim = oracle_run(c, run, states[0])
+    print(f"circular {phase} {ofi} {tiling}: 200 steps", flush=True)
+    sim.step(200)
+    rg = sim.diagnostics(0)
+    ro = osim.run(200)
+    r0n = units.nm_to_norm(c.r0_nm, 0.8)
+    dx, du = _compare_state(sim, osim, r0n, 1e-9, 1e-9)
+    print(f"max|dx|/R0 = {dx:.3e}  max|du|/max|u| = {du:.3e}  events gpu={rg[-1][21]} oracle={ro[-1][21]}")
+    assert dx <= 1e-9 and du <= 1e-9
+    _compare_records(rg, ro, ENERGY_COLS, 1e-10)
+    assert np.array_equal(rg[:, 21], ro[:, 21]) and np.array_equal(rg[:, 24:41], ro[:, 24:41])
+    if phase == "dipole" and ofi == "laser_only":
+        assert ro[-1][21] > 0  # the check ran with a field that ionizes
+
+
+def test_circular_orbit_on_gpu():
+    """One electron started on u = a (cos t, sin t, 0) in the circular dipole field stays on
+    it (the exact orbit, v parallel to B); at dt = 0.05 over t = 20 the Boris error is ~dt^2."""
+    import paper_1307_3711_amd as lc
+    from workloads.species import SPECIES
+    a, t0, dt = 1.0, 0.3, 0.05
+    lam = 0.8
+    inten = (a / lc.units(lam, 1e16)["a0"]) ** 2 * 1e16  # intensity whose a0 is a
+    cfg = lc.make_config("fp64", ionize=False, dt=dt, t0=t0, diag_every=0)
+    d = lc.make_cluster(SPECIES["Ar"], 1.0, 0, 1, inten, envelope="flat", weight=1.0, polarization="circular")
+    sim = lc.Simulation(cfg, [d])
+    assert lc.units(lam, inten)["a0"] == pytest.approx(a, rel=1e-12)
+    sim.init_from_host(0, np.zeros((1, 3)), np.array([[a * math.cos(t0), a * math.sin(t0), 0.0]]),
+                       np.array([-1], np.int8))
+    sim.start()
+    nst = 400
+    sim.step(nst)
+    g = sim.particles(0)
+    t = t0 + nst * dt
+    th = t - dt / 2
+    gam = math.sqrt(1 + a * a)
+    ue = np.array([a * math.cos(th), a * math.sin(th), 0.0])
+    xe = (a / gam) * np.array([math.sin(t) - math.sin(t0), math.cos(t0) - math.cos(t), 0.0])
+    eu = np.max(np.abs(g["u"][0] - ue))
+    ex = np.max(np.abs(g["x"][0] - xe))  # positions in c/w
+    print(f"circular orbit: |du| = {eu:.3e}, |dx| = {ex:.3e}", flush=True)
+    assert eu < 5e-4 and ex < 2e-3
+    sim.close()
