@@ -11,6 +11,7 @@ docstring).  The absolute physics outputs the paper plots (ion energy spectra, c
 fractions) are not available, so agreement with the paper's figures is not pinned.
 """
 import ctypes
+import math
 import os
 import subprocess
 
@@ -49,6 +50,10 @@ def build(force=False):
     return _LIB
 
 
+DET_BINS = 120                # ion energy histogram: 20 bins per decade, 1 eV .. 1 MeV
+DET_SLOTS = DET_BINS + 2      # plus underflow and overflow
+
+
 class Params(ctypes.Structure):
     _fields_ = [
         ("dt", ctypes.c_double), ("t0", ctypes.c_double), ("eps2", ctypes.c_double),
@@ -64,6 +69,11 @@ class Params(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("cluster", ctypes.c_uint64), ("n_ion", ctypes.c_int64),
         ("polarization", ctypes.c_int32), ("pad", ctypes.c_int32),
     ]
+
+
+class Detector(ctypes.Structure):
+    _fields_ = [("r2", ctypes.c_double), ("cos2", ctypes.c_double), ("edges", ctypes.c_double * (DET_BINS + 1)),
+                ("counts", ctypes.POINTER(ctypes.c_int64)), ("seen", ctypes.POINTER(ctypes.c_int8))]
 
 
 _lib_handle = None
@@ -94,8 +104,11 @@ def lib():
         L.or_start.argtypes = [pp, ctypes.c_int64, dp, dp, dp, dp, dp, dp, i8p, dp]
         L.or_start.restype = ctypes.c_double
         L.or_run.argtypes = [pp, ctypes.c_int64, i64p, dp, dp, dp, dp, dp, dp, i8p, dp, dp, dp,
-                             ctypes.c_int64, ctypes.c_int64, dp, dp, dp, ctypes.c_int64]
+                             ctypes.c_int64, ctypes.c_int64, dp, dp, dp, ctypes.c_int64, ctypes.POINTER(Detector)]
         L.or_run.restype = ctypes.c_int64
+        L.or_detector_init.argtypes = [ctypes.POINTER(Detector), ctypes.c_double, ctypes.c_double]
+        L.or_detector_init.restype = None
+        L.or_det_slots.restype = ctypes.c_int
         L.or_state_field.argtypes = [pp, ctypes.c_int64, dp, dp, dp, i8p, dp, dp, dp, dp, dp]
         L.or_threads.restype = ctypes.c_int
         _lib_handle = L
@@ -247,12 +260,32 @@ class Sim:
         self.counters = np.zeros(2)
         self.step_index = 0
         self.ke_start = None
+        self.det = None
+        self.r0_norm = None
 
     @classmethod
     def from_workload(cls, cluster, run, state, cluster_index=0, **override):
         p = make_params(cluster, run, cluster_index, **override)
         x = units.nm_to_norm(np.asarray(state["x_nm"], np.float64), cluster.laser.lambda_um)
-        return cls(p, cluster.capacity, x, np.asarray(state["u"], np.float64), state["Z"])
+        sim = cls(p, cluster.capacity, x, np.asarray(state["u"], np.float64), state["Z"])
+        sim.r0_norm = units.nm_to_norm(cluster.r0_nm, cluster.laser.lambda_um)
+        return sim
+
+    def enable_detectors(self, distance, half_angle_deg=30.0):
+        """Ion detectors at `distance` (c/w) from the centre on the x, y and z axes with the given
+        acceptance half-angle; counts accumulate over every later step."""
+        self.det_counts = np.zeros((4, DET_SLOTS), np.int64)
+        self.det_seen = np.zeros(self.cap, np.int8)
+        d = Detector()
+        lib().or_detector_init(ctypes.byref(d), float(distance), math.radians(half_angle_deg))
+        d.counts = self.det_counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        d.seen = self.det_seen.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
+        self.det = d
+
+    def iedf(self):
+        """Detector counts (4 x DET_SLOTS int64: every ion, then the x, y and z axes; slot 0 is
+        below the first edge, slot DET_BINS + 1 at or above the last) and the bin edges in eV."""
+        return self.det_counts.copy(), np.array(self.det.edges[:])
 
     def start(self):
         """Leap-frog start (backward half kick); returns KE at t0 - dt/2."""
@@ -273,7 +306,7 @@ class Sim:
                          _dp(self.x[1]), _dp(self.x[2]), _dp(self.u[0]), _dp(self.u[1]),
                          _dp(self.u[2]), self.Z.ctypes.data_as(i8p), _dp(self.wl), _dp(self.wc),
                          _dp(self.wsp), self.step_index, nsteps, _dp(self.work), _dp(self.counters),
-                         _dp(rec), max_rec)
+                         _dp(rec), max_rec, ctypes.byref(self.det) if self.det is not None else None)
         self.step_index += nsteps
         return rec[:k]
 

@@ -21,6 +21,8 @@
  *   or_adk_rate       - ADK tunnelling rate (cited in Sec. II; standard l = m = 0 form).
  *   ionization        - Monte-Carlo test P = 1 - exp(-nu dt) against alpha in (0,1]
  *                       (Sec. II), electron spawned next to the ion.
+ *   or_detect         - ion detectors and the time-integrated ion energy distribution
+ *                       (Sec. III anisotropy study: detectors at 9 R0, 30 degree acceptance).
  *   or_philox4x64_10  - Philox4x64-10 counter-based generator (Salmon et al., SC'11).
  */
 #include <math.h>
@@ -368,12 +370,63 @@ static void or_record(const or_params* p, int64_t step, int64_t n, const double*
   rec[22] = or_envelope(p, t);
 }
 
+/* ------------------------------------------------------------------ detectors */
+/* Ion detectors of the paper's anisotropy study (Sec. III): detectors at a distance D from
+ * the cluster centre on the +-x (laser polarization), +-y and +-z axes; an ion is counted
+ * once, at the first step its distance from the centre reaches D, by the detectors of every
+ * axis whose direction its position vector makes an angle below the acceptance half-angle
+ * with.  The time-integrated ion energy distribution is the histogram of the kinetic energy
+ * of one real ion, M (gamma - 1) m_e c^2 in eV, at that step: 20 log-spaced bins per decade
+ * from 1 eV to 1 MeV plus an underflow and an overflow bin, counted in macro-ions. */
+#define OR_DET_BINS 120
+#define OR_DET_SLOTS (OR_DET_BINS + 2)
+
+typedef struct {
+  double r2;                      /* D^2 ((c/w)^2)                                   */
+  double cos2;                    /* cos^2 of the acceptance half-angle              */
+  double edges[OR_DET_BINS + 1];  /* bin edges in eV                                 */
+  int64_t* counts;                /* [4][OR_DET_SLOTS]: every ion, then the x, y, z axes */
+  int8_t* seen;                   /* per index: 1 once counted                       */
+} or_detector;
+
+void or_detector_init(or_detector* d, double dist, double half_angle) {
+  d->r2 = dist * dist;
+  double c = cos(half_angle);
+  d->cos2 = c * c;
+  for (int k = 0; k <= OR_DET_BINS; ++k) d->edges[k] = pow(10.0, (double)k / 20.0);
+}
+
+/* Slot of energy e: the number of edges not above it (0 underflow, OR_DET_BINS + 1 overflow). */
+static int or_det_slot(const or_detector* d, double e) {
+  int k = 0;
+  while (k <= OR_DET_BINS && d->edges[k] <= e) ++k;
+  return k;
+}
+
+static void or_detect(const or_params* p, const or_detector* d, const double* x, const double* y,
+                      const double* z, const double* ux, const double* uy, const double* uz,
+                      const int8_t* Z) {
+  for (int64_t i = 0; i < p->n_ion; ++i) {
+    if (Z[i] <= 0 || d->seen[i]) continue;
+    double r2 = x[i] * x[i] + y[i] * y[i] + z[i] * z[i];
+    if (r2 < d->r2) continue;
+    d->seen[i] = 1;
+    double ev = or_mass(p, Z[i]) * or_gm1(ux[i], uy[i], uz[i]) * p->mec2_ev;
+    int slot = or_det_slot(d, ev);
+    d->counts[slot] += 1;
+    double c[3] = {x[i], y[i], z[i]};
+    for (int a = 0; a < 3; ++a)
+      if (c[a] * c[a] > d->cos2 * r2) d->counts[(a + 1) * OR_DET_SLOTS + slot] += 1;
+  }
+}
+
 /* One time step n (absolute index).  Field at x^n, laser at t^n = t0 + n dt, Boris push to
  * u^{n+1/2}, x^{n+1}, work split W_L / W_C, optional record, then the ionization check of
  * every ion in ascending index.  Returns the number of records written (0 or 1). */
 static int or_step(const or_params* p, int64_t step, int64_t cap, int64_t* n_io, double* x, double* y,
                    double* z, double* ux, double* uy, double* uz, int8_t* Z, double* wl, double* wc,
-                   double* wsp, const or_scratch* s, double* dropped, double* events, double* rec) {
+                   double* wsp, const or_scratch* s, double* dropped, double* events, double* rec,
+                   const or_detector* det) {
   int64_t n = *n_io;
   double t = p->t0 + (double)step * p->dt;
   int diag = (p->diag_every > 0) && (step % p->diag_every == 0);
@@ -411,6 +464,8 @@ static int or_step(const or_params* p, int64_t step, int64_t cap, int64_t* n_io,
     y[i] += p->dt * un[1] / gn;
     z[i] += p->dt * un[2] / gn;
   }
+
+  if (det) or_detect(p, det, x, y, z, ux, uy, uz, Z);
 
   int wrote = 0;
   if (diag && rec) {
@@ -471,13 +526,14 @@ static int or_step(const or_params* p, int64_t step, int64_t cap, int64_t* n_io,
   return wrote;
 }
 
-/* Run steps [step0, step0 + nsteps).  work must hold 8*cap doubles.  Records go to rec
+/* Run steps [step0, step0 + nsteps), counting detected ions in det unless it is NULL.  work
+ * must hold 8*cap doubles.  Records go to rec
  * (OR_REC doubles each, at most max_rec); returns the number written.  counters[0] holds
  * dropped spawns and counters[1] ionization events, both carried across calls. */
 int64_t or_run(const or_params* p, int64_t cap, int64_t* n_io, double* x, double* y, double* z,
                double* ux, double* uy, double* uz, int8_t* Z, double* wl, double* wc, double* wsp,
                int64_t step0, int64_t nsteps, double* work, double* counters, double* rec,
-               int64_t max_rec) {
+               int64_t max_rec, const or_detector* det) {
   or_scratch s;
   s.q = work;
   s.ex = work + cap;
@@ -491,7 +547,7 @@ int64_t or_run(const or_params* p, int64_t cap, int64_t* n_io, double* x, double
   for (int64_t k = 0; k < nsteps; ++k) {
     double* r = (rec && nrec < max_rec) ? rec + nrec * OR_REC : NULL;
     nrec += or_step(p, step0 + k, cap, n_io, x, y, z, ux, uy, uz, Z, wl, wc, wsp, &s, &counters[0],
-                    &counters[1], r);
+                    &counters[1], r, det);
   }
   return nrec;
 }
@@ -506,3 +562,4 @@ void or_state_field(const or_params* p, int64_t n, const double* x, const double
 int or_record_size(void) { return OR_REC; }
 int or_threads(void) { return omp_get_max_threads(); }
 int or_max_z(void) { return OR_MAX_Z; }
+int or_det_slots(void) { return OR_DET_SLOTS; }

@@ -463,3 +463,94 @@ def test_record_counts_consistent():
     natoms = units.n_atoms(c.r0_nm, 2.40)
     assert r[oracle.R_ABS_EV] == pytest.approx(r[oracle.R_WL] * units.MEC2_EV / natoms, rel=1e-14)
     assert r[oracle.R_T] == pytest.approx(run.t0 + r[oracle.R_STEP] * run.dt, rel=1e-15)
+
+
+def _d_ion_u(ev):
+    """Momentum u = gamma v of a deuteron with kinetic energy ev (50 digits)."""
+    from workloads.species import SPECIES
+    m = mpmath.mpf(SPECIES["D"]["mass_u"]) * mpmath.mpf(units.U_PER_ME)
+    g = 1 + mpmath.mpf(ev) / (m * mpmath.mpf(units.MEC2_EV))
+    return float(mpmath.sqrt(g * g - 1))
+
+
+def test_detectors_free_streaming():
+    """Ion detectors (Sec. III anisotropy study): with no forces every ion streams at its start
+    momentum, so each one crossing the detector distance D is counted once, at its exact
+    start energy, by the axes whose direction its path makes an angle below 30 degrees with;
+    ions that never reach D and electrons are not counted.  Energies sit mid-bin."""
+    c = Cluster(species="D", r0_nm=1.0, n_ion=8, capacity=9, z_init=1, laser=Laser(envelope="flat"))
+    run = Run(dt=0.5, ionize=False, diag_every=0)
+    deg = math.pi / 180
+    # (direction, kinetic energy in eV, expected axes)
+    ions = [((math.cos(29 * deg), math.sin(29 * deg), 0.0), 150.0, {0}),
+            ((math.cos(31 * deg), -math.sin(31 * deg), 0.0), 3.1e3, set()),
+            ((math.sin(29 * deg), -math.cos(29 * deg), 0.0), 47e3, {1}),
+            ((0.0, math.sin(20 * deg), math.cos(20 * deg)), 830e3, {2}),
+            ((-1.0, 0.0, 0.0), 2.2e6, {0}),
+            ((0.0, 0.0, -1.0), 0.55, {2}),
+            ((1 / math.sqrt(3), 1 / math.sqrt(3), 1 / math.sqrt(3)), 12e3, set())]
+    x = np.zeros((9, 3))
+    u = np.zeros((9, 3))
+    Z = np.ones(9, np.int8)
+    for i, (d, ev, _) in enumerate(ions):
+        x[i] = 0.3e-3 * np.array(d)
+        u[i] = _d_ion_u(ev) * np.array(d)
+    x[7] = (0.0, 0.02, 0.0)          # ion at rest inside D: never reaches it
+    x[8] = (0.001, 0.0, 0.0)         # electron moving out along x: not an ion
+    u[8] = (0.05, 0.0, 0.0)
+    Z[8] = -1
+    p = oracle.make_params(c, run, weight=1.0)
+    p.kappa = 0.0
+    p.a0 = 0.0
+    sim = oracle.Sim(p, 9, x, u, Z)
+    D = 0.025
+    sim.enable_detectors(D, 30.0)
+    sim.start()
+    sim.run(8000)  # the slowest ion (0.55 eV) needs about 7000 steps
+    counts, edges = sim.iedf()
+    assert counts[0].sum() == 7 and sim.det_seen[7] == 0 and sim.det_seen[8] == 0
+    want = np.zeros((4, oracle.DET_SLOTS), np.int64)
+    for d, ev, axes in ions:
+        slot = int(np.searchsorted(edges, ev, side="right"))
+        lo = edges[slot - 1] if slot > 0 else 0.0
+        hi = edges[slot] if slot <= oracle.DET_BINS else np.inf
+        assert lo * 1.02 < ev < hi / 1.02  # mid-bin: the slot does not depend on rounding
+        want[0, slot] += 1
+        for a in axes:
+            want[a + 1, slot] += 1
+    assert np.array_equal(counts, want)
+    assert counts[0, 0] == 1 and counts[0, oracle.DET_BINS + 1] == 1  # underflow and overflow
+
+
+def test_iedf_uniform_sphere_explosion():
+    """A uniform sphere of ions explodes with shells in order: a shell starting at r0 that
+    encloses N_enc ions has, on reaching the detectors at D = 9 R0, the kinetic energy
+    kappa Z^2 w N_enc (1/r0 - 1/D) per real ion.  The detected histogram matches these
+    energies of the same ions (Kolmogorov distance < 0.04), every ion is detected, and the
+    per-axis counts match the solid-angle fraction 1 - cos 30 deg of an isotropic explosion."""
+    n = 800
+    c = Cluster(species="D", r0_nm=3.0, n_ion=n, capacity=2 * n, z_init=1, laser=Laser(envelope="flat"))
+    run = Run(dt=2.0, ionize=False, diag_every=0, softening_nm=0.01)
+    st = initial_state(c, 9)
+    st = {"x_nm": st["x_nm"][:n], "u": st["u"][:n], "Z": st["Z"][:n], "n_ion": n}
+    sim = oracle.Sim.from_workload(c, run, st)
+    sim.p.a0 = 0.0
+    x0 = sim.positions().copy()
+    D = 9.0 * sim.r0_norm
+    sim.enable_detectors(D, 30.0)
+    sim.start()
+    sim.run(3000)
+    counts, edges = sim.iedf()
+    assert counts[0].sum() == n
+    r0 = np.linalg.norm(x0, axis=1)
+    nenc = np.empty(n)
+    nenc[np.argsort(r0)] = np.arange(n)
+    p = sim.p
+    e = p.kappa * p.weight * nenc * (1.0 / r0 - 1.0 / D) * p.mec2_ev
+    pred = np.bincount(np.searchsorted(edges, e, side="right"), minlength=oracle.DET_SLOTS)
+    ks = np.max(np.abs(np.cumsum(counts[0]) - np.cumsum(pred))) / n
+    assert ks < 0.04
+    f = 1.0 - math.cos(math.pi / 6)
+    sigma = math.sqrt(f * (1 - f) / n)
+    for a in range(3):
+        assert abs(counts[a + 1].sum() / n - f) < 4.5 * sigma
