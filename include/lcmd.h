@@ -35,9 +35,11 @@
 extern "C" {
 #endif
 
-#define LC_API_VERSION 2
+#define LC_API_VERSION 3
 #define LC_MAX_Z 16       /* size of the per-charge tables (charge states 0..15)        */
 #define LC_REC 48         /* doubles per diagnostic record                              */
+#define LC_DET_BINS 120   /* ion energy histogram: 20 log bins per decade, 1 eV .. 1 MeV */
+#define LC_DET_SLOTS (LC_DET_BINS + 2) /* the bins plus underflow and overflow         */
 
 typedef enum {
   LC_OK = 0,
@@ -100,6 +102,9 @@ typedef struct {
                           /*   24 M (LC_FP64) bytes per slot, slots rounded up to 512 per */
                           /*   cluster; 0: not available; not for LC_FP32_KAHAN          */
   uint64_t seed;          /* Philox key word 0 (word 1 is the cluster index)            */
+  double detector_r0;     /* ion detectors at this multiple of each cluster's R0 from   */
+                          /*   its centre (Sec. III anisotropy study: 9); 0: none       */
+  double detector_half_angle_deg; /* their acceptance half-angle, in (0, 90) (Sec. III: 30) */
 } lc_config;
 
 /* One cluster, in physical units.  Species data (Wigner-Seitz radius, mass, ionization
@@ -205,6 +210,21 @@ int lc_read_particles(lc_sim* sim, int32_t cluster, double* x, double* u, int8_t
  * (n_steps reached) is not part of the pass and its rows are not meaningful.  Synchronizes
  * the stream. */
 int lc_read_field(lc_sim* sim, int32_t cluster, double* E, int64_t cap, int64_t* n_out);
+
+/* Time-integrated ion energy distribution at the detectors of one cluster (the Sec. III
+ * anisotropy study: detectors at distance D = detector_r0 * R0 from the cluster centre on
+ * the x axis (laser polarization), the y axis and the z axis, both signs of each).  An ion
+ * is counted once, at the end of the first step whose push takes it to a distance >= D,
+ * with its kinetic energy M (gamma - 1) m_e c^2 (eV per real ion, momentum of that push);
+ * every axis whose direction its position makes an angle below the half-angle with counts
+ * it too.  counts (4 x LC_DET_SLOTS int64, host): row 0 every detected ion, rows 1..3 the
+ * x, y and z axes; slot 0 holds energies below edges[0], slot k (1 <= k <= LC_DET_BINS)
+ * energies in [edges[k-1], edges[k]), slot LC_DET_BINS + 1 energies >= edges[LC_DET_BINS].
+ * Counts are macro-ions (multiply by the cluster weight for real ions) and are exact
+ * integers, independent of scheduling.  edges_ev (LC_DET_BINS + 1 doubles, host) may be
+ * NULL; edge k is 10^(k/20) eV.  LC_E_STATE if the handle has no detectors.  Synchronizes
+ * the stream and returns a latched device error if one occurred. */
+int lc_read_iedf(lc_sim* sim, int32_t cluster, int64_t* counts, double* edges_ev);
 
 /* Current time-step index (host mirror of the device counter). */
 int64_t lc_step_index(const lc_sim* sim);

@@ -15,6 +15,8 @@ LIB_PATH = os.path.join(_HERE, "liblcmd.so")
 
 LC_MAX_Z = 16
 LC_REC = 48
+LC_DET_BINS = 120
+LC_DET_SLOTS = LC_DET_BINS + 2
 
 LC_OK, LC_E_INVALID, LC_E_CAPACITY, LC_E_NONFINITE, LC_E_HIP, LC_E_STATE, LC_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 PRECISIONS = {"fp64": 0, "fp32_acc64": 1, "fp32_kahan": 2}
@@ -42,7 +44,7 @@ class Config(ctypes.Structure):
         ("ofi_field", ctypes.c_int32), ("lambda_um", ctypes.c_double), ("dt", ctypes.c_double),
         ("t0", ctypes.c_double), ("softening_nm", ctypes.c_double), ("diag_every", ctypes.c_int32),
         ("max_records", ctypes.c_int32), ("max_splits", ctypes.c_int32), ("max_pair_blocks", ctypes.c_int32),
-        ("seed", ctypes.c_uint64),
+        ("seed", ctypes.c_uint64), ("detector_r0", ctypes.c_double), ("detector_half_angle_deg", ctypes.c_double),
     ]
 
 
@@ -113,6 +115,7 @@ def lib():
         "lc_read_diagnostics": ([vp, ctypes.c_int32, dp, ctypes.c_int32, i32p], ctypes.c_int),
         "lc_read_particles": ([vp, ctypes.c_int32, dp, dp, i8p, dp, dp, ctypes.c_int64, i64p], ctypes.c_int),
         "lc_read_field": ([vp, ctypes.c_int32, dp, ctypes.c_int64, i64p], ctypes.c_int),
+        "lc_read_iedf": ([vp, ctypes.c_int32, i64p, dp], ctypes.c_int),
         "lc_step_index": ([vp], ctypes.c_int64),
         "lc_cluster_counters": ([vp, ctypes.c_int32, dp], ctypes.c_int),
         "lc_time_particle_kernels": ([vp, ctypes.c_int32, dp], ctypes.c_int),
@@ -161,7 +164,8 @@ def units(lambda_um, intensity_wcm2=0.0):
 
 
 def make_config(precision="fp64", ionize=True, ofi_field="laser_only", lambda_um=0.8, dt=0.05, t0=0.0,
-                softening_nm=0.1, diag_every=10, max_records=1024, max_splits=32, seed=0, max_pair_blocks=0):
+                softening_nm=0.1, diag_every=10, max_records=1024, max_splits=32, seed=0, max_pair_blocks=0,
+                detector_r0=0.0, detector_half_angle_deg=30.0):
     c = Config()
     c.struct_size = ctypes.sizeof(Config)
     c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -170,6 +174,7 @@ def make_config(precision="fp64", ionize=True, ofi_field="laser_only", lambda_um
     c.lambda_um, c.dt, c.t0, c.softening_nm = lambda_um, dt, t0, softening_nm
     c.diag_every, c.max_records, c.max_splits, c.seed = diag_every, max_records, max_splits, seed
     c.max_pair_blocks = max_pair_blocks
+    c.detector_r0, c.detector_half_angle_deg = detector_r0, detector_half_angle_deg
     return c
 
 
@@ -284,6 +289,15 @@ class Simulation:
         _check(lib().lc_read_field(self.h, cluster, E.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), cap,
                                    ctypes.byref(n)), self.h)
         return E[:n.value]
+
+    def iedf(self, cluster=0):
+        """Detector counts (4 x LC_DET_SLOTS int64: every detected ion, then the x, y and z axes)
+        and the LC_DET_BINS + 1 energy bin edges in eV (lc_read_iedf)."""
+        counts = np.zeros((4, LC_DET_SLOTS), np.int64)
+        edges = np.zeros(LC_DET_BINS + 1)
+        _check(lib().lc_read_iedf(self.h, cluster, counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                  edges.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), self.h)
+        return counts, edges
 
     def time_particle_kernels(self, reps=20):
         """Average ms of the push kernel and of the ionization kernels (lc_time_particle_kernels)."""

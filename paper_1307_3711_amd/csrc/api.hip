@@ -60,7 +60,7 @@ int64_t n3_round(int64_t cap) { return (cap + 511) / 512 * 512; }
 
 struct Layout {
   size_t x, y, z, ux, uy, uz, wl, wc, wsp, kebar, pos4, posq, Z, cid, part, n3part, flag, ib_count, ib_cluster;
-  size_t cp, dyn, order, tile_start, tile_total, queue, err, step, diag_part, records, total;
+  size_t cp, dyn, order, tile_start, tile_total, queue, det_seen, det_counts, det_edges, err, step, diag_part, records, total;
   int64_t n_total;
   int n_ion_blocks;
 };
@@ -80,6 +80,11 @@ bool valid_config(const lc_config* cfg, std::string* why) {
   if (cfg->max_pair_blocks > 0 && cfg->precision == LC_FP32_KAHAN) { *why = "no pair-once kernel for LC_FP32_KAHAN"; return false; }
   if (cfg->ionize != 0 && cfg->ionize != 1) { *why = "ionize must be 0 or 1"; return false; }
   if (cfg->ofi_field != LC_LASER_ONLY && cfg->ofi_field != LC_LOCAL) { *why = "unknown ofi_field"; return false; }
+  if (!(cfg->detector_r0 >= 0.0) || !std::isfinite(cfg->detector_r0)) { *why = "detector_r0 must be >= 0"; return false; }
+  if (cfg->detector_r0 > 0.0 && !(cfg->detector_half_angle_deg > 0.0 && cfg->detector_half_angle_deg < 90.0)) {
+    *why = "detector_half_angle_deg must be in (0, 90)";
+    return false;
+  }
   return true;
 }
 
@@ -136,6 +141,9 @@ Layout make_layout(const lc_config* cfg, const lc_cluster* cl, int C) {
   L.tile_start = take(sizeof(int32_t) * (C + 1));
   L.tile_total = take(sizeof(int32_t));
   L.queue = take(sizeof(int32_t));
+  L.det_seen = take((size_t)NT);
+  L.det_counts = take(sizeof(unsigned long long) * (size_t)C * 4 * LC_DET_SLOTS);
+  L.det_edges = take(sizeof(double) * (LC_DET_BINS + 1));
   L.err = take(sizeof(int32_t));
   L.step = take(sizeof(int64_t));
   L.diag_part = take(sizeof(double) * (size_t)C * kDiagBlocks * kDiagQ);
@@ -412,6 +420,9 @@ int lc_create(lc_sim** out, const lc_config* cfg, const lc_cluster* clusters, in
   d.cp = (ClusterParams*)(b + L.cp); d.dyn = (ClusterDyn*)(b + L.dyn);
   d.order = (int32_t*)(b + L.order); d.tile_start = (int32_t*)(b + L.tile_start);
   d.tile_total = (int32_t*)(b + L.tile_total); d.queue = (int32_t*)(b + L.queue);
+  d.det_seen = (int8_t*)(b + L.det_seen);
+  d.det_counts = (unsigned long long*)(b + L.det_counts);
+  d.det_edges = (double*)(b + L.det_edges);
   d.err = (int32_t*)(b + L.err); d.step = (int64_t*)(b + L.step);
   d.diag_part = (double*)(b + L.diag_part); d.records = (double*)(b + L.records);
 
@@ -429,6 +440,11 @@ int lc_create(lc_sim** out, const lc_config* cfg, const lc_cluster* clusters, in
   rc.n3_rows = cfg->max_pair_blocks;
   rc.n_total = L.n_total;
   rc.mec2_ev = kMec2Ev;
+  rc.det_on = cfg->detector_r0 > 0.0 ? 1 : 0;
+  if (rc.det_on) {
+    const double ca = std::cos(cfg->detector_half_angle_deg * (M_PI / 180.0));
+    rc.det_cos2 = ca * ca;
+  }
 
   // Per-cluster tables.
   std::vector<ClusterParams> cps(n_clusters);
@@ -440,6 +456,10 @@ int lc_create(lc_sim** out, const lc_config* cfg, const lc_cluster* clusters, in
     ClusterParams p{};
     p.off = off;
     p.n3_off = n3_off;
+    if (rc.det_on) {
+      const double dist = cfg->detector_r0 * (k.r0_nm * 1e-9 * s->u.k);
+      p.det_r2 = dist * dist;
+    }
     n3_off += 3 * (int64_t)cfg->max_pair_blocks * n3_round(k.capacity);
     p.cap = k.capacity;
     p.n_ion = k.n_ion;
@@ -499,11 +519,21 @@ int lc_create(lc_sim** out, const lc_config* cfg, const lc_cluster* clusters, in
   if (e == hipSuccess) e = hipMemcpy(d.err, &zero32, sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d.queue, &zero32, sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) {
+    // detector histogram edges 10^(k/20) eV and zero counts (ions are seen once per run)
+    std::vector<double> edges(LC_DET_BINS + 1);
+    for (int k = 0; k <= LC_DET_BINS; ++k) edges[k] = std::pow(10.0, (double)k / 20.0);
+    e = hipMemcpy(d.det_edges, edges.data(), sizeof(double) * edges.size(), hipMemcpyHostToDevice);
+    std::vector<unsigned long long> zc((size_t)n_clusters * 4 * LC_DET_SLOTS, 0ull);
+    if (e == hipSuccess)
+      e = hipMemcpy(d.det_counts, zc.data(), sizeof(unsigned long long) * zc.size(), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) {
     const int64_t NT = L.n_total;
     const int nb = (int)((NT + kBlock - 1) / kBlock);
     double* dz[] = {d.x, d.y, d.z, d.ux, d.uy, d.uz, d.wl, d.wc, d.wsp, d.kebar};
     for (double* p : dz) k_fill_f64<<<nb, kBlock, 0, s->stream>>>(p, NT, 0.0);
     k_fill_i8<<<nb, kBlock, 0, s->stream>>>(d.Z, NT, 0);
+    k_fill_i8<<<nb, kBlock, 0, s->stream>>>(d.det_seen, NT, 0);
     k_fill_i32<<<nb, kBlock, 0, s->stream>>>(d.flag, NT, 0);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -693,6 +723,22 @@ int lc_read_diagnostics(lc_sim* s, int32_t cluster, double* records, int32_t max
     }
   }
   *n_out = (int32_t)take;
+  return latched_error(s);
+}
+
+int lc_read_iedf(lc_sim* s, int32_t cluster, int64_t* counts, double* edges_ev) {
+  if (!s || !counts) return LC_E_INVALID;
+  if (cluster < 0 || cluster >= s->C) return fail(s, LC_E_INVALID, "cluster index out of range");
+  if (!s->rc.det_on) return fail(s, LC_E_STATE, "lc_read_iedf: the handle has no detectors (detector_r0 = 0)");
+  hipError_t e = hipStreamSynchronize(s->stream);
+  std::vector<unsigned long long> h(4 * LC_DET_SLOTS);
+  if (e == hipSuccess)
+    e = hipMemcpy(h.data(), s->s.det_counts + (size_t)cluster * 4 * LC_DET_SLOTS, sizeof(unsigned long long) * h.size(),
+                  hipMemcpyDeviceToHost);
+  if (e == hipSuccess && edges_ev)
+    e = hipMemcpy(edges_ev, s->s.det_edges, sizeof(double) * (LC_DET_BINS + 1), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(s, e, "lc_read_iedf");
+  for (size_t k = 0; k < h.size(); ++k) counts[k] = (int64_t)h[k];
   return latched_error(s);
 }
 

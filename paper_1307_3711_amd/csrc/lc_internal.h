@@ -53,7 +53,8 @@ struct ClusterParams {
   int32_t ion_block0;   // first entry of this cluster in the ion-block table
   int32_t n_ion_blocks;
   int32_t polarization;  // LC_LINEAR_X or LC_CIRCULAR
-  int64_t n3_off;       // first float of this cluster's pair-once partial rows (see force.hip)
+  int64_t n3_off;
+  double det_r2;        // squared detector distance (c/w)^2 (detectors on)       // first float of this cluster's pair-once partial rows (see force.hip)
 };
 
 // Per-cluster dynamic state, written by the kernels.
@@ -90,6 +91,9 @@ struct RunConst {
   int32_t n3_rows;      // M: partial rows per target block of the pair-once kernel (0: none)
   int64_t n_total;      // total slots (sum of capacities)
   double mec2_ev;       // electron rest energy (eV) for the absorbed-energy column
+  int32_t det_on;       // ion detectors present
+  int32_t pad;
+  double det_cos2;      // cos^2 of the detectors' acceptance half-angle
 };
 
 // Pointers into the caller-owned state.
@@ -119,6 +123,9 @@ struct DevState {
   int32_t* tile_start;  // [n_clusters + 1] first tile of each order position this step
   int32_t* tile_total;  // tiles this step
   int32_t* queue;       // persistent-kernel work counter
+  int8_t* det_seen;     // 1 once an ion has been counted by the detectors [slot]
+  unsigned long long* det_counts;  // [cluster][4][LC_DET_SLOTS] detected macro-ions
+  double* det_edges;    // LC_DET_BINS + 1 energy bin edges (eV)
   int32_t* err;         // latched error flags
   int64_t* step;        // absolute index of the current step group's first step
   double* diag_part;    // [cluster][kDiagBlocks][kDiagQ]

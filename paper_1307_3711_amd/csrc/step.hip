@@ -173,6 +173,30 @@ __device__ inline PState load_pstate(const DevState& s, int64_t g) {
   return p;
 }
 
+// Ion detectors (Sec. III anisotropy study): an ion is counted once, when a push first takes it
+// to the detector distance, in the energy slot of M (gamma - 1) m_e c^2 (eV per real ion) for
+// every ion and for each axis whose direction its position is within the acceptance cone of.
+// Counts are integers (order-independent atomics); the slot is the number of edges <= E.
+__device__ inline void detect_ion(const DevState& s, const RunConst& rc, const ClusterParams& cp, int c, int64_t g,
+                                  double x, double y, double z, double M, double ux, double uy, double uz) {
+  if (s.det_seen[g]) return;
+  const double r2 = x * x + y * y + z * z;
+  if (r2 < cp.det_r2) return;
+  s.det_seen[g] = 1;
+  const double ev = M * gm1(ux, uy, uz) * rc.mec2_ev;
+  int lo = 0, hi = LC_DET_BINS + 1;  // first edge index with edges[k] > ev, in [0, LC_DET_BINS + 1]
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (s.det_edges[mid] <= ev) lo = mid + 1;
+    else hi = mid;
+  }
+  unsigned long long* h = s.det_counts + (size_t)c * 4 * LC_DET_SLOTS + lo;
+  atomicAdd(h, 1ull);
+  const double cc[3] = {x, y, z};
+  for (int a = 0; a < 3; ++a)
+    if (cc[a] * cc[a] > rc.det_cos2 * r2) atomicAdd(h + (a + 1) * LC_DET_SLOTS, 1ull);
+}
+
 // Relativistic Boris step of live particle g (cluster c) at step index n in the Coulomb field
 // (ecx, ecy, ecz) from state p: u^{n-1/2} -> u^{n+1/2}, x^n -> x^{n+1}, with the exact discrete work split
 // W_L / W_C, optional KE(n) for the diagnostics, and the refresh of the source record the next
@@ -227,6 +251,7 @@ __device__ inline void push_one(const DevState& s, const RunConst& rc, int64_t g
   write_source(s, PREC, g, x, y, z, cp.kw * (double)zc);
   if (!(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(unx) && isfinite(uny) && isfinite(unz)))
     atomicOr(s.err, kFlagNonfinite);
+  if (rc.det_on && zc > 0) detect_ion(s, rc, cp, c, g, x, y, z, M, unx, uny, unz);  // only ion slots hold Z > 0
 }
 
 template <int PREC>
