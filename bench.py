@@ -13,6 +13,7 @@ sample of the same workload on this host's cores.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -232,7 +233,8 @@ def bench_particles(args):
     nc = args.clusters if args.clusters != 256 else 1024
     c = Cluster(species="Ar", r0_nm=6.0, n_ion=2048, capacity=8192, z_init=1, z_max=8,
                 laser=Laser(intensity_wcm2=1e15, envelope="flat"))
-    cfg = lc.make_config("fp32_acc64", ionize=True, diag_every=0, max_records=1, max_splits=1, seed=1, t0=1.3)
+    cfg = lc.make_config("fp32_acc64", ionize=True, diag_every=0, max_records=1, max_splits=1, seed=1, t0=1.3,
+                         detector_r0=9.0 if args.detectors else 0.0)
     d = lc.make_cluster(SPECIES["Ar"], c.r0_nm, c.n_ion, c.capacity, c.laser.intensity_wcm2, envelope="flat",
                         polarization=args.polarization)
     sim = lc.Simulation(cfg, [d] * nc)
@@ -251,7 +253,7 @@ def bench_particles(args):
            "ms_per_step": round(t["push_ms"], 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"{nc} Ar clusters x (2048 Ar+ + 2048 e-), capacity 8192, 1e15 W/cm2 flat, "
-                                  f"{args.polarization} polarization",
+                                  f"{args.polarization} polarization" + (", detectors at 9 R0" if args.detectors else ""),
                       "live_particles": n_live, "ions": nc * c.n_ion},
            "roofline": {"bound": "hbm", "achieved": round(push_gbs, 1), "peak": 8000.0, "unit": "GB/s",
                         "frac": round(push_gbs / 8000.0, 4), "traffic": None, "kernel": "k_push",
@@ -336,6 +338,73 @@ def bench_xe(args):
         out["error_vs_fp64"] = {"over_steps": n64, "rel_KE": rel(5), "rel_PE": rel(7), "rel_W_laser": rel(8),
                                 "events_fp32": float(a[-1, 21]), "events_fp64": float(b[-1, 21]),
                                 "max_abs_mean_charge": float(np.max(np.abs(a[:, 18] - b[:, 18])))}
+    print(json.dumps(out), flush=True)
+
+
+def bench_iedf(args):
+    """The Sec. III anisotropy study on synthetic input: Ar cluster of R0 = 8.2 nm (5000 Ar+
+    macro-ions + 5000 e-, capacity for Ar8+), 806 nm, 8e15 W/cm^2, 100 fs Gaussian, ionization
+    on, detectors at 9 R0 on the polarization axis (x) and across it (y), 30 degree acceptance.
+    Reports the run's throughput and the time-integrated ion energy distributions."""
+    import numpy as np
+    import torch
+    import paper_1307_3711_amd as lc
+    from workloads import ar_anisotropy, initial_state
+    from workloads.species import SPECIES
+    c, run = ar_anisotropy()
+    steps = args.steps if args.steps_given else c.n_steps
+    st = initial_state(c, run.seed)
+    mpb = lc.pair_blocks_for([c.capacity], 256)
+    cfg = lc.make_config("fp32_acc64", ionize=True, lambda_um=c.laser.lambda_um, dt=run.dt,
+                         softening_nm=run.softening_nm, diag_every=run.diag_every,
+                         max_records=steps // run.diag_every + 2, max_splits=16, seed=run.seed, max_pair_blocks=mpb,
+                         detector_r0=9.0, detector_half_angle_deg=30.0)
+    d = lc.make_cluster(SPECIES[c.species], c.r0_nm, c.n_ion, c.capacity, c.laser.intensity_wcm2,
+                        envelope=c.laser.envelope, fwhm_fs=c.laser.fwhm_fs, z_max=c.z_max,
+                        electron_offset_nm=c.electron_offset_nm)
+    sim = lc.Simulation(cfg, [d])
+    sim.init_from_host(0, st["x_nm"], st["u"], st["Z"])
+    sim.start()
+    tuned = sim.autotune()
+    sim.set_graph(run.diag_every)
+    sim.stream.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        k = min(5000, steps - done)
+        sim.step(k)
+        done += k
+        sim.stream.synchronize()
+        counts, _ = sim.iedf(0)
+        log(f"  iedf: step {done}/{steps}, N = {sim.counters(0)['n']}, ions detected {counts[0].sum()}")
+    wall = time.perf_counter() - t0
+    counts, edges = sim.iedf(0)
+    rec = sim.diagnostics(0)
+    cnt = sim.counters(0)
+    sim.close()
+    centres = np.concatenate([[edges[0] / 2], np.sqrt(edges[:-1] * edges[1:]), [edges[-1]]])
+
+    def summary(row):
+        n = int(counts[row].sum())
+        mean = float(np.sum(counts[row] * centres) / n) if n else None
+        return {"ions": n, "mean_keV": None if mean is None else round(mean / 1e3, 3),
+                "counts": counts[row].tolist()}
+
+    along, perp = summary(1), summary(2)
+    out = {"metric": "G pair-interactions/s (FP32 pair math + FP64 accumulation), Ar anisotropy run",
+           "value": round(cnt["pairs"] / wall / 1e9, 2), "unit": "Gpair/s", "n_gpus": 1, "steps": steps,
+           "warmup": 0, "ms_per_step": round(wall / steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "fp32+fp64acc", "data": "synthetic",
+           "config": {"workload": "Ar cluster R0=8.2nm (~40k atoms), 5000 Ar+ + 5000 e- (capacity 45k), 806 nm, "
+                                  "8e15 W/cm2, 100 fs Gaussian, ionization to Ar8+, dt=0.05, detectors at 9 R0, "
+                                  "30 deg", "tiling": tuned},
+           "final_macroparticles": cnt["n"], "mean_charge_end": float(rec[-1, 18]),
+           "t_end_fs": float(rec[-1, 0]) * c.laser.lambda_um * 1e-6 / (2 * math.pi * 299792458.0) * 1e15,
+           "ions_detected": int(counts[0].sum()), "along_polarization": along, "perpendicular": perp,
+           "mean_energy_ratio_along_over_perp": (round(along["mean_keV"] / perp["mean_keV"], 4)
+                                                 if along["mean_keV"] and perp["mean_keV"] else None),
+           "bin_edges_eV": edges.tolist()}
     print(json.dumps(out), flush=True)
 
 
@@ -453,7 +522,7 @@ def main():
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--save-data", default="", help="surrogate: write the MD training set (npz) here")
     ap.add_argument("--fp64-steps", type=int, default=2000, help="xe200k: steps of the FP64 comparison run")
-    ap.add_argument("--workload", default="ar20k", choices=["ar20k", "ensemble", "surrogate", "particles", "xe200k",
+    ap.add_argument("--workload", default="ar20k", choices=["ar20k", "ensemble", "surrogate", "particles", "xe200k", "iedf",
                                                             "scan"])
     ap.add_argument("--sizes", default="20000,30000,40000,60000,100000",
                     help="particle counts of the scan workload")
@@ -471,6 +540,7 @@ def main():
     ap.add_argument("--tiling-fp64", default="", help="the same for the FP64 comparison run")
     ap.add_argument("--polarization", default="linear_x", choices=["linear_x", "circular"],
                     help="particles workload: laser polarization")
+    ap.add_argument("--detectors", action="store_true", help="particles workload: ion detectors at 9 R0")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB buffer 3 times (HBM counter calibration for rocprofv3)")
     args = ap.parse_args()
@@ -507,6 +577,8 @@ def main():
         return bench_scan(args)
     if args.workload == "xe200k":
         return bench_xe(args)
+    if args.workload == "iedf":
+        return bench_iedf(args)
 
     import numpy as np
     import torch

@@ -162,14 +162,16 @@ __global__ __launch_bounds__(kBlock) void k_schedule(DevState s, RunConst rc, in
 struct PState {
   double x, y, z, ux, uy, uz, wl, wc;
   int zc;
+  int seen;  // detector flag (with detectors on)
 };
 
-__device__ inline PState load_pstate(const DevState& s, int64_t g) {
+__device__ inline PState load_pstate(const DevState& s, const RunConst& rc, int64_t g) {
   PState p;
   p.x = s.x[g]; p.y = s.y[g]; p.z = s.z[g];
   p.ux = s.ux[g]; p.uy = s.uy[g]; p.uz = s.uz[g];
   p.wl = s.wl[g]; p.wc = s.wc[g];
   p.zc = s.Z[g];
+  p.seen = rc.det_on ? s.det_seen[g] : 1;
   return p;
 }
 
@@ -177,9 +179,9 @@ __device__ inline PState load_pstate(const DevState& s, int64_t g) {
 // to the detector distance, in the energy slot of M (gamma - 1) m_e c^2 (eV per real ion) for
 // every ion and for each axis whose direction its position is within the acceptance cone of.
 // Counts are integers (order-independent atomics); the slot is the number of edges <= E.
+// Called for ions not counted yet (the flag comes with the particle state).
 __device__ inline void detect_ion(const DevState& s, const RunConst& rc, const ClusterParams& cp, int c, int64_t g,
                                   double x, double y, double z, double M, double ux, double uy, double uz) {
-  if (s.det_seen[g]) return;
   const double r2 = x * x + y * y + z * z;
   if (r2 < cp.det_r2) return;
   s.det_seen[g] = 1;
@@ -251,7 +253,7 @@ __device__ inline void push_one(const DevState& s, const RunConst& rc, int64_t g
   write_source(s, PREC, g, x, y, z, cp.kw * (double)zc);
   if (!(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(unx) && isfinite(uny) && isfinite(unz)))
     atomicOr(s.err, kFlagNonfinite);
-  if (rc.det_on && zc > 0) detect_ion(s, rc, cp, c, g, x, y, z, M, unx, uny, unz);  // only ion slots hold Z > 0
+  if (!p.seen && zc > 0) detect_ion(s, rc, cp, c, g, x, y, z, M, unx, uny, unz);  // only ion slots hold Z > 0
 }
 
 template <int PREC>
@@ -264,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_push(DevState s, RunConst rc, FieldL
   if (g - s.cp[c].off >= d.n_cur) return;
   double ecx, ecy, ecz;
   field_sum(s, rc, fl, g, ecx, ecy, ecz);
-  push_one<PREC>(s, rc, g, c, *s.step + k, diag, ecx, ecy, ecz, load_pstate(s, g));
+  push_one<PREC>(s, rc, g, c, *s.step + k, diag, ecx, ecy, ecz, load_pstate(s, rc, g));
 }
 
 // Fold of the pair-once rows and push in one kernel: kFoldWaves waves over 64 consecutive
@@ -285,7 +287,7 @@ __global__ __launch_bounds__(64 * kFoldWaves) void k_fold_push(DevState s, RunCo
     c = s.cid[g];
     live = s.dyn[c].active && g - s.cp[c].off < s.dyn[c].n_cur;
     if (live) {
-      if (w == 0) ps = load_pstate(s, g);
+      if (w == 0) ps = load_pstate(s, rc, g);
       if (PREC == LC_FP64) n3_row_partial<double>(s, rc, B, g, w, kFoldWaves, e0, e1, e2);
       else n3_row_partial<float>(s, rc, B, g, w, kFoldWaves, e0, e1, e2);
     }

@@ -128,6 +128,17 @@ def xe_200k():
     return c, Run(dt=0.05, ionize=True, diag_every=100, seed=0)
 
 
+def ar_anisotropy(n_ion=5000, n_steps=60000):
+    """The anisotropy study of Sec. III made synthetic: Ar cluster of R0 = 8.2 nm (about 40,000
+    atoms by Eq.(1) with R_W = 2.4 A) lumped into n_ion Ar+ macro-ions and as many electrons,
+    capacity for Ar8+, 806 nm, 8e15 W/cm^2, 100 fs FWHM Gaussian, linear polarization along x,
+    detectors at 9 R0 with 30 degree acceptance (set by the caller)."""
+    laser = Laser(lambda_um=0.806, intensity_wcm2=8e15, envelope="gauss_field", fwhm_fs=100.0)
+    c = Cluster(species="Ar", r0_nm=8.2, n_ion=n_ion, capacity=9 * n_ion, z_init=1, z_max=8, laser=laser,
+                n_steps=n_steps)
+    return c, Run(dt=0.05, ionize=True, diag_every=1000, seed=0)
+
+
 def ensemble(n_clusters=256, seed=0, cap_lo=1000, cap_hi=16000, steps_per_fwhm=None,
              lambda_um=0.8, dt=0.05):
     """Batched ensemble of uneven clusters.
