@@ -27,6 +27,7 @@ _LIB = os.path.join(_HERE, "liblc_oracle.so")
 ENVELOPES = {"gauss_field": 0, "gauss_intensity": 1, "sin2": 2, "flat": 3}
 PHASES = {"dipole": 0, "plane_wave": 1}
 POLARIZATIONS = {"linear_x": 0, "circular": 1}
+BOUNDARIES = {"open": 0, "periodic": 1, "mixed": 2}
 OFI = {"laser_only": 0, "local": 1}
 MAX_Z = 16
 REC = 48
@@ -67,7 +68,8 @@ class Params(ctypes.Structure):
         ("field_au", ctypes.c_double), ("rate_scale", ctypes.c_double),
         ("delta", ctypes.c_double), ("n_atoms", ctypes.c_double), ("mec2_ev", ctypes.c_double),
         ("seed", ctypes.c_uint64), ("cluster", ctypes.c_uint64), ("n_ion", ctypes.c_int64),
-        ("polarization", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("polarization", ctypes.c_int32), ("boundary", ctypes.c_int32),
+        ("box", ctypes.c_double), ("t_switch", ctypes.c_double),
     ]
 
 
@@ -99,6 +101,8 @@ def lib():
         L.or_laser.argtypes = [pp, ctypes.c_double, ctypes.c_double, dp, dp]
         L.or_boris_push.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
         L.or_coulomb_field.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, dp, dp, dp, dp]
+        L.or_coulomb_field_box.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double, dp,
+                                           dp, dp, dp]
         L.or_coulomb_field_at.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int64,
                                           i64p, dp, dp, dp, dp]
         L.or_start.argtypes = [pp, ctypes.c_int64, dp, dp, dp, dp, dp, dp, i8p, dp]
@@ -109,7 +113,7 @@ def lib():
         L.or_detector_init.argtypes = [ctypes.POINTER(Detector), ctypes.c_double, ctypes.c_double]
         L.or_detector_init.restype = None
         L.or_det_slots.restype = ctypes.c_int
-        L.or_state_field.argtypes = [pp, ctypes.c_int64, dp, dp, dp, i8p, dp, dp, dp, dp, dp]
+        L.or_state_field.argtypes = [pp, ctypes.c_double, ctypes.c_int64, dp, dp, dp, i8p, dp, dp, dp, dp, dp]
         L.or_threads.restype = ctypes.c_int
         _lib_handle = L
     return _lib_handle
@@ -153,16 +157,17 @@ def boris_push(zm, dt, E, B, u):
     return out
 
 
-def coulomb_field(x, q, eps2, want_phi=True):
-    """Direct-sum softened field of sources q (field units) at positions x (n x 3)."""
+def coulomb_field(x, q, eps2, want_phi=True, box=0.0):
+    """Direct-sum softened field of sources q (field units) at positions x (n x 3); box > 0:
+    minimum-image separations in a periodic cube of that side."""
     x = np.ascontiguousarray(x, np.float64)
     n = x.shape[0]
     xs = [np.ascontiguousarray(x[:, k]) for k in range(3)]
     q = np.ascontiguousarray(q, np.float64)
     e = [np.zeros(n) for _ in range(3)]
     phi = np.zeros(n) if want_phi else None
-    lib().or_coulomb_field(n, _dp(xs[0]), _dp(xs[1]), _dp(xs[2]), _dp(q), float(eps2), _dp(e[0]),
-                           _dp(e[1]), _dp(e[2]), _dp(phi) if want_phi else None)
+    lib().or_coulomb_field_box(n, _dp(xs[0]), _dp(xs[1]), _dp(xs[2]), _dp(q), float(eps2), float(box), _dp(e[0]),
+                               _dp(e[1]), _dp(e[2]), _dp(phi) if want_phi else None)
     return np.stack(e, axis=1), phi
 
 
@@ -197,6 +202,9 @@ def make_params(cluster, run, cluster_index=0, weight=None, **override):
     p.envelope = ENVELOPES[cluster.laser.envelope]
     p.phase = PHASES[cluster.laser.phase]
     p.polarization = POLARIZATIONS[cluster.laser.polarization]
+    p.boundary = BOUNDARIES[run.boundary]
+    p.box = run.box_r0 * units.nm_to_norm(cluster.r0_nm, lam)
+    p.t_switch = run.t_switch
     p.tau = units.fs_to_norm(cluster.laser.fwhm_fs, lam)
     p.t_sin2 = 2.0 * np.pi * cluster.laser.n_cycles
     natoms = units.n_atoms(cluster.r0_nm, sp["rw_angstrom"])
@@ -317,7 +325,8 @@ class Sim:
         q = np.zeros(n)
         e = [np.zeros(n) for _ in range(3)]
         phi = np.zeros(n)
-        lib().or_state_field(ctypes.byref(self.p), n, _dp(self.x[0]), _dp(self.x[1]), _dp(self.x[2]),
+        t = self.p.t0 + self.step_index * self.p.dt
+        lib().or_state_field(ctypes.byref(self.p), t, n, _dp(self.x[0]), _dp(self.x[1]), _dp(self.x[2]),
                              self.Z.ctypes.data_as(i8p), _dp(q), _dp(e[0]), _dp(e[1]), _dp(e[2]),
                              _dp(phi))
         return np.stack(e, axis=1), phi

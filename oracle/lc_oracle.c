@@ -21,6 +21,8 @@
  *   or_adk_rate       - ADK tunnelling rate (cited in Sec. II; standard l = m = 0 form).
  *   ionization        - Monte-Carlo test P = 1 - exp(-nu dt) against alpha in (0,1]
  *                       (Sec. II), electron spawned next to the ion.
+ *   or_min_image,     - periodic, open or mixed boundaries of the simulation box (Sec. II):
+ *   or_wrap             minimum-image separations and re-entry through the opposite face.
  *   or_detect         - ion detectors and the time-integrated ion energy distribution
  *                       (Sec. III anisotropy study: detectors at 9 R0, 30 degree acceptance).
  *   or_philox4x64_10  - Philox4x64-10 counter-based generator (Salmon et al., SC'11).
@@ -70,6 +72,7 @@ double or_u01(uint64_t x) { return (double)((x >> 11) + 1ULL) * (1.0 / 900719925
 enum { OR_ENV_GAUSS_FIELD = 0, OR_ENV_GAUSS_INTENSITY = 1, OR_ENV_SIN2 = 2, OR_ENV_FLAT = 3 };
 enum { OR_PHASE_DIPOLE = 0, OR_PHASE_PLANE_WAVE = 1 };
 enum { OR_POL_LINEAR_X = 0, OR_POL_CIRCULAR = 1 };
+enum { OR_OPEN = 0, OR_PERIODIC = 1, OR_MIXED = 2 };
 enum { OR_OFI_LASER_ONLY = 0, OR_OFI_LOCAL = 1 };
 enum { OR_PURPOSE_ALPHA = 2, OR_PURPOSE_DIRECTION = 3 };
 
@@ -101,24 +104,43 @@ typedef struct {
   uint64_t cluster;     /* Philox key word 1                                       */
   int64_t n_ion;        /* ions occupy indices [0, n_ion)                          */
   int32_t polarization; /* OR_POL_*                                                */
-  int32_t pad;
+  int32_t boundary;     /* OR_OPEN, OR_PERIODIC, or OR_MIXED (periodic while t < t_switch) */
+  double box;           /* side L of the periodic cube centred on the cluster (c/w)  */
+  double t_switch;      /* OR_MIXED: first time (1/w) with open boundaries             */
 } or_params;
+
+/* ------------------------------------------------------------------ boundaries */
+/* Sec. II: periodic boundaries on the faces of a cube of side R_IC = 20 R0 around the cluster
+ * stand in for the neighbouring clusters; open boundaries, or periodic ones first and open
+ * ones afterwards (mixed), are the other options.  Periodic here means the minimum-image
+ * convention: a pair interacts through the nearest periodic copy of the partner, and a
+ * particle leaving the cube re-enters through the opposite face. */
+static double or_min_image(double d, double L) { return (L > 0.0) ? d - L * nearbyint(d / L) : d; }
+
+static double or_wrap(double x, double L) { return x - L * floor(x / L + 0.5); }
+
+/* Side of the periodic cube in force at time t, or 0 when the boundaries are open. */
+static double or_box_at(const or_params* p, double t) {
+  if (p->boundary == OR_PERIODIC || (p->boundary == OR_MIXED && t < p->t_switch)) return p->box;
+  return 0.0;
+}
 
 /* ------------------------------------------------------------------ S2: field */
 /* E_i = sum_{j != i} q_j (r_i - r_j) / (|r_i - r_j|^2 + eps^2)^{3/2}
  * phi_i = sum_{j != i} q_j / (|r_i - r_j|^2 + eps^2)^{1/2}
  * q_j is the source strength in field units (kappa * weight * Z_j).  The j loop runs in
- * ascending order for every i. */
-void or_coulomb_field(int64_t n, const double* x, const double* y, const double* z, const double* q,
-                      double eps2, double* ex, double* ey, double* ez, double* phi) {
+ * ascending order for every i.  L > 0: separations by the minimum-image convention in a
+ * periodic cube of side L. */
+void or_coulomb_field_box(int64_t n, const double* x, const double* y, const double* z, const double* q,
+                          double eps2, double L, double* ex, double* ey, double* ez, double* phi) {
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
     for (int64_t j = 0; j < n; ++j) {
       if (j == i) continue;
-      double dx = x[i] - x[j];
-      double dy = y[i] - y[j];
-      double dz = z[i] - z[j];
+      double dx = or_min_image(x[i] - x[j], L);
+      double dy = or_min_image(y[i] - y[j], L);
+      double dz = or_min_image(z[i] - z[j], L);
       double r2 = dx * dx + dy * dy + dz * dz + eps2;
       double inv = 1.0 / sqrt(r2);
       double inv3 = inv * inv * inv;
@@ -133,6 +155,11 @@ void or_coulomb_field(int64_t n, const double* x, const double* y, const double*
     ez[i] = sz;
     if (phi) phi[i] = sp;
   }
+}
+
+void or_coulomb_field(int64_t n, const double* x, const double* y, const double* z, const double* q,
+                      double eps2, double* ex, double* ey, double* ez, double* phi) {
+  or_coulomb_field_box(n, x, y, z, q, eps2, 0.0, ex, ey, ez, phi);
 }
 
 /* The same sum evaluated only at the m targets listed in idx (for sampled checks of large
@@ -275,7 +302,7 @@ double or_start(const or_params* p, int64_t n, const double* x, const double* y,
   double* ey = work + 2 * n;
   double* ez = work + 3 * n;
   or_charges(p, n, Z, q);
-  or_coulomb_field(n, x, y, z, q, p->eps2, ex, ey, ez, NULL);
+  or_coulomb_field_box(n, x, y, z, q, p->eps2, or_box_at(p, p->t0), ex, ey, ez, NULL);
   double ke = 0.0;
   for (int64_t i = 0; i < n; ++i) {
     double EL[3], BL[3];
@@ -430,8 +457,9 @@ static int or_step(const or_params* p, int64_t step, int64_t cap, int64_t* n_io,
   int64_t n = *n_io;
   double t = p->t0 + (double)step * p->dt;
   int diag = (p->diag_every > 0) && (step % p->diag_every == 0);
+  double L = or_box_at(p, t);
   or_charges(p, n, Z, s->q);
-  or_coulomb_field(n, x, y, z, s->q, p->eps2, s->ex, s->ey, s->ez, s->phi);
+  or_coulomb_field_box(n, x, y, z, s->q, p->eps2, L, s->ex, s->ey, s->ez, s->phi);
 
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
@@ -463,6 +491,11 @@ static int or_step(const or_params* p, int64_t step, int64_t cap, int64_t* n_io,
     x[i] += p->dt * un[0] / gn;
     y[i] += p->dt * un[1] / gn;
     z[i] += p->dt * un[2] / gn;
+    if (L > 0.0) {
+      x[i] = or_wrap(x[i], L);
+      y[i] = or_wrap(y[i], L);
+      z[i] = or_wrap(z[i], L);
+    }
   }
 
   if (det) or_detect(p, det, x, y, z, ux, uy, uz, Z);
@@ -510,6 +543,11 @@ static int or_step(const or_params* p, int64_t step, int64_t cap, int64_t* n_io,
       x[e] = x[i] + p->delta * st * cos(ph);
       y[e] = y[i] + p->delta * st * sin(ph);
       z[e] = z[i] + p->delta * ct;
+      if (L > 0.0) {
+        x[e] = or_wrap(x[e], L);
+        y[e] = or_wrap(y[e], L);
+        z[e] = or_wrap(z[e], L);
+      }
       ux[e] = ux[i];
       uy[e] = uy[i];
       uz[e] = uz[i];
@@ -552,11 +590,11 @@ int64_t or_run(const or_params* p, int64_t cap, int64_t* n_io, double* x, double
   return nrec;
 }
 
-/* Field of the current state only (the S2 step alone), for parity on a fixed state. */
-void or_state_field(const or_params* p, int64_t n, const double* x, const double* y, const double* z,
+/* Field of the current state only (the S2 step alone) at time t, for parity on a fixed state. */
+void or_state_field(const or_params* p, double t, int64_t n, const double* x, const double* y, const double* z,
                     const int8_t* Z, double* q_work, double* ex, double* ey, double* ez, double* phi) {
   or_charges(p, n, Z, q_work);
-  or_coulomb_field(n, x, y, z, q_work, p->eps2, ex, ey, ez, phi);
+  or_coulomb_field_box(n, x, y, z, q_work, p->eps2, or_box_at(p, t), ex, ey, ez, phi);
 }
 
 int or_record_size(void) { return OR_REC; }

@@ -554,3 +554,95 @@ def test_iedf_uniform_sphere_explosion():
     sigma = math.sqrt(f * (1 - f) / n)
     for a in range(3):
         assert abs(counts[a + 1].sum() / n - f) < 4.5 * sigma
+
+
+def test_min_image_field_brute_force():
+    """Periodic boundaries (Sec. II, cube of side L): the field and potential with every pair
+    taken through the nearest of the 27 periodic copies of the partner, enumerated and
+    summed at 50 digits, match the oracle's minimum-image sum."""
+    rng = np.random.default_rng(17)
+    n, L, eps = 12, 0.05, 1e-3
+    x = rng.uniform(-L / 2, L / 2, (n, 3))
+    q = rng.choice([-1.0, 1.0, 3.0], n) * 2.2e-8
+    E, phi = oracle.coulomb_field(x, q, eps * eps, box=L)
+    shifts = [(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)]
+    for i in range(n):
+        acc = [mpmath.mpf(0)] * 4
+        scale = mpmath.mpf(0)
+        for j in range(n):
+            if j == i:
+                continue
+            best = None
+            for sh in shifts:
+                d = [mpmath.mpf(x[i][k]) - mpmath.mpf(x[j][k]) - sh[k] * mpmath.mpf(L) for k in range(3)]
+                r2 = d[0] ** 2 + d[1] ** 2 + d[2] ** 2
+                if best is None or r2 < best[0]:
+                    best = (r2, d)
+            r2, d = best
+            s = r2 + mpmath.mpf(eps) ** 2
+            inv = 1 / mpmath.sqrt(s)
+            for k in range(3):
+                acc[k] += mpmath.mpf(q[j]) * d[k] * inv ** 3
+            acc[3] += mpmath.mpf(q[j]) * inv
+            scale += abs(mpmath.mpf(q[j])) * inv ** 2
+        for k in range(3):
+            assert abs(E[i][k] - float(acc[k])) <= 1e-13 * float(scale)
+        assert abs(phi[i] - float(acc[3])) <= 1e-13 * float(scale) * L
+
+
+def _streaming_electron(boundary, t_switch, nsteps):
+    c = Cluster(species="Ar", r0_nm=1.0, n_ion=0, capacity=1, laser=Laser(envelope="flat"))
+    run = Run(dt=0.5, ionize=False, diag_every=0, boundary=boundary, box_r0=2.0, t_switch=t_switch)
+    p = oracle.make_params(c, run, weight=1.0)
+    p.a0 = 0.0
+    u = np.array([0.3, 0.2, -0.1])
+    x0 = np.array([0.004, -0.006, 0.002])
+    sim = oracle.Sim(p, 1, x0[None, :], u[None, :], np.array([-1], np.int8))
+    sim.start()
+    sim.run(nsteps)
+    v = u / math.sqrt(1.0 + u @ u)
+    return sim.positions()[0], x0, v, p
+
+
+@pytest.mark.parametrize("boundary", ["periodic", "mixed"])
+def test_free_streaming_through_the_box(boundary):
+    """A particle streaming freely leaves the periodic cube through one face and re-enters
+    through the opposite one: after m periodic steps it sits at ((x0 + m dt v + L/2) mod L)
+    - L/2; in the mixed mode the open steps after the switch then carry it on unwrapped."""
+    nsteps = 400
+    m = nsteps if boundary == "periodic" else 250
+    pos, x0, v, p = _streaming_electron(boundary, (m - 0.5) * 0.5, nsteps)
+    L = p.box
+    assert L > 0 and nsteps * 0.5 * np.max(np.abs(v)) > 3 * L  # several crossings
+    want = np.mod(x0 + m * p.dt * v + L / 2, L) - L / 2 + (nsteps - m) * p.dt * v
+    assert np.max(np.abs(pos - want)) <= 1e-12 * L * nsteps
+
+
+def test_periodic_momentum_newton3_and_box():
+    """In a periodic cube barely wider than the cluster the minimum-image forces stay pairwise
+    opposite: sum_i w Z_i E_C,i vanishes to rounding and, with the laser off, the total
+    momentum stays at its start value; every particle stays inside the cube, spawned
+    electrons included (ionization on)."""
+    c = Cluster(species="Ar", r0_nm=2.0, n_ion=100, capacity=900, z_init=1, z_max=8,
+                laser=Laser(intensity_wcm2=3e17, envelope="flat"))
+    run = Run(dt=0.05, ionize=True, diag_every=1, seed=3, boundary="periodic", box_r0=2.5)
+    sim = oracle.Sim.from_workload(c, run, initial_state(c, 3))
+    sim.p.a0 = 0.0
+    sim.start()
+    rec = sim.run(60)
+    for r in rec:
+        assert np.linalg.norm(r[oracle.R_F:oracle.R_F + 3]) <= 1e-13 * r[oracle.R_FABS]
+    p0, p1 = rec[0][oracle.R_P:oracle.R_P + 3], rec[-1][oracle.R_P:oracle.R_P + 3]
+    scale = np.sum(np.abs(sim.momenta()) * sim.p.mass_ion * sim.p.weight)
+    assert np.linalg.norm(p1 - p0) <= 1e-12 * scale
+    L = sim.p.box
+    assert np.all(np.abs(sim.positions()) <= L / 2)
+    # the laser on: ionization spawns electrons; they and every other particle stay inside
+    sim2 = oracle.Sim.from_workload(c, run, initial_state(c, 3))
+    sim2.start()
+    rec2 = sim2.run(60)
+    assert rec2[-1][oracle.R_EVENTS] > 0 and sim2.N > 200
+    assert np.all(np.abs(sim2.positions()) <= L / 2)
+    lhs = rec2[-1][oracle.R_KE_HALF] - sim2.ke_start
+    rhs = rec2[-1][oracle.R_WL] + rec2[-1][oracle.R_WC] + rec2[-1][oracle.R_WSP]
+    assert abs(lhs - rhs) <= 1e-11 * (abs(rec2[-1][oracle.R_WL]) + abs(rec2[-1][oracle.R_WC]) + abs(sim2.ke_start))

@@ -60,6 +60,9 @@ class Run:
     ofi_field: str = "laser_only"     # laser_only | local
     diag_every: int = 10
     seed: int = 0
+    boundary: str = "open"            # open | periodic | mixed (Sec. II)
+    box_r0: float = 20.0              # side of the periodic cube in units of R0 (R_IC = 20 R0)
+    t_switch: float = math.inf        # mixed: first time (1/w) with open boundaries
 
 
 def n_atoms_input(cluster):
