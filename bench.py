@@ -31,14 +31,14 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def make_sim(precision, c, run, st, graph, tiling=None):
+def make_sim(precision, c, run, st, graph, tiling=None, boundary="open"):
     import paper_1307_3711_amd as lc
     from workloads.species import SPECIES
     # room for the pair-once kernel (blocks of 128 slots and up) where the precision allows it
     mpb = lc.pair_blocks_for([c.capacity], 128) if precision in ("fp32_acc64", "fp64") else 0
     cfg = lc.make_config(precision, ionize=run.ionize, dt=run.dt, softening_nm=run.softening_nm,
                          diag_every=run.diag_every, max_records=256, max_splits=64, seed=run.seed,
-                         max_pair_blocks=mpb)
+                         max_pair_blocks=mpb, boundary=boundary, box_r0=run.box_r0)
     desc = lc.make_cluster(SPECIES[c.species], c.r0_nm, c.n_ion, c.capacity, c.laser.intensity_wcm2,
                            envelope=c.laser.envelope, fwhm_fs=c.laser.fwhm_fs, z_max=c.z_max,
                            electron_offset_nm=c.electron_offset_nm)
@@ -541,6 +541,8 @@ def main():
     ap.add_argument("--polarization", default="linear_x", choices=["linear_x", "circular"],
                     help="particles workload: laser polarization")
     ap.add_argument("--detectors", action="store_true", help="particles workload: ion detectors at 9 R0")
+    ap.add_argument("--boundary", default="open", choices=["open", "periodic"],
+                    help="ar20k: boundaries of the simulation box (periodic: cube of 20 R0)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB buffer 3 times (HBM counter calibration for rocprofv3)")
     args = ap.parse_args()
@@ -591,7 +593,7 @@ def main():
     pairs = float(n) * float(n)
 
     log(f"bench: {n} macroparticles, fp32_acc64, autotune")
-    sim, tuned = make_sim("fp32_acc64", c, run, st, args.graph, tiling)
+    sim, tuned = make_sim("fp32_acc64", c, run, st, args.graph, tiling, args.boundary)
     log(f"bench: tiling {tuned}; warmup {args.warmup}")
     sim.step(args.warmup)
     sim.stream.synchronize()
@@ -604,7 +606,7 @@ def main():
     avg_force_s = force_ms / max(force_n, 1) * 1e-3
     achieved = FLOPS_PER_PAIR * pairs / avg_force_s / 1e12
     value = args.steps * pairs / wall / 1e9
-    crec = counter_record(tuned, n)
+    crec = counter_record(tuned, n) if args.boundary == "open" else None
     evals = pair_evaluations(n, tuned)
     kname = "k_force_n3" if tuned.get("newton3") else "k_force_f32"
     out = {
@@ -613,7 +615,8 @@ def main():
         "ms_per_step": round(wall / args.steps * 1e3, 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "fp32+fp64acc", "data": "synthetic",
         "config": {"workload": "Ar cluster R0=8nm, 20k macroparticles (10k Ar+ + 10k e-), 1e16 W/cm2, "
-                               "30 fs Gaussian, dt=0.05, softening 0.1 nm, charges frozen",
+                               "30 fs Gaussian, dt=0.05, softening 0.1 nm, charges frozen"
+                               + ("" if args.boundary == "open" else f", {args.boundary} boundaries (cube of 20 R0)"),
                    "n_particles": n, "pairs_per_step": pairs, "tiling": tuned, "graph_steps": args.graph},
         "cluster_steps_per_s": round(args.steps / wall, 2),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -629,7 +632,7 @@ def main():
     total_steps = args.warmup + args.steps + args.profile_steps
     if not args.no_fp64:
         log("bench: fp64 path on the same steps")
-        sim64, tuned64 = make_sim("fp64", c, run, st, args.graph, tiling64)
+        sim64, tuned64 = make_sim("fp64", c, run, st, args.graph, tiling64, args.boundary)
         sim64.step(args.warmup)
         wall64 = timed_steps(sim64, args.steps)
         prof64 = sim64.profile_steps(args.profile_steps)
@@ -637,7 +640,7 @@ def main():
         f64_ms, f64_n = prof64["field"]
         avg64_s = f64_ms / max(f64_n, 1) * 1e-3
         ach64 = FLOPS_PER_PAIR * pairs / avg64_s / 1e12
-        crec64 = counter_record(tuned64, n, "fp64")
+        crec64 = counter_record(tuned64, n, "fp64") if args.boundary == "open" else None
         p32 = sim.particles(0)
         p64 = sim64.particles(0)
         r0n = c.r0_nm * lc.units(0.8)["k_per_nm"]

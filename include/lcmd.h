@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define LC_API_VERSION 3
+#define LC_API_VERSION 4
 #define LC_MAX_Z 16       /* size of the per-charge tables (charge states 0..15)        */
 #define LC_REC 48         /* doubles per diagnostic record                              */
 #define LC_DET_BINS 120   /* ion energy histogram: 20 log bins per decade, 1 eV .. 1 MeV */
@@ -72,6 +72,17 @@ typedef enum {
   LC_PLANE_WAVE = 1       /* test mode: phase t - z, wave along +z; ionization must be off */
 } lc_phase;
 
+/* Boundaries of the simulation box (Sec. II): a cube of side box_r0 * R0 centred on each
+ * cluster (the paper takes the inter-cluster distance R_IC = 20 R0).  Periodic: every pair
+ * interacts through the nearest periodic copy of the partner (minimum image) and a particle
+ * leaving the cube re-enters through the opposite face.  Mixed: periodic for the steps with
+ * t^n < t_switch, open afterwards. */
+typedef enum {
+  LC_OPEN = 0,
+  LC_PERIODIC = 1,
+  LC_MIXED = 2
+} lc_boundary;
+
 /* Polarization of the laser field (Eqs.(4)-(9); the magnetic field is z^ x E in both). */
 typedef enum {
   LC_LINEAR_X = 0,        /* E = a(t) (sin psi, 0, 0), B = a(t) (0, sin psi, 0)             */
@@ -105,6 +116,10 @@ typedef struct {
   double detector_r0;     /* ion detectors at this multiple of each cluster's R0 from   */
                           /*   its centre (Sec. III anisotropy study: 9); 0: none       */
   double detector_half_angle_deg; /* their acceptance half-angle, in (0, 90) (Sec. III: 30) */
+  int32_t boundary;       /* lc_boundary; periodic and mixed need LC_FP64 or LC_FP32_ACC64 */
+  int32_t reserved;
+  double box_r0;          /* side of the periodic cube in units of each cluster's R0 (> 0) */
+  double t_switch;        /* LC_MIXED: first time (1/w) of open boundaries              */
 } lc_config;
 
 /* One cluster, in physical units.  Species data (Wigner-Seitz radius, mass, ionization

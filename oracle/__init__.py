@@ -69,7 +69,8 @@ class Params(ctypes.Structure):
         ("delta", ctypes.c_double), ("n_atoms", ctypes.c_double), ("mec2_ev", ctypes.c_double),
         ("seed", ctypes.c_uint64), ("cluster", ctypes.c_uint64), ("n_ion", ctypes.c_int64),
         ("polarization", ctypes.c_int32), ("boundary", ctypes.c_int32),
-        ("box", ctypes.c_double), ("t_switch", ctypes.c_double),
+        ("box", ctypes.c_double), ("t_switch", ctypes.c_double), ("image32", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
     ]
 
 
@@ -101,8 +102,8 @@ def lib():
         L.or_laser.argtypes = [pp, ctypes.c_double, ctypes.c_double, dp, dp]
         L.or_boris_push.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
         L.or_coulomb_field.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, dp, dp, dp, dp]
-        L.or_coulomb_field_box.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double, dp,
-                                           dp, dp, dp]
+        L.or_coulomb_field_box.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_int, dp, dp, dp, dp]
         L.or_coulomb_field_at.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int64,
                                           i64p, dp, dp, dp, dp]
         L.or_start.argtypes = [pp, ctypes.c_int64, dp, dp, dp, dp, dp, dp, i8p, dp]
@@ -157,16 +158,18 @@ def boris_push(zm, dt, E, B, u):
     return out
 
 
-def coulomb_field(x, q, eps2, want_phi=True, box=0.0):
+def coulomb_field(x, q, eps2, want_phi=True, box=0.0, image32=False):
     """Direct-sum softened field of sources q (field units) at positions x (n x 3); box > 0:
-    minimum-image separations in a periodic cube of that side."""
+    minimum-image separations in a periodic cube of that side (image32: the periodic copy
+    chosen from FP32 positions, as FP32 pair kernels choose it)."""
     x = np.ascontiguousarray(x, np.float64)
     n = x.shape[0]
     xs = [np.ascontiguousarray(x[:, k]) for k in range(3)]
     q = np.ascontiguousarray(q, np.float64)
     e = [np.zeros(n) for _ in range(3)]
     phi = np.zeros(n) if want_phi else None
-    lib().or_coulomb_field_box(n, _dp(xs[0]), _dp(xs[1]), _dp(xs[2]), _dp(q), float(eps2), float(box), _dp(e[0]),
+    lib().or_coulomb_field_box(n, _dp(xs[0]), _dp(xs[1]), _dp(xs[2]), _dp(q), float(eps2), float(box),
+                               1 if image32 else 0, _dp(e[0]),
                                _dp(e[1]), _dp(e[2]), _dp(phi) if want_phi else None)
     return np.stack(e, axis=1), phi
 

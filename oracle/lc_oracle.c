@@ -21,7 +21,7 @@
  *   or_adk_rate       - ADK tunnelling rate (cited in Sec. II; standard l = m = 0 form).
  *   ionization        - Monte-Carlo test P = 1 - exp(-nu dt) against alpha in (0,1]
  *                       (Sec. II), electron spawned next to the ion.
- *   or_min_image,     - periodic, open or mixed boundaries of the simulation box (Sec. II):
+ *   or_sep,           - periodic, open or mixed boundaries of the simulation box (Sec. II):
  *   or_wrap             minimum-image separations and re-entry through the opposite face.
  *   or_detect         - ion detectors and the time-integrated ion energy distribution
  *                       (Sec. III anisotropy study: detectors at 9 R0, 30 degree acceptance).
@@ -107,6 +107,8 @@ typedef struct {
   int32_t boundary;     /* OR_OPEN, OR_PERIODIC, or OR_MIXED (periodic while t < t_switch) */
   double box;           /* side L of the periodic cube centred on the cluster (c/w)  */
   double t_switch;      /* OR_MIXED: first time (1/w) with open boundaries             */
+  int32_t image32;      /* 1: periodic copy chosen in FP32 from FP32 positions (the      */
+  int32_t pad;          /*    decision of FP32 pair kernels); 0: in FP64                 */
 } or_params;
 
 /* ------------------------------------------------------------------ boundaries */
@@ -115,7 +117,22 @@ typedef struct {
  * ones afterwards (mixed), are the other options.  Periodic here means the minimum-image
  * convention: a pair interacts through the nearest periodic copy of the partner, and a
  * particle leaving the cube re-enters through the opposite face. */
-static double or_min_image(double d, double L) { return (L > 0.0) ? d - L * nearbyint(d / L) : d; }
+/* Separation xi - xj through the nearest periodic copy (L > 0).  Which copy is nearest is an
+ * integer decided by floating point; image32 takes it as a pair kernel working on FP32
+ * positions does, so that both sides decide alike for pairs within rounding of L/2. */
+static double or_sep(double xi, double xj, double L, int image32) {
+  double d = xi - xj;
+  if (!(L > 0.0)) return d;
+  double k;
+  if (image32) {
+    float d32 = (float)xi - (float)xj;
+    float il32 = 1.0f / (float)L;
+    k = (double)rintf(d32 * il32);
+  } else {
+    k = nearbyint(d / L);
+  }
+  return d - L * k;
+}
 
 static double or_wrap(double x, double L) { return x - L * floor(x / L + 0.5); }
 
@@ -132,15 +149,15 @@ static double or_box_at(const or_params* p, double t) {
  * ascending order for every i.  L > 0: separations by the minimum-image convention in a
  * periodic cube of side L. */
 void or_coulomb_field_box(int64_t n, const double* x, const double* y, const double* z, const double* q,
-                          double eps2, double L, double* ex, double* ey, double* ez, double* phi) {
+                          double eps2, double L, int image32, double* ex, double* ey, double* ez, double* phi) {
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
     for (int64_t j = 0; j < n; ++j) {
       if (j == i) continue;
-      double dx = or_min_image(x[i] - x[j], L);
-      double dy = or_min_image(y[i] - y[j], L);
-      double dz = or_min_image(z[i] - z[j], L);
+      double dx = or_sep(x[i], x[j], L, image32);
+      double dy = or_sep(y[i], y[j], L, image32);
+      double dz = or_sep(z[i], z[j], L, image32);
       double r2 = dx * dx + dy * dy + dz * dz + eps2;
       double inv = 1.0 / sqrt(r2);
       double inv3 = inv * inv * inv;
@@ -159,7 +176,7 @@ void or_coulomb_field_box(int64_t n, const double* x, const double* y, const dou
 
 void or_coulomb_field(int64_t n, const double* x, const double* y, const double* z, const double* q,
                       double eps2, double* ex, double* ey, double* ez, double* phi) {
-  or_coulomb_field_box(n, x, y, z, q, eps2, 0.0, ex, ey, ez, phi);
+  or_coulomb_field_box(n, x, y, z, q, eps2, 0.0, 0, ex, ey, ez, phi);
 }
 
 /* The same sum evaluated only at the m targets listed in idx (for sampled checks of large
@@ -302,7 +319,7 @@ double or_start(const or_params* p, int64_t n, const double* x, const double* y,
   double* ey = work + 2 * n;
   double* ez = work + 3 * n;
   or_charges(p, n, Z, q);
-  or_coulomb_field_box(n, x, y, z, q, p->eps2, or_box_at(p, p->t0), ex, ey, ez, NULL);
+  or_coulomb_field_box(n, x, y, z, q, p->eps2, or_box_at(p, p->t0), p->image32, ex, ey, ez, NULL);
   double ke = 0.0;
   for (int64_t i = 0; i < n; ++i) {
     double EL[3], BL[3];
@@ -459,7 +476,7 @@ static int or_step(const or_params* p, int64_t step, int64_t cap, int64_t* n_io,
   int diag = (p->diag_every > 0) && (step % p->diag_every == 0);
   double L = or_box_at(p, t);
   or_charges(p, n, Z, s->q);
-  or_coulomb_field_box(n, x, y, z, s->q, p->eps2, L, s->ex, s->ey, s->ez, s->phi);
+  or_coulomb_field_box(n, x, y, z, s->q, p->eps2, L, p->image32, s->ex, s->ey, s->ez, s->phi);
 
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
@@ -594,7 +611,7 @@ int64_t or_run(const or_params* p, int64_t cap, int64_t* n_io, double* x, double
 void or_state_field(const or_params* p, double t, int64_t n, const double* x, const double* y, const double* z,
                     const int8_t* Z, double* q_work, double* ex, double* ey, double* ez, double* phi) {
   or_charges(p, n, Z, q_work);
-  or_coulomb_field_box(n, x, y, z, q_work, p->eps2, or_box_at(p, t), ex, ey, ez, phi);
+  or_coulomb_field_box(n, x, y, z, q_work, p->eps2, or_box_at(p, t), p->image32, ex, ey, ez, phi);
 }
 
 int or_record_size(void) { return OR_REC; }

@@ -23,6 +23,7 @@ PRECISIONS = {"fp64": 0, "fp32_acc64": 1, "fp32_kahan": 2}
 ENVELOPES = {"gauss_field": 0, "gauss_intensity": 1, "sin2": 2, "flat": 3}
 PHASES = {"dipole": 0, "plane_wave": 1}
 POLARIZATIONS = {"linear_x": 0, "circular": 1}
+BOUNDARIES = {"open": 0, "periodic": 1, "mixed": 2}
 OFI = {"laser_only": 0, "local": 1}
 
 # record columns (see include/lcmd.h)
@@ -45,6 +46,8 @@ class Config(ctypes.Structure):
         ("t0", ctypes.c_double), ("softening_nm", ctypes.c_double), ("diag_every", ctypes.c_int32),
         ("max_records", ctypes.c_int32), ("max_splits", ctypes.c_int32), ("max_pair_blocks", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("detector_r0", ctypes.c_double), ("detector_half_angle_deg", ctypes.c_double),
+        ("boundary", ctypes.c_int32), ("reserved", ctypes.c_int32), ("box_r0", ctypes.c_double),
+        ("t_switch", ctypes.c_double),
     ]
 
 
@@ -165,7 +168,7 @@ def units(lambda_um, intensity_wcm2=0.0):
 
 def make_config(precision="fp64", ionize=True, ofi_field="laser_only", lambda_um=0.8, dt=0.05, t0=0.0,
                 softening_nm=0.1, diag_every=10, max_records=1024, max_splits=32, seed=0, max_pair_blocks=0,
-                detector_r0=0.0, detector_half_angle_deg=30.0):
+                detector_r0=0.0, detector_half_angle_deg=30.0, boundary="open", box_r0=20.0, t_switch=float("inf")):
     c = Config()
     c.struct_size = ctypes.sizeof(Config)
     c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -175,6 +178,7 @@ def make_config(precision="fp64", ionize=True, ofi_field="laser_only", lambda_um
     c.diag_every, c.max_records, c.max_splits, c.seed = diag_every, max_records, max_splits, seed
     c.max_pair_blocks = max_pair_blocks
     c.detector_r0, c.detector_half_angle_deg = detector_r0, detector_half_angle_deg
+    c.boundary, c.box_r0, c.t_switch = BOUNDARIES[boundary], box_r0, t_switch
     return c
 
 

@@ -20,10 +20,7 @@ FLAGS = [
 ]
 
 
-def build(verbose=False):
-    srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    tmp = LIB + ".tmp"
-    cmd = ["hipcc"] + FLAGS + ["-o", tmp] + srcs
+def _run(cmd, what, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -31,9 +28,25 @@ def build(verbose=False):
     errs = [l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l]
     if r.returncode != 0:
         sys.stderr.write("\n".join(errs) + "\n")
-        raise RuntimeError("hipcc failed building liblcmd.so")
+        raise RuntimeError(f"hipcc failed building {what}")
     if verbose and errs:
         sys.stderr.write("\n".join(errs) + "\n")
+
+
+def build(verbose=False):
+    """Compile every source to an object in parallel (one hipcc per file), then link."""
+    from concurrent.futures import ThreadPoolExecutor
+    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    obj_dir = os.path.join(HERE, "_build")
+    os.makedirs(obj_dir, exist_ok=True)
+    objs = [os.path.join(obj_dir, os.path.splitext(s)[0] + ".o") for s in srcs]
+    cflags = [f for f in FLAGS if f != "-shared"]
+    jobs = [(["hipcc"] + cflags + ["-c", "-o", o, os.path.join(CSRC, s)], s) for s, o in zip(srcs, objs)]
+    with ThreadPoolExecutor(max_workers=min(len(jobs), os.cpu_count() or 1)) as ex:
+        for f in [ex.submit(_run, cmd, what, verbose) for cmd, what in jobs]:
+            f.result()
+    tmp = LIB + ".tmp"
+    _run(["hipcc"] + FLAGS + ["-o", tmp] + objs, "liblcmd.so", verbose)
     os.replace(tmp, LIB)
     return LIB
 

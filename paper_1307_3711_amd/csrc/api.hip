@@ -81,6 +81,12 @@ bool valid_config(const lc_config* cfg, std::string* why) {
   if (cfg->ionize != 0 && cfg->ionize != 1) { *why = "ionize must be 0 or 1"; return false; }
   if (cfg->ofi_field != LC_LASER_ONLY && cfg->ofi_field != LC_LOCAL) { *why = "unknown ofi_field"; return false; }
   if (!(cfg->detector_r0 >= 0.0) || !std::isfinite(cfg->detector_r0)) { *why = "detector_r0 must be >= 0"; return false; }
+  if (cfg->boundary < LC_OPEN || cfg->boundary > LC_MIXED) { *why = "unknown boundary"; return false; }
+  if (cfg->boundary != LC_OPEN) {
+    if (!(cfg->box_r0 > 0.0) || !std::isfinite(cfg->box_r0)) { *why = "box_r0 must be > 0"; return false; }
+    if (cfg->precision == LC_FP32_KAHAN) { *why = "periodic boundaries need LC_FP64 or LC_FP32_ACC64"; return false; }
+    if (cfg->boundary == LC_MIXED && std::isnan(cfg->t_switch)) { *why = "t_switch must not be NaN"; return false; }
+  }
   if (cfg->detector_r0 > 0.0 && !(cfg->detector_half_angle_deg > 0.0 && cfg->detector_half_angle_deg < 90.0)) {
     *why = "detector_half_angle_deg must be in (0, 90)";
     return false;
@@ -214,6 +220,7 @@ struct lc_sim {
   bool started = false;
   int graph_steps = 0;
   hipGraphExec_t gexec = nullptr;
+  bool graph_pbc = false;   // boundary mode of the captured steps' field passes
   hipGraph_t graph = nullptr;
   std::string last_error;
   Units u;
@@ -229,6 +236,9 @@ int fail(lc_sim* s, int code, const std::string& msg) {
 int hip_fail(lc_sim* s, hipError_t e, const char* where) {
   return fail(s, LC_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
 }
+
+// Periodic boundaries in force at this step (its field pass, push and spawns).
+bool pbc_step(const lc_sim* s, int64_t step) { return periodic_at(s->rc, s->rc.t0 + (double)step * s->rc.dt); }
 
 bool is_diag_step(const lc_sim* s, int64_t step) {
   return s->cfg.diag_every > 0 && (step % s->cfg.diag_every) == 0;
@@ -306,7 +316,8 @@ hipError_t enqueue_steps(lc_sim* s, int count, int64_t first_step) {
     const bool diag = is_diag_step(s, first_step + k);
     const bool n3 = n3_pass(s, ft, diag);
     const FieldLayout fl = field_layout(ft, n3);
-    hipError_t e = launch_force(s->s, s->rc, s->cfg.precision, ft, diag, force_grid(s, ft, n3), s->stream, false);
+    hipError_t e = launch_force(s->s, s->rc, s->cfg.precision, ft, diag, pbc_step(s, first_step + k),
+                                force_grid(s, ft, n3), s->stream, false);
     if (e != hipSuccess) return e;
     e = n3 ? launch_fold_push(s->s, s->rc, s->cfg.precision, n3_block_size(ft), 0, diag, s->stream)
            : launch_push(s->s, s->rc, s->cfg.precision, fl, 0, diag, s->stream);
@@ -441,6 +452,8 @@ int lc_create(lc_sim** out, const lc_config* cfg, const lc_cluster* clusters, in
   rc.n_total = L.n_total;
   rc.mec2_ev = kMec2Ev;
   rc.det_on = cfg->detector_r0 > 0.0 ? 1 : 0;
+  rc.boundary = cfg->boundary;
+  rc.t_switch = cfg->t_switch;
   if (rc.det_on) {
     const double ca = std::cos(cfg->detector_half_angle_deg * (M_PI / 180.0));
     rc.det_cos2 = ca * ca;
@@ -460,6 +473,7 @@ int lc_create(lc_sim** out, const lc_config* cfg, const lc_cluster* clusters, in
       const double dist = cfg->detector_r0 * (k.r0_nm * 1e-9 * s->u.k);
       p.det_r2 = dist * dist;
     }
+    p.box = (cfg->boundary != LC_OPEN) ? cfg->box_r0 * (k.r0_nm * 1e-9 * s->u.k) : 0.0;
     n3_off += 3 * (int64_t)cfg->max_pair_blocks * n3_round(k.capacity);
     p.cap = k.capacity;
     p.n_ion = k.n_ion;
@@ -599,7 +613,8 @@ int lc_start(lc_sim* s) {
   const bool n3 = n3_pass(s, ft, false);
   hipError_t e = launch_refresh_sources(s->s, s->rc, s->cfg.precision, s->stream);
   if (e == hipSuccess) e = schedule(s, ft, n3, false);
-  if (e == hipSuccess) e = launch_force(s->s, s->rc, s->cfg.precision, ft, false, force_grid(s, ft, n3), s->stream);
+  if (e == hipSuccess)
+    e = launch_force(s->s, s->rc, s->cfg.precision, ft, false, pbc_step(s, 0), force_grid(s, ft, n3), s->stream);
   if (e == hipSuccess) e = launch_start_kick(s->s, s->rc, s->cfg.precision, field_layout(ft, n3), s->stream);
   // tables of step 0
   if (e == hipSuccess) e = schedule(s, ft, n3_pass(s, ft, is_diag_step(s, 0)), false);
@@ -627,16 +642,22 @@ int lc_step(lc_sim* s, int64_t n_steps) {
   while (left > 0) {
     const int G = s->graph_steps;
     const bool aligned = de <= 0 || (s->step % de) == 0;
-    if (G > 0 && left >= G && aligned) {
+    // a captured group of steps bakes in the boundary mode of its field passes: replay only
+    // where the mode is the same for the whole group (it changes at most once, periodic to open)
+    const bool pbc = pbc_step(s, s->step);
+    const bool one_mode = G <= 0 || pbc_step(s, s->step + G - 1) == pbc;
+    if (G > 0 && left >= G && aligned && one_mode) {
+      if (s->gexec && s->graph_pbc != pbc) drop_graph(s);
       if (!s->gexec) {
         hipError_t e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(s, e, "hipStreamBeginCapture");
-        hipError_t e2 = enqueue_steps(s, G, 0);
+        hipError_t e2 = enqueue_steps(s, G, s->step);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(s->stream, &g);
         if (e2 != hipSuccess) { if (g) (void)hipGraphDestroy(g); return hip_fail(s, e2, "capturing steps"); }
         if (e != hipSuccess) return hip_fail(s, e, "hipStreamEndCapture");
         s->graph = g;
+        s->graph_pbc = pbc;
         e = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0);
         if (e != hipSuccess) { drop_graph(s); return hip_fail(s, e, "hipGraphInstantiate"); }
       }
@@ -894,7 +915,8 @@ int field_snapshot(lc_sim* s, const ForceTiling& ft, std::vector<double>& out) {
   const int64_t NT = s->L.n_total;
   const bool n3 = n3_pass(s, ft, false);
   hipError_t e = schedule(s, ft, n3, false);
-  if (e == hipSuccess) e = launch_force(s->s, s->rc, s->cfg.precision, ft, false, force_grid(s, ft, n3), s->stream);
+  if (e == hipSuccess)
+    e = launch_force(s->s, s->rc, s->cfg.precision, ft, false, pbc_step(s, s->step), force_grid(s, ft, n3), s->stream);
   if (e == hipSuccess) {
     // all reads of split 0 happen in the same thread before its writes
     k_fold_partials<<<(int)((NT + kBlock - 1) / kBlock), kBlock, 0, s->stream>>>(s->s, s->rc, field_layout(ft, n3));
@@ -998,11 +1020,12 @@ extern "C" int lc_autotune(lc_sim* s, const char* cache_json, lc_tuning* chosen)
     const bool n3 = ft.newton3 != 0;
     const int grid = force_grid(s, ft, n3);
     hipError_t e = schedule(s, ft, n3, false);
-    if (e == hipSuccess) e = launch_force(s->s, s->rc, prec, ft, false, grid, s->stream);  // warm
+    const bool pbc = pbc_step(s, s->step);
+    if (e == hipSuccess) e = launch_force(s->s, s->rc, prec, ft, false, pbc, grid, s->stream);  // warm
     if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
     for (int r = 0; r < reps && e == hipSuccess; ++r) {
       e = schedule(s, ft, n3, false);
-      if (e == hipSuccess) e = launch_force(s->s, s->rc, prec, ft, false, grid, s->stream);
+      if (e == hipSuccess) e = launch_force(s->s, s->rc, prec, ft, false, pbc, grid, s->stream);
     }
     if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -1107,7 +1130,8 @@ extern "C" int lc_profile_steps(lc_sim* s, int64_t n_steps, double* out_ms, int6
       hipEvent_t* E = &ev[8 * k];
       e = hipEventRecord(E[0], s->stream);
       if (e == hipSuccess)
-        e = launch_force(s->s, s->rc, s->cfg.precision, ft, diag, force_grid(s, ft, n3), s->stream, false);
+        e = launch_force(s->s, s->rc, s->cfg.precision, ft, diag, pbc_step(s, s->step), force_grid(s, ft, n3),
+                         s->stream, false);
       if (e == hipSuccess) e = hipEventRecord(E[1], s->stream);
       used[4 * k + 0] = 1;
       // with a pair-once tiling the one-sided pass of a diagnostic step (potential included)

@@ -80,6 +80,11 @@ __device__ inline double rsq64(double x) {
   return __builtin_fma(y * e, p, y);
 }
 
+// Minimum-image separation in a periodic cube of side L (iL = 1/L): the nearest periodic copy
+// of the partner (Sec. II periodic boundaries); a separation inside (-L/2, L/2) is unchanged.
+__device__ inline float min_image(float d, float L, float iL) { return __builtin_fmaf(-L, __builtin_rintf(d * iL), d); }
+__device__ inline double min_image(double d, double L, double iL) { return __builtin_fma(-L, __builtin_rint(d * iL), d); }
+
 __device__ inline float n3_rsq(float x) { return rsq32(x); }
 __device__ inline double n3_rsq(double x) { return rsq64(x); }
 
@@ -90,19 +95,24 @@ __device__ inline double n3_rsq(double x) { return rsq64(x); }
 // src is an LDS tile, or a global source array read with wave-uniform indices (the compiler
 // then issues scalar loads and the pair arithmetic takes SGPR operands).  The sums and the
 // Kahan compensations (cx..cpc) accumulate onto the caller's registers.
-template <int R, bool PHI, bool KAHAN, bool UNIFORM, int U, typename P>
+template <int R, bool PHI, bool KAHAN, bool UNIFORM, int U, bool PBC, typename P>
 __device__ inline void pair_loop(P src, int kb, int per, int64_t jt, const int64_t* ii, const float* xi,
                                  const float* yi, const float* zi, float eps2f, float* fx, float* fy, float* fz,
-                                 float* fp, float* cx, float* cy, float* cz, float* cpc) {
+                                 float* fp, float* cx, float* cy, float* cz, float* cpc, float L, float iL) {
   for (int k = kb; k < kb + per; k += U) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const float4 sj = src[k + u];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const float dx = xi[r] - sj.x;
-        const float dy = yi[r] - sj.y;
-        const float dz = zi[r] - sj.z;
+        float dx = xi[r] - sj.x;
+        float dy = yi[r] - sj.y;
+        float dz = zi[r] - sj.z;
+        if (PBC) {
+          dx = min_image(dx, L, iL);
+          dy = min_image(dy, L, iL);
+          dz = min_image(dz, L, iL);
+        }
         float r2 = __builtin_fmaf(dx, dx, eps2f);
         r2 = __builtin_fmaf(dy, dy, r2);
         r2 = __builtin_fmaf(dz, dz, r2);
@@ -133,7 +143,7 @@ __device__ inline void pair_loop(P src, int kb, int per, int64_t jt, const int64
 }
 
 // ----------------------------------------------------------------------------- FP32 body
-template <int R, int WJ, bool PHI, bool KAHAN, bool SCALAR>
+template <int R, int WJ, bool PHI, bool KAHAN, bool SCALAR, bool PBC>
 __device__ void tile_f32(const ForceArgs<float4>& a, const float4* __restrict__ gsrc, int t, float4* lds) {
   int c, ib, s;
   decode_tile(a.map, t, a.S, c, ib, s);
@@ -163,6 +173,8 @@ __device__ void tile_f32(const ForceArgs<float4>& a, const float4* __restrict__ 
 #pragma unroll
   for (int r = 0; r < R; ++r) { ex[r] = ey[r] = ez[r] = ep[r] = 0.0; }
   const float eps2f = (float)a.eps2;
+  const float L = PBC ? (float)cp.box : 0.f;
+  const float iL = PBC ? 1.f / L : 0.f;
 
   if constexpr (SCALAR) {
     // Sources straight from global memory with wave-uniform indices: scalar loads, SGPR
@@ -185,13 +197,15 @@ __device__ void tile_f32(const ForceArgs<float4>& a, const float4* __restrict__ 
       for (int r = 0; r < R; ++r) { fx[r] = fy[r] = fz[r] = fp[r] = 0.f; cx[r] = cy[r] = cz[r] = cpc[r] = 0.f; }
       const float4* __restrict__ seg = base + jt;
       if (uniform) {
-        pair_loop<R, PHI, KAHAN, true, kU>(seg, 0, main, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy, cz, cpc);
-        pair_loop<R, PHI, KAHAN, true, 1>(seg, main, cnt - main, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy, cz,
-                                          cpc);
+        pair_loop<R, PHI, KAHAN, true, kU, PBC>(seg, 0, main, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy, cz, cpc,
+                                                 L, iL);
+        pair_loop<R, PHI, KAHAN, true, 1, PBC>(seg, main, cnt - main, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy,
+                                               cz, cpc, L, iL);
       } else {
-        pair_loop<R, PHI, KAHAN, false, kU>(seg, 0, main, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy, cz, cpc);
-        pair_loop<R, PHI, KAHAN, false, 1>(seg, main, cnt - main, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy, cz,
-                                           cpc);
+        pair_loop<R, PHI, KAHAN, false, kU, PBC>(seg, 0, main, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy, cz,
+                                                  cpc, L, iL);
+        pair_loop<R, PHI, KAHAN, false, 1, PBC>(seg, main, cnt - main, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx,
+                                                cy, cz, cpc, L, iL);
       }
       const double qs = uniform ? (double)q0 : 1.0;
 #pragma unroll
@@ -208,28 +222,32 @@ __device__ void tile_f32(const ForceArgs<float4>& a, const float4* __restrict__ 
     const int cntp = (cnt + kU * WJ - 1) / (kU * WJ) * (kU * WJ);
     // Padding entries sit at 1e30: r^2 overflows to +inf, v_rsq_f32(+inf) = +0, so they add
     // exactly zero on both inner loops.  A tile whose sources all carry the same charge takes
-    // the uniform loop, which factors the charge out of the pair term.
+    // the uniform loop, which factors the charge out of the pair term.  With periodic
+    // boundaries the minimum image would bring such an entry close, so padding sits at the
+    // origin with zero charge and every tile takes the loop that multiplies by the charge.
     const float q0 = a.src[off + jt].w;
     int same = 1;
     __syncthreads();
     for (int k = tid; k < cntp; k += kBlock) {
-      float4 v = make_float4(1e30f, 1e30f, 1e30f, 0.f);
+      float4 v = PBC ? make_float4(0.f, 0.f, 0.f, 0.f) : make_float4(1e30f, 1e30f, 1e30f, 0.f);
       if (k < cnt) {
         v = a.src[off + jt + k];
         same &= (v.w == q0);
       }
       lds[k] = v;
     }
-    const int uniform = __syncthreads_and(same);
+    const int uniform = __syncthreads_and(same) && !PBC;
     const int per = cntp / WJ;
     const int kb = jw * per;
     float fx[R], fy[R], fz[R], fp[R], cx[R], cy[R], cz[R], cpc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) { fx[r] = fy[r] = fz[r] = fp[r] = 0.f; cx[r] = cy[r] = cz[r] = cpc[r] = 0.f; }
-    if (uniform)
-      pair_loop<R, PHI, KAHAN, true, kU>(lds, kb, per, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy, cz, cpc);
+    if (uniform && !PBC)
+      pair_loop<R, PHI, KAHAN, true, kU, PBC>(lds, kb, per, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy, cz, cpc,
+                                              L, iL);
     else
-      pair_loop<R, PHI, KAHAN, false, kU>(lds, kb, per, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy, cz, cpc);
+      pair_loop<R, PHI, KAHAN, false, kU, PBC>(lds, kb, per, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy, cz, cpc,
+                                               L, iL);
     const double qs = uniform ? (double)q0 : 1.0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -285,7 +303,7 @@ __device__ void tile_f32(const ForceArgs<float4>& a, const float4* __restrict__ 
 }
 
 // ----------------------------------------------------------------------------- FP64 body
-template <int R, int WJ, bool PHI>
+template <int R, int WJ, bool PHI, bool PBC>
 __device__ void tile_f64(const ForceArgs<double4>& a, int t, double4* lds) {
   int c, ib, s;
   decode_tile(a.map, t, a.S, c, ib, s);
@@ -315,6 +333,8 @@ __device__ void tile_f64(const ForceArgs<double4>& a, int t, double4* lds) {
 #pragma unroll
   for (int r = 0; r < R; ++r) { ex[r] = ey[r] = ez[r] = ep[r] = 0.0; }
   const double eps2 = a.eps2;
+  const double L = PBC ? cp.box : 0.0;
+  const double iL = PBC ? 1.0 / L : 0.0;
 
   for (int64_t jt = j0; jt < j1; jt += a.T) {
     const int cnt = (int)((j1 - jt < a.T) ? (j1 - jt) : a.T);
@@ -331,9 +351,14 @@ __device__ void tile_f64(const ForceArgs<double4>& a, int t, double4* lds) {
         const double4 sj = lds[k + u];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const double dx = xi[r] - sj.x;
-          const double dy = yi[r] - sj.y;
-          const double dz = zi[r] - sj.z;
+          double dx = xi[r] - sj.x;
+          double dy = yi[r] - sj.y;
+          double dz = zi[r] - sj.z;
+          if (PBC) {
+            dx = min_image(dx, L, iL);
+            dy = min_image(dy, L, iL);
+            dz = min_image(dz, L, iL);
+          }
           double r2 = __builtin_fma(dx, dx, eps2);
           r2 = __builtin_fma(dy, dy, r2);
           r2 = __builtin_fma(dz, dz, r2);
@@ -491,16 +516,22 @@ __host__ __device__ constexpr int n3_slices(int waves) { return waves * 4 * kN3S
 // sum_r q_r s_r (r_i - r_j) of the chunk's sources, returned in (ax, ay, az) of lane l for
 // source l.
 // U rotations of the chunk from the register buffers (bx, by, bz, bq) holding their sources.
-template <typename T, int R, int U, bool US, bool UT, bool JSIDE>
+template <typename T, int R, int U, bool US, bool UT, bool JSIDE, bool PBC>
 __device__ inline void n3_steps(const T* bx, const T* by, const T* bz, const T* bq, const T* xi, const T* yi,
-                                const T* zi, const T* qi, T eps2f, T* fx, T* fy, T* fz, T& rx, T& ry, T& rz) {
+                                const T* zi, const T* qi, T eps2f, T* fx, T* fy, T* fz, T& rx, T& ry, T& rz, T L,
+                                T iL) {
 #pragma unroll
   for (int u = 0; u < U; ++u) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const T dx = xi[r] - bx[u];
-      const T dy = yi[r] - by[u];
-      const T dz = zi[r] - bz[u];
+      T dx = xi[r] - bx[u];
+      T dy = yi[r] - by[u];
+      T dz = zi[r] - bz[u];
+      if (PBC) {
+        dx = min_image(dx, L, iL);
+        dy = min_image(dy, L, iL);
+        dz = min_image(dz, L, iL);
+      }
       T r2 = n3_fma(dx, dx, eps2f);
       r2 = n3_fma(dy, dy, r2);
       r2 = n3_fma(dz, dz, r2);
@@ -544,9 +575,9 @@ __device__ inline void n3_load(const T* sx, int k, T* bx, T* by, T* bz, T* bq) {
 // source l.  Software pipelined over two register buffers: the sources of the next U
 // rotations are read while the current U are used (the slice has kN3Slice >= 128 + U
 // entries, so the read after the last rotation stays inside it).
-template <typename T, int R, bool US, bool UT, bool JSIDE>
+template <typename T, int R, bool US, bool UT, bool JSIDE, bool PBC>
 __device__ inline void n3_chunk(const T* sb, int lane, const T* xi, const T* yi, const T* zi, const T* qi, T eps2f,
-                                T* fx, T* fy, T* fz, T& ax, T& ay, T& az) {
+                                T* fx, T* fy, T* fz, T& ax, T& ay, T& az, T L, T iL) {
   constexpr int U = (R >= 4 || sizeof(T) == 8) ? 2 : 4;  // rotations per register buffer
   static_assert(128 + U <= kN3Slice && 64 % (2 * U) == 0, "prefetch stays inside the wave's slice");
   const T* sx = sb + lane;
@@ -555,9 +586,9 @@ __device__ inline void n3_chunk(const T* sb, int lane, const T* xi, const T* yi,
   n3_load<T, U, US>(sx, 0, ax_, ay_, az_, aq_);
   for (int k0 = 0; k0 < 64; k0 += 2 * U) {
     n3_load<T, U, US>(sx, k0 + U, bx_, by_, bz_, bq_);
-    n3_steps<T, R, U, US, UT, JSIDE>(ax_, ay_, az_, aq_, xi, yi, zi, qi, eps2f, fx, fy, fz, rx, ry, rz);
+    n3_steps<T, R, U, US, UT, JSIDE, PBC>(ax_, ay_, az_, aq_, xi, yi, zi, qi, eps2f, fx, fy, fz, rx, ry, rz, L, iL);
     n3_load<T, U, US>(sx, k0 + 2 * U, ax_, ay_, az_, aq_);
-    n3_steps<T, R, U, US, UT, JSIDE>(bx_, by_, bz_, bq_, xi, yi, zi, qi, eps2f, fx, fy, fz, rx, ry, rz);
+    n3_steps<T, R, U, US, UT, JSIDE, PBC>(bx_, by_, bz_, bq_, xi, yi, zi, qi, eps2f, fx, fy, fz, rx, ry, rz, L, iL);
   }
   ax = rx;
   ay = ry;
@@ -571,7 +602,7 @@ __host__ __device__ constexpr int n3_groups(int R, int WJ) { return (R == WJ && 
 __host__ __device__ constexpr int n3_waves(int R, int WJ) { return n3_groups(R, WJ) * WJ; }
 __host__ __device__ constexpr int n3_block(int R, int WJ) { return n3_groups(R, WJ) * 64 * R; }
 
-template <typename T, int R, int WJ>
+template <typename T, int R, int WJ, bool PBC>
 __device__ void tile_n3(const N3Args<T>& a, int t, T* lds) {
   using V4 = typename N3Type<T>::V4;
   constexpr T kFar = N3Type<T>::kFar;
@@ -606,14 +637,21 @@ __device__ void tile_n3(const N3Args<T>& a, int t, T* lds) {
       const V4 p = src[ii];
       xi[r] = p.x; yi[r] = p.y; zi[r] = p.z; qi[r] = p.w;
       same_t &= (p.w == qT);
+    } else if (PBC) {
+      // the minimum image would bring a far entry close: zero charge at the origin instead
+      xi[r] = yi[r] = zi[r] = 0;
+      qi[r] = 0;
     } else {
       // far away: both sides add exactly zero (see N3Type)
       xi[r] = yi[r] = zi[r] = kFar;
       qi[r] = qT;
     }
   }
-  const bool ut = __all(same_t);
+  // periodic boundaries: no uniform-charge factoring (the padding carries charge 0)
+  const bool ut = __all(same_t) && !PBC;
   const T eps2f = (T)a.eps2;
+  const T L = PBC ? (T)cp.box : T(0);
+  const T iL = PBC ? T(1) / L : T(0);
   T ex[R], ey[R], ez[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) ex[r] = ey[r] = ez[r] = 0;
@@ -625,9 +663,10 @@ __device__ void tile_n3(const N3Args<T>& a, int t, T* lds) {
       const int64_t jj = jb + lane;
       V4 sv;
       if (jj < n) sv = src[jj];
+      else if (PBC) { sv.x = 0; sv.y = 0; sv.z = 0; sv.w = 0; }
       else { sv.x = kFar; sv.y = kFar; sv.z = kFar; sv.w = 0; }
       const T qs0 = src[jb].w;
-      const bool us = __all(jj >= n || sv.w == qs0);
+      const bool us = __all(jj >= n || sv.w == qs0) && !PBC;
       sb[lane] = sv.x;
       sb[lane + 64] = sv.x;
       sb[kN3Slice + lane] = sv.y;
@@ -640,17 +679,20 @@ __device__ void tile_n3(const N3Args<T>& a, int t, T* lds) {
       T cx[R], cy[R], cz[R], ax, ay, az;
 #pragma unroll
       for (int r = 0; r < R; ++r) cx[r] = cy[r] = cz[r] = 0;
-      if (jside) {
+      if constexpr (PBC) {
+        if (jside) n3_chunk<T, R, false, false, true, true>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az, L, iL);
+        else n3_chunk<T, R, false, false, false, true>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az, L, iL);
+      } else if (jside) {
         if (us) {
-          if (ut) n3_chunk<T, R, true, true, true>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az);
-          else n3_chunk<T, R, true, false, true>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az);
+          if (ut) n3_chunk<T, R, true, true, true, false>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az, L, iL);
+          else n3_chunk<T, R, true, false, true, false>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az, L, iL);
         } else {
-          if (ut) n3_chunk<T, R, false, true, true>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az);
-          else n3_chunk<T, R, false, false, true>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az);
+          if (ut) n3_chunk<T, R, false, true, true, false>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az, L, iL);
+          else n3_chunk<T, R, false, false, true, false>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az, L, iL);
         }
       } else {
-        if (us) n3_chunk<T, R, true, true, false>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az);
-        else n3_chunk<T, R, false, true, false>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az);
+        if (us) n3_chunk<T, R, true, true, false, false>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az, L, iL);
+        else n3_chunk<T, R, false, true, false, false>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az, L, iL);
       }
       wave_lds_sync();
       const T fs = us ? qs0 : T(1);
@@ -766,7 +808,7 @@ __global__ __launch_bounds__(64 * kFoldWaves) void k_fold_n3(DevState s, RunCons
 // ----------------------------------------------------------------------------- kernels
 // Occupancy the register allocation aims at: 5 waves per SIMD for FP32 pairs (85 VGPRs at
 // R = 4, no spills; 4 from R = 6), 3 for FP64 pairs (twice the registers per value; 2 from R = 5).
-template <typename T, int R, int WJ>
+template <typename T, int R, int WJ, bool PBC>
 __global__ __launch_bounds__(64 * n3_waves(R, WJ))
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? (R >= 5 ? 2 : 3) : (R >= 6 ? 4 : 5))))
 void k_force_n3(N3Args<T> a) {
@@ -777,7 +819,7 @@ void k_force_n3(N3Args<T> a) {
     // one tile per block when the grid covers the tiles, else a block-strided walk over them
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
       if (t != (int)blockIdx.x) __syncthreads();
-      tile_n3<T, R, WJ>(a, t, lds_n3);
+      tile_n3<T, R, WJ, PBC>(a, t, lds_n3);
     }
     return;
   }
@@ -788,18 +830,18 @@ void k_force_n3(N3Args<T> a) {
     __syncthreads();
     const int t = sh_t;
     if (t >= total) break;
-    tile_n3<T, R, WJ>(a, t, lds_n3);
+    tile_n3<T, R, WJ, PBC>(a, t, lds_n3);
   }
 }
 
-template <int R, int WJ, bool PHI, bool KAHAN, bool SCALAR>
+template <int R, int WJ, bool PHI, bool KAHAN, bool SCALAR, bool PBC>
 __global__ __launch_bounds__(kBlock) void k_force_f32(ForceArgs<float4> a, const float4* __restrict__ gsrc) {
   extern __shared__ float4 lds32[];
   const int total = *a.map.tile_total;
   if (!a.persistent) {
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
       if (t != (int)blockIdx.x) __syncthreads();
-      tile_f32<R, WJ, PHI, KAHAN, SCALAR>(a, gsrc, t, lds32);
+      tile_f32<R, WJ, PHI, KAHAN, SCALAR, PBC>(a, gsrc, t, lds32);
     }
     return;
   }
@@ -810,18 +852,18 @@ __global__ __launch_bounds__(kBlock) void k_force_f32(ForceArgs<float4> a, const
     __syncthreads();
     const int t = sh_t;
     if (t >= total) break;
-    tile_f32<R, WJ, PHI, KAHAN, SCALAR>(a, gsrc, t, lds32);
+    tile_f32<R, WJ, PHI, KAHAN, SCALAR, PBC>(a, gsrc, t, lds32);
   }
 }
 
-template <int R, int WJ, bool PHI>
+template <int R, int WJ, bool PHI, bool PBC>
 __global__ __launch_bounds__(kBlock) void k_force_f64(ForceArgs<double4> a) {
   extern __shared__ double4 lds64[];
   const int total = *a.map.tile_total;
   if (!a.persistent) {
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
       if (t != (int)blockIdx.x) __syncthreads();
-      tile_f64<R, WJ, PHI>(a, t, lds64);
+      tile_f64<R, WJ, PHI, PBC>(a, t, lds64);
     }
     return;
   }
@@ -832,7 +874,7 @@ __global__ __launch_bounds__(kBlock) void k_force_f64(ForceArgs<double4> a) {
     __syncthreads();
     const int t = sh_t;
     if (t >= total) break;
-    tile_f64<R, WJ, PHI>(a, t, lds64);
+    tile_f64<R, WJ, PHI, PBC>(a, t, lds64);
   }
 }
 
@@ -843,31 +885,48 @@ size_t force_lds_bytes(int precision, const ForceTiling& ft, bool phi) {
   return tile > red ? tile : red;
 }
 
+// pbc: minimum-image separations (periodic boundaries); not with Kahan sums.
 template <int R, int WJ>
-hipError_t dispatch_f32(const ForceArgs<float4>& a, bool phi, int kahan, int scalar, int grid, size_t lds,
+hipError_t dispatch_f32(const ForceArgs<float4>& a, bool phi, int kahan, int scalar, bool pbc, int grid, size_t lds,
                         hipStream_t st) {
+  if (pbc) {
+    if (kahan) return hipErrorInvalidValue;
+    if (scalar) {
+      if (phi) k_force_f32<R, WJ, true, false, true, true><<<grid, kBlock, lds, st>>>(a, a.src);
+      else k_force_f32<R, WJ, false, false, true, true><<<grid, kBlock, lds, st>>>(a, a.src);
+    } else {
+      if (phi) k_force_f32<R, WJ, true, false, false, true><<<grid, kBlock, lds, st>>>(a, a.src);
+      else k_force_f32<R, WJ, false, false, false, true><<<grid, kBlock, lds, st>>>(a, a.src);
+    }
+    return hipGetLastError();
+  }
   if (scalar) {
     if (kahan) {
-      if (phi) k_force_f32<R, WJ, true, true, true><<<grid, kBlock, lds, st>>>(a, a.src);
-      else k_force_f32<R, WJ, false, true, true><<<grid, kBlock, lds, st>>>(a, a.src);
+      if (phi) k_force_f32<R, WJ, true, true, true, false><<<grid, kBlock, lds, st>>>(a, a.src);
+      else k_force_f32<R, WJ, false, true, true, false><<<grid, kBlock, lds, st>>>(a, a.src);
     } else {
-      if (phi) k_force_f32<R, WJ, true, false, true><<<grid, kBlock, lds, st>>>(a, a.src);
-      else k_force_f32<R, WJ, false, false, true><<<grid, kBlock, lds, st>>>(a, a.src);
+      if (phi) k_force_f32<R, WJ, true, false, true, false><<<grid, kBlock, lds, st>>>(a, a.src);
+      else k_force_f32<R, WJ, false, false, true, false><<<grid, kBlock, lds, st>>>(a, a.src);
     }
   } else if (kahan) {
-    if (phi) k_force_f32<R, WJ, true, true, false><<<grid, kBlock, lds, st>>>(a, a.src);
-    else k_force_f32<R, WJ, false, true, false><<<grid, kBlock, lds, st>>>(a, a.src);
+    if (phi) k_force_f32<R, WJ, true, true, false, false><<<grid, kBlock, lds, st>>>(a, a.src);
+    else k_force_f32<R, WJ, false, true, false, false><<<grid, kBlock, lds, st>>>(a, a.src);
   } else {
-    if (phi) k_force_f32<R, WJ, true, false, false><<<grid, kBlock, lds, st>>>(a, a.src);
-    else k_force_f32<R, WJ, false, false, false><<<grid, kBlock, lds, st>>>(a, a.src);
+    if (phi) k_force_f32<R, WJ, true, false, false, false><<<grid, kBlock, lds, st>>>(a, a.src);
+    else k_force_f32<R, WJ, false, false, false, false><<<grid, kBlock, lds, st>>>(a, a.src);
   }
   return hipGetLastError();
 }
 
 template <int R, int WJ>
-hipError_t dispatch_f64(const ForceArgs<double4>& a, bool phi, int grid, size_t lds, hipStream_t st) {
-  if (phi) k_force_f64<R, WJ, true><<<grid, kBlock, lds, st>>>(a);
-  else k_force_f64<R, WJ, false><<<grid, kBlock, lds, st>>>(a);
+hipError_t dispatch_f64(const ForceArgs<double4>& a, bool phi, bool pbc, int grid, size_t lds, hipStream_t st) {
+  if (pbc) {
+    if (phi) k_force_f64<R, WJ, true, true><<<grid, kBlock, lds, st>>>(a);
+    else k_force_f64<R, WJ, false, true><<<grid, kBlock, lds, st>>>(a);
+  } else {
+    if (phi) k_force_f64<R, WJ, true, false><<<grid, kBlock, lds, st>>>(a);
+    else k_force_f64<R, WJ, false, false><<<grid, kBlock, lds, st>>>(a);
+  }
   return hipGetLastError();
 }
 
@@ -899,7 +958,8 @@ int n3_resident_t(const ForceTiling& ft) {
   hipError_t e = hipErrorInvalidValue;
   switch (ft.WJ * 16 + ft.R) {
 #define LC_N3_OCC(R_, WJ_)                                                                         \
-  case WJ_ * 16 + R_: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<T, R_, WJ_>, threads, lds); break;
+  case WJ_ * 16 + R_:                                                                               \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_n3<T, R_, WJ_, false>, threads, lds); break;
     LC_N3_SHAPES(LC_N3_OCC)
 #undef LC_N3_OCC
     default: break;
@@ -916,12 +976,15 @@ int n3_resident_per_cu(int precision, const ForceTiling& ft) {
 }
 
 template <typename T>
-hipError_t launch_n3(const ForceTiling& ft, const N3Args<T>& a, int grid, hipStream_t st) {
+hipError_t launch_n3(const ForceTiling& ft, const N3Args<T>& a, int grid, bool pbc, hipStream_t st) {
   const size_t lds = n3_lds_bytes(ft, sizeof(T));
   const int threads = 64 * n3_waves(ft.R, ft.WJ);
   switch (ft.WJ * 16 + ft.R) {
-#define LC_N3_LAUNCH(R_, WJ_) \
-  case WJ_ * 16 + R_: k_force_n3<T, R_, WJ_><<<grid, threads, lds, st>>>(a); break;
+#define LC_N3_LAUNCH(R_, WJ_)                                                     \
+  case WJ_ * 16 + R_:                                                             \
+    if (pbc) k_force_n3<T, R_, WJ_, true><<<grid, threads, lds, st>>>(a);        \
+    else k_force_n3<T, R_, WJ_, false><<<grid, threads, lds, st>>>(a);           \
+    break;
     LC_N3_SHAPES(LC_N3_LAUNCH)
 #undef LC_N3_LAUNCH
     default: return hipErrorInvalidValue;
@@ -938,26 +1001,26 @@ hipError_t launch_n3(const ForceTiling& ft, const N3Args<T>& a, int grid, hipStr
   }
 
 hipError_t launch_generic(int precision, const ForceTiling& ft, const TileMap& map, const void* src,
-                          double* part, int64_t stride, double eps2, bool phi, int grid, hipStream_t st) {
+                          double* part, int64_t stride, double eps2, bool phi, bool pbc, int grid, hipStream_t st) {
   const size_t lds = force_lds_bytes(precision, ft, phi);
   if (precision == LC_FP64) {
     ForceArgs<double4> a{(const double4*)src, part, stride, eps2, ft.T, ft.S, ft.persistent, map};
     switch (ft.R) {
-      case 1: LC_WJ_SWITCH(1, dispatch_f64, a, phi, grid, lds, st)
-      case 2: LC_WJ_SWITCH(2, dispatch_f64, a, phi, grid, lds, st)
-      case 4: LC_WJ_SWITCH(4, dispatch_f64, a, phi, grid, lds, st)
+      case 1: LC_WJ_SWITCH(1, dispatch_f64, a, phi, pbc, grid, lds, st)
+      case 2: LC_WJ_SWITCH(2, dispatch_f64, a, phi, pbc, grid, lds, st)
+      case 4: LC_WJ_SWITCH(4, dispatch_f64, a, phi, pbc, grid, lds, st)
       default: return hipErrorInvalidValue;
     }
   }
   ForceArgs<float4> a{(const float4*)src, part, stride, eps2, ft.T, ft.S, ft.persistent, map};
   const int kahan = (precision == LC_FP32_KAHAN);
   switch (ft.R) {
-    case 1: LC_WJ_SWITCH(1, dispatch_f32, a, phi, kahan, ft.scalar_src, grid, lds, st)
-    case 2: LC_WJ_SWITCH(2, dispatch_f32, a, phi, kahan, ft.scalar_src, grid, lds, st)
-    case 4: LC_WJ_SWITCH(4, dispatch_f32, a, phi, kahan, ft.scalar_src, grid, lds, st)
+    case 1: LC_WJ_SWITCH(1, dispatch_f32, a, phi, kahan, ft.scalar_src, pbc, grid, lds, st)
+    case 2: LC_WJ_SWITCH(2, dispatch_f32, a, phi, kahan, ft.scalar_src, pbc, grid, lds, st)
+    case 4: LC_WJ_SWITCH(4, dispatch_f32, a, phi, kahan, ft.scalar_src, pbc, grid, lds, st)
     case 8:
       if (ft.WJ != 1) return hipErrorInvalidValue;
-      return dispatch_f32<8, 1>(a, phi, kahan, ft.scalar_src, grid, lds, st);
+      return dispatch_f32<8, 1>(a, phi, kahan, ft.scalar_src, pbc, grid, lds, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1105,7 +1168,7 @@ bool force_tiling_valid(int precision, const ForceTiling& ft) {
 }
 
 hipError_t launch_force(const DevState& s, const RunConst& rc, int precision, const ForceTiling& ft,
-                        bool want_phi, int grid_blocks, hipStream_t st, bool fold_n3) {
+                        bool want_phi, bool pbc, int grid_blocks, hipStream_t st, bool fold_n3) {
   TileMap map{s.tile_start, s.order, s.cp, s.dyn, s.tile_total, s.queue, rc.n_clusters};
   if (ft.newton3 && !want_phi) {
     if (precision == LC_FP32_KAHAN || rc.n3_rows <= 0) return hipErrorInvalidValue;
@@ -1113,12 +1176,12 @@ hipError_t launch_force(const DevState& s, const RunConst& rc, int precision, co
     const int fb = (int)((rc.n_total + 63) / 64);
     if (precision == LC_FP64) {
       N3Args<double> a{s.posq, (double*)s.n3part, rc.n3_rows, rc.eps2, ft.persistent, map};
-      e = launch_n3(ft, a, grid_blocks, st);
+      e = launch_n3(ft, a, grid_blocks, pbc, st);
       if (e != hipSuccess || !fold_n3) return e;
       k_fold_n3<double><<<fb, 64 * kFoldWaves, 0, st>>>(s, rc, n3_block(ft.R, ft.WJ));
     } else {
       N3Args<float> a{s.pos4, (float*)s.n3part, rc.n3_rows, rc.eps2, ft.persistent, map};
-      e = launch_n3(ft, a, grid_blocks, st);
+      e = launch_n3(ft, a, grid_blocks, pbc, st);
       if (e != hipSuccess || !fold_n3) return e;
       k_fold_n3<float><<<fb, 64 * kFoldWaves, 0, st>>>(s, rc, n3_block(ft.R, ft.WJ));
     }
@@ -1126,7 +1189,7 @@ hipError_t launch_force(const DevState& s, const RunConst& rc, int precision, co
   }
   const void* src = (precision == LC_FP64) ? (const void*)s.posq : (const void*)s.pos4;
   const ForceTiling fr = ft.newton3 ? regular_tiling(precision, ft) : ft;
-  return launch_generic(precision, fr, map, src, s.part, rc.n_total, rc.eps2, want_phi, grid_blocks, st);
+  return launch_generic(precision, fr, map, src, s.part, rc.n_total, rc.eps2, want_phi, pbc, grid_blocks, st);
 }
 
 size_t field_workspace_bytes(int precision, int64_t n, const ForceTiling& ft) {
@@ -1169,18 +1232,18 @@ hipError_t launch_field_standalone(int precision, int64_t n, const double* xyzq,
     if (phi) return hipErrorInvalidValue;
     if (precision == LC_FP64) {
       N3Args<double> a{(const double4*)w.src, (double*)w.part, ib, eps2, ft.persistent, map};
-      e = launch_n3(ft, a, grid, st);
+      e = launch_n3(ft, a, grid, false, st);
       if (e != hipSuccess) return e;
       k_sum_n3<double><<<pb, kBlock, 0, st>>>((const double*)w.part, n, TI, E);
     } else {
       N3Args<float> a{(const float4*)w.src, (float*)w.part, ib, eps2, ft.persistent, map};
-      e = launch_n3(ft, a, grid, st);
+      e = launch_n3(ft, a, grid, false, st);
       if (e != hipSuccess) return e;
       k_sum_n3<float><<<pb, kBlock, 0, st>>>((const float*)w.part, n, TI, E);
     }
     return hipGetLastError();
   }
-  e = launch_generic(precision, ft, map, w.src, w.part, n, eps2, phi != nullptr, grid, st);
+  e = launch_generic(precision, ft, map, w.src, w.part, n, eps2, phi != nullptr, false, grid, st);
   if (e != hipSuccess) return e;
   k_sum_partials<<<pb, kBlock, 0, st>>>(w.part, n, ft.S, E, phi);
   return hipGetLastError();

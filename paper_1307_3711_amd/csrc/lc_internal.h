@@ -54,7 +54,8 @@ struct ClusterParams {
   int32_t n_ion_blocks;
   int32_t polarization;  // LC_LINEAR_X or LC_CIRCULAR
   int64_t n3_off;
-  double det_r2;        // squared detector distance (c/w)^2 (detectors on)       // first float of this cluster's pair-once partial rows (see force.hip)
+  double det_r2;        // squared detector distance (c/w)^2 (detectors on)
+  double box;           // side of the periodic cube around the cluster (c/w); 0: open boundaries       // first float of this cluster's pair-once partial rows (see force.hip)
 };
 
 // Per-cluster dynamic state, written by the kernels.
@@ -92,9 +93,16 @@ struct RunConst {
   int64_t n_total;      // total slots (sum of capacities)
   double mec2_ev;       // electron rest energy (eV) for the absorbed-energy column
   int32_t det_on;       // ion detectors present
-  int32_t pad;
+  int32_t boundary;     // LC_OPEN, LC_PERIODIC or LC_MIXED
   double det_cos2;      // cos^2 of the detectors' acceptance half-angle
+  double t_switch;      // LC_MIXED: first time (1/w) with open boundaries
 };
+
+// Periodic boundaries in force at time t (the step's t^n): always for LC_PERIODIC, before
+// t_switch for LC_MIXED, never for LC_OPEN.  Host and device take the same decision.
+__host__ __device__ inline bool periodic_at(const RunConst& rc, double t) {
+  return rc.boundary == LC_PERIODIC || (rc.boundary == LC_MIXED && t < rc.t_switch);
+}
 
 // Pointers into the caller-owned state.
 struct DevState {
@@ -201,7 +209,7 @@ __device__ inline void n3_row_partial(const DevState& s, const RunConst& rc, int
 // A pass without the potential takes the pair-once kernel when ft.newton3 is set.
 // fold_n3 = false leaves the rows unsummed for launch_fold_push.
 hipError_t launch_force(const DevState& s, const RunConst& rc, int precision, const ForceTiling& ft,
-                        bool want_phi, int grid_blocks, hipStream_t st, bool fold_n3 = true);
+                        bool want_phi, bool pbc, int grid_blocks, hipStream_t st, bool fold_n3 = true);
 // n3: build the pair-once tile tables (blocks of n3_block_size(ft)) instead of target blocks
 // times splits.
 hipError_t launch_schedule(const DevState& s, const RunConst& rc, const ForceTiling& ft, bool n3, bool advance,

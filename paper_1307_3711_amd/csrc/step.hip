@@ -79,6 +79,10 @@ __device__ inline void write_source(const DevState& s, int precision, int64_t g,
 
 // Laser electric field (ax, ay, 0) at time t and height z (Eqs.(4)-(9)); the magnetic field
 // is z^ x E = (-ay, ax, 0) for both polarizations (b0 = a0).
+// Periodic boundaries (Sec. II): a particle leaving the cube of side L centred on the cluster
+// re-enters through the opposite face, x -> x - L floor(x / L + 1/2) in [-L/2, L/2).
+__device__ inline double wrap_box(double x, double L) { return x - L * floor(x / L + 0.5); }
+
 __device__ inline void laser_at(const ClusterParams& cp, const ClusterDyn& d, double t, double z, double& ax,
                                 double& ay) {
   if (cp.phase == LC_DIPOLE) {
@@ -248,6 +252,11 @@ __device__ inline void push_one(const DevState& s, const RunConst& rc, int64_t g
   x += rc.dt * unx / gn;
   y += rc.dt * uny / gn;
   z += rc.dt * unz / gn;
+  if (periodic_at(rc, t)) {
+    x = wrap_box(x, cp.box);
+    y = wrap_box(y, cp.box);
+    z = wrap_box(z, cp.box);
+  }
   s.ux[g] = unx; s.uy[g] = uny; s.uz[g] = unz;
   s.x[g] = x; s.y[g] = y; s.z[g] = z;
   write_source(s, PREC, g, x, y, z, cp.kw * (double)zc);
@@ -549,9 +558,14 @@ __global__ __launch_bounds__(kBlock) void k_ionize_spawn(DevState s, RunConst rc
       const double ct = 2.0 * unit_interval(r.v[0]) - 1.0;
       const double ph = 2.0 * M_PI * unit_interval(r.v[1]);
       const double st = sqrt(fmax(0.0, 1.0 - ct * ct));
-      const double xe = s.x[gi] + cp.delta * st * cos(ph);
-      const double ye = s.y[gi] + cp.delta * st * sin(ph);
-      const double ze = s.z[gi] + cp.delta * ct;
+      double xe = s.x[gi] + cp.delta * st * cos(ph);
+      double ye = s.y[gi] + cp.delta * st * sin(ph);
+      double ze = s.z[gi] + cp.delta * ct;
+      if (periodic_at(rc, rc.t0 + (double)n * rc.dt)) {
+        xe = wrap_box(xe, cp.box);
+        ye = wrap_box(ye, cp.box);
+        ze = wrap_box(ze, cp.box);
+      }
       const double ux = s.ux[gi], uy = s.uy[gi], uz = s.uz[gi];
       s.x[ge] = xe; s.y[ge] = ye; s.z[ge] = ze;
       s.ux[ge] = ux; s.uy[ge] = uy; s.uz[ge] = uz;

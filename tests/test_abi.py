@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_version_and_error_strings():
     L = lc.lib()
-    assert L.lc_version() == 3
+    assert L.lc_version() == 4
     for code in [0, -1, -2, -3, -4, -5, -6]:
         assert L.lc_error_string(code)
     assert L.lc_error_string(0).decode() == "ok"
@@ -81,10 +81,12 @@ def test_state_bytes_scales_with_capacity():
 @pytest.mark.parametrize("field,value", [("dt", 0.0), ("dt", -1.0), ("softening_nm", 0.0), ("lambda_um", 0.0),
                                          ("max_splits", 0), ("max_splits", 65), ("precision", 7),
                                          ("diag_every", -1), ("struct_size", 8), ("detector_r0", -1.0),
-                                         ("detector_half_angle_deg", 90.0), ("detector_half_angle_deg", 0.0)])
+                                         ("detector_half_angle_deg", 90.0), ("detector_half_angle_deg", 0.0),
+                                         ("boundary", 3), ("box_r0", 0.0), ("box_r0", -2.0), ("precision", 2)])
 def test_invalid_config_rejected(field, value):
     c, run = small_ar()
-    cfg = lc.make_config("fp64", detector_r0=9.0 if field.startswith("detector_half") else 0.0)
+    cfg = lc.make_config("fp64", detector_r0=9.0 if field.startswith("detector_half") else 0.0,
+                         boundary="periodic" if field in ("box_r0", "precision") else "open")
     assert _bytes(cfg, [_desc(c)]) > 0
     setattr(cfg, field, value)
     assert _bytes(cfg, [_desc(c)]) == 0

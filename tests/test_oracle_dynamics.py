@@ -646,3 +646,26 @@ def test_periodic_momentum_newton3_and_box():
     lhs = rec2[-1][oracle.R_KE_HALF] - sim2.ke_start
     rhs = rec2[-1][oracle.R_WL] + rec2[-1][oracle.R_WC] + rec2[-1][oracle.R_WSP]
     assert abs(lhs - rhs) <= 1e-11 * (abs(rec2[-1][oracle.R_WL]) + abs(rec2[-1][oracle.R_WC]) + abs(sim2.ke_start))
+
+
+def test_image_decision_in_fp32():
+    """Which periodic copy is nearest is an integer decided by floating point.  With image32
+    the oracle decides it from FP32 positions: x_i = 1/4 + 1e-9 rounds to 1/4 in FP32, so a
+    partner at -1/4 in a cube of side 1 sits at exactly half the box and the tie goes to the
+    copy at +1/2 (round half to even), while in FP64 the copy at -1/2 + 1e-9 is nearer; away
+    from half-box ties both decisions agree bitwise."""
+    x = np.array([[0.25 + 1e-9, 0.0, 0.0], [-0.25, 0.0, 0.0]])
+    q = np.array([0.0, 1.0])
+    e64, _ = oracle.coulomb_field(x, q, 1e-6, box=1.0)
+    e32, _ = oracle.coulomb_field(x, q, 1e-6, box=1.0, image32=True)
+    assert e64[0][0] < 0 < e32[0][0]
+    assert abs(e64[0][0] + e32[0][0]) < 1e-6 * abs(e32[0][0])
+    rng = np.random.default_rng(5)
+    xr = rng.uniform(-0.5, 0.5, (40, 3))
+    d = xr[:, None, :] - xr[None, :, :]
+    frac = np.abs(np.abs(d) - 0.5)
+    assert frac[frac > 0].min() > 1e-6  # no pair near a tie
+    qr = rng.choice([-1.0, 1.0], 40)
+    a, pa = oracle.coulomb_field(xr, qr, 1e-4, box=1.0)
+    b, pb = oracle.coulomb_field(xr, qr, 1e-4, box=1.0, image32=True)
+    assert np.array_equal(a, b) and np.array_equal(pa, pb)
