@@ -28,6 +28,7 @@ ENVELOPES = {"gauss_field": 0, "gauss_intensity": 1, "sin2": 2, "flat": 3}
 PHASES = {"dipole": 0, "plane_wave": 1}
 POLARIZATIONS = {"linear_x": 0, "circular": 1}
 BOUNDARIES = {"open": 0, "periodic": 1, "mixed": 2}
+LOTZ_A = 4.5e-14              # Lotz constant a (cm^2 eV^2) of the outermost-subshell form
 OFI = {"laser_only": 0, "local": 1}
 MAX_Z = 16
 REC = 48
@@ -70,7 +71,9 @@ class Params(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("cluster", ctypes.c_uint64), ("n_ion", ctypes.c_int64),
         ("polarization", ctypes.c_int32), ("boundary", ctypes.c_int32),
         ("box", ctypes.c_double), ("t_switch", ctypes.c_double), ("image32", ctypes.c_int32),
-        ("pad", ctypes.c_int32),
+        ("collisional", ctypes.c_int32), ("lotz_a", ctypes.c_double), ("lotz_q", ctypes.c_double * MAX_Z),
+        ("ci_ip_ev", ctypes.c_double * MAX_Z), ("ci_r0", ctypes.c_double), ("ne_per_macro", ctypes.c_double),
+        ("s_per_unit", ctypes.c_double),
     ]
 
 
@@ -111,6 +114,10 @@ def lib():
         L.or_run.argtypes = [pp, ctypes.c_int64, i64p, dp, dp, dp, dp, dp, dp, i8p, dp, dp, dp,
                              ctypes.c_int64, ctypes.c_int64, dp, dp, dp, ctypes.c_int64, ctypes.POINTER(Detector)]
         L.or_run.restype = ctypes.c_int64
+        L.or_e1.argtypes = [ctypes.c_double]
+        L.or_e1.restype = ctypes.c_double
+        L.or_lotz_rate.argtypes = [ctypes.c_double] * 4
+        L.or_lotz_rate.restype = ctypes.c_double
         L.or_detector_init.argtypes = [ctypes.POINTER(Detector), ctypes.c_double, ctypes.c_double]
         L.or_detector_init.restype = None
         L.or_det_slots.restype = ctypes.c_int
@@ -229,9 +236,28 @@ def make_params(cluster, run, cluster_index=0, weight=None, **override):
     p.seed = run.seed
     p.cluster = cluster_index
     p.n_ion = cluster.n_ion
+    # collisional ionization (Lotz, outermost subshell; sphere of the initial radius)
+    p.collisional = 1 if run.collisional else 0
+    p.lotz_a = LOTZ_A
+    for k in range(MAX_Z):
+        p.lotz_q[k] = sp["outer_q"][k] if k < len(sp.get("outer_q", [])) else 0.0
+        p.ci_ip_ev[k] = sp["ip_ev"][k] if k < len(sp["ip_ev"]) else 0.0
+    p.ci_r0 = units.nm_to_norm(cluster.r0_nm, lam)
+    r0_cm = cluster.r0_nm * 1e-7
+    p.ne_per_macro = p.weight / (4.0 / 3.0 * math.pi * r0_cm ** 3)
+    p.s_per_unit = 1.0 / units.omega(lam)
     for k, v in override.items():
         setattr(p, k, v)
     return p
+
+
+def e1(x):
+    return lib().or_e1(float(x))
+
+
+def lotz_rate(a, q, p_ev, t_ev):
+    """Maxwellian Lotz ionization rate coefficient (cm^3/s)."""
+    return lib().or_lotz_rate(float(a), float(q), float(p_ev), float(t_ev))
 
 
 def envelope(p, t):

@@ -21,6 +21,9 @@
  *   or_adk_rate       - ADK tunnelling rate (cited in Sec. II; standard l = m = 0 form).
  *   ionization        - Monte-Carlo test P = 1 - exp(-nu dt) against alpha in (0,1]
  *                       (Sec. II), electron spawned next to the ion.
+ *   or_lotz_rate      - collisional ionization rate (Sec. II: nu_total = nu_ofi + nu_ci), Lotz
+ *                       form with the electron density and temperature of the cluster sphere.
+ *   or_e1             - exponential integral E1 (series and continued fraction).
  *   or_sep,           - periodic, open or mixed boundaries of the simulation box (Sec. II):
  *   or_wrap             minimum-image separations and re-entry through the opposite face.
  *   or_detect         - ion detectors and the time-integrated ion energy distribution
@@ -108,7 +111,15 @@ typedef struct {
   double box;           /* side L of the periodic cube centred on the cluster (c/w)  */
   double t_switch;      /* OR_MIXED: first time (1/w) with open boundaries             */
   int32_t image32;      /* 1: periodic copy chosen in FP32 from FP32 positions (the      */
-  int32_t pad;          /*    decision of FP32 pair kernels); 0: in FP64                 */
+                        /*    decision of FP32 pair kernels); 0: in FP64                 */
+  int32_t collisional;  /* 1: add the collisional ionization rate to the ADK rate      */
+  double lotz_a;        /* Lotz constant a (cm^2 eV^2)                                 */
+  double lotz_q[OR_MAX_Z];  /* electrons in the outermost subshell of charge state Z  */
+  double ci_ip_ev[OR_MAX_Z]; /* ionization energy Z -> Z+1 (eV)                      */
+  double ci_r0;         /* radius of the sphere the electron density and temperature are
+                           taken over, and inside which ions see them (c/w)            */
+  double ne_per_macro;  /* real electrons per cm^3 that one macro-electron in it adds    */
+  double s_per_unit;    /* seconds per unit of time (1/w)                               */
 } or_params;
 
 /* ------------------------------------------------------------------ boundaries */
@@ -292,6 +303,55 @@ double or_adk_rate(double ip, double zc, double f) {
   double log_c2 = 2.0 * ns * log(2.0) - log(ns) - lgamma(2.0 * ns);
   double log_nu = log_c2 + log(ip) + (2.0 * ns - 1.0) * log(2.0 * f0 / f) - 2.0 * f0 / (3.0 * f);
   return exp(log_nu);
+}
+
+/* ------------------------------------------------------------------ collisional ionization */
+/* Sec. II adds a collisional rate nu_ci to the tunnelling rate before the Monte-Carlo test.
+ * The rate per ion is n_e <sigma v>, with the Lotz electron-impact cross-section of the
+ * outermost subshell, sigma(E) = a q ln(E/P) / (E P) for E > P (q electrons bound by P), and a
+ * Maxwellian electron energy distribution of temperature T:
+ *   <sigma v> = int_P^inf sigma(E) sqrt(2E/m_e) 2 sqrt(E/pi) T^{-3/2} exp(-E/T) dE
+ *             = 2 sqrt(2/(pi m_e)) a q E1(P/T) / (P sqrt(T))
+ * (the logarithm integrated by parts).  n_e and T are taken over the electrons inside the
+ * sphere of the initial cluster radius: n_e = (real electrons inside) / (sphere volume),
+ * T = (2/3) x their mean kinetic energy; ions inside the sphere see them, ions outside none. */
+#define OR_EV_J 1.602176634e-19
+#define OR_ME_KG 9.1093837015e-31
+
+/* E1(x), x > 0: power series E1 = -gamma - ln x - sum_k (-x)^k / (k k!) for x <= 1
+ * (Abramowitz & Stegun 5.1.11), else the continued fraction of A&S 5.1.22 evaluated by the
+ * modified Lentz method. */
+double or_e1(double x) {
+  if (x <= 1.0) {
+    double sum = 0.0, term = 1.0;
+    for (int k = 1; k < 100; ++k) {
+      term *= -x / (double)k;
+      double add = term / (double)k;
+      sum += add;
+      if (fabs(add) <= 1e-18 * fabs(sum)) break;
+    }
+    return -0.57721566490153286061 - log(x) - sum;
+  }
+  const double tiny = 1e-300;
+  double b = x + 1.0, c = 1.0 / tiny, d = 1.0 / b, h = d;
+  for (int i = 1; i < 1000; ++i) {
+    double an = -(double)i * (double)i;
+    b += 2.0;
+    d = 1.0 / (an * d + b);
+    c = b + an / c;
+    double del = c * d;
+    h *= del;
+    if (fabs(del - 1.0) <= 1e-16) break;
+  }
+  return h * exp(-x);
+}
+
+/* <sigma v> (cm^3/s) for Lotz constant a (cm^2 eV^2), q outer electrons bound by P (eV), at
+ * electron temperature T (eV); 0 without electrons or temperature. */
+double or_lotz_rate(double a, double q, double P, double T) {
+  if (!(T > 0.0) || !(q > 0.0) || !(P > 0.0)) return 0.0;
+  double v1 = sqrt(2.0 * OR_EV_J / OR_ME_KG) * 100.0; /* sqrt(2 E / m_e) at E = 1 eV, cm/s */
+  return 2.0 / sqrt(M_PI) * v1 * a * q * or_e1(P / T) / (P * sqrt(T));
 }
 
 /* ------------------------------------------------------------------ helpers */
@@ -525,6 +585,18 @@ static int or_step(const or_params* p, int64_t step, int64_t cap, int64_t* n_io,
 
   if (p->ionize) {
     uint64_t key[2] = {p->seed, p->cluster};
+    double ne = 0.0, te = 0.0; /* electron density (cm^-3) and temperature (eV) in the sphere */
+    double rr = p->ci_r0 * p->ci_r0;
+    if (p->collisional) {
+      double cnt = 0.0, ke = 0.0;
+      for (int64_t j = 0; j < n; ++j) {
+        if (Z[j] >= 0 || x[j] * x[j] + y[j] * y[j] + z[j] * z[j] >= rr) continue;
+        cnt += 1.0;
+        ke += or_gm1(ux[j], uy[j], uz[j]);
+      }
+      ne = cnt * p->ne_per_macro;
+      te = (cnt > 0.0) ? (2.0 / 3.0) * (ke / cnt) * p->mec2_ev : 0.0;
+    }
     int64_t n_base = n;
     for (int64_t i = 0; i < p->n_ion; ++i) {
       if (Z[i] < 0 || Z[i] >= p->z_max) continue;
@@ -541,6 +613,8 @@ static int or_step(const or_params* p, int64_t step, int64_t cap, int64_t* n_io,
         F = fabs(s->elx[i]);
       }
       double nu = or_adk_rate(ip, (double)Z[i] + 1.0, F * p->field_au) * p->rate_scale;
+      if (p->collisional && x[i] * x[i] + y[i] * y[i] + z[i] * z[i] < rr)
+        nu += ne * or_lotz_rate(p->lotz_a, p->lotz_q[Z[i]], p->ci_ip_ev[Z[i]], te) * p->s_per_unit;
       double P = -expm1(-nu * p->dt);
       uint64_t ctr[4] = {(uint64_t)i, (uint64_t)step, OR_PURPOSE_ALPHA, 0};
       uint64_t r[4];

@@ -7,6 +7,7 @@ energy identity, energy bookkeeping with second-order convergence), finite diffe
 the potential, brute force at 50 digits, and Monte-Carlo statistics with a known survival
 law.
 """
+import dataclasses
 import math
 
 import mpmath
@@ -669,3 +670,74 @@ def test_image_decision_in_fp32():
     a, pa = oracle.coulomb_field(xr, qr, 1e-4, box=1.0)
     b, pb = oracle.coulomb_field(xr, qr, 1e-4, box=1.0, image32=True)
     assert np.array_equal(a, b) and np.array_equal(pa, pb)
+
+
+def _ci_cloud(seed=31, n_ion=3000, n_e=2000, t_ev=100.0, surv=0.5, nsteps=40):
+    """Ions Ar+ at rest within R0/4 and a cloud of electrons within R0/2 whose momenta all have
+    the magnitude of kinetic energy 3 t_ev / 2 (temperature t_ev), no laser and no Coulomb
+    coupling; spawned electrons land 2.5 R0 away, outside the sphere.  The weight is chosen so
+    that the collisional rate gives survival `surv` after nsteps steps."""
+    from scipy.integrate import quad
+    from workloads.species import SPECIES
+    r0_nm = 100.0
+    c = Cluster(species="Ar", r0_nm=r0_nm, n_ion=n_ion, capacity=2 * n_ion + n_e, z_init=1, z_max=2,
+                electron_offset_nm=2.5 * r0_nm, laser=Laser(intensity_wcm2=0.0, envelope="flat"))
+    run = Run(dt=0.05, ionize=True, collisional=True, diag_every=0, seed=seed)
+    me, ev = 9.1093837015e-31, 1.602176634e-19
+    P = SPECIES["Ar"]["ip_ev"][1]
+    q = SPECIES["Ar"]["outer_q"][1]
+
+    def f(E):
+        sigma = 4.5e-14 * q * math.log(E / P) / (E * P)
+        return sigma * math.sqrt(2.0 * E * ev / me) * 100.0 * 2.0 * math.sqrt(E / math.pi) * t_ev ** -1.5 \
+            * math.exp(-E / t_ev)
+    sv = quad(f, P, P + 60 * t_ev, limit=400, epsrel=1e-12)[0]
+    s_unit = 0.8e-6 / (2 * math.pi * units.C_LIGHT)
+    nu = -math.log(surv) / (nsteps * run.dt * s_unit)
+    vol = 4.0 / 3.0 * math.pi * (r0_nm * 1e-7) ** 3
+    w = nu / sv * vol / n_e
+    rng = np.random.default_rng(seed)
+
+    def ball(n, r):
+        v = rng.normal(size=(n, 3))
+        v /= np.linalg.norm(v, axis=1)[:, None]
+        return v * (r * rng.random(n) ** (1 / 3))[:, None]
+    r0 = units.nm_to_norm(r0_nm, 0.8)
+    x = np.concatenate([ball(n_ion, r0 / 4), ball(n_e, r0 / 2)])
+    g = 1.0 + 1.5 * t_ev / units.MEC2_EV
+    u = np.concatenate([np.zeros((n_ion, 3)), ball(n_e, 1.0)])
+    u[n_ion:] *= (math.sqrt(g * g - 1.0) / np.linalg.norm(u[n_ion:], axis=1))[:, None]
+    Z = np.concatenate([np.ones(n_ion, np.int8), -np.ones(n_e, np.int8)])
+    return c, run, x, u, Z, w, nu, s_unit
+
+
+@pytest.mark.parametrize("t_ev", [10.0, 100.0])
+def test_collisional_survival_law(t_ev):
+    """With the collisional rate on and nothing else changing (frozen cloud), an Ar+ ion inside
+    the sphere survives n steps with probability exp(-n_e <sigma v> n dt); <sigma v> here is the
+    numerical Maxwellian average of the Lotz cross-section, n_e the cloud's real electrons per
+    volume of the sphere.  Binomial count at 4.5 sigma.  At 10 eV (below the 27.6 eV binding
+    energy) the rate changes steeply with the temperature, at 100 eV little."""
+    c, run, x, u, Z, w, nu, s_unit = _ci_cloud(t_ev=t_ev)
+    p = oracle.make_params(c, run, weight=w)
+    p.kappa = 0.0
+    sim = oracle.Sim(p, c.capacity, x, u, Z)
+    sim.start()
+    nsteps = 40
+    sim.run(nsteps)
+    n_ion = c.n_ion
+    surv = np.mean(sim.charges()[:n_ion] == 1)
+    expect = math.exp(-nu * nsteps * run.dt * s_unit)
+    sigma = math.sqrt(expect * (1 - expect) / n_ion)
+    assert 0.3 < expect < 0.7
+    assert abs(surv - expect) < 4.5 * sigma
+    # spawned electrons sit outside the sphere, so they did not change the estimate
+    xs = sim.positions()[n_ion + 2000:]
+    assert np.all(np.linalg.norm(xs, axis=1) > units.nm_to_norm(c.r0_nm, 0.8))
+    # without the collisional term nothing ionizes (no laser)
+    p0 = oracle.make_params(c, dataclasses.replace(run, collisional=False), weight=w)
+    p0.kappa = 0.0
+    sim0 = oracle.Sim(p0, c.capacity, x, u, Z)
+    sim0.start()
+    sim0.run(nsteps)
+    assert np.all(sim0.charges()[:n_ion] == 1)

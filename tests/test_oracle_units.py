@@ -185,3 +185,27 @@ def test_laser_components_circular():
         assert np.linalg.norm(E) == pytest.approx(p.a0, rel=1e-14)
         assert abs(E @ B) < 1e-15 * p.a0 ** 2
         assert np.cross(E, B) == pytest.approx([0.0, 0.0, p.a0 ** 2], rel=1e-13, abs=1e-18)
+
+
+def test_exponential_integral_matches_scipy():
+    """E1 from the series (x <= 1) and the continued fraction (x > 1) against scipy."""
+    from scipy.special import exp1
+    for x in np.concatenate([np.logspace(-8, 2.7, 300), [1.0, 1.0 + 1e-12, 0.999999]]):
+        assert oracle.e1(x) == pytest.approx(float(exp1(x)), rel=2e-15)
+
+
+def test_lotz_rate_is_the_maxwellian_average_of_the_cross_section():
+    """The closed form 2 sqrt(2/(pi m_e)) a q E1(P/T) / (P sqrt T) against the average of the
+    Lotz cross-section a q ln(E/P)/(E P) over a Maxwellian, integrated numerically with the
+    electron speed from the SI constants (CODATA m_e, e)."""
+    from scipy.integrate import quad
+    me, ev = 9.1093837015e-31, 1.602176634e-19
+    a, q = 4.5e-14, 5.0
+    for P, T in [(27.63, 100.0), (27.63, 5.0), (143.46, 40.0), (12.13, 1000.0), (422.6, 30.0)]:
+        def f(E):
+            sigma = a * q * math.log(E / P) / (E * P)
+            v = math.sqrt(2.0 * E * ev / me) * 100.0
+            return sigma * v * 2.0 * math.sqrt(E / math.pi) * T ** -1.5 * math.exp(-E / T)
+        val, err = quad(f, P, P + 60.0 * T, limit=400, epsabs=0.0, epsrel=1e-12)
+        assert oracle.lotz_rate(a, q, P, T) == pytest.approx(val, rel=1e-9)
+    assert oracle.lotz_rate(a, q, 27.63, 0.0) == 0.0 and oracle.lotz_rate(a, 0.0, 27.63, 50.0) == 0.0

@@ -63,6 +63,7 @@ class Run:
     boundary: str = "open"            # open | periodic | mixed (Sec. II)
     box_r0: float = 20.0              # side of the periodic cube in units of R0 (R_IC = 20 R0)
     t_switch: float = math.inf        # mixed: first time (1/w) with open boundaries
+    collisional: bool = False         # add the collisional ionization rate (Sec. II)
 
 
 def n_atoms_input(cluster):
