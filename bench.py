@@ -234,7 +234,7 @@ def bench_particles(args):
     c = Cluster(species="Ar", r0_nm=6.0, n_ion=2048, capacity=8192, z_init=1, z_max=8,
                 laser=Laser(intensity_wcm2=1e15, envelope="flat"))
     cfg = lc.make_config("fp32_acc64", ionize=True, diag_every=0, max_records=1, max_splits=1, seed=1, t0=1.3,
-                         detector_r0=9.0 if args.detectors else 0.0)
+                         detector_r0=9.0 if args.detectors else 0.0, collisional=args.collisional)
     d = lc.make_cluster(SPECIES["Ar"], c.r0_nm, c.n_ion, c.capacity, c.laser.intensity_wcm2, envelope="flat",
                         polarization=args.polarization)
     sim = lc.Simulation(cfg, [d] * nc)
@@ -253,7 +253,8 @@ def bench_particles(args):
            "ms_per_step": round(t["push_ms"], 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"{nc} Ar clusters x (2048 Ar+ + 2048 e-), capacity 8192, 1e15 W/cm2 flat, "
-                                  f"{args.polarization} polarization" + (", detectors at 9 R0" if args.detectors else ""),
+                                  f"{args.polarization} polarization" + (", detectors at 9 R0" if args.detectors else "")
+                                  + (", collisional ionization" if args.collisional else ""),
                       "live_particles": n_live, "ions": nc * c.n_ion},
            "roofline": {"bound": "hbm", "achieved": round(push_gbs, 1), "peak": 8000.0, "unit": "GB/s",
                         "frac": round(push_gbs / 8000.0, 4), "traffic": None, "kernel": "k_push",
@@ -541,6 +542,8 @@ def main():
     ap.add_argument("--polarization", default="linear_x", choices=["linear_x", "circular"],
                     help="particles workload: laser polarization")
     ap.add_argument("--detectors", action="store_true", help="particles workload: ion detectors at 9 R0")
+    ap.add_argument("--collisional", action="store_true",
+                    help="particles workload: collisional ionization rate added to the tunnelling rate")
     ap.add_argument("--boundary", default="open", choices=["open", "periodic"],
                     help="ar20k: boundaries of the simulation box (periodic: cube of 20 R0)")
     ap.add_argument("--copy-probe", action="store_true",

@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define LC_API_VERSION 4
+#define LC_API_VERSION 5
 #define LC_MAX_Z 16       /* size of the per-charge tables (charge states 0..15)        */
 #define LC_REC 48         /* doubles per diagnostic record                              */
 #define LC_DET_BINS 120   /* ion energy histogram: 20 log bins per decade, 1 eV .. 1 MeV */
@@ -117,7 +117,13 @@ typedef struct {
                           /*   its centre (Sec. III anisotropy study: 9); 0: none       */
   double detector_half_angle_deg; /* their acceptance half-angle, in (0, 90) (Sec. III: 30) */
   int32_t boundary;       /* lc_boundary; periodic and mixed need LC_FP64 or LC_FP32_ACC64 */
-  int32_t reserved;
+  int32_t collisional;    /* 1 (needs ionize = 1): add the collisional rate n_e <sigma v> to the
+                             tunnelling rate (Sec. II nu_total = nu_ofi + nu_ci).  <sigma v> is the
+                             Lotz electron-impact rate of the ion's outermost subshell averaged
+                             over a Maxwellian, 2 sqrt(2/(pi m_e)) a q E1(P/T) / (P sqrt(T)) with
+                             q = lotz_q[Z], P = ip_ev[Z], a = lotz_a; n_e and T = (2/3) <KE> come
+                             from the electrons inside the sphere of radius R0 around the cluster
+                             centre after each push, and apply to the ions inside it            */
   double box_r0;          /* side of the periodic cube in units of each cluster's R0 (> 0) */
   double t_switch;        /* LC_MIXED: first time (1/w) of open boundaries              */
 } lc_config;
@@ -141,6 +147,9 @@ typedef struct {
   int32_t polarization;       /* lc_polarization                                        */
   double electron_offset_nm;  /* distance of a spawned electron from its ion            */
   int64_t n_steps;            /* the cluster retires after this many steps (0: never)   */
+  double lotz_q[LC_MAX_Z];    /* collisional ionization: electrons in the outermost     */
+                              /*   subshell of charge state k (0: no collisional rate)  */
+  double lotz_a;              /* Lotz constant a (cm^2 eV^2)                            */
 } lc_cluster;
 
 /* Tiling of the Coulomb kernel (the autotuner's search space).  Zeros mean "default". */

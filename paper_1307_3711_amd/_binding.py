@@ -46,7 +46,7 @@ class Config(ctypes.Structure):
         ("t0", ctypes.c_double), ("softening_nm", ctypes.c_double), ("diag_every", ctypes.c_int32),
         ("max_records", ctypes.c_int32), ("max_splits", ctypes.c_int32), ("max_pair_blocks", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("detector_r0", ctypes.c_double), ("detector_half_angle_deg", ctypes.c_double),
-        ("boundary", ctypes.c_int32), ("reserved", ctypes.c_int32), ("box_r0", ctypes.c_double),
+        ("boundary", ctypes.c_int32), ("collisional", ctypes.c_int32), ("box_r0", ctypes.c_double),
         ("t_switch", ctypes.c_double),
     ]
 
@@ -59,6 +59,7 @@ class ClusterDesc(ctypes.Structure):
         ("n_cycles", ctypes.c_double), ("n_ion", ctypes.c_int64), ("capacity", ctypes.c_int64),
         ("weight", ctypes.c_double), ("z_max", ctypes.c_int32), ("polarization", ctypes.c_int32),
         ("electron_offset_nm", ctypes.c_double), ("n_steps", ctypes.c_int64),
+        ("lotz_q", ctypes.c_double * LC_MAX_Z), ("lotz_a", ctypes.c_double),
     ]
 
 
@@ -168,7 +169,8 @@ def units(lambda_um, intensity_wcm2=0.0):
 
 def make_config(precision="fp64", ionize=True, ofi_field="laser_only", lambda_um=0.8, dt=0.05, t0=0.0,
                 softening_nm=0.1, diag_every=10, max_records=1024, max_splits=32, seed=0, max_pair_blocks=0,
-                detector_r0=0.0, detector_half_angle_deg=30.0, boundary="open", box_r0=20.0, t_switch=float("inf")):
+                detector_r0=0.0, detector_half_angle_deg=30.0, boundary="open", box_r0=20.0, t_switch=float("inf"),
+                collisional=False):
     c = Config()
     c.struct_size = ctypes.sizeof(Config)
     c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -179,12 +181,13 @@ def make_config(precision="fp64", ionize=True, ofi_field="laser_only", lambda_um
     c.max_pair_blocks = max_pair_blocks
     c.detector_r0, c.detector_half_angle_deg = detector_r0, detector_half_angle_deg
     c.boundary, c.box_r0, c.t_switch = BOUNDARIES[boundary], box_r0, t_switch
+    c.collisional = 1 if collisional else 0
     return c
 
 
 def make_cluster(species, r0_nm, n_ion, capacity, intensity_wcm2, envelope="gauss_field", fwhm_fs=30.0,
                  n_cycles=10.0, phase="dipole", weight=0.0, z_max=8, electron_offset_nm=0.01, n_steps=0,
-                 polarization="linear_x"):
+                 polarization="linear_x", lotz_a=4.5e-14):
     """species: mapping with rw_angstrom, mass_u and ip_ev (charge state k -> k+1, eV)."""
     d = ClusterDesc()
     d.r0_nm, d.rw_angstrom, d.mass_u = r0_nm, species["rw_angstrom"], species["mass_u"]
@@ -194,6 +197,9 @@ def make_cluster(species, r0_nm, n_ion, capacity, intensity_wcm2, envelope="gaus
     d.envelope = ENVELOPES[envelope]
     d.phase = PHASES[phase]
     d.polarization = POLARIZATIONS[polarization]
+    for k in range(LC_MAX_Z):
+        d.lotz_q[k] = species.get("outer_q", [])[k] if k < len(species.get("outer_q", [])) else 0.0
+    d.lotz_a = lotz_a
     d.fwhm_fs, d.n_cycles = fwhm_fs, n_cycles
     d.n_ion, d.capacity, d.weight, d.z_max = n_ion, capacity, weight, z_max
     d.electron_offset_nm, d.n_steps = electron_offset_nm, n_steps

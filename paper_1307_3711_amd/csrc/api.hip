@@ -60,7 +60,7 @@ int64_t n3_round(int64_t cap) { return (cap + 511) / 512 * 512; }
 
 struct Layout {
   size_t x, y, z, ux, uy, uz, wl, wc, wsp, kebar, pos4, posq, Z, cid, part, n3part, flag, ib_count, ib_cluster;
-  size_t cp, dyn, order, tile_start, tile_total, queue, det_seen, det_counts, det_edges, err, step, diag_part, records, total;
+  size_t cp, dyn, order, tile_start, tile_total, queue, det_seen, det_counts, det_edges, ci_part, err, step, diag_part, records, total;
   int64_t n_total;
   int n_ion_blocks;
 };
@@ -82,6 +82,8 @@ bool valid_config(const lc_config* cfg, std::string* why) {
   if (cfg->ofi_field != LC_LASER_ONLY && cfg->ofi_field != LC_LOCAL) { *why = "unknown ofi_field"; return false; }
   if (!(cfg->detector_r0 >= 0.0) || !std::isfinite(cfg->detector_r0)) { *why = "detector_r0 must be >= 0"; return false; }
   if (cfg->boundary < LC_OPEN || cfg->boundary > LC_MIXED) { *why = "unknown boundary"; return false; }
+  if (cfg->collisional != 0 && cfg->collisional != 1) { *why = "collisional must be 0 or 1"; return false; }
+  if (cfg->collisional && !cfg->ionize) { *why = "collisional ionization needs ionize = 1"; return false; }
   if (cfg->boundary != LC_OPEN) {
     if (!(cfg->box_r0 > 0.0) || !std::isfinite(cfg->box_r0)) { *why = "box_r0 must be > 0"; return false; }
     if (cfg->precision == LC_FP32_KAHAN) { *why = "periodic boundaries need LC_FP64 or LC_FP32_ACC64"; return false; }
@@ -110,6 +112,9 @@ bool valid_cluster(const lc_config* cfg, const lc_cluster& c, std::string* why) 
   if (c.z_max < 0 || c.z_max > LC_MAX_Z - 1) { *why = "z_max out of range"; return false; }
   if (!(c.electron_offset_nm >= 0.0)) { *why = "electron_offset_nm must be >= 0"; return false; }
   if (c.n_steps < 0) { *why = "n_steps must be >= 0"; return false; }
+  if (!(c.lotz_a >= 0.0) || !std::isfinite(c.lotz_a)) { *why = "lotz_a must be >= 0"; return false; }
+  for (int z = 0; z < LC_MAX_Z; ++z)
+    if (!(c.lotz_q[z] >= 0.0) || !std::isfinite(c.lotz_q[z])) { *why = "lotz_q must be >= 0"; return false; }
   return true;
 }
 
@@ -150,6 +155,7 @@ Layout make_layout(const lc_config* cfg, const lc_cluster* cl, int C) {
   L.det_seen = take((size_t)NT);
   L.det_counts = take(sizeof(unsigned long long) * (size_t)C * 4 * LC_DET_SLOTS);
   L.det_edges = take(sizeof(double) * (LC_DET_BINS + 1));
+  L.ci_part = take(sizeof(double) * (size_t)C * kDiagBlocks * 2);
   L.err = take(sizeof(int32_t));
   L.step = take(sizeof(int64_t));
   L.diag_part = take(sizeof(double) * (size_t)C * kDiagBlocks * kDiagQ);
@@ -434,6 +440,7 @@ int lc_create(lc_sim** out, const lc_config* cfg, const lc_cluster* clusters, in
   d.det_seen = (int8_t*)(b + L.det_seen);
   d.det_counts = (unsigned long long*)(b + L.det_counts);
   d.det_edges = (double*)(b + L.det_edges);
+  d.ci_part = (double*)(b + L.ci_part);
   d.err = (int32_t*)(b + L.err); d.step = (int64_t*)(b + L.step);
   d.diag_part = (double*)(b + L.diag_part); d.records = (double*)(b + L.records);
 
@@ -454,6 +461,12 @@ int lc_create(lc_sim** out, const lc_config* cfg, const lc_cluster* clusters, in
   rc.det_on = cfg->detector_r0 > 0.0 ? 1 : 0;
   rc.boundary = cfg->boundary;
   rc.t_switch = cfg->t_switch;
+  rc.collisional = cfg->collisional;
+  {
+    int64_t cap_max = 1;
+    for (int c = 0; c < n_clusters; ++c) cap_max = std::max<int64_t>(cap_max, clusters[c].capacity);
+    rc.ci_blocks = (int32_t)std::min<int64_t>(kDiagBlocks, (cap_max + 2047) / 2048);
+  }
   if (rc.det_on) {
     const double ca = std::cos(cfg->detector_half_angle_deg * (M_PI / 180.0));
     rc.det_cos2 = ca * ca;
@@ -481,6 +494,21 @@ int lc_create(lc_sim** out, const lc_config* cfg, const lc_cluster* clusters, in
     p.n_atoms = std::pow(k.r0_nm * 10.0 / k.rw_angstrom, 3.0);  // Eq.(1)
     p.weight = k.weight > 0.0 ? k.weight : p.n_atoms / (double)k.n_ion;
     p.mass_ion = k.mass_u * kMuOverMe;
+    {
+      // collisional ionization: Lotz rate over the electrons inside the initial sphere (needs
+      // the weight, set above)
+      const double r0n = k.r0_nm * 1e-9 * s->u.k;
+      const double r0_cm = k.r0_nm * 1e-7;
+      const double v1 = std::sqrt(2.0 * kQe / kMe) * 100.0;  // cm/s at 1 eV
+      for (int z = 0; z < LC_MAX_Z; ++z) {
+        p.lotz_q[z] = k.lotz_q[z];
+        p.ci_ip_ev[z] = k.ip_ev[z];
+      }
+      p.lotz_av = 2.0 / std::sqrt(M_PI) * v1 * k.lotz_a;
+      p.ci_r2 = r0n * r0n;
+      p.ne_per_macro = p.weight / (4.0 / 3.0 * M_PI * std::pow(r0_cm, 3.0));
+      p.s_per_unit = 1.0 / (kC * s->u.k);
+    }
     p.kw = s->u.kappa * p.weight;
     p.a0 = a0_of(k.intensity_wcm2, cfg->lambda_um);  // Eq.(2)
     p.tau = k.fwhm_fs * 1e-15 * s->u.omega;

@@ -55,7 +55,16 @@ struct ClusterParams {
   int32_t polarization;  // LC_LINEAR_X or LC_CIRCULAR
   int64_t n3_off;
   double det_r2;        // squared detector distance (c/w)^2 (detectors on)
-  double box;           // side of the periodic cube around the cluster (c/w); 0: open boundaries       // first float of this cluster's pair-once partial rows (see force.hip)
+  double box;           // side of the periodic cube around the cluster (c/w); 0: open boundaries
+  // collisional ionization (Lotz): outer-subshell electrons and binding energy (eV) per
+  // charge state, a * 2 sqrt(2/(pi m_e)) (cm^3/s eV^(3/2)), the estimate's sphere, the
+  // real electrons per cm^3 of one macro-electron in it, seconds per unit of time
+  double lotz_q[LC_MAX_Z];
+  double ci_ip_ev[LC_MAX_Z];
+  double lotz_av;
+  double ci_r2;
+  double ne_per_macro;
+  double s_per_unit;       // first float of this cluster's pair-once partial rows (see force.hip)
 };
 
 // Per-cluster dynamic state, written by the kernels.
@@ -74,6 +83,7 @@ struct ClusterDyn {
   int32_t i_blocks;     // target blocks this step
   int32_t active;       // 1 while step < n_steps
   double pairs;         // sum over the steps taken of n_cur^2 (pair interactions evaluated)
+  double ci_nu[LC_MAX_Z];  // collisional rate n_e <sigma v> per charge state this step (1/w units)
   int64_t n_sched;      // particle count the current step's tiles were built for
   int64_t steps_done;   // steps this cluster has taken
 };
@@ -94,6 +104,8 @@ struct RunConst {
   double mec2_ev;       // electron rest energy (eV) for the absorbed-energy column
   int32_t det_on;       // ion detectors present
   int32_t boundary;     // LC_OPEN, LC_PERIODIC or LC_MIXED
+  int32_t collisional;  // collisional ionization rate added to the tunnelling rate
+  int32_t ci_blocks;    // blocks per cluster of the electron density/temperature reduction
   double det_cos2;      // cos^2 of the detectors' acceptance half-angle
   double t_switch;      // LC_MIXED: first time (1/w) with open boundaries
 };
@@ -137,6 +149,7 @@ struct DevState {
   int32_t* err;         // latched error flags
   int64_t* step;        // absolute index of the current step group's first step
   double* diag_part;    // [cluster][kDiagBlocks][kDiagQ]
+  double* ci_part;      // [cluster][kDiagBlocks][2] electron count and kinetic energy in the sphere
   double* records;      // [cluster][max_records][LC_REC]
 };
 

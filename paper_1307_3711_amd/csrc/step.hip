@@ -476,6 +476,94 @@ __global__ __launch_bounds__(64) void k_diag_final(DevState s, RunConst rc, int6
   if (i == 0) d.rec_count += 1;
 }
 
+// ----------------------------------------------------------------------------- collisional rate
+// Exponential integral E1(x) for x > 0: the power series -gamma - ln x - sum_k (-x)^k/(k k!)
+// up to x = 1 (Abramowitz & Stegun 5.1.11), the continued fraction of A&S 5.1.22 (modified
+// Lentz evaluation) beyond.
+__device__ inline double expint_e1(double x) {
+  if (x <= 1.0) {
+    double t = 1.0, acc = 0.0;
+    for (int k = 1; k < 100; ++k) {
+      t = t * (-x / (double)k);
+      const double add = t / (double)k;
+      acc += add;
+      if (fabs(add) <= 1e-18 * fabs(acc)) break;
+    }
+    return -0.57721566490153286061 - log(x) - acc;
+  }
+  double b = x + 1.0, cc = 1e300, dd = 1.0 / b, h = dd;
+  for (int i = 1; i < 1000; ++i) {
+    const double an = -(double)i * (double)i;
+    b += 2.0;
+    dd = 1.0 / (an * dd + b);
+    cc = b + an / cc;
+    const double del = cc * dd;
+    h *= del;
+    if (fabs(del - 1.0) <= 1e-16) break;
+  }
+  return h * exp(-x);
+}
+
+// Maxwellian Lotz rate coefficient (cm^3/s) of an ion with q outer electrons bound by P eV at
+// electron temperature T eV; av = a 2 sqrt(2/(pi m_e)) in cm^3/s eV^(3/2).
+__device__ inline double lotz_rate(double av, double q, double P, double T) {
+  if (!(T > 0.0) || !(q > 0.0) || !(P > 0.0)) return 0.0;
+  return av * q * expint_e1(P / T) / (P * sqrt(T));
+}
+
+// Electron count and kinetic energy (sum of gamma - 1) inside the sphere of radius R0 about
+// the cluster centre: rc.ci_blocks blocks per cluster (sized by the largest capacity, at most
+// kDiagBlocks) over its electron slots, fixed-order reductions (as the diagnostics).
+__global__ __launch_bounds__(kBlock) void k_ci_partial(DevState s, RunConst rc) {
+  __shared__ double sh[4][2];
+  const int c = blockIdx.y;
+  const ClusterParams& cp = s.cp[c];
+  const ClusterDyn& d = s.dyn[c];
+  double cnt = 0.0, ke = 0.0;
+  if (d.active) {
+    for (int64_t li = cp.n_ion + (int64_t)blockIdx.x * kBlock + threadIdx.x; li < d.n_cur;
+         li += (int64_t)rc.ci_blocks * kBlock) {
+      const int64_t g = cp.off + li;
+      const double x = s.x[g], y = s.y[g], z = s.z[g];
+      if (x * x + y * y + z * z < cp.ci_r2) {
+        cnt += 1.0;
+        ke += gm1(s.ux[g], s.uy[g], s.uz[g]);
+      }
+    }
+  }
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const double a = wave_sum(cnt), b = wave_sum(ke);
+  if (lane == 0) { sh[wv][0] = a; sh[wv][1] = b; }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const int i = threadIdx.x;
+    s.ci_part[((int64_t)c * kDiagBlocks + blockIdx.x) * 2 + i] = ((sh[0][i] + sh[1][i]) + sh[2][i]) + sh[3][i];
+  }
+}
+
+// n_e (cm^-3) and T = (2/3) <KE> (eV) from the partials in block order, then the rate of every
+// charge state in units of 1/w.
+__global__ __launch_bounds__(64) void k_ci_final(DevState s, RunConst rc) {
+  __shared__ double sh_ne, sh_te;
+  const int c = blockIdx.x;
+  const ClusterParams& cp = s.cp[c];
+  ClusterDyn& d = s.dyn[c];
+  if (threadIdx.x == 0) {
+    double cnt = 0.0, ke = 0.0;
+    for (int b = 0; b < rc.ci_blocks; ++b) {
+      cnt += s.ci_part[((int64_t)c * kDiagBlocks + b) * 2];
+      ke += s.ci_part[((int64_t)c * kDiagBlocks + b) * 2 + 1];
+    }
+    sh_ne = cnt * cp.ne_per_macro;
+    sh_te = (cnt > 0.0) ? (2.0 / 3.0) * (ke / cnt) * rc.mec2_ev : 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x < LC_MAX_Z) {
+    const int z = threadIdx.x;
+    d.ci_nu[z] = sh_ne * lotz_rate(cp.lotz_av, cp.lotz_q[z], cp.ci_ip_ev[z], sh_te) * cp.s_per_unit;
+  }
+}
+
 // ----------------------------------------------------------------------------- ionization (S4)
 // Flag every ion whose uniform draw alpha in (0,1] falls below P = 1 - exp(-nu dt), nu the
 // ADK rate at the driving field; count flags per ion block.
@@ -509,6 +597,10 @@ __global__ __launch_bounds__(kBlock) void k_ionize_check(DevState s, RunConst rc
       const double fa = F * cp.field_au;
       double nu = 0.0;
       if (fa >= 1e-6) nu = exp(cp.adk_logc[zc] - cp.adk_expo[zc] * log(fa) - cp.adk_f23[zc] / fa) * cp.rate_scale;
+      if (rc.collisional) {
+        const double x = s.x[g], y = s.y[g], z = s.z[g];
+        if (x * x + y * y + z * z < cp.ci_r2) nu += d.ci_nu[zc];
+      }
       const double P = -expm1(-nu * rc.dt);
       const U64x4 r = philox(rc.seed, (uint64_t)c, (uint64_t)li, (uint64_t)n, kPurposeAlpha, 0);
       const double alpha = unit_interval(r.v[0]);
@@ -643,6 +735,10 @@ hipError_t launch_diag(const DevState& s, const RunConst& rc, const FieldLayout&
 hipError_t launch_ionize(const DevState& s, const RunConst& rc, int precision, const FieldLayout& fl, int64_t k,
                          int n_ion_blocks, hipStream_t st) {
   if (n_ion_blocks <= 0) return hipSuccess;
+  if (rc.collisional) {  // this step's electron density, temperature and collisional rates
+    k_ci_partial<<<dim3(rc.ci_blocks, rc.n_clusters), kBlock, 0, st>>>(s, rc);
+    k_ci_final<<<rc.n_clusters, 64, 0, st>>>(s, rc);
+  }
   if (precision == LC_FP64) {
     k_ionize_check<LC_FP64><<<n_ion_blocks, kBlock, 0, st>>>(s, rc, fl, k);
     k_ionize_spawn<LC_FP64><<<n_ion_blocks, kBlock, 0, st>>>(s, rc, k);

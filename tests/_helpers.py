@@ -36,7 +36,8 @@ def gpu_run(clusters, run, precision="fp64", states=None, max_records=4096, weig
     cfg = lc.make_config(precision, ionize=run.ionize, ofi_field=run.ofi_field, lambda_um=lam, dt=run.dt, t0=run.t0,
                          softening_nm=run.softening_nm, diag_every=run.diag_every, max_records=max_records,
                          max_splits=max_splits, seed=run.seed, max_pair_blocks=max_pair_blocks,
-                         boundary=run.boundary, box_r0=run.box_r0, t_switch=run.t_switch)
+                         boundary=run.boundary, box_r0=run.box_r0, t_switch=run.t_switch,
+                         collisional=run.collisional)
     ds = descs(clusters, weight)
     if n_steps_per_cluster is not None:
         for d, n in zip(ds, n_steps_per_cluster):

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_version_and_error_strings():
     L = lc.lib()
-    assert L.lc_version() == 4
+    assert L.lc_version() == 5
     for code in [0, -1, -2, -3, -4, -5, -6]:
         assert L.lc_error_string(code)
     assert L.lc_error_string(0).decode() == "ok"
@@ -82,11 +82,13 @@ def test_state_bytes_scales_with_capacity():
                                          ("max_splits", 0), ("max_splits", 65), ("precision", 7),
                                          ("diag_every", -1), ("struct_size", 8), ("detector_r0", -1.0),
                                          ("detector_half_angle_deg", 90.0), ("detector_half_angle_deg", 0.0),
-                                         ("boundary", 3), ("box_r0", 0.0), ("box_r0", -2.0), ("precision", 2)])
+                                         ("boundary", 3), ("box_r0", 0.0), ("box_r0", -2.0), ("precision", 2),
+                                         ("collisional", 2), ("ionize", 0)])
 def test_invalid_config_rejected(field, value):
     c, run = small_ar()
     cfg = lc.make_config("fp64", detector_r0=9.0 if field.startswith("detector_half") else 0.0,
-                         boundary="periodic" if field in ("box_r0", "precision") else "open")
+                         boundary="periodic" if field in ("box_r0", "precision") else "open",
+                         collisional=field == "ionize")
     assert _bytes(cfg, [_desc(c)]) > 0
     setattr(cfg, field, value)
     assert _bytes(cfg, [_desc(c)]) == 0
@@ -94,7 +96,7 @@ def test_invalid_config_rejected(field, value):
 
 @pytest.mark.parametrize("field,value", [("capacity", 100), ("z_max", 16), ("z_max", -1), ("r0_nm", 0.0),
                                          ("envelope", 9), ("n_ion", -1), ("fwhm_fs", 0.0), ("polarization", 2),
-                                         ("polarization", -1)])
+                                         ("polarization", -1), ("lotz_a", -1.0)])
 def test_invalid_cluster_rejected(field, value):
     c, run = small_ar()
     d = _desc(c)
