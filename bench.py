@@ -409,6 +409,62 @@ def bench_iedf(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_lumping(args):
+    """The Sec. III lumping study on synthetic input: the D_8007 cluster (R0 from Eq.(1) with
+    R_W = 1.70 A), 857 nm, 5e16 W/cm^2, 25 fs Gaussian, run as one ensemble of copies lumped
+    into 40 .. 500 ion macroparticles (one electron each; deuterium is fully ionized), four
+    independent random placements per lumping.  Reports per lumping the final mean ion energy
+    (mean and standard deviation over the placements) and mean / maximum (the paper: about
+    3/5), and the spread of the mean over the lumpings (the paper: 7 % for a 92 % change of
+    N_atoms / N_macro)."""
+    import numpy as np
+    import paper_1307_3711_amd as lc
+    from paper_1307_3711_amd.ensemble import run_ensemble
+    from workloads import Cluster, Laser, initial_state
+    from workloads.species import SPECIES
+    lam = 0.857
+    r0 = SPECIES["D"]["rw_angstrom"] * 8007 ** (1.0 / 3.0) / 10.0
+    laser = Laser(lambda_um=lam, intensity_wcm2=5e16, envelope="gauss_field", fwhm_fs=25.0)
+    counts = [40, 60, 80, 120, 160, 200, 300, 400, 500]
+    copies = 4
+    t_end_fs = 300.0
+    w_fs = 2.0 * math.pi * 299792458.0 / (lam * 1e-6) * 1e-15
+    steps = args.steps if args.steps_given else int(math.ceil(t_end_fs * w_fs / 0.05))
+    cl = [Cluster(species="D", r0_nm=r0, n_ion=n, capacity=2 * n, z_init=1, z_max=1, laser=laser, n_steps=steps)
+          for n in counts for _ in range(copies)]
+    descs = [lc.make_cluster(SPECIES["D"], c.r0_nm, c.n_ion, c.capacity, laser.intensity_wcm2, envelope=laser.envelope,
+                             fwhm_fs=laser.fwhm_fs, z_max=1, n_steps=steps) for c in cl]
+    states = [initial_state(c, args.seed, i) for i, c in enumerate(cl)]
+    log(f"lumping: D_8007 (R0 = {r0:.3f} nm) at {counts} ion macroparticles x {copies} placements, {steps} steps")
+    out = run_ensemble(descs, states, "fp64", lambda_um=lam, seed=args.seed, diag_every=1000, autotune=False,
+                       keep_particles=True)
+    mass = SPECIES["D"]["mass_u"] * 931494102.42  # eV
+    rows = []
+    for k, n in enumerate(counts):
+        means, ratios = [], []
+        for parts in out["particles"][k * copies:(k + 1) * copies]:
+            ion = parts["Z"] > 0
+            u2 = np.sum(parts["u"][ion] ** 2, axis=1)
+            ke = mass * u2 / (1.0 + np.sqrt(1.0 + u2))  # M (gamma - 1) c^2 per real ion, eV
+            means.append(ke.mean() / 1e3)
+            ratios.append(ke.mean() / ke.max())
+        rows.append({"n_macro_ions": n, "n_atoms_per_macro": round(8007 / n, 2),
+                     "mean_keV": round(float(np.mean(means)), 4), "mean_keV_std": round(float(np.std(means)), 4),
+                     "mean_over_max": round(float(np.mean(ratios)), 4)})
+    m = np.array([r["mean_keV"] for r in rows])
+    res = {"metric": "cluster-steps/s (FP64), D_8007 lumping ensemble", "value": round(out["cluster_steps"] / out["wall_s"], 1),
+           "unit": "cluster-steps/s", "n_gpus": 1, "steps": steps, "warmup": 0,
+           "ms_per_step": round(out["wall_s"] / steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"D_8007 (R0 {r0:.3f} nm), 857 nm, 5e16 W/cm2, 25 fs Gaussian, {t_end_fs:.0f} fs, "
+                                  f"lumped into {counts[0]}..{counts[-1]} ion macroparticles, {copies} placements each"},
+           "lumpings": rows,
+           "mean_energy_spread": round(float((m.max() - m.min()) / m.mean()), 4),
+           "mean_energy_40_vs_500": round(float(abs(rows[0]["mean_keV"] - rows[-1]["mean_keV"]) / rows[-1]["mean_keV"]), 4),
+           "atoms_per_macro_change": round(1.0 - counts[0] / counts[-1], 4)}
+    print(json.dumps(res), flush=True)
+
+
 def _features_of(cl):
     from paper_1307_3711_amd.ensemble import features
     from workloads.species import SPECIES
@@ -524,6 +580,7 @@ def main():
     ap.add_argument("--save-data", default="", help="surrogate: write the MD training set (npz) here")
     ap.add_argument("--fp64-steps", type=int, default=2000, help="xe200k: steps of the FP64 comparison run")
     ap.add_argument("--workload", default="ar20k", choices=["ar20k", "ensemble", "surrogate", "particles", "xe200k", "iedf",
+                                                            "lumping",
                                                             "scan"])
     ap.add_argument("--sizes", default="20000,30000,40000,60000,100000",
                     help="particle counts of the scan workload")
@@ -584,6 +641,8 @@ def main():
         return bench_xe(args)
     if args.workload == "iedf":
         return bench_iedf(args)
+    if args.workload == "lumping":
+        return bench_lumping(args)
 
     import numpy as np
     import torch

@@ -14,14 +14,16 @@ from ._binding import R_ABS_EV, R_MEANZ, Simulation, make_config, pair_blocks_fo
 
 
 def run_ensemble(descs, states, precision="fp32_acc64", dt=0.05, softening_nm=0.1, seed=0, diag_every=50,
-                 graph_steps=50, autotune=True, max_steps=None, tiling=None, progress=None):
+                 graph_steps=50, autotune=True, max_steps=None, tiling=None, progress=None, lambda_um=0.8,
+                 keep_particles=False):
     """Integrate every cluster until it retires.  descs: lc_cluster descriptions with n_steps
     set; states: initial particle arrays (x_nm, u, Z) per cluster.  Returns a dict with the
-    last diagnostic record of each cluster, per-cluster counters and the timed wall clock."""
+    last diagnostic record of each cluster, per-cluster counters and the timed wall clock (and
+    each cluster's final particles with keep_particles)."""
     # room for the pair-once kernel (blocks of 128 slots and up) where the precision allows it
     mpb = pair_blocks_for([d.capacity for d in descs], 128) if precision in ("fp32_acc64", "fp64") else 0
-    cfg = make_config(precision, ionize=True, dt=dt, softening_nm=softening_nm, diag_every=diag_every,
-                      max_records=4, max_splits=8, seed=seed, max_pair_blocks=mpb)
+    cfg = make_config(precision, ionize=True, lambda_um=lambda_um, dt=dt, softening_nm=softening_nm,
+                      diag_every=diag_every, max_records=4, max_splits=8, seed=seed, max_pair_blocks=mpb)
     sim = Simulation(cfg, descs)
     for i, st in enumerate(states):
         sim.init_from_host(i, st["x_nm"], st["u"], st["Z"])
@@ -52,13 +54,18 @@ def run_ensemble(descs, states, precision="fp32_acc64", dt=0.05, softening_nm=0.
     wall = time.perf_counter() - t0
     last = []
     counters = []
+    parts = []
     for i in range(len(descs)):
         rec = sim.diagnostics(i)
         last.append(rec[-1] if rec.shape[0] else np.full(48, np.nan))
         counters.append(sim.counters(i))
+        if keep_particles:
+            parts.append(sim.particles(i))
     out = {"last": np.array(last), "counters": counters, "wall_s": wall, "steps": total, "tiling": tuned or sim.tuning(),
            "pairs": float(sum(c["pairs"] for c in counters)),
            "cluster_steps": int(sum(c["steps"] for c in counters))}
+    if keep_particles:
+        out["particles"] = parts
     sim.close()
     return out
 
