@@ -545,14 +545,20 @@ __global__ __launch_bounds__(kBlock) void k_ci_partial(DevState s, RunConst rc) 
 // charge state in units of 1/w.
 __global__ __launch_bounds__(64) void k_ci_final(DevState s, RunConst rc) {
   __shared__ double sh_ne, sh_te;
+  __shared__ double sh_part[kDiagBlocks][2];
   const int c = blockIdx.x;
   const ClusterParams& cp = s.cp[c];
   ClusterDyn& d = s.dyn[c];
+  if (threadIdx.x < rc.ci_blocks) {  // the partials load in parallel, then add in block order
+    sh_part[threadIdx.x][0] = s.ci_part[((int64_t)c * kDiagBlocks + threadIdx.x) * 2];
+    sh_part[threadIdx.x][1] = s.ci_part[((int64_t)c * kDiagBlocks + threadIdx.x) * 2 + 1];
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     double cnt = 0.0, ke = 0.0;
     for (int b = 0; b < rc.ci_blocks; ++b) {
-      cnt += s.ci_part[((int64_t)c * kDiagBlocks + b) * 2];
-      ke += s.ci_part[((int64_t)c * kDiagBlocks + b) * 2 + 1];
+      cnt += sh_part[b][0];
+      ke += sh_part[b][1];
     }
     sh_ne = cnt * cp.ne_per_macro;
     sh_te = (cnt > 0.0) ? (2.0 / 3.0) * (ke / cnt) * rc.mec2_ev : 0.0;
