@@ -7,8 +7,11 @@
  * the laser field of Eqs.(4)-(9) under the Eq.(3) envelope in the dipole approximation, a
  * relativistic Boris push, and the Monte-Carlo optical-field-ionization check with the
  * ADK rate (P = 1 - exp(-nu dt) against a uniform draw 0 < alpha <= 1), which spawns an
- * electron next to each ionized atom.  Units are the paper's: fields in a0 = eE/(m_e w c)
- * (b0 = a0), time in 1/w, length in c/w, momentum u = gamma v / c, energy in m_e c^2.
+ * electron next to each ionized atom.  Options of the same section: linear or circular
+ * polarization, open, periodic or mixed boundaries of the simulation box, and the
+ * collisional ionization rate added to the tunnelling rate; and the ion detectors of the
+ * Sec. III anisotropy study.  Units are the paper's: fields in a0 = eE/(m_e w c) (b0 = a0),
+ * time in 1/w, length in c/w, momentum u = gamma v / c, energy in m_e c^2.
  *
  * Conventions for every entry point:
  *   - Return value: LC_OK (0) or a negative lc_status.  No exceptions cross the ABI.
@@ -186,7 +189,8 @@ size_t lc_state_bytes(const lc_config* cfg, const lc_cluster* clusters, int32_t 
 /* Create a handle over caller-owned device memory d_state (>= lc_state_bytes bytes) on
  * stream hip_stream.  Converts units on the host (Eq.(1), Eq.(2), kappa = r_e k, ADK
  * constants) and uploads the per-cluster tables.  LC_E_INVALID on a bad configuration
- * (non-positive dt or softening, z_max out of range, capacity < 2 n_ion, ...). */
+ * (non-positive dt or softening, z_max out of range, capacity < n_ion, periodic boundaries
+ * with LC_FP32_KAHAN, collisional ionization without ionization, ...). */
 int lc_create(lc_sim** out, const lc_config* cfg, const lc_cluster* clusters, int32_t n_clusters,
               void* d_state, size_t bytes, void* hip_stream);
 
@@ -201,8 +205,9 @@ int lc_init_from_host(lc_sim* sim, int32_t cluster, int64_t n, const double* x_n
  * u^{-1/2} = u^0 - (Z/M)(dt/2)(E + v^0 x B).  Must follow lc_init_from_host. */
 int lc_start(lc_sim* sim);
 
-/* Enqueue n_steps time steps (field, push, diagnostics every diag_every steps,
- * ionization).  Asynchronous. */
+/* Enqueue n_steps time steps: the field pass (minimum image on periodic steps), the push
+ * (wrap into the periodic cube, detector check), diagnostics every diag_every steps, the
+ * collisional estimate and the ionization check with spawns.  Asynchronous. */
 int lc_step(lc_sim* sim, int64_t n_steps);
 
 /* Capture steps_per_graph steps into one hipGraph that lc_step replays (0 turns graph
