@@ -771,7 +771,7 @@ __device__ void tile_n3(const N3Args<T>& a, int t, T* lds) {
 }
 
 // Row sums of the pair-once pass: a block of kFoldWaves waves takes 64 consecutive global
-// slots; wave w adds rows m = w, w + 8, ... (coalesced across the lanes), and wave 0 combines
+// slots; wave w adds rows m = w, w + kFoldWaves, ... (coalesced across the lanes), and wave 0 combines
 // the partial sums in order.  Writes E into components 0..2 of split 0 for live slots of
 // active clusters.
 template <typename Tr>

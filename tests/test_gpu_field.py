@@ -18,7 +18,7 @@ import pytest
 
 import oracle
 from oracle import units
-from workloads import Cluster, Laser, Run, ar_20k, initial_state
+from workloads import Cluster, ar_20k, initial_state
 
 from _helpers import gpu_available
 
