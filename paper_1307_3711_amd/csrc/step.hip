@@ -95,12 +95,60 @@ __device__ inline void laser_at(const ClusterParams& cp, const ClusterDyn& d, do
 }
 
 // ----------------------------------------------------------------------------- schedule (S6)
-// One block: per cluster, active flag, laser value at t^n, target blocks and tiles of step n;
-// exclusive scan of tiles over clusters in `order` (largest first).  advance = 1 ends a step:
+// A single workgroup: per cluster, active flag, laser value at t^n, target blocks and tiles of
+// step n; exclusive scan of tiles over clusters in `order` (largest first).  advance = 1 ends a step:
 // it counts the step just taken (n_sched^2 pair interactions of every cluster that was
 // active) and moves the device step index on; advance = 0 rebuilds the tables of the current
 // step (after the tiling changed).  n3: tiles of the pair-once kernel, nb (nb + 1) / 2 per
 // cluster for nb blocks of TI slots; otherwise target blocks of TI times S source splits.
+// Step bookkeeping of the cluster at order position p for step n at time t; returns its tiles.
+__device__ inline int32_t schedule_cluster(const DevState& s, int p, int TI, int S, int n3, int advance, int64_t n,
+                                           double t) {
+  const int c = s.order[p];
+  const ClusterParams& cp = s.cp[c];
+  ClusterDyn& d = s.dyn[c];
+  if (advance && d.active) {
+    d.pairs += (double)d.n_sched * (double)d.n_sched;
+    d.steps_done += 1;
+  }
+  const int active = (n < cp.n_steps) ? 1 : 0;
+  const int64_t ncur = d.n_cur;
+  d.n_sched = ncur;
+  const int ib = active ? (int)((ncur + TI - 1) / TI) : 0;
+  const int32_t tiles = n3 ? (int32_t)((int64_t)ib * (ib + 1) / 2) : ib * S;
+  const double env = envelope(cp, t);
+  d.env = env;
+  d.laser_e = env * sin(t);
+  d.laser_ey = (cp.polarization == LC_CIRCULAR) ? -(env * cos(t)) : 0.0;
+  d.active = active;
+  d.i_blocks = ib;
+  d.n_tiles = tiles;
+  return tiles;
+}
+
+// Up to 64 clusters: one wave, the scan across its lanes without barriers.
+__global__ __launch_bounds__(64) void k_schedule_wave(DevState s, RunConst rc, int TI, int S, int n3, int advance) {
+  const int p = threadIdx.x;
+  const int64_t n = *s.step + advance;
+  const double t = rc.t0 + (double)n * rc.dt;
+  const int32_t tiles = (p < rc.n_clusters) ? schedule_cluster(s, p, TI, S, n3, advance, n, t) : 0;
+  int32_t v = tiles;
+  for (int o = 1; o < 64; o <<= 1) {  // inclusive scan over the lanes
+    const int32_t u = __shfl_up(v, o, 64);
+    if (p >= o) v += u;
+  }
+  if (p < rc.n_clusters) {
+    s.tile_start[p] = v - tiles;
+    s.dyn[s.order[p]].tile0 = v - tiles;
+  }
+  if (p == 63) {  // lanes past the last cluster add no tiles, so lane 63 holds the total
+    s.tile_start[rc.n_clusters] = v;
+    *s.tile_total = v;
+    *s.queue = 0;
+    if (advance) *s.step = n;  // every lane read the old index at the start
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_schedule(DevState s, RunConst rc, int TI, int S, int n3,
                                                      int advance) {
   __shared__ int32_t sh_scan[kBlock];
@@ -112,28 +160,7 @@ __global__ __launch_bounds__(kBlock) void k_schedule(DevState s, RunConst rc, in
   __syncthreads();
   for (int base = 0; base < rc.n_clusters; base += kBlock) {
     const int p = base + tid;
-    int32_t tiles = 0;
-    if (p < rc.n_clusters) {
-      const int c = s.order[p];
-      const ClusterParams& cp = s.cp[c];
-      ClusterDyn& d = s.dyn[c];
-      if (advance && d.active) {
-        d.pairs += (double)d.n_sched * (double)d.n_sched;
-        d.steps_done += 1;
-      }
-      const int active = (n < cp.n_steps) ? 1 : 0;
-      const int64_t ncur = d.n_cur;
-      d.n_sched = ncur;
-      const int ib = active ? (int)((ncur + TI - 1) / TI) : 0;
-      tiles = n3 ? (int32_t)((int64_t)ib * (ib + 1) / 2) : ib * S;
-      const double env = envelope(cp, t);
-      d.env = env;
-      d.laser_e = env * sin(t);
-      d.laser_ey = (cp.polarization == LC_CIRCULAR) ? -(env * cos(t)) : 0.0;
-      d.active = active;
-      d.i_blocks = ib;
-      d.n_tiles = tiles;
-    }
+    const int32_t tiles = (p < rc.n_clusters) ? schedule_cluster(s, p, TI, S, n3, advance, n, t) : 0;
     sh_scan[tid] = tiles;
     __syncthreads();
     for (int o = 1; o < kBlock; o <<= 1) {  // Hillis-Steele inclusive scan
@@ -705,7 +732,8 @@ int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 hipError_t launch_schedule(const DevState& s, const RunConst& rc, const ForceTiling& ft, bool n3, bool advance,
                            hipStream_t st) {
   const int TI = n3 ? n3_block_size(ft) : force_tile_targets(ft);
-  k_schedule<<<1, kBlock, 0, st>>>(s, rc, TI, ft.S, n3 ? 1 : 0, advance ? 1 : 0);
+  if (rc.n_clusters <= 64) k_schedule_wave<<<1, 64, 0, st>>>(s, rc, TI, ft.S, n3 ? 1 : 0, advance ? 1 : 0);
+  else k_schedule<<<1, kBlock, 0, st>>>(s, rc, TI, ft.S, n3 ? 1 : 0, advance ? 1 : 0);
   return hipGetLastError();
 }
 

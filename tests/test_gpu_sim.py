@@ -221,6 +221,32 @@ def test_ensemble_matches_oracle_per_cluster():
             assert err <= max(1e-10, 100 * sp), (col, err, sp)
 
 
+@pytest.mark.parametrize("n_clusters", [64, 65, 300])
+def test_many_clusters_against_oracle(n_clusters):
+    """Enough clusters that the per-step schedule takes each of its forms (one wave up to 64
+    clusters, a workgroup scan above that, with a carry across chunks of 256): every cluster of
+    an uneven ensemble of tiny clusters with lengths of 1 to 6 steps against its own oracle
+    run (FP64, rounding-level), and the steps and pair interactions each cluster counted
+    (N^2 per step at the step's particle count) against the oracle's particle counts."""
+    cl = ensemble(n_clusters, seed=11, cap_lo=20, cap_hi=200)
+    steps = [1 + (i * 7) % 6 for i in range(n_clusters)]
+    run = Run(dt=0.05, ionize=True, diag_every=2, seed=11)
+    states = [initial_state(c, run.seed, i) for i, c in enumerate(cl)]
+    sim, _ = gpu_run(cl, run, "fp64", states=states, n_steps_per_cluster=steps)
+    sim.step(max(steps) + 1)
+    for i, c in enumerate(cl):
+        osim = oracle_run(c, run, states[i], cluster_index=i)
+        pairs = 0.0
+        for _ in range(steps[i]):
+            pairs += float(osim.N) ** 2
+            osim.run(1)
+        dx, du = _compare_state(sim, osim, units.nm_to_norm(c.r0_nm, 0.8), 0, 0, cluster=i)
+        assert dx <= 1e-10 and du <= 1e-9, (i, dx, du)
+        cnt = sim.counters(i)
+        assert cnt["steps"] == steps[i] and cnt["n"] == osim.N and cnt["pairs"] == pairs, (i, cnt, pairs)
+    print(f"{n_clusters} clusters: every cluster within 1e-10 R0 of its oracle run", flush=True)
+
+
 @pytest.mark.parametrize("precision,tiling", [("fp32_acc64", t) for t in N3_TILINGS + [dict(R=4, WJ=2, newton3=1),
                                                                                        dict(R=1, WJ=1, newton3=1, persistent=1)]]
                          + [("fp64", dict(R=2, WJ=2, newton3=1)), ("fp64", dict(R=4, WJ=4, newton3=1, persistent=1))])
