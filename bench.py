@@ -15,6 +15,7 @@ import argparse
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -68,10 +69,10 @@ def kernel_code_digest(path):
     return hashlib.sha256("\n".join(lines).encode()).hexdigest()
 
 
-def counter_record(tuned, n, precision="fp32_acc64"):
+def counter_record(tuned, n, precision="fp32_acc64", boundary="open"):
     """The committed rocprofv3 counter record (HBM bytes per launch, VALU instructions) of the
-    Coulomb kernel this precision and tiling run, or None when the kernel code or the tiling
-    has changed since the counters were taken."""
+    Coulomb kernel this precision, boundary and tiling run, or None when the kernel code or the
+    tiling has changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "k_force_ar20k_counters.json")
     try:
         recs = json.load(open(path))["records"]
@@ -81,7 +82,7 @@ def counter_record(tuned, n, precision="fp32_acc64"):
     for rec in recs:
         if rec.get("force_hip_code_sha256") != digest or rec["n_particles"] != n:
             continue
-        if rec.get("precision", "fp32_acc64") != precision:
+        if rec.get("precision", "fp32_acc64") != precision or rec.get("boundary", "open") != boundary:
             continue
         if all(tuned.get(k) == v for k, v in rec["tiling"].items()):
             return rec
@@ -110,21 +111,42 @@ def timed_steps(sim, steps):
     return time.perf_counter() - t0
 
 
-def cpu_baseline(c, run, st, n, target_s=15.0):
-    """The FP64 oracle, as it is, on a bounded number of steps of the same workload."""
+def _oracle_steps(c, run, st, k=None, target_s=10.0):
+    """Start the oracle on the state, take one calibration step, then time k steps (k sized to
+    about target_s when not given); returns (k, seconds, positions after the run)."""
     import oracle
     osim = oracle.Sim.from_workload(c, run, st)
     osim.start()
     t0 = time.perf_counter()
     osim.run(1)
     t1 = time.perf_counter() - t0
-    k = max(1, min(200, int(target_s / max(t1, 1e-6))))
+    if k is None:
+        k = max(1, min(200, int(target_s / max(t1, 1e-6))))
     t0 = time.perf_counter()
     osim.run(k)
-    dt = time.perf_counter() - t0
-    return {"value": k * n * n / dt / 1e9, "unit": "Gpair/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{k} steps of the same 20k-macroparticle state after 1 calibration step "
-                      f"(FP64, {dt:.1f} s)"}
+    return k, time.perf_counter() - t0, osim.positions()
+
+
+def cpu_baseline(c, run, st, n, target_s=10.0):
+    """The FP64 oracle, as it is (gcc -O2), on a bounded number of steps of the same workload;
+    beside it, for context, the same source built with -O3 -march=native on this host (same
+    arithmetic: contraction and fast math stay off, which the equal positions confirm)."""
+    import tempfile
+    import numpy as np
+    import oracle
+    k, dt, x = _oracle_steps(c, run, st, target_s=target_s)
+    out = {"value": k * n * n / dt / 1e9, "unit": "Gpair/s", "cores": oracle.threads(), "kind": "oracle",
+           "sample": f"{k} steps of the same 20k-macroparticle state after 1 calibration step "
+                     f"(FP64, gcc -O2, {dt:.1f} s)"}
+    try:
+        with tempfile.TemporaryDirectory() as d:
+            with oracle.library(oracle.build_native(os.path.join(d, "liblc_oracle_native.so"))):
+                _, dtn, xn = _oracle_steps(c, run, st, k=k)
+        out["native"] = {"value": k * n * n / dtn / 1e9, "flags": "-O3 -march=native",
+                         "same_positions": bool(np.array_equal(x, xn)), "seconds": round(dtn, 2)}
+    except (OSError, subprocess.CalledProcessError) as e:
+        out["native"] = {"value": None, "error": str(e)[:200]}
+    return out
 
 
 def ensemble_inputs(n_clusters, seed, steps_scale=1.0):
@@ -668,7 +690,7 @@ def main():
     avg_force_s = force_ms / max(force_n, 1) * 1e-3
     achieved = FLOPS_PER_PAIR * pairs / avg_force_s / 1e12
     value = args.steps * pairs / wall / 1e9
-    crec = counter_record(tuned, n) if args.boundary == "open" else None
+    crec = counter_record(tuned, n, "fp32_acc64", args.boundary)
     evals = pair_evaluations(n, tuned)
     kname = "k_force_n3" if tuned.get("newton3") else "k_force_f32"
     out = {
@@ -702,7 +724,7 @@ def main():
         f64_ms, f64_n = prof64["field"]
         avg64_s = f64_ms / max(f64_n, 1) * 1e-3
         ach64 = FLOPS_PER_PAIR * pairs / avg64_s / 1e12
-        crec64 = counter_record(tuned64, n, "fp64") if args.boundary == "open" else None
+        crec64 = counter_record(tuned64, n, "fp64", args.boundary)
         p32 = sim.particles(0)
         p64 = sim64.particles(0)
         r0n = c.r0_nm * lc.units(0.8)["k_per_nm"]

@@ -10,6 +10,7 @@ forms, invariants, brute force at high precision or library routines (see each t
 docstring).  The absolute physics outputs the paper plots (ion energy spectra, charge-state
 fractions) are not available, so agreement with the paper's figures is not pinned.
 """
+import contextlib
 import ctypes
 import math
 import os
@@ -40,16 +41,39 @@ R_P, R_F, R_FABS, R_MEANZ, R_ABS_EV, R_DROPPED, R_EVENTS, R_ENV = 11, 14, 17, 18
 R_ZHIST = 24
 
 
+def _compile(out, opt):
+    cmd = ["gcc", *opt, "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+           "-std=gnu11", "-o", out, _SRC, "-lm"]
+    subprocess.check_call(cmd)
+
+
 def build(force=False):
     """Compile the oracle with g++-free plain C: gcc -O2 -fopenmp -ffp-contract=off."""
     if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
         return _LIB
     tmp = _LIB + ".tmp"
-    cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-           "-std=gnu11", "-o", tmp, _SRC, "-lm"]
-    subprocess.check_call(cmd)
+    _compile(tmp, ["-O2"])
     os.replace(tmp, _LIB)
     return _LIB
+
+
+def build_native(out):
+    """The same source with -O3 -march=native (still no contraction, no fast math, so the same
+    arithmetic), for a stronger CPU timing on the machine that builds it; never shipped."""
+    _compile(out, ["-O3", "-march=native"])
+    return out
+
+
+@contextlib.contextmanager
+def library(path):
+    """Run the oracle from another build of its source (see build_native) inside the block."""
+    global _lib_handle
+    old = _lib_handle
+    _lib_handle = _load(path)
+    try:
+        yield
+    finally:
+        _lib_handle = old
 
 
 DET_BINS = 120                # ion energy histogram: 20 bins per decade, 1 eV .. 1 MeV
@@ -70,7 +94,7 @@ class Params(ctypes.Structure):
         ("delta", ctypes.c_double), ("n_atoms", ctypes.c_double), ("mec2_ev", ctypes.c_double),
         ("seed", ctypes.c_uint64), ("cluster", ctypes.c_uint64), ("n_ion", ctypes.c_int64),
         ("polarization", ctypes.c_int32), ("boundary", ctypes.c_int32),
-        ("box", ctypes.c_double), ("t_switch", ctypes.c_double), ("image32", ctypes.c_int32),
+        ("box", ctypes.c_double), ("t_switch", ctypes.c_double), ("grid32", ctypes.c_int32),
         ("collisional", ctypes.c_int32), ("lotz_a", ctypes.c_double), ("lotz_q", ctypes.c_double * MAX_Z),
         ("ci_ip_ev", ctypes.c_double * MAX_Z), ("ci_r0", ctypes.c_double), ("ne_per_macro", ctypes.c_double),
         ("s_per_unit", ctypes.c_double),
@@ -89,42 +113,46 @@ def lib():
     global _lib_handle
     if _lib_handle is None:
         build()
-        L = ctypes.CDLL(_LIB)
-        dp = ctypes.POINTER(ctypes.c_double)
-        i8p = ctypes.POINTER(ctypes.c_int8)
-        u64p = ctypes.POINTER(ctypes.c_uint64)
-        i64p = ctypes.POINTER(ctypes.c_int64)
-        pp = ctypes.POINTER(Params)
-        L.or_philox4x64_10.argtypes = [u64p, u64p, u64p]
-        L.or_u01.argtypes = [ctypes.c_uint64]
-        L.or_u01.restype = ctypes.c_double
-        L.or_adk_rate.argtypes = [ctypes.c_double] * 3
-        L.or_adk_rate.restype = ctypes.c_double
-        L.or_envelope.argtypes = [pp, ctypes.c_double]
-        L.or_envelope.restype = ctypes.c_double
-        L.or_laser.argtypes = [pp, ctypes.c_double, ctypes.c_double, dp, dp]
-        L.or_boris_push.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
-        L.or_coulomb_field.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, dp, dp, dp, dp]
-        L.or_coulomb_field_box.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
-                                           ctypes.c_int, dp, dp, dp, dp]
-        L.or_coulomb_field_at.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int64,
-                                          i64p, dp, dp, dp, dp]
-        L.or_start.argtypes = [pp, ctypes.c_int64, dp, dp, dp, dp, dp, dp, i8p, dp]
-        L.or_start.restype = ctypes.c_double
-        L.or_run.argtypes = [pp, ctypes.c_int64, i64p, dp, dp, dp, dp, dp, dp, i8p, dp, dp, dp,
-                             ctypes.c_int64, ctypes.c_int64, dp, dp, dp, ctypes.c_int64, ctypes.POINTER(Detector)]
-        L.or_run.restype = ctypes.c_int64
-        L.or_e1.argtypes = [ctypes.c_double]
-        L.or_e1.restype = ctypes.c_double
-        L.or_lotz_rate.argtypes = [ctypes.c_double] * 4
-        L.or_lotz_rate.restype = ctypes.c_double
-        L.or_detector_init.argtypes = [ctypes.POINTER(Detector), ctypes.c_double, ctypes.c_double]
-        L.or_detector_init.restype = None
-        L.or_det_slots.restype = ctypes.c_int
-        L.or_state_field.argtypes = [pp, ctypes.c_double, ctypes.c_int64, dp, dp, dp, i8p, dp, dp, dp, dp, dp]
-        L.or_threads.restype = ctypes.c_int
-        _lib_handle = L
+        _lib_handle = _load(_LIB)
     return _lib_handle
+
+
+def _load(path):
+    L = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    i8p = ctypes.POINTER(ctypes.c_int8)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    pp = ctypes.POINTER(Params)
+    L.or_philox4x64_10.argtypes = [u64p, u64p, u64p]
+    L.or_u01.argtypes = [ctypes.c_uint64]
+    L.or_u01.restype = ctypes.c_double
+    L.or_adk_rate.argtypes = [ctypes.c_double] * 3
+    L.or_adk_rate.restype = ctypes.c_double
+    L.or_envelope.argtypes = [pp, ctypes.c_double]
+    L.or_envelope.restype = ctypes.c_double
+    L.or_laser.argtypes = [pp, ctypes.c_double, ctypes.c_double, dp, dp]
+    L.or_boris_push.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
+    L.or_coulomb_field.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, dp, dp, dp, dp]
+    L.or_coulomb_field_box.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_int, dp, dp, dp, dp]
+    L.or_coulomb_field_at.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int64,
+                                      i64p, dp, dp, dp, dp]
+    L.or_start.argtypes = [pp, ctypes.c_int64, dp, dp, dp, dp, dp, dp, i8p, dp]
+    L.or_start.restype = ctypes.c_double
+    L.or_run.argtypes = [pp, ctypes.c_int64, i64p, dp, dp, dp, dp, dp, dp, i8p, dp, dp, dp,
+                         ctypes.c_int64, ctypes.c_int64, dp, dp, dp, ctypes.c_int64, ctypes.POINTER(Detector)]
+    L.or_run.restype = ctypes.c_int64
+    L.or_e1.argtypes = [ctypes.c_double]
+    L.or_e1.restype = ctypes.c_double
+    L.or_lotz_rate.argtypes = [ctypes.c_double] * 4
+    L.or_lotz_rate.restype = ctypes.c_double
+    L.or_detector_init.argtypes = [ctypes.POINTER(Detector), ctypes.c_double, ctypes.c_double]
+    L.or_detector_init.restype = None
+    L.or_det_slots.restype = ctypes.c_int
+    L.or_state_field.argtypes = [pp, ctypes.c_double, ctypes.c_int64, dp, dp, dp, i8p, dp, dp, dp, dp, dp]
+    L.or_threads.restype = ctypes.c_int
+    return L
 
 
 def threads():
@@ -165,10 +193,10 @@ def boris_push(zm, dt, E, B, u):
     return out
 
 
-def coulomb_field(x, q, eps2, want_phi=True, box=0.0, image32=False):
+def coulomb_field(x, q, eps2, want_phi=True, box=0.0, grid32=False):
     """Direct-sum softened field of sources q (field units) at positions x (n x 3); box > 0:
-    minimum-image separations in a periodic cube of that side (image32: the periodic copy
-    chosen from FP32 positions, as FP32 pair kernels choose it)."""
+    minimum-image separations in a periodic cube of that side (grid32: from the positions on
+    the cube's 32-bit grid, as the FP32 pair kernels take them)."""
     x = np.ascontiguousarray(x, np.float64)
     n = x.shape[0]
     xs = [np.ascontiguousarray(x[:, k]) for k in range(3)]
@@ -176,7 +204,7 @@ def coulomb_field(x, q, eps2, want_phi=True, box=0.0, image32=False):
     e = [np.zeros(n) for _ in range(3)]
     phi = np.zeros(n) if want_phi else None
     lib().or_coulomb_field_box(n, _dp(xs[0]), _dp(xs[1]), _dp(xs[2]), _dp(q), float(eps2), float(box),
-                               1 if image32 else 0, _dp(e[0]),
+                               1 if grid32 else 0, _dp(e[0]),
                                _dp(e[1]), _dp(e[2]), _dp(phi) if want_phi else None)
     return np.stack(e, axis=1), phi
 

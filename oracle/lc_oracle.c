@@ -110,8 +110,8 @@ typedef struct {
   int32_t boundary;     /* OR_OPEN, OR_PERIODIC, or OR_MIXED (periodic while t < t_switch) */
   double box;           /* side L of the periodic cube centred on the cluster (c/w)  */
   double t_switch;      /* OR_MIXED: first time (1/w) with open boundaries             */
-  int32_t image32;      /* 1: periodic copy chosen in FP32 from FP32 positions (the      */
-                        /*    decision of FP32 pair kernels); 0: in FP64                 */
+  int32_t grid32;       /* 1: periodic separations from positions on the 32-bit grid of  */
+                        /*    the cube (the FP32 pair kernels' records); 0: in FP64      */
   int32_t collisional;  /* 1: add the collisional ionization rate to the ADK rate      */
   double lotz_a;        /* Lotz constant a (cm^2 eV^2)                                 */
   double lotz_q[OR_MAX_Z];  /* electrons in the outermost subshell of charge state Z  */
@@ -128,21 +128,27 @@ typedef struct {
  * ones afterwards (mixed), are the other options.  Periodic here means the minimum-image
  * convention: a pair interacts through the nearest periodic copy of the partner, and a
  * particle leaving the cube re-enters through the opposite face. */
+/* Position x on the 32-bit grid of the cube of side L: the integer nearest x 2^32 / L, taken
+ * modulo 2^32 (reduced to [-2^31, 2^31] in floating point first, then exactly). */
+static uint32_t or_grid(double x, double L) {
+  const double is = 4294967296.0 / L;
+  const double u = x * is;
+  const double w = u - 4294967296.0 * floor(u * (1.0 / 4294967296.0) + 0.5);
+  return (uint32_t)(int64_t)rint(w);
+}
+
 /* Separation xi - xj through the nearest periodic copy (L > 0).  Which copy is nearest is an
- * integer decided by floating point; image32 takes it as a pair kernel working on FP32
- * positions does, so that both sides decide alike for pairs within rounding of L/2. */
-static double or_sep(double xi, double xj, double L, int image32) {
+ * integer decided by floating point.  grid32 decides it as the FP32 pair kernels do: both
+ * positions on the 32-bit grid of the cube, the separation (L / 2^32) times their difference
+ * as a signed 32-bit integer (a difference of exactly 2^31 grid steps goes to -L/2). */
+static double or_sep(double xi, double xj, double L, int grid32) {
   double d = xi - xj;
   if (!(L > 0.0)) return d;
-  double k;
-  if (image32) {
-    float d32 = (float)xi - (float)xj;
-    float il32 = 1.0f / (float)L;
-    k = (double)rintf(d32 * il32);
-  } else {
-    k = nearbyint(d / L);
+  if (grid32) {
+    const int32_t k = (int32_t)(or_grid(xi, L) - or_grid(xj, L));
+    return (double)k * (L / 4294967296.0);
   }
-  return d - L * k;
+  return d - L * nearbyint(d / L);
 }
 
 static double or_wrap(double x, double L) { return x - L * floor(x / L + 0.5); }
@@ -160,15 +166,15 @@ static double or_box_at(const or_params* p, double t) {
  * ascending order for every i.  L > 0: separations by the minimum-image convention in a
  * periodic cube of side L. */
 void or_coulomb_field_box(int64_t n, const double* x, const double* y, const double* z, const double* q,
-                          double eps2, double L, int image32, double* ex, double* ey, double* ez, double* phi) {
+                          double eps2, double L, int grid32, double* ex, double* ey, double* ez, double* phi) {
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
     for (int64_t j = 0; j < n; ++j) {
       if (j == i) continue;
-      double dx = or_sep(x[i], x[j], L, image32);
-      double dy = or_sep(y[i], y[j], L, image32);
-      double dz = or_sep(z[i], z[j], L, image32);
+      double dx = or_sep(x[i], x[j], L, grid32);
+      double dy = or_sep(y[i], y[j], L, grid32);
+      double dz = or_sep(z[i], z[j], L, grid32);
       double r2 = dx * dx + dy * dy + dz * dz + eps2;
       double inv = 1.0 / sqrt(r2);
       double inv3 = inv * inv * inv;
@@ -379,7 +385,7 @@ double or_start(const or_params* p, int64_t n, const double* x, const double* y,
   double* ey = work + 2 * n;
   double* ez = work + 3 * n;
   or_charges(p, n, Z, q);
-  or_coulomb_field_box(n, x, y, z, q, p->eps2, or_box_at(p, p->t0), p->image32, ex, ey, ez, NULL);
+  or_coulomb_field_box(n, x, y, z, q, p->eps2, or_box_at(p, p->t0), p->grid32, ex, ey, ez, NULL);
   double ke = 0.0;
   for (int64_t i = 0; i < n; ++i) {
     double EL[3], BL[3];
@@ -536,7 +542,7 @@ static int or_step(const or_params* p, int64_t step, int64_t cap, int64_t* n_io,
   int diag = (p->diag_every > 0) && (step % p->diag_every == 0);
   double L = or_box_at(p, t);
   or_charges(p, n, Z, s->q);
-  or_coulomb_field_box(n, x, y, z, s->q, p->eps2, L, p->image32, s->ex, s->ey, s->ez, s->phi);
+  or_coulomb_field_box(n, x, y, z, s->q, p->eps2, L, p->grid32, s->ex, s->ey, s->ez, s->phi);
 
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
@@ -685,7 +691,7 @@ int64_t or_run(const or_params* p, int64_t cap, int64_t* n_io, double* x, double
 void or_state_field(const or_params* p, double t, int64_t n, const double* x, const double* y, const double* z,
                     const int8_t* Z, double* q_work, double* ex, double* ey, double* ez, double* phi) {
   or_charges(p, n, Z, q_work);
-  or_coulomb_field_box(n, x, y, z, q_work, p->eps2, or_box_at(p, t), p->image32, ex, ey, ez, phi);
+  or_coulomb_field_box(n, x, y, z, q_work, p->eps2, or_box_at(p, t), p->grid32, ex, ey, ez, phi);
 }
 
 int or_record_size(void) { return OR_REC; }

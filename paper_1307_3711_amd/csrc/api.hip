@@ -639,7 +639,7 @@ int lc_start(lc_sim* s) {
   ForceTiling ft = s->ft;
   ft.S = s->S_eff;
   const bool n3 = n3_pass(s, ft, false);
-  hipError_t e = launch_refresh_sources(s->s, s->rc, s->cfg.precision, s->stream);
+  hipError_t e = launch_refresh_sources(s->s, s->rc, s->cfg.precision, pbc_step(s, 0), s->stream);
   if (e == hipSuccess) e = schedule(s, ft, n3, false);
   if (e == hipSuccess)
     e = launch_force(s->s, s->rc, s->cfg.precision, ft, false, pbc_step(s, 0), force_grid(s, ft, n3), s->stream);

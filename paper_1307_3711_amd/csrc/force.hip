@@ -82,8 +82,35 @@ __device__ inline double rsq64(double x) {
 
 // Minimum-image separation in a periodic cube of side L (iL = 1/L): the nearest periodic copy
 // of the partner (Sec. II periodic boundaries); a separation inside (-L/2, L/2) is unchanged.
-__device__ inline float min_image(float d, float L, float iL) { return __builtin_fmaf(-L, __builtin_rintf(d * iL), d); }
+// FP64 records hold coordinates, and the copy is the rounded multiple of L.
 __device__ inline double min_image(double d, double L, double iL) { return __builtin_fma(-L, __builtin_rint(d * iL), d); }
+
+// FP32 records of a periodic pass hold the cube on a 32-bit grid (coordinate x as the integer
+// nearest x 2^32 / L, modulo 2^32; the charge as q (2^32 / L)^2): the wrapping integer
+// difference of two records is the minimum-image separation in grid units, one subtraction and
+// one conversion per component, and the pair terms in grid units are the field in physical
+// units (the potential is 2^32 / L times its physical value).
+__device__ inline float grid_sep(float a, float b) {
+  return (float)(int32_t)(__float_as_uint(a) - __float_as_uint(b));
+}
+
+template <typename T, bool PBC>
+__device__ inline T pair_sep(T a, T b, T L, T iL) {
+  if constexpr (!PBC) return a - b;
+  else if constexpr (sizeof(T) == 4) return grid_sep(a, b);
+  else return min_image(a - b, L, iL);
+}
+
+// eps^2 of a pass: in grid units, (eps 2^32 / L)^2, for FP32 records of a periodic pass.
+template <typename T, bool PBC>
+__device__ inline T pass_eps2(double eps2, double box) {
+  if constexpr (PBC && sizeof(T) == 4) {
+    const double is = 4294967296.0 / box;
+    return (T)(eps2 * (is * is));
+  } else {
+    return (T)eps2;
+  }
+}
 
 __device__ inline float n3_rsq(float x) { return rsq32(x); }
 __device__ inline double n3_rsq(double x) { return rsq64(x); }
@@ -98,21 +125,16 @@ __device__ inline double n3_rsq(double x) { return rsq64(x); }
 template <int R, bool PHI, bool KAHAN, bool UNIFORM, int U, bool PBC, typename P>
 __device__ inline void pair_loop(P src, int kb, int per, int64_t jt, const int64_t* ii, const float* xi,
                                  const float* yi, const float* zi, float eps2f, float* fx, float* fy, float* fz,
-                                 float* fp, float* cx, float* cy, float* cz, float* cpc, float L, float iL) {
+                                 float* fp, float* cx, float* cy, float* cz, float* cpc) {
   for (int k = kb; k < kb + per; k += U) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const float4 sj = src[k + u];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        float dx = xi[r] - sj.x;
-        float dy = yi[r] - sj.y;
-        float dz = zi[r] - sj.z;
-        if (PBC) {
-          dx = min_image(dx, L, iL);
-          dy = min_image(dy, L, iL);
-          dz = min_image(dz, L, iL);
-        }
+        const float dx = pair_sep<float, PBC>(xi[r], sj.x, 0.f, 0.f);
+        const float dy = pair_sep<float, PBC>(yi[r], sj.y, 0.f, 0.f);
+        const float dz = pair_sep<float, PBC>(zi[r], sj.z, 0.f, 0.f);
         float r2 = __builtin_fmaf(dx, dx, eps2f);
         r2 = __builtin_fmaf(dy, dy, r2);
         r2 = __builtin_fmaf(dz, dz, r2);
@@ -172,9 +194,7 @@ __device__ void tile_f32(const ForceArgs<float4>& a, const float4* __restrict__ 
   double ex[R], ey[R], ez[R], ep[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) { ex[r] = ey[r] = ez[r] = ep[r] = 0.0; }
-  const float eps2f = (float)a.eps2;
-  const float L = PBC ? (float)cp.box : 0.f;
-  const float iL = PBC ? 1.f / L : 0.f;
+  const float eps2f = pass_eps2<float, PBC>(a.eps2, cp.box);
 
   if constexpr (SCALAR) {
     // Sources straight from global memory with wave-uniform indices: scalar loads, SGPR
@@ -197,15 +217,14 @@ __device__ void tile_f32(const ForceArgs<float4>& a, const float4* __restrict__ 
       for (int r = 0; r < R; ++r) { fx[r] = fy[r] = fz[r] = fp[r] = 0.f; cx[r] = cy[r] = cz[r] = cpc[r] = 0.f; }
       const float4* __restrict__ seg = base + jt;
       if (uniform) {
-        pair_loop<R, PHI, KAHAN, true, kU, PBC>(seg, 0, main, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy, cz, cpc,
-                                                 L, iL);
+        pair_loop<R, PHI, KAHAN, true, kU, PBC>(seg, 0, main, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy, cz, cpc);
         pair_loop<R, PHI, KAHAN, true, 1, PBC>(seg, main, cnt - main, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy,
-                                               cz, cpc, L, iL);
+                                               cz, cpc);
       } else {
         pair_loop<R, PHI, KAHAN, false, kU, PBC>(seg, 0, main, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy, cz,
-                                                  cpc, L, iL);
+                                                  cpc);
         pair_loop<R, PHI, KAHAN, false, 1, PBC>(seg, main, cnt - main, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx,
-                                                cy, cz, cpc, L, iL);
+                                                cy, cz, cpc);
       }
       const double qs = uniform ? (double)q0 : 1.0;
 #pragma unroll
@@ -243,11 +262,9 @@ __device__ void tile_f32(const ForceArgs<float4>& a, const float4* __restrict__ 
 #pragma unroll
     for (int r = 0; r < R; ++r) { fx[r] = fy[r] = fz[r] = fp[r] = 0.f; cx[r] = cy[r] = cz[r] = cpc[r] = 0.f; }
     if (uniform && !PBC)
-      pair_loop<R, PHI, KAHAN, true, kU, PBC>(lds, kb, per, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy, cz, cpc,
-                                              L, iL);
+      pair_loop<R, PHI, KAHAN, true, kU, PBC>(lds, kb, per, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy, cz, cpc);
     else
-      pair_loop<R, PHI, KAHAN, false, kU, PBC>(lds, kb, per, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy, cz, cpc,
-                                               L, iL);
+      pair_loop<R, PHI, KAHAN, false, kU, PBC>(lds, kb, per, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy, cz, cpc);
     const double qs = uniform ? (double)q0 : 1.0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -295,7 +312,7 @@ __device__ void tile_f32(const ForceArgs<float4>& a, const float4* __restrict__ 
         base[0] = ex[r];
         base[a.stride] = ey[r];
         base[2 * a.stride] = ez[r];
-        if (PHI) base[3 * a.stride] = ep[r];
+        if (PHI) base[3 * a.stride] = PBC ? ep[r] * (cp.box * (1.0 / 4294967296.0)) : ep[r];
       }
     }
   }
@@ -524,14 +541,9 @@ __device__ inline void n3_steps(const T* bx, const T* by, const T* bz, const T* 
   for (int u = 0; u < U; ++u) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      T dx = xi[r] - bx[u];
-      T dy = yi[r] - by[u];
-      T dz = zi[r] - bz[u];
-      if (PBC) {
-        dx = min_image(dx, L, iL);
-        dy = min_image(dy, L, iL);
-        dz = min_image(dz, L, iL);
-      }
+      const T dx = pair_sep<T, PBC>(xi[r], bx[u], L, iL);
+      const T dy = pair_sep<T, PBC>(yi[r], by[u], L, iL);
+      const T dz = pair_sep<T, PBC>(zi[r], bz[u], L, iL);
       T r2 = n3_fma(dx, dx, eps2f);
       r2 = n3_fma(dy, dy, r2);
       r2 = n3_fma(dz, dz, r2);
@@ -649,7 +661,7 @@ __device__ void tile_n3(const N3Args<T>& a, int t, T* lds) {
   }
   // periodic boundaries: no uniform-charge factoring (the padding carries charge 0)
   const bool ut = __all(same_t) && !PBC;
-  const T eps2f = (T)a.eps2;
+  const T eps2f = pass_eps2<T, PBC>(a.eps2, cp.box);
   const T L = PBC ? (T)cp.box : T(0);
   const T iL = PBC ? T(1) / L : T(0);
   T ex[R], ey[R], ez[R];

@@ -238,7 +238,8 @@ hipError_t launch_start_kick(const DevState& s, const RunConst& rc, int precisio
 hipError_t launch_diag(const DevState& s, const RunConst& rc, const FieldLayout& fl, int64_t k, hipStream_t st);
 hipError_t launch_ionize(const DevState& s, const RunConst& rc, int precision, const FieldLayout& fl, int64_t k,
                          int n_ion_blocks, hipStream_t st);
-hipError_t launch_refresh_sources(const DevState& s, const RunConst& rc, int precision, hipStream_t st);
+// Source records of every live slot for the field pass of a step (pbc: that step is periodic).
+hipError_t launch_refresh_sources(const DevState& s, const RunConst& rc, int precision, bool pbc, hipStream_t st);
 
 // Standalone field (lc_field).
 hipError_t launch_field_standalone(int precision, int64_t n, const double* xyzq, double eps2, double* E,

@@ -71,10 +71,27 @@ __device__ inline double unit_interval(uint64_t x) {
 constexpr uint64_t kPurposeAlpha = 2;
 constexpr uint64_t kPurposeDirection = 3;
 
-__device__ inline void write_source(const DevState& s, int precision, int64_t g, double x, double y, double z,
-                                    double q) {
-  if (precision == LC_FP64) s.posq[g] = make_double4(x, y, z, q);
-  else s.pos4[g] = make_float4((float)x, (float)y, (float)z, (float)q);
+// Coordinate x on the 32-bit grid of a periodic cube (is = 2^32 / L): the integer nearest
+// x is, reduced modulo 2^32 (to [-2^31, 2^31] first, so the conversion is exact for any
+// position), as the bit pattern of the FP32 record's component.
+__device__ inline float grid_coord(double x, double is) {
+  const double u = x * is;
+  const double w = u - 4294967296.0 * floor(u * (1.0 / 4294967296.0) + 0.5);
+  return __uint_as_float((uint32_t)(int64_t)rint(w));
+}
+
+// Source record of slot g for the field pass of a step: {x, y, z, q}; FP32 records of a
+// periodic pass hold the grid coordinates and q (2^32 / L)^2 (the pair kernels' grid units).
+__device__ inline void write_source(const DevState& s, int precision, bool grid, double box, int64_t g, double x,
+                                    double y, double z, double q) {
+  if (precision == LC_FP64) {
+    s.posq[g] = make_double4(x, y, z, q);
+  } else if (grid) {
+    const double is = 4294967296.0 / box;
+    s.pos4[g] = make_float4(grid_coord(x, is), grid_coord(y, is), grid_coord(z, is), (float)(q * (is * is)));
+  } else {
+    s.pos4[g] = make_float4((float)x, (float)y, (float)z, (float)q);
+  }
 }
 
 // Laser electric field (ax, ay, 0) at time t and height z (Eqs.(4)-(9)); the magnetic field
@@ -286,7 +303,8 @@ __device__ inline void push_one(const DevState& s, const RunConst& rc, int64_t g
   }
   s.ux[g] = unx; s.uy[g] = uny; s.uz[g] = unz;
   s.x[g] = x; s.y[g] = y; s.z[g] = z;
-  write_source(s, PREC, g, x, y, z, cp.kw * (double)zc);
+  // records for the field pass of step n + 1, in that step's form
+  write_source(s, PREC, periodic_at(rc, rc.t0 + (double)(n + 1) * rc.dt), cp.box, g, x, y, z, cp.kw * (double)zc);
   if (!(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(unx) && isfinite(uny) && isfinite(unz)))
     atomicOr(s.err, kFlagNonfinite);
   if (!p.seen && zc > 0) detect_ion(s, rc, cp, c, g, x, y, z, M, unx, uny, unz);  // only ion slots hold Z > 0
@@ -698,10 +716,11 @@ __global__ __launch_bounds__(kBlock) void k_ionize_spawn(DevState s, RunConst rc
       s.wl[ge] = 0.0;
       s.wc[ge] = 0.0;
       s.wsp[ge] = cp.weight * gm1(ux, uy, uz);
-      write_source(s, PREC, ge, xe, ye, ze, -cp.kw);
+      const bool grid = periodic_at(rc, rc.t0 + (double)(n + 1) * rc.dt);  // records for step n + 1
+      write_source(s, PREC, grid, cp.box, ge, xe, ye, ze, -cp.kw);
       const int znew = s.Z[gi] + 1;
       s.Z[gi] = (int8_t)znew;
-      write_source(s, PREC, gi, s.x[gi], s.y[gi], s.z[gi], cp.kw * (double)znew);
+      write_source(s, PREC, grid, cp.box, gi, s.x[gi], s.y[gi], s.z[gi], cp.kw * (double)znew);
     }
   }
   if (b == cp.n_ion_blocks - 1 && threadIdx.x == 0) {
@@ -716,13 +735,13 @@ __global__ __launch_bounds__(kBlock) void k_ionize_spawn(DevState s, RunConst rc
 }
 
 template <int PREC>
-__global__ __launch_bounds__(kBlock) void k_refresh_sources(DevState s, RunConst rc) {
+__global__ __launch_bounds__(kBlock) void k_refresh_sources(DevState s, RunConst rc, int grid) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (g >= rc.n_total) return;
   const int c = s.cid[g];
   const ClusterParams& cp = s.cp[c];
   if (g - cp.off >= s.dyn[c].n_cur) return;
-  write_source(s, PREC, g, s.x[g], s.y[g], s.z[g], cp.kw * (double)s.Z[g]);
+  write_source(s, PREC, grid != 0, cp.box, g, s.x[g], s.y[g], s.z[g], cp.kw * (double)s.Z[g]);
 }
 
 int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
@@ -783,9 +802,9 @@ hipError_t launch_ionize(const DevState& s, const RunConst& rc, int precision, c
   return hipGetLastError();
 }
 
-hipError_t launch_refresh_sources(const DevState& s, const RunConst& rc, int precision, hipStream_t st) {
-  if (precision == LC_FP64) k_refresh_sources<LC_FP64><<<blocks_for(rc.n_total), kBlock, 0, st>>>(s, rc);
-  else k_refresh_sources<LC_FP32_ACC64><<<blocks_for(rc.n_total), kBlock, 0, st>>>(s, rc);
+hipError_t launch_refresh_sources(const DevState& s, const RunConst& rc, int precision, bool pbc, hipStream_t st) {
+  if (precision == LC_FP64) k_refresh_sources<LC_FP64><<<blocks_for(rc.n_total), kBlock, 0, st>>>(s, rc, 0);
+  else k_refresh_sources<LC_FP32_ACC64><<<blocks_for(rc.n_total), kBlock, 0, st>>>(s, rc, pbc ? 1 : 0);
   return hipGetLastError();
 }
 

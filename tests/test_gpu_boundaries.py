@@ -9,14 +9,15 @@ so that every part of the boundary handling acts within 200 steps.
 Tolerances (fixed before measuring):
   FP64 runs: as for open boundaries, max |dx| / R0 <= 1e-9, max |du| <= 1e-9 max |u|, KE, PE,
         W_L, W_C within 1e-10 relative.
-  FP32 pairs: which periodic copy is nearest is an integer decided by floating point, and the
-        FP32 kernels decide it from FP32 positions.  A single field pass on a fixed wrapped
-        state is compared with the oracle taking the same decision (image32) on the kernel's
-        FP32 operands: |dE| <= 64 u S1_i as for open boundaries.  FP32 runs are not compared
-        orbit by orbit: once FP32 force rounding has moved the positions (1e-5 R0), pairs
-        near half the box are decided from different positions on the two sides, and the
-        minimum-image force jumps there; they are checked for staying in the cube and for the
-        exact discrete energy identity instead.
+  FP32 pairs: which periodic copy is nearest is an integer decided by floating point; the
+        FP32 kernels take separations from positions on the cube's 32-bit grid (the wrapped
+        integer difference).  A single field pass on a fixed wrapped state is compared with
+        the oracle taking the same grid (grid32) on the same FP64 positions: |dE| <= 64 u S1_i
+        as for open boundaries.  FP32 runs are not compared orbit by orbit: once FP32 force
+        rounding has moved the positions (1e-5 R0), pairs near half the box are decided from
+        different positions on the two sides, and the minimum-image force jumps there; they
+        are checked for staying in the cube and for the exact discrete energy identity
+        instead.
 """
 import dataclasses
 
@@ -34,9 +35,9 @@ pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="n
 U32 = 2.0**-24
 
 
-def _oracle(c, run, state, image32=False):
+def _oracle(c, run, state, grid32=False):
     sim = oracle.Sim.from_workload(c, run, state)
-    sim.p.image32 = 1 if image32 else 0
+    sim.p.grid32 = 1 if grid32 else 0
     sim.start()
     return sim
 
@@ -101,11 +102,11 @@ def test_periodic_field_fp32_matches_oracle(tiling):
     x = g["x"]
     L = osim.p.box
     q = osim.p.kappa * osim.p.weight * g["Z"].astype(np.float64)
-    xr = x.astype(np.float32).astype(np.float64)
-    qr = q.astype(np.float32).astype(np.float64)
-    eps2 = float(np.float32(osim.p.eps2))
-    Eo, _ = oracle.coulomb_field(xr, qr, eps2, want_phi=False, box=float(np.float32(L)), image32=True)
+    Eo, _ = oracle.coulomb_field(x, q, osim.p.eps2, want_phi=False, box=L, grid32=True)
     d = x[:, None, :] - x[None, :, :]
+    # no pair within 4 grid steps of half the box, where an ulp of L could change the copy
+    tie = np.abs(np.abs(d) - L / 2) / (L * 2.0**-32)
+    assert tie.min() > 4
     d -= L * np.rint(d / L)
     r2 = np.sum(d * d, axis=2)
     t = np.abs(q)[None, :] * np.sqrt(r2) / (r2 + osim.p.eps2) ** 1.5
@@ -151,3 +152,85 @@ def test_mixed_boundary_graph_replay_bitwise():
         sim.close()
     for a, b in zip(out[0], out[1]):
         assert np.array_equal(a, b)
+
+
+def _fp32_field_error(E, x, q, eps2, L=None):
+    """max |E - E_oracle| / S1 with the oracle on the kernel's operands: the cube's grid for a
+    periodic pass (L given), FP32-rounded positions, charges and eps^2 for an open one."""
+    if L is not None:
+        Eo, _ = oracle.coulomb_field(x, q, eps2, want_phi=False, box=L, grid32=True)
+    else:
+        r32 = lambda v: np.asarray(v, np.float32).astype(np.float64)
+        Eo, _ = oracle.coulomb_field(r32(x), r32(q), float(np.float32(eps2)), want_phi=False)
+    d = x[:, None, :] - x[None, :, :]
+    if L is not None:
+        assert (np.abs(np.abs(d) - L / 2) / (L * 2.0**-32)).min() > 4
+        d -= L * np.rint(d / L)
+    r2 = np.sum(d * d, axis=2)
+    t = np.abs(q)[None, :] * np.sqrt(r2) / (r2 + eps2) ** 1.5
+    np.fill_diagonal(t, 0.0)
+    return np.max(np.abs(E - Eo) / t.sum(axis=1)[:, None])
+
+
+@pytest.mark.parametrize("tiling", [dict(R=4, WJ=4, newton3=1), dict(R=2, WJ=2, S=4),
+                                    dict(R=1, WJ=4, T=1024, S=8, scalar=1)])
+def test_mixed_fp32_records_across_the_switch(tiling):
+    """FP32 source records change form at the switch (grid coordinates while periodic, plain
+    coordinates afterwards; the push of a step writes them in the form of the next step's
+    pass): the passes of the last periodic step (99, t = 4.95) and the first open one (100,
+    t = 5) each against the oracle on the GPU's positions, 64 u S1."""
+    import paper_1307_3711_amd as lc
+    c, run = _case("mixed")
+    mpb = lc.pair_blocks_for([c.capacity]) if tiling.get("newton3") else 0
+    sim, states = gpu_run([c], run, "fp32_acc64", tuning=tiling, max_pair_blocks=mpb)
+    op = _oracle(c, run, states[0]).p
+    for steps, periodic in ((99, True), (1, False)):
+        sim.step(steps)
+        g = sim.particles(0)
+        E = sim.field(0)
+        q = op.kappa * op.weight * g["Z"].astype(np.float64)
+        err = _fp32_field_error(E, g["x"], q, op.eps2, op.box if periodic else None)
+        print(f"{tiling} step {99 if periodic else 100} ({'periodic' if periodic else 'open'}): "
+              f"max |dE| / S1 = {err / U32:.1f} u", flush=True)
+        assert err <= 64 * U32
+    sim.close()
+
+
+def test_half_box_tie_on_the_grid():
+    """Two ions exactly half a box apart along x on the grid (2^30 grid steps either side of
+    the centre): the wrapped difference is -2^31 grid steps whichever ion is the target, so
+    each ion sees the other's copy on its +x side (r_i - r_j' = -L/2), in the FP32 kernels
+    (one block: every pair evaluated from both ends) as in the grid oracle.  The FP64 oracle
+    with the second ion moved by 1e-6 L to either side of the tie tells the copies apart for
+    each ion."""
+    import paper_1307_3711_amd as lc
+    from workloads import Cluster, Laser, Run
+    c = Cluster(species="Ar", r0_nm=2.5, n_ion=2, capacity=4, z_init=1, z_max=1,
+                laser=Laser(intensity_wcm2=0.0, envelope="flat"), n_steps=10)
+    run = Run(dt=0.05, ionize=False, boundary="periodic", box_r0=4.0, diag_every=0)
+    kn = units.nm_to_norm(1.0, 0.8)
+    L = run.box_r0 * units.nm_to_norm(c.r0_nm, 0.8)
+    xg = 2.0**30 * (L / 2.0**32)  # on the grid
+    x = np.array([[xg, 0, 0], [-xg, 0, 0], [0, 0.3 * L, 0], [0.1 * L, -0.2 * L, 0.1 * L]]) / kn
+    state = {"x_nm": x, "u": np.zeros_like(x), "Z": np.array([1, 1, -1, -1], np.int8), "n_ion": 2}
+    for tiling in (dict(R=4, WJ=4, newton3=1), dict(R=2, WJ=2, S=2)):
+        mpb = lc.pair_blocks_for([c.capacity]) if tiling.get("newton3") else 0
+        sim, _ = gpu_run([c], run, "fp32_acc64", states=[state], tuning=tiling, max_pair_blocks=mpb)
+        g = sim.particles(0)
+        E = sim.field(0)
+        sim.close()
+        op = _oracle(c, run, state).p
+        q = op.kappa * op.weight * g["Z"].astype(np.float64)
+        Eg, _ = oracle.coulomb_field(g["x"], q, op.eps2, want_phi=False, box=op.box, grid32=True)
+        near = {}
+        for side, dx in (("-L/2", -1e-6), ("+L/2", 1e-6)):
+            xs = g["x"].copy()
+            xs[1, 0] += dx * op.box  # ion 0 minus ion 1: just over or just under half the box
+            near[side], _ = oracle.coulomb_field(xs, q, op.eps2, want_phi=False, box=op.box)
+        scale = np.max(np.abs(Eg))
+        # ion 0 sees ion 1's copy at x0 + L/2, as when ion 0 - ion 1 is just over L/2 (first
+        # nudge); ion 1 sees ion 0's copy at x1 + L/2, as when it is just under (second nudge)
+        for ion, same, other in ((0, "-L/2", "+L/2"), (1, "+L/2", "-L/2")):
+            assert np.max(np.abs(Eg[ion] - near[same][ion])) <= 1e-4 * scale
+            assert np.max(np.abs(Eg[ion] - near[other][ion])) > 1e-2 * scale
+        assert np.max(np.abs(E - Eg)) <= 64 * U32 * scale, (tiling, E, Eg)

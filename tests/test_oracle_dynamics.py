@@ -649,27 +649,44 @@ def test_periodic_momentum_newton3_and_box():
     assert abs(lhs - rhs) <= 1e-11 * (abs(rec2[-1][oracle.R_WL]) + abs(rec2[-1][oracle.R_WC]) + abs(sim2.ke_start))
 
 
-def test_image_decision_in_fp32():
-    """Which periodic copy is nearest is an integer decided by floating point.  With image32
-    the oracle decides it from FP32 positions: x_i = 1/4 + 1e-9 rounds to 1/4 in FP32, so a
-    partner at -1/4 in a cube of side 1 sits at exactly half the box and the tie goes to the
-    copy at +1/2 (round half to even), while in FP64 the copy at -1/2 + 1e-9 is nearer; away
-    from half-box ties both decisions agree bitwise."""
-    x = np.array([[0.25 + 1e-9, 0.0, 0.0], [-0.25, 0.0, 0.0]])
+def test_grid32_separations():
+    """FP32 periodic passes take separations from positions on the cube's 32-bit grid (side L
+    spans 2^32 steps; the wrapped integer difference is the minimum image).  Pinned by what the
+    definition fixes: at an exact half-box tie the wrap gives -L/2 where the FP64 rounding
+    gives +L/2; dyadic positions already on the grid (L = 1) give the FP64 minimum image bit
+    for bit; moving a particle by whole box sides changes nothing, bit for bit, also from
+    beyond a face; elsewhere the field moves by no more than quantization by L 2^-33 allows."""
+    x = np.array([[0.25, 0.0, 0.0], [-0.25, 0.0, 0.0]])
     q = np.array([0.0, 1.0])
     e64, _ = oracle.coulomb_field(x, q, 1e-6, box=1.0)
-    e32, _ = oracle.coulomb_field(x, q, 1e-6, box=1.0, image32=True)
-    assert e64[0][0] < 0 < e32[0][0]
-    assert abs(e64[0][0] + e32[0][0]) < 1e-6 * abs(e32[0][0])
+    e32, _ = oracle.coulomb_field(x, q, 1e-6, box=1.0, grid32=True)
+    assert e64[0][0] > 0 and e32[0][0] == -e64[0][0]
     rng = np.random.default_rng(5)
-    xr = rng.uniform(-0.5, 0.5, (40, 3))
-    d = xr[:, None, :] - xr[None, :, :]
-    frac = np.abs(np.abs(d) - 0.5)
-    assert frac[frac > 0].min() > 1e-6  # no pair near a tie
+    xd = rng.integers(-2**19, 2**19, (40, 3)) / 2.0**20  # dyadic, inside (-1/2, 1/2)
+    d = xd[:, None, :] - xd[None, :, :]
+    assert np.all(np.abs(np.abs(d) - 0.5) > 0)  # no exact tie
     qr = rng.choice([-1.0, 1.0], 40)
-    a, pa = oracle.coulomb_field(xr, qr, 1e-4, box=1.0)
-    b, pb = oracle.coulomb_field(xr, qr, 1e-4, box=1.0, image32=True)
+    a, pa = oracle.coulomb_field(xd, qr, 1e-4, box=1.0)
+    b, pb = oracle.coulomb_field(xd, qr, 1e-4, box=1.0, grid32=True)
     assert np.array_equal(a, b) and np.array_equal(pa, pb)
+    shift = rng.integers(-3, 4, (40, 3)).astype(np.float64)
+    c, pc = oracle.coulomb_field(xd + shift, qr, 1e-4, box=1.0, grid32=True)
+    assert np.array_equal(b, c) and np.array_equal(pb, pc)
+    L = 1.3
+    xr = rng.uniform(-0.65, 0.65, (40, 3))
+    dd = xr[:, None, :] - xr[None, :, :]
+    frac = np.abs(np.abs(dd) - L / 2)
+    assert frac[frac > 0].min() > 1e-6  # no pair near a tie
+    eps2 = 1e-4
+    f64, p64 = oracle.coulomb_field(xr, qr, eps2, box=L)
+    f32, p32 = oracle.coulomb_field(xr, qr, eps2, box=L, grid32=True)
+    dd -= L * np.rint(dd / L)
+    r2 = np.sum(dd * dd, axis=2) + eps2
+    s1 = np.sum(np.where(np.eye(40, dtype=bool), 0.0, 1.0 / r2), axis=1)  # sum of |q| / (r^2 + eps^2)
+    # each separation moves by at most L 2^-32; a term q d / (r^2+eps^2)^{3/2} by at most 3 times that
+    # over (r^2 + eps^2)^{3/2}, below 3 L 2^-32 / eps times s1
+    assert np.max(np.abs(f32 - f64) / s1[:, None]) <= 3 * L * 2.0**-32 / math.sqrt(eps2)
+    assert 0 < np.max(np.abs(f32 - f64))
 
 
 def _ci_cloud(seed=31, n_ion=3000, n_e=2000, t_ev=100.0, surv=0.5, nsteps=40):
@@ -741,3 +758,23 @@ def test_collisional_survival_law(t_ev):
     sim0.start()
     sim0.run(nsteps)
     assert np.all(sim0.charges()[:n_ion] == 1)
+
+
+def test_native_build_takes_the_same_arithmetic(tmp_path):
+    """The stronger CPU timing builds the oracle's source again with -O3 -march=native; with
+    contraction and fast math still off it must reproduce the plain build bit for bit (the small
+    argon run with ionization and diagnostics, 20 steps)."""
+    c, run = small_ar()
+    st = initial_state(c, run.seed)
+
+    def states():
+        s = oracle.Sim.from_workload(c, run, st)
+        s.start()
+        rec = s.run(20)
+        return s.positions(), s.momenta(), s.charges(), rec
+
+    ref = states()
+    with oracle.library(oracle.build_native(str(tmp_path / "liblc_oracle_native.so"))):
+        nat = states()
+    for a, b in zip(ref, nat):
+        assert np.array_equal(a, b)
