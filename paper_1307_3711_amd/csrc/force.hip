@@ -243,7 +243,7 @@ __device__ void tile_f32(const ForceArgs<float4>& a, const float4* __restrict__ 
     // exactly zero on both inner loops.  A tile whose sources all carry the same charge takes
     // the uniform loop, which factors the charge out of the pair term.  With periodic
     // boundaries the minimum image would bring such an entry close, so padding sits at the
-    // origin with zero charge and every tile takes the loop that multiplies by the charge.
+    // origin with zero charge, and only a tile without padding takes the uniform loop.
     const float q0 = a.src[off + jt].w;
     int same = 1;
     __syncthreads();
@@ -255,13 +255,13 @@ __device__ void tile_f32(const ForceArgs<float4>& a, const float4* __restrict__ 
       }
       lds[k] = v;
     }
-    const int uniform = __syncthreads_and(same) && !PBC;
+    const int uniform = __syncthreads_and(same) && (!PBC || cnt == cntp);
     const int per = cntp / WJ;
     const int kb = jw * per;
     float fx[R], fy[R], fz[R], fp[R], cx[R], cy[R], cz[R], cpc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) { fx[r] = fy[r] = fz[r] = fp[r] = 0.f; cx[r] = cy[r] = cz[r] = cpc[r] = 0.f; }
-    if (uniform && !PBC)
+    if (uniform)
       pair_loop<R, PHI, KAHAN, true, kU, PBC>(lds, kb, per, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy, cz, cpc);
     else
       pair_loop<R, PHI, KAHAN, false, kU, PBC>(lds, kb, per, jt, ii, xi, yi, zi, eps2f, fx, fy, fz, fp, cx, cy, cz, cpc);
@@ -659,8 +659,9 @@ __device__ void tile_n3(const N3Args<T>& a, int t, T* lds) {
       qi[r] = qT;
     }
   }
-  // periodic boundaries: no uniform-charge factoring (the padding carries charge 0)
-  const bool ut = __all(same_t) && !PBC;
+  // periodic boundaries: the padding carries charge 0, so the target charge is factored out
+  // only for a wave without padding
+  const bool ut = __all(same_t) && (!PBC || i0 + TGT <= n);
   const T eps2f = pass_eps2<T, PBC>(a.eps2, cp.box);
   const T L = PBC ? (T)cp.box : T(0);
   const T iL = PBC ? T(1) / L : T(0);
@@ -678,7 +679,7 @@ __device__ void tile_n3(const N3Args<T>& a, int t, T* lds) {
       else if (PBC) { sv.x = 0; sv.y = 0; sv.z = 0; sv.w = 0; }
       else { sv.x = kFar; sv.y = kFar; sv.z = kFar; sv.w = 0; }
       const T qs0 = src[jb].w;
-      const bool us = __all(jj >= n || sv.w == qs0) && !PBC;
+      const bool us = PBC ? __all(jj < n && sv.w == qs0) : __all(jj >= n || sv.w == qs0);
       sb[lane] = sv.x;
       sb[lane + 64] = sv.x;
       sb[kN3Slice + lane] = sv.y;
@@ -691,20 +692,17 @@ __device__ void tile_n3(const N3Args<T>& a, int t, T* lds) {
       T cx[R], cy[R], cz[R], ax, ay, az;
 #pragma unroll
       for (int r = 0; r < R; ++r) cx[r] = cy[r] = cz[r] = 0;
-      if constexpr (PBC) {
-        if (jside) n3_chunk<T, R, false, false, true, true>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az, L, iL);
-        else n3_chunk<T, R, false, false, false, true>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az, L, iL);
-      } else if (jside) {
+      if (jside) {
         if (us) {
-          if (ut) n3_chunk<T, R, true, true, true, false>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az, L, iL);
-          else n3_chunk<T, R, true, false, true, false>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az, L, iL);
+          if (ut) n3_chunk<T, R, true, true, true, PBC>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az, L, iL);
+          else n3_chunk<T, R, true, false, true, PBC>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az, L, iL);
         } else {
-          if (ut) n3_chunk<T, R, false, true, true, false>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az, L, iL);
-          else n3_chunk<T, R, false, false, true, false>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az, L, iL);
+          if (ut) n3_chunk<T, R, false, true, true, PBC>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az, L, iL);
+          else n3_chunk<T, R, false, false, true, PBC>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az, L, iL);
         }
       } else {
-        if (us) n3_chunk<T, R, true, true, false, false>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az, L, iL);
-        else n3_chunk<T, R, false, true, false, false>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az, L, iL);
+        if (us) n3_chunk<T, R, true, true, false, PBC>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az, L, iL);
+        else n3_chunk<T, R, false, true, false, PBC>(sb, lane, xi, yi, zi, qi, eps2f, cx, cy, cz, ax, ay, az, L, iL);
       }
       wave_lds_sync();
       const T fs = us ? qs0 : T(1);
