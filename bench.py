@@ -183,7 +183,8 @@ def bench_ensemble(args):
            "data": "synthetic",
            "config": {"workload": f"{len(cl)} Ar/Xe clusters, capacity log-uniform 1k-16k, R0 2-10 nm, "
                                   "1e15-1e17 W/cm2, FWHM 20-100 fs, t_end = 4 FWHM, ionization on",
-                      "seed": args.seed, "tiling": r32["tiling"], "total_capacity": int(sum(c.capacity for c in cl))},
+                      "seed": args.seed, "tiling": r32["tiling"], "tilings": r32["tunings"],
+                      "total_capacity": int(sum(c.capacity for c in cl))},
            "gpairs_per_s": round(r32["pairs"] / r32["wall_s"] / 1e9, 2), "pairs": r32["pairs"],
            "wall_s": round(r32["wall_s"], 3)}
     if not args.no_fp64:

@@ -15,11 +15,21 @@ from ._binding import R_ABS_EV, R_MEANZ, Simulation, make_config, pair_blocks_fo
 
 def run_ensemble(descs, states, precision="fp32_acc64", dt=0.05, softening_nm=0.1, seed=0, diag_every=50,
                  graph_steps=50, autotune=True, max_steps=None, tiling=None, progress=None, lambda_um=0.8,
-                 keep_particles=False):
+                 keep_particles=False, adapt=True, probe_steps=100):
     """Integrate every cluster until it retires.  descs: lc_cluster descriptions with n_steps
     set; states: initial particle arrays (x_nm, u, Z) per cluster.  Returns a dict with the
     last diagnostic record of each cluster, per-cluster counters and the timed wall clock (and
-    each cluster's final particles with keep_particles)."""
+    each cluster's final particles with keep_particles).
+
+    With autotune the tiling is chosen at the start.  Ionization grows the clusters from their
+    initial counts towards capacity, which favours the pair-once pass (its row fold costs less
+    against a larger pair count), so a run that starts on the one-sided pass checks, with
+    adapt, whether the pair-once pass (R = WJ = 4, persistent) has become faster: a chunk of
+    steps opens with two timed stretches of probe_steps real steps, one on each pass, and
+    keeps the faster; after a loss the next check waits twice as many chunks (up to 8), after
+    a win there are no more checks.  The probes advance the run like any other steps, so a
+    check costs two synchronizations and a graph capture.  The choice follows measured times,
+    so FP32 results of two runs may differ at rounding level where they chose differently."""
     # room for the pair-once kernel (blocks of 128 slots and up) where the precision allows it
     mpb = pair_blocks_for([d.capacity for d in descs], 128) if precision in ("fp32_acc64", "fp64") else 0
     cfg = make_config(precision, ionize=True, lambda_um=lambda_um, dt=dt, softening_nm=softening_nm,
@@ -43,9 +53,45 @@ def run_ensemble(descs, states, precision="fp32_acc64", dt=0.05, softening_nm=0.
     t0 = time.perf_counter()
     chunk = max(graph_steps or 1, 1) * 20
     done = 0
+    tunings = [dict(tuned, at_step=0)] if tuned else []
+    other = None
+    if adapt and tuned and mpb and not tuned["newton3"]:
+        other = dict(R=4, WJ=4, newton3=1, persistent=1)
+    wait, interval = 0, 1
+
+    def timed(n):
+        sim.stream.synchronize()
+        t = time.perf_counter()
+        sim.step(n)
+        sim.stream.synchronize()
+        return time.perf_counter() - t
+
+    warm = max(graph_steps or 1, 1)  # the steps that capture a new graph stay out of the timing
     while done < total:
         k = min(chunk, total - done)
-        sim.step(k)
+        if other is not None and wait > 0:
+            wait -= 1
+            sim.step(k)
+        elif other is not None and k >= 2 * (probe_steps + warm):
+            cur = sim.tuning()
+            t_cur = timed(probe_steps)
+            sim.set_tuning(**other)
+            if graph_steps:
+                sim.set_graph(graph_steps)
+            sim.step(warm)
+            t_other = timed(probe_steps)
+            if t_other < t_cur:
+                tunings.append(dict(sim.tuning(), at_step=done + probe_steps))
+                other = None
+            else:
+                sim.set_tuning(**cur)
+                if graph_steps:
+                    sim.set_graph(graph_steps)
+                interval = min(2 * interval, 8)
+                wait = interval - 1
+            sim.step(k - 2 * probe_steps - warm)
+        else:
+            sim.step(k)
         done += k
         if progress:
             sim.stream.synchronize()
@@ -61,7 +107,8 @@ def run_ensemble(descs, states, precision="fp32_acc64", dt=0.05, softening_nm=0.
         counters.append(sim.counters(i))
         if keep_particles:
             parts.append(sim.particles(i))
-    out = {"last": np.array(last), "counters": counters, "wall_s": wall, "steps": total, "tiling": tuned or sim.tuning(),
+    out = {"last": np.array(last), "counters": counters, "wall_s": wall, "steps": total, "tiling": sim.tuning(),
+           "tunings": tunings,
            "pairs": float(sum(c["pairs"] for c in counters)),
            "cluster_steps": int(sum(c["steps"] for c in counters))}
     if keep_particles:

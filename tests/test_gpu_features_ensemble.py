@@ -100,3 +100,32 @@ def test_circular_in_periodic_cube(tiling):
     print(f"circular + periodic {tiling}: max|dx|/R0 = {dx:.3e}", flush=True)
     assert dx <= 1e-9
     sim.close()
+
+
+def test_adaptive_pass_choice_keeps_the_run_exact():
+    """An autotuned ensemble run that checks, on real steps, whether the pair-once pass has
+    become faster (the pass may change mid-run): every cluster takes exactly its steps and
+    retires, the tiling log starts with the autotuner's choice and can only add the pair-once
+    pass, and the exact discrete energy identity KE(n+1/2) - KE(-1/2) = W_L + W_C + spawn KE
+    holds for every cluster (it holds for whatever field each step used)."""
+    import paper_1307_3711_amd as lc
+    from paper_1307_3711_amd.ensemble import run_ensemble
+    from workloads import ensemble, initial_state
+    from workloads.species import SPECIES
+    cl = ensemble(24, seed=9, cap_lo=300, cap_hi=3000)
+    steps = [1200 + 60 * i for i in range(len(cl))]
+    descs = [lc.make_cluster(SPECIES[c.species], c.r0_nm, c.n_ion, c.capacity, c.laser.intensity_wcm2,
+                             envelope=c.laser.envelope, fwhm_fs=c.laser.fwhm_fs, z_max=c.z_max, n_steps=n)
+             for c, n in zip(cl, steps)]
+    states = [initial_state(c, 9, i) for i, c in enumerate(cl)]
+    r = run_ensemble(descs, states, "fp32_acc64", seed=9, diag_every=50, graph_steps=10, probe_steps=40)
+    print("tilings:", r["tunings"], flush=True)
+    assert 1 <= len(r["tunings"]) <= 2 and r["tunings"][0]["at_step"] == 0
+    if len(r["tunings"]) == 2:
+        assert r["tunings"][1]["newton3"] == 1 and r["tunings"][0]["newton3"] == 0
+    for i, cnt in enumerate(r["counters"]):
+        assert cnt["steps"] == steps[i]
+    rec = r["last"]
+    ident = np.abs(rec[:, 5] - rec[:, 23] - (rec[:, 8] + rec[:, 9] + rec[:, 10]))
+    scale = np.abs(rec[:, 8]) + np.abs(rec[:, 9]) + rec[:, 10] + np.abs(rec[:, 23])
+    assert np.max(ident / scale) <= 1e-11
