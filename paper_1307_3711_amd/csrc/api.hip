@@ -456,6 +456,14 @@ int lc_create(lc_sim** out, const lc_config* cfg, const lc_cluster* clusters, in
   rc.diag_every = cfg->diag_every;
   rc.max_records = cfg->diag_every > 0 ? cfg->max_records : 1;
   rc.n3_rows = cfg->max_pair_blocks;
+  {
+    double s1 = 0.0, s2 = 0.0;
+    for (int c = 0; c < n_clusters; ++c) {
+      s1 += (double)clusters[c].capacity;
+      s2 += (double)clusters[c].capacity * (double)clusters[c].capacity;
+    }
+    rc.cap_slot_mean = s1 > 0.0 ? s2 / s1 : 0.0;
+  }
   rc.n_total = L.n_total;
   rc.mec2_ev = kMec2Ev;
   rc.det_on = cfg->detector_r0 > 0.0 ? 1 : 0;

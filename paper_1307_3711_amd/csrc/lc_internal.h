@@ -106,6 +106,7 @@ struct RunConst {
   int32_t boundary;     // LC_OPEN, LC_PERIODIC or LC_MIXED
   int32_t collisional;  // collisional ionization rate added to the tunnelling rate
   int32_t ci_blocks;    // blocks per cluster of the electron density/temperature reduction
+  double cap_slot_mean; // sum of capacity^2 over sum of capacity: the capacity of a typical slot's cluster
   double det_cos2;      // cos^2 of the detectors' acceptance half-angle
   double t_switch;      // LC_MIXED: first time (1/w) with open boundaries
 };
@@ -187,6 +188,19 @@ __device__ inline void field_sum(const DevState& s, const RunConst& rc, const Fi
 // sums of global slot g over the rows m = w, w + ways, w + 2 ways, ... < nb of its block, in
 // that order (FP64).  Blocks of `ways` waves over 64 consecutive slots read them coalesced.
 constexpr int kFoldWaves = 8;
+
+// Waves per 64 slots of the fused fold and push.  A slot has one row per block of its cluster:
+// with many rows (48 and up for a typical slot) 8 waves keep enough loads in flight; with few,
+// most of 8 waves would idle, so the count is the smallest of 2, 4, 8 that still launches
+// about 4096 waves (4 per SIMD).  Measured: 20k-slot cluster (79 rows) 8 waves; 256-cluster
+// ensemble of 1.4M slots (about 33 rows) 2 waves, 8 % faster than 8.
+inline int fold_waves(const RunConst& rc, int B) {
+  if (rc.cap_slot_mean >= 48.0 * (double)B) return 8;
+  const int64_t groups = (rc.n_total + 63) / 64;
+  int fw = 2;
+  while (fw < 8 && groups * fw < 4096) fw *= 2;
+  return fw;
+}
 
 template <typename Tr>
 __device__ inline void n3_row_partial(const DevState& s, const RunConst& rc, int B, int64_t g, int w, int ways,

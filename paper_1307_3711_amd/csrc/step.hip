@@ -323,13 +323,13 @@ __global__ __launch_bounds__(kBlock) void k_push(DevState s, RunConst rc, FieldL
   push_one<PREC>(s, rc, g, c, *s.step + k, diag, ecx, ecy, ecz, load_pstate(s, rc, g));
 }
 
-// Fold of the pair-once rows and push in one kernel: kFoldWaves waves over 64 consecutive
-// slots add their share of the rows, wave 0 combines them in order, keeps the field in split 0
-// (read by the ionization check) and pushes.  Wave 0 loads the particle state before its rows
-// so both latencies overlap.
-template <int PREC>
-__global__ __launch_bounds__(64 * kFoldWaves) void k_fold_push(DevState s, RunConst rc, int B, int64_t k, int diag) {
-  __shared__ double red[kFoldWaves - 1][3][64];
+// Fold of the pair-once rows and push in one kernel: FW waves over 64 consecutive slots add
+// their share of the rows, wave 0 combines them in order, keeps the field in split 0 (read by
+// the ionization check) and pushes.  Wave 0 loads the particle state before its rows so both
+// latencies overlap.
+template <int PREC, int FW>
+__global__ __launch_bounds__(64 * FW) void k_fold_push(DevState s, RunConst rc, int B, int64_t k, int diag) {
+  __shared__ double red[FW - 1][3][64];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t g = (int64_t)blockIdx.x * 64 + lane;
@@ -342,8 +342,8 @@ __global__ __launch_bounds__(64 * kFoldWaves) void k_fold_push(DevState s, RunCo
     live = s.dyn[c].active && g - s.cp[c].off < s.dyn[c].n_cur;
     if (live) {
       if (w == 0) ps = load_pstate(s, rc, g);
-      if (PREC == LC_FP64) n3_row_partial<double>(s, rc, B, g, w, kFoldWaves, e0, e1, e2);
-      else n3_row_partial<float>(s, rc, B, g, w, kFoldWaves, e0, e1, e2);
+      if (PREC == LC_FP64) n3_row_partial<double>(s, rc, B, g, w, FW, e0, e1, e2);
+      else n3_row_partial<float>(s, rc, B, g, w, FW, e0, e1, e2);
     }
   }
   if (w > 0) {
@@ -353,7 +353,7 @@ __global__ __launch_bounds__(64 * kFoldWaves) void k_fold_push(DevState s, RunCo
   }
   __syncthreads();
   if (w == 0 && live) {
-    for (int q = 0; q < kFoldWaves - 1; ++q) {
+    for (int q = 0; q < FW - 1; ++q) {
       e0 += red[q][0][lane];
       e1 += red[q][1][lane];
       e2 += red[q][2][lane];
@@ -763,11 +763,20 @@ hipError_t launch_push(const DevState& s, const RunConst& rc, int precision, con
   return hipGetLastError();
 }
 
+template <int PREC>
+void fold_push_waves(int fw, int blocks, const DevState& s, const RunConst& rc, int B, int64_t k, int diag,
+                     hipStream_t st) {
+  if (fw <= 2) k_fold_push<PREC, 2><<<blocks, 128, 0, st>>>(s, rc, B, k, diag);
+  else if (fw <= 4) k_fold_push<PREC, 4><<<blocks, 256, 0, st>>>(s, rc, B, k, diag);
+  else k_fold_push<PREC, 8><<<blocks, 512, 0, st>>>(s, rc, B, k, diag);
+}
+
 hipError_t launch_fold_push(const DevState& s, const RunConst& rc, int precision, int B, int64_t k, bool diag,
                             hipStream_t st) {
   const int blocks = (int)((rc.n_total + 63) / 64);
-  if (precision == LC_FP64) k_fold_push<LC_FP64><<<blocks, 64 * kFoldWaves, 0, st>>>(s, rc, B, k, diag ? 1 : 0);
-  else k_fold_push<LC_FP32_ACC64><<<blocks, 64 * kFoldWaves, 0, st>>>(s, rc, B, k, diag ? 1 : 0);
+  const int fw = fold_waves(rc, B);
+  if (precision == LC_FP64) fold_push_waves<LC_FP64>(fw, blocks, s, rc, B, k, diag ? 1 : 0, st);
+  else fold_push_waves<LC_FP32_ACC64>(fw, blocks, s, rc, B, k, diag ? 1 : 0, st);
   return hipGetLastError();
 }
 

@@ -247,6 +247,38 @@ def test_many_clusters_against_oracle(n_clusters):
     print(f"{n_clusters} clusters: every cluster within 1e-10 R0 of its oracle run", flush=True)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_acc64"])
+@pytest.mark.parametrize("n_clusters", [20, 300])
+def test_fold_widths_against_oracle(n_clusters, precision):
+    """The fused fold and push takes 2, 4 or 8 waves per 64 slots by the size of the run:
+    clusters of capacity 4500 (about 1000 particles, 4 blocks of 256 slots each, so every slot
+    sums 4 rows) give 90k slots (1407 groups of 64: 4 waves) for 20 clusters and 1.35M slots
+    (21k groups: 2 waves) for 300.  Pair-once passes (diagnostic steps 0 and 5 take the
+    one-sided pass), each cluster against its own oracle run: FP64 after 8 steps within 1e-10
+    R0; FP32 pairs after 4 steps within 1e-4 R0 as for the small argon runs (with up to 145
+    atoms per macro-ion these clusters amplify rounding about 1e4-fold in 8 steps, as the FP64
+    runs show, which would take FP32 rounding to the tolerance itself)."""
+    import paper_1307_3711_amd as lc
+    cl = ensemble(n_clusters, seed=21, cap_lo=4500, cap_hi=4500)
+    run = Run(dt=0.05, ionize=True, diag_every=5, seed=21)
+    states = [initial_state(c, run.seed, i) for i, c in enumerate(cl)]
+    nsteps = 8 if precision == "fp64" else 4
+    sim, _ = gpu_run(cl, run, precision, states=states, n_steps_per_cluster=[nsteps] * n_clusters,
+                     tuning=dict(R=4, WJ=4, newton3=1), max_pair_blocks=lc.pair_blocks_for([c.capacity for c in cl]))
+    sim.step(nsteps)
+    tol = 1e-10 if precision == "fp64" else 1e-4
+    worst = 0.0
+    for i, c in enumerate(cl):
+        if precision == "fp32_acc64" and i % 10:
+            continue  # every tenth cluster (the oracle's time)
+        osim = oracle_run(c, run, states[i], cluster_index=i)
+        osim.run(nsteps)
+        dx, du = _compare_state(sim, osim, units.nm_to_norm(c.r0_nm, 0.8), 0, 0, cluster=i)
+        worst = max(worst, dx)
+        assert dx <= tol, (i, dx, du)
+    print(f"{n_clusters} clusters {precision}: max |dx| / R0 = {worst:.2e}", flush=True)
+
+
 @pytest.mark.parametrize("precision,tiling", [("fp32_acc64", t) for t in N3_TILINGS + [dict(R=4, WJ=2, newton3=1),
                                                                                        dict(R=1, WJ=1, newton3=1, persistent=1)]]
                          + [("fp64", dict(R=2, WJ=2, newton3=1)), ("fp64", dict(R=4, WJ=4, newton3=1, persistent=1))])
