@@ -53,10 +53,13 @@ double a0_of(double intensity, double lambda_um) { return std::sqrt(intensity * 
 
 size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// Pair-once partial rows: cluster c gets 3 M n3_round(cap_c) floats, enough for nb <= M blocks
-// of any pair-once block size (128, 256 or 512 slots, all dividing 512).
+// Pair-once partial rows: cluster c gets 3 M n3_round(cap_c) row elements.  With blocks of B
+// slots (128 to 512) and nb = ceil(cap / B) <= M blocks, row (K, m) of K, m < nb starts at
+// (K M + m) 3 B, so the rows end below 3 M nb B, and nb B = cap rounded up to a multiple of B
+// is at most cap rounded up to 512 plus 512 for every B up to 512: the square shapes' blocks
+// of 192, 320 and 384 slots do not divide 512, hence the extra block.
 constexpr int kMaxPairBlocks = 32768;
-int64_t n3_round(int64_t cap) { return (cap + 511) / 512 * 512; }
+int64_t n3_round(int64_t cap) { return (cap + 511) / 512 * 512 + 512; }
 
 struct Layout {
   size_t x, y, z, ux, uy, uz, wl, wc, wsp, kebar, pos4, posq, Z, cid, part, n3part, flag, ib_count, ib_cluster;
@@ -269,6 +272,7 @@ bool n3_fits(const lc_sim* s, const ForceTiling& ft) {
   for (int c = 0; c < s->C; ++c) {
     const int64_t nb = (s->cl[c].capacity + B - 1) / B;
     if (nb > s->cfg.max_pair_blocks) return false;
+    if (nb * B > n3_round(s->cl[c].capacity)) return false;  // the cluster's rows must fit its share
     tiles += nb * (nb + 1) / 2;
   }
   return tiles <= std::numeric_limits<int32_t>::max();
@@ -276,7 +280,9 @@ bool n3_fits(const lc_sim* s, const ForceTiling& ft) {
 
 int choose_splits(const lc_sim* s, const ForceTiling& ft) {
   if (ft.S > 0) return std::min(ft.S, s->cfg.max_splits);
-  const int TI = force_tile_targets(ft);
+  // splits serve the one-sided passes: a pair-once tiling's diagnostic steps run its regular
+  // form (the square shapes have no one-sided form of their own: 4 / WJ target groups is 0)
+  const int TI = force_tile_targets(ft.newton3 ? regular_tiling(s->cfg.precision, ft) : ft);
   int64_t tiles = 0;
   for (int c = 0; c < s->C; ++c) tiles += (std::max<int64_t>(s->n_host[c], 1) + TI - 1) / TI;
   const int64_t want = 4LL * device_cus();

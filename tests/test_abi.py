@@ -123,12 +123,14 @@ def test_field_workspace_size():
 
 
 def test_pair_once_rows_in_state_bytes():
-    """max_pair_blocks M adds 3 M FP32 rows per slot, slots rounded up to 512 per cluster."""
+    """max_pair_blocks M adds 3 M FP32 rows per slot, slots rounded up to 512 per cluster plus
+    one more 512-slot block (blocks of 192, 320 or 384 slots round a capacity past the next
+    multiple of 512: capacity 1000 in blocks of 192 spans 1152 slots)."""
     c, run = small_ar()
     d = _desc(c)
     base = _bytes(lc.make_config("fp32_acc64", max_splits=8), [d])
     with_rows = _bytes(lc.make_config("fp32_acc64", max_splits=8, max_pair_blocks=10), [d])
-    slots = -(-c.capacity // 512) * 512
+    slots = -(-c.capacity // 512) * 512 + 512
     assert abs((with_rows - base) - 12 * 10 * slots) <= 256
     base64 = _bytes(lc.make_config("fp64", max_splits=8), [d])
     rows64 = _bytes(lc.make_config("fp64", max_splits=8, max_pair_blocks=10), [d])

@@ -279,6 +279,54 @@ def test_fold_widths_against_oracle(n_clusters, precision):
     print(f"{n_clusters} clusters {precision}: max |dx| / R0 = {worst:.2e}", flush=True)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_acc64"])
+@pytest.mark.parametrize("shape", [3, 5, 6])
+def test_square_pair_once_blocks_fit_full_clusters(shape, precision):
+    """Square pair-once shapes have blocks of 192, 320 and 384 slots, which do not divide the
+    512-slot rounding of a cluster's share of the row buffer: two deuterium clusters that start
+    full (capacity 1000, 500 D+ + 500 e-) must keep their rows inside their own shares.  Each
+    cluster's field against the oracle (FP64 1e-12 S1; FP32 64 u S1 on FP32-rounded operands),
+    then, in FP64, 5 steps against the oracle (1e-10 R0): rows spilling into the neighbour's
+    share or the state behind the buffer would show in one or the other."""
+    import paper_1307_3711_amd as lc
+    from workloads.species import SPECIES
+    if shape == 6 and precision == "fp64":
+        pytest.skip("no FP64 (6,6) pair-once kernel (81 KB of LDS per block)")
+    laser = Laser(intensity_wcm2=5e16, envelope="gauss_field", fwhm_fs=25.0)
+    cl = [Cluster(species="D", r0_nm=8.0 - k, n_ion=500, capacity=1000, z_init=1, z_max=1, laser=laser, n_steps=50)
+          for k in range(2)]
+    run = Run(dt=0.05, ionize=False, diag_every=0, seed=4)
+    states = [initial_state(c, run.seed, i) for i, c in enumerate(cl)]
+    tiling = dict(R=shape, WJ=shape, newton3=1)
+    sim, _ = gpu_run(cl, run, precision, states=states, tuning=tiling,
+                     max_pair_blocks=lc.pair_blocks_for([c.capacity for c in cl]))
+    fp64 = precision == "fp64"
+    eps2 = units.nm_to_norm(run.softening_nm, 0.8) ** 2
+    tol = 1e-12 if fp64 else 64 * 2.0**-24
+    for i, c in enumerate(cl):
+        g = sim.particles(i)
+        E = sim.field(i)
+        w = units.n_atoms(c.r0_nm, SPECIES[c.species]["rw_angstrom"]) / c.n_ion
+        q = units.kappa(0.8) * w * g["Z"].astype(np.float64)
+        xr, qr, e2 = g["x"], q, eps2
+        if not fp64:
+            xr = xr.astype(np.float32).astype(np.float64)
+            qr = qr.astype(np.float32).astype(np.float64)
+            e2 = float(np.float32(eps2))
+        Eo, _ = oracle.coulomb_field(xr, qr, e2)
+        s1 = field_scale(xr, qr, e2)
+        print(f"({shape},{shape}) {precision} cluster {i}: field maxrel "
+              f"{np.max(np.abs(E - Eo) / (s1[:, None] + 1e-300)):.2e}", flush=True)
+        assert g["n"] == c.capacity and np.all(np.abs(E - Eo) <= tol * s1[:, None] + 1e-300)
+    if fp64:
+        sim.step(5)
+        for i, c in enumerate(cl):
+            osim = oracle_run(c, run, states[i], cluster_index=i)
+            osim.run(5)
+            dx, du = _compare_state(sim, osim, units.nm_to_norm(c.r0_nm, 0.8), 0, 0, cluster=i)
+            assert dx <= 1e-10 and du <= 1e-9, (i, dx, du)
+
+
 @pytest.mark.parametrize("precision,tiling", [("fp32_acc64", t) for t in N3_TILINGS + [dict(R=4, WJ=2, newton3=1),
                                                                                        dict(R=1, WJ=1, newton3=1, persistent=1)]]
                          + [("fp64", dict(R=2, WJ=2, newton3=1)), ("fp64", dict(R=4, WJ=4, newton3=1, persistent=1))])
