@@ -432,6 +432,72 @@ def bench_iedf(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_paper_scaling(args):
+    """The run behind the paper's timing figure (Sec. III, Fig. 7), on synthetic input: a
+    deuterium cluster of radius 80 A, fully ionized at the start (D+ with its electron beside
+    it), 3000 macroparticles, 5000 steps.  The figure's laser is not given; this takes the
+    deuterium study's 5e16 W/cm^2 and 25 fs at 800 nm.  The paper prints no absolute times (the
+    figure is not in the text; it states the hardware, a 6-core Xeon E5645 at 2.40 GHz, and
+    the fitted laws, time ~ N^2 and ~ cores^-2).  Reports the wall time of the 5000 steps on
+    the GPU (FP32 pairs with FP64 accumulation, and FP64), the FP64 oracle's time for the same
+    steps on the host, and the GPU time per step over N = 1000 .. 24000 macroparticles with
+    the fitted exponent."""
+    import numpy as np
+    import oracle
+    from workloads import Cluster, Laser, Run, initial_state
+    laser = Laser(lambda_um=0.8, intensity_wcm2=5e16, envelope="gauss_field", fwhm_fs=25.0)
+    steps = args.steps if args.steps_given else 5000
+    run = Run(dt=0.05, ionize=False, diag_every=1000, seed=args.seed)
+
+    def case(n_macro):
+        c = Cluster(species="D", r0_nm=8.0, n_ion=n_macro // 2, capacity=n_macro, z_init=1, z_max=1, laser=laser,
+                    n_steps=steps)
+        return c, initial_state(c, args.seed)
+
+    c, st = case(3000)
+    out = {"metric": "wall seconds, 5000 steps of the paper's 3000-macroparticle deuterium cluster (Fig. 7 run)",
+           "unit": "s", "n_gpus": 1, "steps": steps, "warmup": args.warmup, "higher_is_better": False,
+           "scaling": "strong", "vs_baseline": None, "dtype": "fp32+fp64acc", "data": "synthetic",
+           "config": {"workload": "D cluster, R0 = 8 nm, fully ionized (1500 D+ + 1500 e-), 5e16 W/cm2, 25 fs, "
+                                  "800 nm, dt = 0.05"}}
+    for prec in ("fp32_acc64", "fp64"):
+        sim, tuned = make_sim(prec, c, run, st, args.graph)
+        sim.step(args.warmup)
+        wall = timed_steps(sim, steps)
+        sim.close()
+        log(f"paper scaling: {prec} {steps} steps in {wall:.3f} s ({tuned})")
+        if prec == "fp32_acc64":
+            out["value"] = round(wall, 4)
+            out["ms_per_step"] = round(wall / steps * 1e3, 5)
+            out["tiling"] = tuned
+        else:
+            out["fp64"] = {"value": round(wall, 4), "unit": "s", "tiling": tuned}
+    if not args.no_cpu_baseline:
+        osim = oracle.Sim.from_workload(c, run, st)
+        osim.start()
+        t0 = time.perf_counter()
+        osim.run(steps)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(dt, 3), "unit": "s", "cores": oracle.threads(), "kind": "oracle",
+                               "sample": f"the same {steps} steps in FP64 (gcc -O2)"}
+        log(f"paper scaling: oracle {dt:.2f} s on {oracle.threads()} threads")
+    sweep = []
+    for n in (1000, 3000, 6000, 12000, 24000):
+        cn, stn = case(n)
+        sim, _ = make_sim("fp64", cn, run, stn, args.graph)
+        sim.step(args.warmup)
+        k = 1000
+        wall = timed_steps(sim, k)
+        sim.close()
+        sweep.append({"n_macro": n, "ms_per_step_fp64": round(wall / k * 1e3, 5)})
+    ns = np.array([r["n_macro"] for r in sweep], dtype=float)
+    ts = np.array([r["ms_per_step_fp64"] for r in sweep])
+    out["n_sweep"] = sweep
+    # exponent of time ~ N^p over the three largest sizes (small N is launch-bound on the GPU)
+    out["n_exponent_fp64"] = round(float(np.polyfit(np.log(ns[-3:]), np.log(ts[-3:]), 1)[0]), 3)
+    print(json.dumps(out), flush=True)
+
+
 def bench_lumping(args):
     """The Sec. III lumping study on synthetic input: the D_8007 cluster (R0 from Eq.(1) with
     R_W = 1.70 A), 857 nm, 5e16 W/cm^2, 25 fs Gaussian, run as one ensemble of copies lumped
@@ -604,7 +670,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2000, help="xe200k: steps of the FP64 comparison run")
     ap.add_argument("--workload", default="ar20k", choices=["ar20k", "ensemble", "surrogate", "particles", "xe200k", "iedf",
                                                             "lumping",
-                                                            "scan"])
+                                                            "scan", "paper_scaling"])
     ap.add_argument("--sizes", default="20000,30000,40000,60000,100000",
                     help="particle counts of the scan workload")
     ap.add_argument("--reps", type=int, default=50)
@@ -666,6 +732,8 @@ def main():
         return bench_iedf(args)
     if args.workload == "lumping":
         return bench_lumping(args)
+    if args.workload == "paper_scaling":
+        return bench_paper_scaling(args)
 
     import numpy as np
     import torch
