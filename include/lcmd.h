@@ -114,7 +114,8 @@ typedef struct {
   int32_t max_pair_blocks;/* M >= 0: room for the pair-once kernel (lc_tuning.newton3) on  */
                           /*   clusters of up to M blocks; costs 12 M (LC_FP32_ACC64) or  */
                           /*   24 M (LC_FP64) bytes per slot, slots rounded up to 512 per */
-                          /*   cluster; 0: not available; not for LC_FP32_KAHAN          */
+                          /*   cluster plus 512 more (blocks of 192-384 slots do not      */
+                          /*   divide 512); 0: not available; not for LC_FP32_KAHAN       */
   uint64_t seed;          /* Philox key word 0 (word 1 is the cluster index)            */
   double detector_r0;     /* ion detectors at this multiple of each cluster's R0 from   */
                           /*   its centre (Sec. III anisotropy study: 9); 0: none       */
