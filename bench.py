@@ -165,6 +165,33 @@ def ensemble_inputs(n_clusters, seed, steps_scale=1.0):
     return cl, descs, states
 
 
+def ensemble_cpu_baseline(cl, states, r32, n_sample=8, steps=200):
+    """The FP64 oracle on a stratified sample of the ensemble (every len/n_sample-th cluster
+    by capacity, `steps` steps each): its cost per step is a N^2, so its pair rate on the
+    sample, applied to the pair count the GPU run evaluated, gives the oracle's time for the
+    whole run and its cluster-steps/s."""
+    import oracle
+    from workloads import Run
+    order = sorted(range(len(cl)), key=lambda i: cl[i].capacity)
+    pick = [order[(2 * k + 1) * len(order) // (2 * n_sample)] for k in range(n_sample)]
+    run = Run(dt=0.05, ionize=True, diag_every=50, seed=0)
+    pairs, secs = 0.0, 0.0
+    for i in pick:
+        osim = oracle.Sim.from_workload(cl[i], run, states[i], i)
+        osim.start()
+        t0 = time.perf_counter()
+        for _ in range(steps // 50):
+            pairs += 50.0 * float(osim.N) ** 2  # the count at the start of each stretch
+            osim.run(50)
+        secs += time.perf_counter() - t0
+    rate = pairs / secs
+    cpu_wall = r32["pairs"] / rate
+    return {"value": round(r32["cluster_steps"] / cpu_wall, 2), "unit": "cluster-steps/s", "cores": oracle.threads(),
+            "kind": "oracle", "sample": f"{n_sample} clusters stratified by capacity x {steps} steps "
+                                        f"({secs:.1f} s, {rate / 1e9:.2f} G pair/s), extrapolated to the run's "
+                                        f"{r32['pairs']:.3g} pair interactions"}
+
+
 def bench_ensemble(args):
     """256 uneven clusters (Ar/Xe, 1k-16k capacity, 2-10 nm, 1e15-1e17 W/cm^2, 20-100 fs),
     each run to t_end = 4 FWHM (or --steps), FP32+FP64acc vs the FP64 path on the same work."""
@@ -187,6 +214,8 @@ def bench_ensemble(args):
                       "total_capacity": int(sum(c.capacity for c in cl))},
            "gpairs_per_s": round(r32["pairs"] / r32["wall_s"] / 1e9, 2), "pairs": r32["pairs"],
            "wall_s": round(r32["wall_s"], 3)}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = ensemble_cpu_baseline(cl, states, r32)
     if not args.no_fp64:
         r64 = run_ensemble(descs, states, "fp64", max_steps=max_steps, graph_steps=args.graph // 2 or 50,
                            progress=lambda d, t: log(f"  fp64 step {d}/{t}"))
