@@ -377,6 +377,22 @@ def bench_xe(args):
            "energy_identity_max_rel_residual": ident_rel,
            "records": {"t": rec[:, 0].tolist(), "N": rec[:, 2].tolist(), "mean_Z": rec[:, 18].tolist(),
                        "absorbed_eV_per_atom": rec[:, 19].tolist()}}
+    if not args.no_cpu_baseline:
+        # the FP64 oracle on 20 steps from the same start (44,444 macroparticles); its cost per
+        # step is a N^2, so its pair rate gives its time for the run's pair count
+        import oracle
+        osim = oracle.Sim.from_workload(c, run, st)
+        osim.start()
+        n0 = float(osim.N)
+        t0 = time.perf_counter()
+        osim.run(20)
+        dt = time.perf_counter() - t0
+        rate = 20 * n0 * n0 / dt
+        out["cpu_baseline"] = {"value": round(rate / 1e9, 3), "unit": "Gpair/s", "cores": oracle.threads(),
+                               "kind": "oracle",
+                               "sample": f"20 steps at the start ({int(n0)} macroparticles, {dt:.1f} s); the run's "
+                                         f"{r32['counters']['pairs']:.3g} pair interactions at this rate: "
+                                         f"{r32['counters']['pairs'] / rate / 3600:.1f} h"}
     if not args.no_fp64:
         n64 = min(args.fp64_steps, steps)
         r64 = _xe_run("fp64", c, run, st, n64)
