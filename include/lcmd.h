@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define LC_API_VERSION 5
+#define LC_API_VERSION 6
 #define LC_MAX_Z 16       /* size of the per-charge tables (charge states 0..15)        */
 #define LC_REC 48         /* doubles per diagnostic record                              */
 #define LC_DET_BINS 120   /* ion energy histogram: 20 log bins per decade, 1 eV .. 1 MeV */
@@ -184,6 +184,18 @@ typedef struct lc_sim lc_sim;
 
 /* ---------------------------------------------------------------- simulation */
 
+/* Host-side check of the pair-once partial rows (no device work).  The pair-once kernel cuts a
+ * cluster into nb = ceil(capacity / B) blocks of B slots and writes, for target block K and
+ * partner block m (both < nb), component d of local slot l at row element ((K M + m) 3 + d) B + l
+ * of the cluster's share of 3 M (capacity rounded up to 512, plus 512) elements, M =
+ * max_pair_blocks; the fold reads the same elements.  For the pair-once shape (R, WJ) (see
+ * lc_tuning.newton3) out[0] = B, out[1] = nb, out[2] = the share in elements.  Returns LC_OK if
+ * lc_set_tuning accepts this shape for a cluster of this capacity (its rows then stay inside
+ * the share), LC_E_INVALID if it does not (nb > M, rows beyond the share) or the shape,
+ * precision or sizes are invalid. */
+int lc_pair_rows_fit(int32_t precision, int32_t R, int32_t WJ, int64_t capacity, int32_t max_pair_blocks,
+                     int64_t out[3]);
+
 /* Bytes of caller-owned device memory lc_create() needs; 0 if the arguments are invalid. */
 size_t lc_state_bytes(const lc_config* cfg, const lc_cluster* clusters, int32_t n_clusters);
 
@@ -202,8 +214,24 @@ int lc_create(lc_sim** out, const lc_config* cfg, const lc_cluster* clusters, in
 int lc_init_from_host(lc_sim* sim, int32_t cluster, int64_t n, const double* x_nm, const double* u,
                       const int8_t* Z);
 
+/* Seeded initial placement on the device (Sec. II: the atoms of a cluster, Eq.(1) of them,
+ * sit at random inside the sphere of radius R0 and are lumped into n_ion ion macroparticles
+ * of weight N_atoms / n_ion; every ion starts with charge z_init and z_init electrons at
+ * electron_offset_nm from it).  Draws from Philox4x64-10 keyed by (lc_config.seed, cluster
+ * index): ion i takes the counter (i, 0, 0, 0), whose first three 64-bit words u1, u2, u3
+ * (as ((w >> 11) + 1) 2^-53 in (0, 1]) place it at radius R0 u1^{1/3}, polar cosine 2 u2 - 1
+ * and azimuth 2 pi u3; electron e = i z_init + k of ion i (0 <= k < z_init) takes (e, 0, 1, 0)
+ * and its first two words give the polar cosine and azimuth of its offset.  Slots: the ions
+ * in [0, n_ion), then the electrons grouped by parent; momenta zero.  cluster: one cluster
+ * index, or -1 for every cluster.  LC_E_INVALID if z_init is outside [0, z_max] or
+ * n_ion (1 + z_init) exceeds a capacity.  Synchronizes the stream; replaces lc_init_from_host
+ * for the clusters it places. */
+int lc_init_generate(lc_sim* sim, int32_t cluster, int32_t z_init);
+
 /* Leap-frog start for every cluster: a field pass at t0, then the backward half kick
- * u^{-1/2} = u^0 - (Z/M)(dt/2)(E + v^0 x B).  Must follow lc_init_from_host. */
+ * u^{-1/2} = u^0 - (Z/M)(dt/2)(E + v^0 x B).  Must follow lc_init_from_host or
+ * lc_init_generate.  The paper does not say how the leap-frog is started; this backward half
+ * kick with the full Lorentz force at t0 is the reading taken. */
 int lc_start(lc_sim* sim);
 
 /* Enqueue n_steps time steps: the field pass (minimum image on periodic steps), the push

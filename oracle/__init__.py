@@ -94,7 +94,7 @@ class Params(ctypes.Structure):
         ("delta", ctypes.c_double), ("n_atoms", ctypes.c_double), ("mec2_ev", ctypes.c_double),
         ("seed", ctypes.c_uint64), ("cluster", ctypes.c_uint64), ("n_ion", ctypes.c_int64),
         ("polarization", ctypes.c_int32), ("boundary", ctypes.c_int32),
-        ("box", ctypes.c_double), ("t_switch", ctypes.c_double), ("grid32", ctypes.c_int32),
+        ("box", ctypes.c_double), ("t_switch", ctypes.c_double),
         ("collisional", ctypes.c_int32), ("lotz_a", ctypes.c_double), ("lotz_q", ctypes.c_double * MAX_Z),
         ("ci_ip_ev", ctypes.c_double * MAX_Z), ("ci_r0", ctypes.c_double), ("ne_per_macro", ctypes.c_double),
         ("s_per_unit", ctypes.c_double),
@@ -135,7 +135,10 @@ def _load(path):
     L.or_boris_push.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
     L.or_coulomb_field.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, dp, dp, dp, dp]
     L.or_coulomb_field_box.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
-                                       ctypes.c_int, dp, dp, dp, dp]
+                                       dp, dp, dp, dp]
+    L.or_init.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
+                          ctypes.c_double, dp, dp, dp, i8p]
+    L.or_init.restype = None
     L.or_coulomb_field_at.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int64,
                                       i64p, dp, dp, dp, dp]
     L.or_start.argtypes = [pp, ctypes.c_int64, dp, dp, dp, dp, dp, dp, i8p, dp]
@@ -193,10 +196,9 @@ def boris_push(zm, dt, E, B, u):
     return out
 
 
-def coulomb_field(x, q, eps2, want_phi=True, box=0.0, grid32=False):
+def coulomb_field(x, q, eps2, want_phi=True, box=0.0):
     """Direct-sum softened field of sources q (field units) at positions x (n x 3); box > 0:
-    minimum-image separations in a periodic cube of that side (grid32: from the positions on
-    the cube's 32-bit grid, as the FP32 pair kernels take them)."""
+    minimum-image separations in a periodic cube of that side."""
     x = np.ascontiguousarray(x, np.float64)
     n = x.shape[0]
     xs = [np.ascontiguousarray(x[:, k]) for k in range(3)]
@@ -204,8 +206,7 @@ def coulomb_field(x, q, eps2, want_phi=True, box=0.0, grid32=False):
     e = [np.zeros(n) for _ in range(3)]
     phi = np.zeros(n) if want_phi else None
     lib().or_coulomb_field_box(n, _dp(xs[0]), _dp(xs[1]), _dp(xs[2]), _dp(q), float(eps2), float(box),
-                               1 if grid32 else 0, _dp(e[0]),
-                               _dp(e[1]), _dp(e[2]), _dp(phi) if want_phi else None)
+                               _dp(e[0]), _dp(e[1]), _dp(e[2]), _dp(phi) if want_phi else None)
     return np.stack(e, axis=1), phi
 
 
@@ -223,6 +224,18 @@ def coulomb_field_at(x, q, eps2, idx, want_phi=True):
                               idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(e[0]), _dp(e[1]),
                               _dp(e[2]), _dp(phi) if want_phi else None)
     return np.stack(e, axis=1), phi
+
+
+def init_cluster(seed, cluster_index, n_ion, z_init, r0, delta):
+    """Initial placement of one cluster (Sec. II random atoms inside R0, lumped into n_ion ion
+    macroparticles, each with z_init electrons at distance delta): positions (n x 3, c/w) and
+    charge numbers (int8) in the order ions, then electrons by parent."""
+    n = int(n_ion) * (1 + int(z_init))
+    xs = [np.zeros(n) for _ in range(3)]
+    Z = np.zeros(n, np.int8)
+    lib().or_init(int(seed), int(cluster_index), int(n_ion), int(z_init), float(r0), float(delta),
+                  _dp(xs[0]), _dp(xs[1]), _dp(xs[2]), Z.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)))
+    return np.stack(xs, axis=1), Z
 
 
 # ----------------------------------------------------------------------------- parameters

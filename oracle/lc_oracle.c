@@ -29,6 +29,7 @@
  *   or_detect         - ion detectors and the time-integrated ion energy distribution
  *                       (Sec. III anisotropy study: detectors at 9 R0, 30 degree acceptance).
  *   or_philox4x64_10  - Philox4x64-10 counter-based generator (Salmon et al., SC'11).
+ *   or_init           - random placement of the ions inside R0 and of their electrons (Sec. II).
  */
 #include <math.h>
 #include <omp.h>
@@ -110,8 +111,6 @@ typedef struct {
   int32_t boundary;     /* OR_OPEN, OR_PERIODIC, or OR_MIXED (periodic while t < t_switch) */
   double box;           /* side L of the periodic cube centred on the cluster (c/w)  */
   double t_switch;      /* OR_MIXED: first time (1/w) with open boundaries             */
-  int32_t grid32;       /* 1: periodic separations from positions on the 32-bit grid of  */
-                        /*    the cube (the FP32 pair kernels' records); 0: in FP64      */
   int32_t collisional;  /* 1: add the collisional ionization rate to the ADK rate      */
   double lotz_a;        /* Lotz constant a (cm^2 eV^2)                                 */
   double lotz_q[OR_MAX_Z];  /* electrons in the outermost subshell of charge state Z  */
@@ -128,26 +127,12 @@ typedef struct {
  * ones afterwards (mixed), are the other options.  Periodic here means the minimum-image
  * convention: a pair interacts through the nearest periodic copy of the partner, and a
  * particle leaving the cube re-enters through the opposite face. */
-/* Position x on the 32-bit grid of the cube of side L: the integer nearest x 2^32 / L, taken
- * modulo 2^32 (reduced to [-2^31, 2^31] in floating point first, then exactly). */
-static uint32_t or_grid(double x, double L) {
-  const double is = 4294967296.0 / L;
-  const double u = x * is;
-  const double w = u - 4294967296.0 * floor(u * (1.0 / 4294967296.0) + 0.5);
-  return (uint32_t)(int64_t)rint(w);
-}
-
-/* Separation xi - xj through the nearest periodic copy (L > 0).  Which copy is nearest is an
- * integer decided by floating point.  grid32 decides it as the FP32 pair kernels do: both
- * positions on the 32-bit grid of the cube, the separation (L / 2^32) times their difference
- * as a signed 32-bit integer (a difference of exactly 2^31 grid steps goes to -L/2). */
-static double or_sep(double xi, double xj, double L, int grid32) {
+/* Separation xi - xj through the nearest periodic copy (L > 0): d - L round(d / L), so a
+ * separation inside (-L/2, L/2) is unchanged.  Which copy is nearest is an integer decided in
+ * FP64 here; at an exact tie of L/2 the rounding (half to even) keeps d. */
+static double or_sep(double xi, double xj, double L) {
   double d = xi - xj;
   if (!(L > 0.0)) return d;
-  if (grid32) {
-    const int32_t k = (int32_t)(or_grid(xi, L) - or_grid(xj, L));
-    return (double)k * (L / 4294967296.0);
-  }
   return d - L * nearbyint(d / L);
 }
 
@@ -165,64 +150,60 @@ static double or_box_at(const or_params* p, double t) {
  * q_j is the source strength in field units (kappa * weight * Z_j).  The j loop runs in
  * ascending order for every i.  L > 0: separations by the minimum-image convention in a
  * periodic cube of side L. */
+static void or_field_one(int64_t i, int64_t n, const double* x, const double* y, const double* z,
+                         const double* q, double eps2, double L, double out[4]) {
+  double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
+  for (int64_t j = 0; j < n; ++j) {
+    if (j == i) continue;
+    double dx = or_sep(x[i], x[j], L);
+    double dy = or_sep(y[i], y[j], L);
+    double dz = or_sep(z[i], z[j], L);
+    double r2 = dx * dx + dy * dy + dz * dz + eps2;
+    double inv = 1.0 / sqrt(r2);
+    double inv3 = inv * inv * inv;
+    double s = q[j] * inv3;
+    sx += s * dx;
+    sy += s * dy;
+    sz += s * dz;
+    sp += q[j] * inv;
+  }
+  out[0] = sx;
+  out[1] = sy;
+  out[2] = sz;
+  out[3] = sp;
+}
+
 void or_coulomb_field_box(int64_t n, const double* x, const double* y, const double* z, const double* q,
-                          double eps2, double L, int grid32, double* ex, double* ey, double* ez, double* phi) {
+                          double eps2, double L, double* ex, double* ey, double* ez, double* phi) {
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
-    double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
-    for (int64_t j = 0; j < n; ++j) {
-      if (j == i) continue;
-      double dx = or_sep(x[i], x[j], L, grid32);
-      double dy = or_sep(y[i], y[j], L, grid32);
-      double dz = or_sep(z[i], z[j], L, grid32);
-      double r2 = dx * dx + dy * dy + dz * dz + eps2;
-      double inv = 1.0 / sqrt(r2);
-      double inv3 = inv * inv * inv;
-      double s = q[j] * inv3;
-      sx += s * dx;
-      sy += s * dy;
-      sz += s * dz;
-      sp += q[j] * inv;
-    }
-    ex[i] = sx;
-    ey[i] = sy;
-    ez[i] = sz;
-    if (phi) phi[i] = sp;
+    double o[4];
+    or_field_one(i, n, x, y, z, q, eps2, L, o);
+    ex[i] = o[0];
+    ey[i] = o[1];
+    ez[i] = o[2];
+    if (phi) phi[i] = o[3];
   }
 }
 
 void or_coulomb_field(int64_t n, const double* x, const double* y, const double* z, const double* q,
                       double eps2, double* ex, double* ey, double* ez, double* phi) {
-  or_coulomb_field_box(n, x, y, z, q, eps2, 0.0, 0, ex, ey, ez, phi);
+  or_coulomb_field_box(n, x, y, z, q, eps2, 0.0, ex, ey, ez, phi);
 }
 
 /* The same sum evaluated only at the m targets listed in idx (for sampled checks of large
- * states); outputs are indexed by position in idx. */
+ * states, open boundaries); outputs are indexed by position in idx. */
 void or_coulomb_field_at(int64_t n, const double* x, const double* y, const double* z, const double* q,
                          double eps2, int64_t m, const int64_t* idx, double* ex, double* ey, double* ez,
                          double* phi) {
 #pragma omp parallel for schedule(static)
   for (int64_t k = 0; k < m; ++k) {
-    int64_t i = idx[k];
-    double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
-    for (int64_t j = 0; j < n; ++j) {
-      if (j == i) continue;
-      double dx = x[i] - x[j];
-      double dy = y[i] - y[j];
-      double dz = z[i] - z[j];
-      double r2 = dx * dx + dy * dy + dz * dz + eps2;
-      double inv = 1.0 / sqrt(r2);
-      double inv3 = inv * inv * inv;
-      double s = q[j] * inv3;
-      sx += s * dx;
-      sy += s * dy;
-      sz += s * dz;
-      sp += q[j] * inv;
-    }
-    ex[k] = sx;
-    ey[k] = sy;
-    ez[k] = sz;
-    if (phi) phi[k] = sp;
+    double o[4];
+    or_field_one(idx[k], n, x, y, z, q, eps2, 0.0, o);
+    ex[k] = o[0];
+    ey[k] = o[1];
+    ez[k] = o[2];
+    if (phi) phi[k] = o[3];
   }
 }
 
@@ -374,6 +355,59 @@ static void or_charges(const or_params* p, int64_t n, const int8_t* Z, double* q
   for (int64_t i = 0; i < n; ++i) q[i] = p->kappa * p->weight * (double)Z[i];
 }
 
+/* ------------------------------------------------------------------ initial placement */
+/* Sec. II builds a cluster of radius R0 from atoms placed at random inside it and lumps them
+ * into macroparticles (Eq.(1) gives the atom count; the weight is N_atoms / n_ion).  Each ion
+ * starts with charge z_init and z_init electrons next to it.  Random numbers come from
+ * Philox4x64-10 keyed by (seed, cluster):
+ *   ion i (0 <= i < n_ion): counter (i, 0, 0, 0); its first three words give u1, u2, u3 in
+ *     (0, 1] and the ion sits at radius R0 u1^{1/3} (uniform in volume) in the direction of
+ *     polar cosine 2 u2 - 1 and azimuth 2 pi u3 (uniform on the sphere);
+ *   electron e = i z_init + k of ion i (0 <= k < z_init): counter (e, 0, 1, 0); two words give
+ *     the polar cosine and azimuth of its offset delta from the ion.
+ * Order: the ions, then the electrons grouped by parent ion.  Momenta are zero.  x, y, z, Z
+ * hold n_ion (1 + z_init) entries; positions in c/w. */
+enum { OR_PURPOSE_ION = 0, OR_PURPOSE_ELECTRON = 1 };
+
+static void or_direction(double u_cos, double u_phi, double d[3]) {
+  double ct = 2.0 * u_cos - 1.0;
+  double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+  double ph = 2.0 * M_PI * u_phi;
+  d[0] = st * cos(ph);
+  d[1] = st * sin(ph);
+  d[2] = ct;
+}
+
+void or_init(uint64_t seed, uint64_t cluster, int64_t n_ion, int32_t z_init, double r0, double delta,
+             double* x, double* y, double* z, int8_t* Z) {
+  uint64_t key[2] = {seed, cluster};
+  for (int64_t i = 0; i < n_ion; ++i) {
+    uint64_t ctr[4] = {(uint64_t)i, 0, OR_PURPOSE_ION, 0};
+    uint64_t r[4];
+    or_philox4x64_10(key, ctr, r);
+    double rad = r0 * cbrt(or_u01(r[0]));
+    double d[3];
+    or_direction(or_u01(r[1]), or_u01(r[2]), d);
+    x[i] = rad * d[0];
+    y[i] = rad * d[1];
+    z[i] = rad * d[2];
+    Z[i] = (int8_t)z_init;
+  }
+  for (int64_t i = 0; i < n_ion; ++i)
+    for (int32_t k = 0; k < z_init; ++k) {
+      int64_t e = i * z_init + k;
+      uint64_t ctr[4] = {(uint64_t)e, 0, OR_PURPOSE_ELECTRON, 0};
+      uint64_t r[4];
+      or_philox4x64_10(key, ctr, r);
+      double d[3];
+      or_direction(or_u01(r[0]), or_u01(r[1]), d);
+      x[n_ion + e] = x[i] + delta * d[0];
+      y[n_ion + e] = y[i] + delta * d[1];
+      z[n_ion + e] = z[i] + delta * d[2];
+      Z[n_ion + e] = -1;
+    }
+}
+
 /* ------------------------------------------------------------------ start */
 /* Leap-frog start: one field pass at t0, then a backward half kick with the full
  * Lorentz force, u^{-1/2} = u^0 - (Z/M)(dt/2)(E + v^0 x B).  Returns sum w M (gamma - 1)
@@ -385,7 +419,7 @@ double or_start(const or_params* p, int64_t n, const double* x, const double* y,
   double* ey = work + 2 * n;
   double* ez = work + 3 * n;
   or_charges(p, n, Z, q);
-  or_coulomb_field_box(n, x, y, z, q, p->eps2, or_box_at(p, p->t0), p->grid32, ex, ey, ez, NULL);
+  or_coulomb_field_box(n, x, y, z, q, p->eps2, or_box_at(p, p->t0), ex, ey, ez, NULL);
   double ke = 0.0;
   for (int64_t i = 0; i < n; ++i) {
     double EL[3], BL[3];
@@ -542,7 +576,7 @@ static int or_step(const or_params* p, int64_t step, int64_t cap, int64_t* n_io,
   int diag = (p->diag_every > 0) && (step % p->diag_every == 0);
   double L = or_box_at(p, t);
   or_charges(p, n, Z, s->q);
-  or_coulomb_field_box(n, x, y, z, s->q, p->eps2, L, p->grid32, s->ex, s->ey, s->ez, s->phi);
+  or_coulomb_field_box(n, x, y, z, s->q, p->eps2, L, s->ex, s->ey, s->ez, s->phi);
 
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
@@ -691,7 +725,7 @@ int64_t or_run(const or_params* p, int64_t cap, int64_t* n_io, double* x, double
 void or_state_field(const or_params* p, double t, int64_t n, const double* x, const double* y, const double* z,
                     const int8_t* Z, double* q_work, double* ex, double* ey, double* ez, double* phi) {
   or_charges(p, n, Z, q_work);
-  or_coulomb_field_box(n, x, y, z, q_work, p->eps2, or_box_at(p, t), p->grid32, ex, ey, ez, phi);
+  or_coulomb_field_box(n, x, y, z, q_work, p->eps2, or_box_at(p, t), ex, ey, ez, phi);
 }
 
 int or_record_size(void) { return OR_REC; }

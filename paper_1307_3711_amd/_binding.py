@@ -113,7 +113,10 @@ def lib():
         "lc_state_bytes": ([cfgp, clp, ctypes.c_int32], ctypes.c_size_t),
         "lc_create": ([ctypes.POINTER(vp), cfgp, clp, ctypes.c_int32, vp, ctypes.c_size_t, vp], ctypes.c_int),
         "lc_init_from_host": ([vp, ctypes.c_int32, ctypes.c_int64, dp, dp, i8p], ctypes.c_int),
+        "lc_init_generate": ([vp, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
         "lc_start": ([vp], ctypes.c_int),
+        "lc_pair_rows_fit": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, i64p],
+                             ctypes.c_int),
         "lc_step": ([vp, ctypes.c_int64], ctypes.c_int),
         "lc_set_graph": ([vp, ctypes.c_int32], ctypes.c_int),
         "lc_read_diagnostics": ([vp, ctypes.c_int32, dp, ctypes.c_int32, i32p], ctypes.c_int),
@@ -253,6 +256,10 @@ class Simulation:
         dp = ctypes.POINTER(ctypes.c_double)
         _check(lib().lc_init_from_host(self.h, cluster, n, x_nm.ctypes.data_as(dp), u.ctypes.data_as(dp),
                                        Z.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))), self.h)
+
+    def init_generate(self, cluster=-1, z_init=1):
+        """Seeded initial placement on the device (cluster -1: every cluster)."""
+        _check(lib().lc_init_generate(self.h, int(cluster), int(z_init)), self.h)
 
     def start(self):
         _check(lib().lc_start(self.h), self.h)

@@ -62,7 +62,7 @@ constexpr int kMaxPairBlocks = 32768;
 int64_t n3_round(int64_t cap) { return (cap + 511) / 512 * 512 + 512; }
 
 struct Layout {
-  size_t x, y, z, ux, uy, uz, wl, wc, wsp, kebar, pos4, posq, Z, cid, part, n3part, flag, ib_count, ib_cluster;
+  size_t x, y, z, ux, uy, uz, wl, wc, wsp, kebar, pos4, posq, Z, cid, part, n3part, flag, ib_count, ib_off, ib_cluster;
   size_t cp, dyn, order, tile_start, tile_total, queue, det_seen, det_counts, det_edges, ci_part, err, step, diag_part, records, total;
   int64_t n_total;
   int n_ion_blocks;
@@ -148,6 +148,7 @@ Layout make_layout(const lc_config* cfg, const lc_cluster* cl, int C) {
   L.n3part = take(row_elem * 3 * (size_t)cfg->max_pair_blocks * (size_t)n3_slots);
   L.flag = take(sizeof(int32_t) * (size_t)NT);
   L.ib_count = take(sizeof(int32_t) * (size_t)std::max(ib, 1));
+  L.ib_off = take(sizeof(int32_t) * (size_t)std::max(ib, 1));
   L.ib_cluster = take(sizeof(int32_t) * (size_t)std::max(ib, 1));
   L.cp = take(sizeof(ClusterParams) * C);
   L.dyn = take(sizeof(ClusterDyn) * C);
@@ -263,16 +264,23 @@ FieldLayout field_layout(const ForceTiling& ft, bool n3) {
   return fl;
 }
 
-// A pair-once tiling fits when every cluster's capacity spans at most max_pair_blocks blocks.
+// The pair-once rows of a cluster of capacity cap with blocks of B slots and M rows per block fit
+// its share when it spans at most M blocks and nb B <= n3_round(cap): the last row, (nb - 1, nb - 1),
+// ends at ((nb - 1) M + nb) 3 B <= 3 M nb B <= 3 M n3_round(cap) elements.
+bool n3_cluster_fits(int64_t cap, int64_t B, int64_t M) {
+  const int64_t nb = (cap + B - 1) / B;
+  return nb <= M && nb * B <= n3_round(cap);
+}
+
+// A pair-once tiling fits when every cluster's rows fit its share.
 bool n3_fits(const lc_sim* s, const ForceTiling& ft) {
   if (!ft.newton3) return true;
   if (s->cfg.max_pair_blocks <= 0 || s->cfg.precision == LC_FP32_KAHAN) return false;
   const int64_t B = n3_block_size(ft);
   int64_t tiles = 0;
   for (int c = 0; c < s->C; ++c) {
+    if (!n3_cluster_fits(s->cl[c].capacity, B, s->cfg.max_pair_blocks)) return false;
     const int64_t nb = (s->cl[c].capacity + B - 1) / B;
-    if (nb > s->cfg.max_pair_blocks) return false;
-    if (nb * B > n3_round(s->cl[c].capacity)) return false;  // the cluster's rows must fit its share
     tiles += nb * (nb + 1) / 2;
   }
   return tiles <= std::numeric_limits<int32_t>::max();
@@ -398,6 +406,23 @@ int lc_units(double lambda_um, double intensity_wcm2, double out[6]) {
   return LC_OK;
 }
 
+int lc_pair_rows_fit(int32_t precision, int32_t R, int32_t WJ, int64_t capacity, int32_t max_pair_blocks,
+                     int64_t out[3]) {
+  if (!out || capacity < 1 || max_pair_blocks < 1 || max_pair_blocks > kMaxPairBlocks) return LC_E_INVALID;
+  if (precision != LC_FP64 && precision != LC_FP32_ACC64) return LC_E_INVALID;
+  ForceTiling ft = default_tiling(precision);
+  ft.R = R;
+  ft.WJ = WJ;
+  ft.S = 1;
+  ft.newton3 = 1;
+  if (!force_tiling_valid(precision, ft)) return LC_E_INVALID;
+  const int64_t B = n3_block_size(ft);
+  out[0] = B;
+  out[1] = (capacity + B - 1) / B;
+  out[2] = 3 * (int64_t)max_pair_blocks * n3_round(capacity);
+  return n3_cluster_fits(capacity, B, max_pair_blocks) ? LC_OK : LC_E_INVALID;
+}
+
 size_t lc_state_bytes(const lc_config* cfg, const lc_cluster* clusters, int32_t n_clusters) {
   std::string why;
   if (!valid_config(cfg, &why) || !clusters || n_clusters < 1) return 0;
@@ -439,6 +464,7 @@ int lc_create(lc_sim** out, const lc_config* cfg, const lc_cluster* clusters, in
   d.Z = (int8_t*)(b + L.Z); d.cid = (int32_t*)(b + L.cid); d.part = (double*)(b + L.part);
   d.n3part = (void*)(b + L.n3part);
   d.flag = (int32_t*)(b + L.flag); d.ib_count = (int32_t*)(b + L.ib_count);
+  d.ib_off = (int32_t*)(b + L.ib_off);
   d.ib_cluster = (int32_t*)(b + L.ib_cluster);
   d.cp = (ClusterParams*)(b + L.cp); d.dyn = (ClusterDyn*)(b + L.dyn);
   d.order = (int32_t*)(b + L.order); d.tile_start = (int32_t*)(b + L.tile_start);
@@ -528,6 +554,7 @@ int lc_create(lc_sim** out, const lc_config* cfg, const lc_cluster* clusters, in
     p.tau = k.fwhm_fs * 1e-15 * s->u.omega;
     p.t_sin2 = 2.0 * kPi * k.n_cycles;
     p.delta = k.electron_offset_nm * 1e-9 * s->u.k;
+    p.r0 = k.r0_nm * 1e-9 * s->u.k;
     p.field_au = s->u.field_au;
     p.rate_scale = s->u.rate;
     for (int z = 0; z < LC_MAX_Z; ++z) {
@@ -643,10 +670,32 @@ int lc_init_from_host(lc_sim* s, int32_t cluster, int64_t n, const double* x_nm,
   return LC_OK;
 }
 
+int lc_init_generate(lc_sim* s, int32_t cluster, int32_t z_init) {
+  if (!s) return LC_E_INVALID;
+  if (cluster < -1 || cluster >= s->C) return fail(s, LC_E_INVALID, "cluster index out of range");
+  const int c0 = cluster < 0 ? 0 : cluster, c1 = cluster < 0 ? s->C : cluster + 1;
+  for (int c = c0; c < c1; ++c) {
+    const lc_cluster& k = s->cl[c];
+    if (z_init < 0 || z_init > k.z_max) return fail(s, LC_E_INVALID, "z_init must be in [0, z_max]");
+    if (k.n_ion * (1 + (int64_t)z_init) > k.capacity)
+      return fail(s, LC_E_INVALID, "n_ion (1 + z_init) exceeds the capacity");
+  }
+  hipError_t e = hipSuccess;
+  for (int c = c0; c < c1 && e == hipSuccess; ++c) e = launch_init_generate(s->s, s->rc, c, s->cl[c].n_ion, z_init, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "lc_init_generate");
+  for (int c = c0; c < c1; ++c) {
+    s->n_host[c] = s->cl[c].n_ion * (1 + (int64_t)z_init);
+    s->inited[c] = 1;
+  }
+  s->started = false;
+  return LC_OK;
+}
+
 int lc_start(lc_sim* s) {
   if (!s) return LC_E_INVALID;
   for (int c = 0; c < s->C; ++c)
-    if (!s->inited[c]) return fail(s, LC_E_STATE, "every cluster needs lc_init_from_host before lc_start");
+    if (!s->inited[c]) return fail(s, LC_E_STATE, "every cluster needs lc_init_from_host or lc_init_generate before lc_start");
   if (s->step != 0) return fail(s, LC_E_STATE, "lc_start after stepping");
   drop_graph(s);
   s->S_eff = choose_splits(s, s->ft);

@@ -37,7 +37,8 @@ struct ClusterParams {
   double a0;            // peak field
   double tau;           // Gaussian FWHM (1/w)
   double t_sin2;        // sin^2 envelope length (1/w)
-  double delta;         // spawn offset (c/w)
+  double delta;         // spawn offset (c/w); also the offset of the initial electrons
+  double r0;            // cluster radius (c/w)
   double n_atoms;       // real atoms (Eq.(1))
   double field_au;      // atomic field units per a0
   double rate_scale;    // 1/w per atomic time unit
@@ -64,7 +65,7 @@ struct ClusterParams {
   double lotz_av;
   double ci_r2;
   double ne_per_macro;
-  double s_per_unit;       // first float of this cluster's pair-once partial rows (see force.hip)
+  double s_per_unit;    // seconds per unit of time (1/w)
 };
 
 // Per-cluster dynamic state, written by the kernels.
@@ -137,6 +138,7 @@ struct DevState {
   void* n3part;         // pair-once partial rows (float or double: the pair type), per cluster from cp.n3_off
   int32_t* flag;        // ionization flags [slot of ion]
   int32_t* ib_count;    // spawns per ion block
+  int32_t* ib_off;      // exclusive prefix of ib_count over all ion blocks
   int32_t* ib_cluster;  // cluster of each ion block
   ClusterParams* cp;
   ClusterDyn* dyn;
@@ -252,6 +254,10 @@ hipError_t launch_start_kick(const DevState& s, const RunConst& rc, int precisio
 hipError_t launch_diag(const DevState& s, const RunConst& rc, const FieldLayout& fl, int64_t k, hipStream_t st);
 hipError_t launch_ionize(const DevState& s, const RunConst& rc, int precision, const FieldLayout& fl, int64_t k,
                          int n_ion_blocks, hipStream_t st);
+// Initial placement of cluster c on the device (Sec. II random atoms inside R0): n_ion ions,
+// each with z_init electrons, and the cluster's live count n_ion (1 + z_init).
+hipError_t launch_init_generate(const DevState& s, const RunConst& rc, int c, int64_t n_ion, int z_init,
+                                hipStream_t st);
 // Source records of every live slot for the field pass of a step (pbc: that step is periodic).
 hipError_t launch_refresh_sources(const DevState& s, const RunConst& rc, int precision, bool pbc, hipStream_t st);
 

@@ -68,6 +68,8 @@ __device__ inline double unit_interval(uint64_t x) {
   return (double)((x >> 11) + 1ULL) * (1.0 / 9007199254740992.0);
 }
 
+constexpr uint64_t kPurposeIon = 0;
+constexpr uint64_t kPurposeElectron = 1;
 constexpr uint64_t kPurposeAlpha = 2;
 constexpr uint64_t kPurposeDirection = 3;
 
@@ -616,10 +618,27 @@ __global__ __launch_bounds__(64) void k_ci_final(DevState s, RunConst rc) {
 }
 
 // ----------------------------------------------------------------------------- ionization (S4)
+// ADK rate (1/w units) of charge state z at field strength fa (atomic units), zero below 1e-6.
+__device__ inline double adk_nu(const ClusterParams& cp, int z, double fa) {
+  if (!(fa >= 1e-6)) return 0.0;
+  return exp(cp.adk_logc[z] - cp.adk_expo[z] * log(fa) - cp.adk_f23[z] / fa) * cp.rate_scale;
+}
+
+// Laser field strength |E_L(t^n)| of the cluster's step (the rate's field with LC_LASER_ONLY).
+__device__ inline double laser_strength(const ClusterParams& cp, const ClusterDyn& d) {
+  return (cp.polarization == LC_CIRCULAR) ? sqrt(d.laser_e * d.laser_e + d.laser_ey * d.laser_ey)
+                                          : fabs(d.laser_e);
+}
+
 // Flag every ion whose uniform draw alpha in (0,1] falls below P = 1 - exp(-nu dt), nu the
-// ADK rate at the driving field; count flags per ion block.
+// ADK rate at the driving field (plus the collisional rate inside the cluster sphere); count
+// flags per ion block.  With the laser-only field the rate depends on the charge state alone,
+// so the first 32 threads of a block evaluate P for every charge state (outside and inside the
+// sphere) once, with the same arithmetic as the per-ion path of LC_LOCAL.  An ion whose P is
+// exactly 0 cannot ionize (alpha > 0) and takes no draw.
 template <int PREC>
 __global__ __launch_bounds__(kBlock) void k_ionize_check(DevState s, RunConst rc, FieldLayout fl, int64_t k) {
+  __shared__ double sh_p[2][LC_MAX_Z];
   const int ibk = blockIdx.x;
   const int c = s.ib_cluster[ibk];
   const ClusterParams& cp = s.cp[c];
@@ -627,35 +646,47 @@ __global__ __launch_bounds__(kBlock) void k_ionize_check(DevState s, RunConst rc
   const int b = ibk - cp.ion_block0;
   const int64_t li = (int64_t)b * kBlock + threadIdx.x;
   if (b == 0 && threadIdx.x == 0) d.n_base = d.n_cur;
+  const bool table = !rc.ofi_local;  // uniform over the launch
+  if (table) {
+    if (threadIdx.x < 2 * LC_MAX_Z) {
+      const int z = threadIdx.x % LC_MAX_Z, inside = threadIdx.x / LC_MAX_Z;
+      double P = 0.0;
+      if (z < cp.z_max && cp.adk_ok[z]) {
+        double nu = adk_nu(cp, z, laser_strength(cp, d) * cp.field_au);
+        if (inside) nu += d.ci_nu[z];
+        P = -expm1(-nu * rc.dt);
+      }
+      sh_p[inside][z] = P;
+    }
+    __syncthreads();
+  }
   int flag = 0;
   if (d.active && li < cp.n_ion) {
     const int64_t g = cp.off + li;
     const int zc = s.Z[g];
     if (zc >= 0 && zc < cp.z_max && cp.adk_ok[zc]) {
-      const int64_t n = *s.step + k;
-      double F;
-      if (rc.ofi_local) {
+      bool inside = false;
+      if (rc.collisional) {
+        const double x = s.x[g], y = s.y[g], z = s.z[g];
+        inside = x * x + y * y + z * z < cp.ci_r2;
+      }
+      double P;
+      if (table) {
+        P = sh_p[inside ? 1 : 0][zc];
+      } else {
         double ex, ey, ez;
         field_sum(s, rc, fl, g, ex, ey, ez);
         ex += d.laser_e;
         ey += d.laser_ey;
-        F = sqrt(ex * ex + ey * ey + ez * ez);
-      } else if (cp.polarization == LC_CIRCULAR) {
-        F = sqrt(d.laser_e * d.laser_e + d.laser_ey * d.laser_ey);
-      } else {
-        F = fabs(d.laser_e);
+        double nu = adk_nu(cp, zc, sqrt(ex * ex + ey * ey + ez * ez) * cp.field_au);
+        if (inside) nu += d.ci_nu[zc];
+        P = -expm1(-nu * rc.dt);
       }
-      const double fa = F * cp.field_au;
-      double nu = 0.0;
-      if (fa >= 1e-6) nu = exp(cp.adk_logc[zc] - cp.adk_expo[zc] * log(fa) - cp.adk_f23[zc] / fa) * cp.rate_scale;
-      if (rc.collisional) {
-        const double x = s.x[g], y = s.y[g], z = s.z[g];
-        if (x * x + y * y + z * z < cp.ci_r2) nu += d.ci_nu[zc];
+      if (P > 0.0) {
+        const int64_t n = *s.step + k;
+        const U64x4 r = philox(rc.seed, (uint64_t)c, (uint64_t)li, (uint64_t)n, kPurposeAlpha, 0);
+        flag = (unit_interval(r.v[0]) < P) ? 1 : 0;
       }
-      const double P = -expm1(-nu * rc.dt);
-      const U64x4 r = philox(rc.seed, (uint64_t)c, (uint64_t)li, (uint64_t)n, kPurposeAlpha, 0);
-      const double alpha = unit_interval(r.v[0]);
-      flag = (alpha < P) ? 1 : 0;
     }
     s.flag[g] = flag;
   }
@@ -663,12 +694,48 @@ __global__ __launch_bounds__(kBlock) void k_ionize_check(DevState s, RunConst rc
   if (threadIdx.x == 0) s.ib_count[ibk] = cnt;
 }
 
+// Exclusive prefix sum of the per-block flag counts over every ion block, in block order (one
+// workgroup, 1024 blocks per pass with a carry; wave scans by lane shuffles, then across the 16
+// waves).  A cluster's ion blocks are contiguous, so the rank base of its block b is
+// ib_off[ion_block0 + b] - ib_off[ion_block0].
+__global__ __launch_bounds__(1024) void k_ionize_scan(DevState s, int n_blocks) {
+  __shared__ int32_t sh_w[16];
+  __shared__ int32_t sh_carry;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (tid == 0) sh_carry = 0;
+  __syncthreads();
+  for (int base = 0; base < n_blocks; base += 1024) {
+    const int i = base + tid;
+    const int32_t v = (i < n_blocks) ? s.ib_count[i] : 0;
+    int32_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) sh_w[w] = x;
+    __syncthreads();
+    if (w == 0) {
+      int32_t t = (lane < 16) ? sh_w[lane] : 0;
+      for (int o = 1; o < 16; o <<= 1) {
+        const int32_t y = __shfl_up(t, o, 64);
+        if (lane >= o) t += y;
+      }
+      if (lane < 16) sh_w[lane] = t;
+    }
+    __syncthreads();
+    const int32_t carry = sh_carry;
+    if (i < n_blocks) s.ib_off[i] = carry + (w > 0 ? sh_w[w - 1] : 0) + x - v;
+    __syncthreads();
+    if (tid == 0) sh_carry = carry + sh_w[15];
+    __syncthreads();
+  }
+}
+
 // Spawn one electron per flagged ion at slot n_base + (rank of the ion among this step's
 // flagged ions, ascending ion index), next to the ion's new position with its momentum.
 template <int PREC>
 __global__ __launch_bounds__(kBlock) void k_ionize_spawn(DevState s, RunConst rc, int64_t k) {
   __shared__ int32_t sh_wave[4];
-  __shared__ int64_t sh_base;
   const int ibk = blockIdx.x;
   const int c = s.ib_cluster[ibk];
   const ClusterParams& cp = s.cp[c];
@@ -676,11 +743,7 @@ __global__ __launch_bounds__(kBlock) void k_ionize_spawn(DevState s, RunConst rc
   const int b = ibk - cp.ion_block0;
   const int64_t li = (int64_t)b * kBlock + threadIdx.x;
   if (!d.active) return;
-  if (threadIdx.x == 0) {
-    int64_t base = 0;
-    for (int q = 0; q < b; ++q) base += s.ib_count[cp.ion_block0 + q];
-    sh_base = base;
-  }
+  const int64_t base = (int64_t)s.ib_off[ibk] - (int64_t)s.ib_off[cp.ion_block0];
   const int flag = (li < cp.n_ion) ? s.flag[cp.off + li] : 0;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint64_t ball = __ballot(flag);
@@ -690,7 +753,7 @@ __global__ __launch_bounds__(kBlock) void k_ionize_spawn(DevState s, RunConst rc
   int wave_off = 0;
   for (int q = 0; q < wv; ++q) wave_off += sh_wave[q];
   const int64_t n_base = d.n_base;
-  const int64_t rank = sh_base + wave_off + below;
+  const int64_t rank = base + wave_off + below;
   if (flag) {
     const int64_t e = n_base + rank;
     if (e < cp.cap) {
@@ -724,7 +787,7 @@ __global__ __launch_bounds__(kBlock) void k_ionize_spawn(DevState s, RunConst rc
     }
   }
   if (b == cp.n_ion_blocks - 1 && threadIdx.x == 0) {
-    const int64_t total = sh_base + sh_wave[0] + sh_wave[1] + sh_wave[2] + sh_wave[3];
+    const int64_t total = base + sh_wave[0] + sh_wave[1] + sh_wave[2] + sh_wave[3];
     const int64_t room = cp.cap - n_base;
     const int64_t fit = total < room ? total : room;
     d.dropped += total - fit;
@@ -732,6 +795,64 @@ __global__ __launch_bounds__(kBlock) void k_ionize_spawn(DevState s, RunConst rc
     d.n_cur = n_base + fit;
     if (total > fit) atomicOr(s.err, kFlagCapacity);
   }
+}
+
+// ----------------------------------------------------------------------------- initial placement
+// Sec. II: the atoms of a cluster sit at random inside the sphere of radius R0 and are lumped
+// into ion macroparticles; each ion starts with charge z_init and z_init electrons at distance
+// delta from it.  Draws: Philox4x64-10 keyed by (seed, cluster), counter (i, 0, 0, 0) for ion i
+// (radius R0 u^{1/3}, polar cosine 2u - 1, azimuth 2 pi u), (e, 0, 1, 0) for electron
+// e = i z_init + k of ion i (direction of its offset).  Slot order: ions, then electrons by
+// parent.  One thread per slot; an electron's thread recomputes its parent's position.
+__device__ inline void unit_direction(uint64_t wc, uint64_t wp, double& dx, double& dy, double& dz) {
+  const double ct = 2.0 * unit_interval(wc) - 1.0;
+  const double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+  const double ph = 2.0 * M_PI * unit_interval(wp);
+  dx = st * cos(ph);
+  dy = st * sin(ph);
+  dz = ct;
+}
+
+__device__ inline void ion_position(const RunConst& rc, int c, double r0, int64_t i, double& x, double& y,
+                                    double& z) {
+  const U64x4 r = philox(rc.seed, (uint64_t)c, (uint64_t)i, 0, kPurposeIon, 0);
+  const double rad = r0 * cbrt(unit_interval(r.v[0]));
+  double dx, dy, dz;
+  unit_direction(r.v[1], r.v[2], dx, dy, dz);
+  x = rad * dx;
+  y = rad * dy;
+  z = rad * dz;
+}
+
+__global__ __launch_bounds__(kBlock) void k_init_generate(DevState s, RunConst rc, int c, int64_t n_ion, int z_init) {
+  const int64_t l = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t n0 = n_ion * (1 + (int64_t)z_init);
+  const ClusterParams& cp = s.cp[c];
+  if (l == 0) {
+    s.dyn[c].n_cur = n0;
+    s.dyn[c].n_base = n0;
+  }
+  if (l >= n0) return;
+  const int64_t g = cp.off + l;
+  double x, y, z;
+  int zc;
+  if (l < n_ion) {
+    ion_position(rc, c, cp.r0, l, x, y, z);
+    zc = z_init;
+  } else {
+    const int64_t e = l - n_ion;
+    ion_position(rc, c, cp.r0, e / z_init, x, y, z);
+    const U64x4 r = philox(rc.seed, (uint64_t)c, (uint64_t)e, 0, kPurposeElectron, 0);
+    double dx, dy, dz;
+    unit_direction(r.v[0], r.v[1], dx, dy, dz);
+    x += cp.delta * dx;
+    y += cp.delta * dy;
+    z += cp.delta * dz;
+    zc = -1;
+  }
+  s.x[g] = x; s.y[g] = y; s.z[g] = z;
+  s.ux[g] = 0.0; s.uy[g] = 0.0; s.uz[g] = 0.0;
+  s.Z[g] = (int8_t)zc;
 }
 
 template <int PREC>
@@ -803,11 +924,20 @@ hipError_t launch_ionize(const DevState& s, const RunConst& rc, int precision, c
   }
   if (precision == LC_FP64) {
     k_ionize_check<LC_FP64><<<n_ion_blocks, kBlock, 0, st>>>(s, rc, fl, k);
+    k_ionize_scan<<<1, 1024, 0, st>>>(s, n_ion_blocks);
     k_ionize_spawn<LC_FP64><<<n_ion_blocks, kBlock, 0, st>>>(s, rc, k);
   } else {
     k_ionize_check<LC_FP32_ACC64><<<n_ion_blocks, kBlock, 0, st>>>(s, rc, fl, k);
+    k_ionize_scan<<<1, 1024, 0, st>>>(s, n_ion_blocks);
     k_ionize_spawn<LC_FP32_ACC64><<<n_ion_blocks, kBlock, 0, st>>>(s, rc, k);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_init_generate(const DevState& s, const RunConst& rc, int c, int64_t n_ion, int z_init,
+                                hipStream_t st) {
+  const int64_t n0 = n_ion * (1 + (int64_t)z_init);
+  k_init_generate<<<blocks_for(n0 > 0 ? n0 : 1), kBlock, 0, st>>>(s, rc, c, n_ion, z_init);
   return hipGetLastError();
 }
 

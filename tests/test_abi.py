@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_version_and_error_strings():
     L = lc.lib()
-    assert L.lc_version() == 5
+    assert L.lc_version() == 6
     for code in [0, -1, -2, -3, -4, -5, -6]:
         assert L.lc_error_string(code)
     assert L.lc_error_string(0).decode() == "ok"
@@ -164,3 +164,57 @@ def test_pair_once_field_workspace(R, WJ, ok):
     else:
         assert wb64 == 0                              # shape needs more LDS than a block may take
     assert L.lc_field_workspace_bytes(2, n, ctypes.byref(t)) == 0   # not for Kahan
+
+
+# Pair-once shapes lc_set_tuning accepts: (R, WJ) with 4/WJ target groups of 64 R slots, and the
+# square shapes R = WJ = 3..6 with one group of 64 R slots.
+PAIR_SHAPES = [(1, 1), (2, 1), (1, 2), (2, 2), (4, 2), (3, 3), (4, 4), (5, 5), (6, 6)]
+
+
+def _block_of(R, WJ):
+    return 64 * R if (R == WJ and R >= 3) else (4 // WJ) * 64 * R
+
+
+def test_pair_once_rows_stay_inside_each_share():
+    """Host-only bound check of the pair-once partial rows (no GPU).  For every pair-once shape
+    and every capacity 1..20000 (a cluster of an ensemble has its own share, so mixes reduce to
+    single capacities), and rows per block M from just enough (ceil(capacity / 128), the
+    binding's choice) to a few more: whenever the library accepts the shape for the capacity,
+    the largest row element the kernel writes and the fold reads, from the documented indexing
+    ((K M + m) 3 + d) B + l with K, m < nb, d < 3, l < B, lies inside the share of 3 M
+    (capacity rounded up to 512, plus 512); and the library rejects the shape when nb exceeds M.
+    Checked against the indexing written out here, not the library's own predicate."""
+    import numpy as np
+    L = lc.lib()
+    out = (ctypes.c_int64 * 3)()
+    caps = np.arange(1, 20001)
+    shapes = 0
+    for prec in (0, 1):
+        for R, WJ in PAIR_SHAPES:
+            B = _block_of(R, WJ)
+            if L.lc_pair_rows_fit(prec, R, WJ, 1, 1, out) != 0:
+                # shapes whose LDS does not fit in FP64 (R, WJ = 2, 1 and 6, 6) are not accepted at all
+                assert prec == 0 and (R, WJ) in ((2, 1), (6, 6))
+                continue
+            shapes += 1
+            for cap in caps:
+                cap = int(cap)
+                m_min = -(-cap // 128)
+                for M in (m_min, m_min + 1, m_min + 7):
+                    rc = L.lc_pair_rows_fit(prec, R, WJ, cap, M, out)
+                    nb = -(-cap // B)
+                    assert out[0] == B and out[1] == nb
+                    if rc == 0:
+                        last = (((nb - 1) * M + (nb - 1)) * 3 + 2) * B + (B - 1)
+                        assert last < out[2], (prec, R, WJ, cap, M)
+                        assert out[2] == 3 * M * ((cap + 511) // 512 * 512 + 512)
+                    else:
+                        assert rc == -1
+                    if nb > M:
+                        assert rc == -1
+                    if nb <= M and nb * B <= (cap + 511) // 512 * 512:
+                        assert rc == 0, (R, WJ, cap, M)  # the share always has room for these
+    assert shapes == 2 * len(PAIR_SHAPES) - 2
+    # invalid shapes and arguments
+    for args in ((1, 3, 1, 100, 4), (1, 7, 7, 100, 4), (2, 4, 4, 100, 4), (1, 4, 4, 0, 4), (1, 4, 4, 100, 0)):
+        assert L.lc_pair_rows_fit(*args, out) == -1

@@ -94,11 +94,14 @@ def test_small_ar_fp32_200_steps(precision, tiling):
     r0n = units.nm_to_norm(c.r0_nm, 0.8)
     g = sim.particles(0)
     print(f"{precision}: N gpu={g['n']} oracle={osim.N}", flush=True)
-    if g["n"] == osim.N and np.array_equal(g["Z"], osim.charges()):
-        dx = np.max(np.abs(g["x"] - osim.positions())) / r0n
-        print(f"{precision}: max|dx|/R0 = {dx:.3e}")
-        assert dx <= 1e-4
-    _compare_records(rg, ro, [5, 6, 8, 9], 1e-4)
+    # with the laser-only field the rate of an ion depends on its charge and t only, and both
+    # sides draw the same alpha: FP32 pair arithmetic cannot change an ionization decision
+    assert g["n"] == osim.N and np.array_equal(g["Z"], osim.charges())
+    assert np.array_equal(rg[:, 21], ro[:, 21]) and np.array_equal(rg[:, 24:41], ro[:, 24:41])
+    dx = np.max(np.abs(g["x"] - osim.positions())) / r0n
+    print(f"{precision}: max|dx|/R0 = {dx:.3e}")
+    assert dx <= 1e-4
+    _compare_records(rg, ro, [5, 6, 7, 8, 9, 10], 1e-4)
 
 
 def test_energy_identity_and_newton3_on_gpu():

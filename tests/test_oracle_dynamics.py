@@ -649,44 +649,152 @@ def test_periodic_momentum_newton3_and_box():
     assert abs(lhs - rhs) <= 1e-11 * (abs(rec2[-1][oracle.R_WL]) + abs(rec2[-1][oracle.R_WC]) + abs(sim2.ke_start))
 
 
-def test_grid32_separations():
-    """FP32 periodic passes take separations from positions on the cube's 32-bit grid (side L
-    spans 2^32 steps; the wrapped integer difference is the minimum image).  Pinned by what the
-    definition fixes: at an exact half-box tie the wrap gives -L/2 where the FP64 rounding
-    gives +L/2; dyadic positions already on the grid (L = 1) give the FP64 minimum image bit
-    for bit; moving a particle by whole box sides changes nothing, bit for bit, also from
-    beyond a face; elsewhere the field moves by no more than quantization by L 2^-33 allows."""
-    x = np.array([[0.25, 0.0, 0.0], [-0.25, 0.0, 0.0]])
-    q = np.array([0.0, 1.0])
-    e64, _ = oracle.coulomb_field(x, q, 1e-6, box=1.0)
-    e32, _ = oracle.coulomb_field(x, q, 1e-6, box=1.0, grid32=True)
-    assert e64[0][0] > 0 and e32[0][0] == -e64[0][0]
-    rng = np.random.default_rng(5)
-    xd = rng.integers(-2**19, 2**19, (40, 3)) / 2.0**20  # dyadic, inside (-1/2, 1/2)
-    d = xd[:, None, :] - xd[None, :, :]
-    assert np.all(np.abs(np.abs(d) - 0.5) > 0)  # no exact tie
-    qr = rng.choice([-1.0, 1.0], 40)
-    a, pa = oracle.coulomb_field(xd, qr, 1e-4, box=1.0)
-    b, pb = oracle.coulomb_field(xd, qr, 1e-4, box=1.0, grid32=True)
-    assert np.array_equal(a, b) and np.array_equal(pa, pb)
-    shift = rng.integers(-3, 4, (40, 3)).astype(np.float64)
-    c, pc = oracle.coulomb_field(xd + shift, qr, 1e-4, box=1.0, grid32=True)
-    assert np.array_equal(b, c) and np.array_equal(pb, pc)
-    L = 1.3
-    xr = rng.uniform(-0.65, 0.65, (40, 3))
-    dd = xr[:, None, :] - xr[None, :, :]
-    frac = np.abs(np.abs(dd) - L / 2)
-    assert frac[frac > 0].min() > 1e-6  # no pair near a tie
-    eps2 = 1e-4
-    f64, p64 = oracle.coulomb_field(xr, qr, eps2, box=L)
-    f32, p32 = oracle.coulomb_field(xr, qr, eps2, box=L, grid32=True)
-    dd -= L * np.rint(dd / L)
-    r2 = np.sum(dd * dd, axis=2) + eps2
-    s1 = np.sum(np.where(np.eye(40, dtype=bool), 0.0, 1.0 / r2), axis=1)  # sum of |q| / (r^2 + eps^2)
-    # each separation moves by at most L 2^-32; a term q d / (r^2+eps^2)^{3/2} by at most 3 times that
-    # over (r^2 + eps^2)^{3/2}, below 3 L 2^-32 / eps times s1
-    assert np.max(np.abs(f32 - f64) / s1[:, None]) <= 3 * L * 2.0**-32 / math.sqrt(eps2)
-    assert 0 < np.max(np.abs(f32 - f64))
+def test_sampled_field_equals_full_sum():
+    """The sampled evaluation (targets listed by index, used for the large-state checks) gives the
+    full direct sum's values at those targets bit for bit, E and potential, including the first
+    and last index and a repeated one."""
+    x, q = _rand_state(300, 11)
+    eps2 = (7.854e-4) ** 2
+    E, phi = oracle.coulomb_field(x, q, eps2)
+    idx = np.array([0, 299, 17, 17, 150, 3, 298, 42])
+    Es, phis = oracle.coulomb_field_at(x, q, eps2, idx)
+    assert np.array_equal(Es, E[idx]) and np.array_equal(phis, phi[idx])
+
+
+def test_local_ofi_without_coulomb_coupling_is_laser_only():
+    """With the Coulomb coupling switched off the local field at an ion is the laser's, so the
+    LOCAL choice (|E_C + E_L|) must take exactly the laser-only decisions: identical charges,
+    positions and records over a run with many ionizations (linear and circular polarization)."""
+    for pol in ("linear_x", "circular"):
+        c = Cluster(species="Ar", r0_nm=2.5, n_ion=400, capacity=4000, z_init=1, z_max=8,
+                    laser=Laser(intensity_wcm2=2e16, envelope="flat", polarization=pol))
+        out = []
+        for ofi in ("laser_only", "local"):
+            run = Run(dt=0.05, t0=math.pi / 2, ionize=True, ofi_field=ofi, diag_every=5, seed=4)
+            sim = oracle.Sim.from_workload(c, run, initial_state(c, 4))
+            sim.p.kappa = 0.0
+            sim.start()
+            rec = sim.run(60)
+            out.append((sim.charges(), sim.positions(), rec))
+        assert out[0][2][-1][oracle.R_EVENTS] > 50
+        for a, b in zip(out[0], out[1]):
+            assert np.array_equal(a, b)
+
+
+def test_local_ofi_survival_law_around_frozen_sources():
+    """LOCAL ionization is driven by |E_C + E_L| at the atom.  n neutral Ar atoms (Z = 0, may
+    ionize once) each have one Ar+ source at distance d along +x; the pairs sit 1 c/w apart on a
+    line, so the field of the other pairs changes E_C by under 1e-5 relative.  Before its
+    ionization a neutral atom neither moves nor makes a field, so E_C at it is the softened
+    Coulomb field of its source, -kappa w d / (d^2 + eps^2)^{3/2} x^, and with a flat laser from
+    t = 0 (E_L = a sin t x^, a = E_C / 2) the atom survives n checks with probability
+    exp(-dt sum_k nu(|E_C + a sin t_k|)).  Binomial count at 4.5 sigma; the laser-only field
+    (a/2 here) and a flipped sign of E_L predict survivals many sigma away."""
+    n = 3000
+    d = 1.0e-3
+    c = Cluster(species="Ar", r0_nm=2.5, n_ion=2 * n, capacity=4 * n, z_init=0, z_max=1,
+                laser=Laser(intensity_wcm2=0.0, envelope="flat"))
+    run = Run(dt=0.05, t0=0.0, ionize=True, ofi_field="local", diag_every=0, seed=8)
+    x = np.zeros((2 * n, 3))
+    x[:n, 0] = np.arange(n) * 1.0
+    x[n:, 0] = x[:n, 0] + d
+    Z = np.concatenate([np.zeros(n, np.int8), np.ones(n, np.int8)])
+    p = oracle.make_params(c, run, weight=1.0)
+    ec = p.kappa * 1.0 * d / (d * d + p.eps2) ** 1.5  # |E_C| at an atom, pointing along -x
+    nsteps = 40
+    ip = p.ip_au[0]
+
+    def survival(fields):
+        lam = sum(oracle.adk_rate(ip, 1.0, f * p.field_au) * p.rate_scale for f in fields) * p.dt
+        return math.exp(-lam)
+    ts = [k * run.dt for k in range(nsteps)]
+    shape = [abs(-1.0 + 0.5 * math.sin(t)) for t in ts]  # |E_C + E_L| / |E_C| with a = |E_C| / 2
+    # the weight (source strength) that makes the expected survival 1/2
+    lo, hi = 0.1, 100.0
+    for _ in range(200):
+        w = math.sqrt(lo * hi)
+        if survival([ec * w * f for f in shape]) > 0.5:
+            lo = w
+        else:
+            hi = w
+    p = oracle.make_params(c, run, weight=w)
+    ec *= w
+    p.a0 = 0.5 * ec
+    sim = oracle.Sim(p, c.capacity, x, np.zeros_like(x), Z)
+    sim.start()
+    sim.run(nsteps)
+    surv = np.mean(sim.charges()[:n] == 0)
+    expect = survival([abs(-ec + p.a0 * math.sin(t)) for t in ts])
+    sigma = math.sqrt(expect * (1 - expect) / n)
+    assert 0.15 < expect < 0.85
+    assert abs(surv - expect) < 4.5 * sigma, (surv, expect, sigma)
+    for wrong in (survival([abs(p.a0 * math.sin(t)) for t in ts]),        # laser only
+                  survival([abs(-ec - p.a0 * math.sin(t)) for t in ts])):  # E_C - E_L
+        assert abs(wrong - expect) > 15 * sigma
+
+
+def _philox_block(key, ctr):
+    """Philox4x64-10 block at counter ctr from numpy's own implementation (which increments the
+    counter before each block, so it starts one below)."""
+    c = list(ctr)
+    for k in range(4):  # counter - 1 with borrow
+        c[k] = (c[k] - 1) % 2**64
+        if c[k] != 2**64 - 1:
+            break
+    g = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=np.array(c, dtype=np.uint64))
+    return [int(v) for v in g.random_raw(4)]
+
+
+def test_initial_placement_counters_and_geometry():
+    """O1 initial placement (Sec. II: atoms at random inside R0, lumped into ion macroparticles,
+    each with z_init electrons next to it).  The draws are numpy's Philox blocks at counter
+    (i, 0, 0, 0) for ion i and (e, 0, 1, 0) for electron e; the ion radius is R0 u^{1/3}, the
+    directions have polar cosine 2u - 1 and azimuth 2 pi u, the electrons sit at delta from
+    their parent (ions first, then electrons by parent).  Values within a few ulp of R0."""
+    seed, cl, n_ion, z_init = 3, 5, 64, 2
+    r0, delta = 0.0196, 7.854e-5
+    x, Z = oracle.init_cluster(seed, cl, n_ion, z_init, r0, delta)
+    assert x.shape == (n_ion * 3, 3)
+    assert np.all(Z[:n_ion] == z_init) and np.all(Z[n_ion:] == -1)
+    u01 = lambda w: ((w >> 11) + 1) * 2.0**-53
+
+    def direction(uc, up):
+        ct = 2.0 * uc - 1.0
+        st = math.sqrt(max(0.0, 1.0 - ct * ct))
+        return np.array([st * math.cos(2 * math.pi * up), st * math.sin(2 * math.pi * up), ct])
+    for i in range(n_ion):
+        w = _philox_block((seed, cl), (i, 0, 0, 0))
+        xi = r0 * u01(w[0]) ** (1.0 / 3.0) * direction(u01(w[1]), u01(w[2]))
+        assert np.max(np.abs(x[i] - xi)) <= 8 * 2.0**-52 * r0
+        for k in range(z_init):
+            e = i * z_init + k
+            we = _philox_block((seed, cl), (e, 0, 1, 0))
+            xe = x[i] + delta * direction(u01(we[0]), u01(we[1]))
+            assert np.max(np.abs(x[n_ion + e] - xe)) <= 8 * 2.0**-52 * r0
+
+
+def test_initial_placement_distribution():
+    """Uniform in the ball: (r/R0)^3, the polar cosine and the azimuth of the ions are uniform, and
+    so are the polar cosine and azimuth of the electron offsets, whose length is delta
+    (Kolmogorov-Smirnov, 20k ions; p > 1e-4); different clusters and seeds draw differently."""
+    from scipy import stats
+    n_ion = 20000
+    r0, delta = 0.05, 1e-4
+    x, Z = oracle.init_cluster(0, 0, n_ion, 1, r0, delta)
+    ions = x[:n_ion]
+    r = np.linalg.norm(ions, axis=1)
+    assert r.max() <= r0 * (1 + 1e-15)
+    off = x[n_ion:] - ions
+    ln = np.linalg.norm(off, axis=1)
+    assert np.max(np.abs(ln - delta)) <= 1e-9 * delta
+    for sample, cdf in (((r / r0) ** 3, stats.uniform(0, 1).cdf), (ions[:, 2] / r, stats.uniform(-1, 2).cdf),
+                        (np.arctan2(ions[:, 1], ions[:, 0]) % (2 * np.pi), stats.uniform(0, 2 * np.pi).cdf),
+                        (off[:, 2] / ln, stats.uniform(-1, 2).cdf),
+                        (np.arctan2(off[:, 1], off[:, 0]) % (2 * np.pi), stats.uniform(0, 2 * np.pi).cdf)):
+        assert stats.kstest(sample, cdf).pvalue > 1e-4
+    x1, _ = oracle.init_cluster(0, 1, 100, 1, r0, delta)
+    x2, _ = oracle.init_cluster(1, 0, 100, 1, r0, delta)
+    assert not np.array_equal(x1, x[:100]) and not np.array_equal(x2, x[:100])
 
 
 def _ci_cloud(seed=31, n_ion=3000, n_e=2000, t_ev=100.0, surv=0.5, nsteps=40):
