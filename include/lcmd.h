@@ -341,6 +341,20 @@ size_t lc_field_workspace_bytes(int32_t precision, int64_t n, const lc_tuning* t
 int lc_field(int32_t precision, int64_t n, const double* d_xyzq, double eps2, double* d_E,
              double* d_phi, void* d_work, size_t work_bytes, const lc_tuning* t, void* hip_stream);
 
+/* Allocation-free variant of lc_field for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and results as lc_field (bitwise, for the same arguments and tiling), with the
+ * workspace in a device array of LC_FIELD_STATIC_MAX_BYTES that the library holds on every
+ * device it runs on until the process ends, instead of a caller-owned d_work.  The caller still
+ * passes the inputs and outputs.  Calls nothing that allocates; the first call on a device
+ * looks the array's address up (make it outside graph capture).  LC_E_INVALID as lc_field,
+ * and when lc_field_workspace_bytes() for the request exceeds LC_FIELD_STATIC_MAX_BYTES.
+ * Every call on a device shares that device's array: calls that overlap on one device (other
+ * streams, other threads) race and give undefined results; calls on one stream are ordered. */
+#define LC_FIELD_STATIC_MAX_BYTES (64u << 20)
+int lc_field_static(int32_t precision, int64_t n, const double* d_xyzq, double eps2, double* d_E,
+                    double* d_phi, const lc_tuning* t, void* hip_stream);
+
 /* ---------------------------------------------------------------- surrogate network */
 /* A small network 4-64-64-2 (SiLU hidden units) that maps standardized features of a
  * cluster run (log R0, log N_atoms from Eq.(1), log peak intensity, log pulse FWHM) to

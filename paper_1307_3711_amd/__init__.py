@@ -4,7 +4,8 @@ Python face of liblcmd.so.  See include/lcmd.h for the C ABI; this package only 
 arguments and lends PyTorch device memory and streams to the library.
 """
 from ._binding import (  # noqa: F401
-    LC_MAX_Z, LC_REC, LC_DET_BINS, LC_DET_SLOTS, LcError, Simulation, Surrogate, field, lib, make_cluster,
+    LC_MAX_Z, LC_REC, LC_DET_BINS, LC_DET_SLOTS, LC_FIELD_STATIC_MAX_BYTES, LcError, Simulation, Surrogate, field,
+    field_static, lib, make_cluster,
     make_config, make_tuning, pair_blocks_for, units,
     PRECISIONS, ENVELOPES, PHASES, OFI, POLARIZATIONS, BOUNDARIES,
     R_T, R_STEP, R_N, R_NION, R_NEL, R_KE_HALF, R_KE_BAR, R_PE, R_WL, R_WC, R_WSP, R_P, R_F, R_FABS,

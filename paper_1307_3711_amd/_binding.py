@@ -146,6 +146,7 @@ def lib():
         "lc_field_workspace_bytes": ([ctypes.c_int32, ctypes.c_int64, tp], ctypes.c_size_t),
         "lc_field": ([ctypes.c_int32, ctypes.c_int64, vp, ctypes.c_double, vp, vp, vp, ctypes.c_size_t, tp, vp],
                      ctypes.c_int),
+        "lc_field_static": ([ctypes.c_int32, ctypes.c_int64, vp, ctypes.c_double, vp, vp, tp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -354,6 +355,29 @@ class Simulation:
 
     def load(self, path):
         _check(lib().lc_load_state(self.h, path.encode()), self.h)
+
+
+LC_FIELD_STATIC_MAX_BYTES = 64 << 20
+
+
+def field_static(xyzq, eps2, precision="fp64", want_phi=True, tuning=None):
+    """As field(), through lc_field_static: no workspace is allocated (the library's device array
+    serves as the workspace); only the outputs are allocated here.  Requests whose workspace would
+    exceed LC_FIELD_STATIC_MAX_BYTES raise LcError."""
+    L = lib()
+    if xyzq.dtype != torch.float64 or not xyzq.is_cuda or xyzq.dim() != 2 or xyzq.shape[0] != 4:
+        raise ValueError("xyzq must be a (4, n) float64 CUDA tensor")
+    xyzq = xyzq.contiguous()
+    n = xyzq.shape[1]
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    tp = ctypes.byref(tuning) if tuning is not None else None
+    E = torch.empty((3, n), dtype=torch.float64, device=xyzq.device)
+    phi = torch.empty(n, dtype=torch.float64, device=xyzq.device) if want_phi else None
+    st = torch.cuda.current_stream(xyzq.device)
+    code = L.lc_field_static(prec, n, ctypes.c_void_p(xyzq.data_ptr()), float(eps2), ctypes.c_void_p(E.data_ptr()),
+                             ctypes.c_void_p(phi.data_ptr()) if want_phi else None, tp, ctypes.c_void_p(st.cuda_stream))
+    _check(code)
+    return E, phi
 
 
 def field(xyzq, eps2, precision="fp64", want_phi=True, tuning=None):

@@ -1282,11 +1282,10 @@ size_t lc_field_workspace_bytes(int32_t precision, int64_t n, const lc_tuning* t
   return field_workspace_bytes(precision, n, ft);
 }
 
-int lc_field(int32_t precision, int64_t n, const double* d_xyzq, double eps2, double* d_E, double* d_phi,
-             void* d_work, size_t work_bytes, const lc_tuning* t, void* hip_stream) {
-  if (precision < LC_FP64 || precision > LC_FP32_KAHAN || n < 0 || !(eps2 > 0.0)) return LC_E_INVALID;
-  if (n > ((int64_t)1 << 30)) return LC_E_INVALID;
-  if (n > 0 && (!d_xyzq || !d_E || !d_work)) return LC_E_INVALID;
+namespace {
+
+// The tiling of a standalone field call (NULL: the precision's default, one split).
+ForceTiling field_tiling(int32_t precision, const lc_tuning* t) {
   ForceTiling ft = default_tiling(precision);
   ft.S = 1;
   if (t) {
@@ -1298,11 +1297,42 @@ int lc_field(int32_t precision, int64_t n, const double* d_xyzq, double eps2, do
     ft.scalar_src = t->scalar_sources ? 1 : 0;
     ft.newton3 = t->newton3 ? 1 : 0;
   }
-  if (!force_tiling_valid(precision, ft)) return LC_E_INVALID;
-  if (ft.newton3 && d_phi) return LC_E_INVALID;
+  return ft;
+}
+
+int field_args_ok(int32_t precision, int64_t n, const double* d_xyzq, double eps2, double* d_E, double* d_phi,
+                  const ForceTiling& ft) {
+  if (precision < LC_FP64 || precision > LC_FP32_KAHAN || n < 0 || !(eps2 > 0.0)) return 0;
+  if (n > ((int64_t)1 << 30)) return 0;
+  if (n > 0 && (!d_xyzq || !d_E)) return 0;
+  if (!force_tiling_valid(precision, ft)) return 0;
+  if (ft.newton3 && d_phi) return 0;
+  return 1;
+}
+
+}  // namespace
+
+int lc_field(int32_t precision, int64_t n, const double* d_xyzq, double eps2, double* d_E, double* d_phi,
+             void* d_work, size_t work_bytes, const lc_tuning* t, void* hip_stream) {
+  const ForceTiling ft = field_tiling(precision, t);
+  if (!field_args_ok(precision, n, d_xyzq, eps2, d_E, d_phi, ft)) return LC_E_INVALID;
+  if (n > 0 && !d_work) return LC_E_INVALID;
   if (((uintptr_t)d_work & 255) != 0) return LC_E_INVALID;
   if (work_bytes < field_workspace_bytes(precision, n, ft)) return LC_E_INVALID;
   hipError_t e = launch_field_standalone(precision, n, d_xyzq, eps2, d_E, d_phi, d_work, ft, (hipStream_t)hip_stream);
+  return e == hipSuccess ? LC_OK : LC_E_HIP;
+}
+
+int lc_field_static(int32_t precision, int64_t n, const double* d_xyzq, double eps2, double* d_E, double* d_phi,
+                    const lc_tuning* t, void* hip_stream) {
+  const ForceTiling ft = field_tiling(precision, t);
+  if (!field_args_ok(precision, n, d_xyzq, eps2, d_E, d_phi, ft)) return LC_E_INVALID;
+  if (field_workspace_bytes(precision, n, ft) > (size_t)LC_FIELD_STATIC_MAX_BYTES) return LC_E_INVALID;
+  if (n == 0) return LC_OK;
+  void* work = nullptr;
+  hipError_t e = field_scratch(&work);
+  if (e == hipSuccess)
+    e = launch_field_standalone(precision, n, d_xyzq, eps2, d_E, d_phi, work, ft, (hipStream_t)hip_stream);
   return e == hipSuccess ? LC_OK : LC_E_HIP;
 }
 

@@ -25,6 +25,7 @@
 //                    block, frozen or equal ion charges) use a loop with the charge factored out.
 //   LC_FP32_KAHAN  : as above with Kahan-compensated FP32 sums within the tile.
 #include <limits>
+#include <mutex>
 
 #include "lc_internal.h"
 
@@ -1200,6 +1201,35 @@ hipError_t launch_force(const DevState& s, const RunConst& rc, int precision, co
   const void* src = (precision == LC_FP64) ? (const void*)s.posq : (const void*)s.pos4;
   const ForceTiling fr = ft.newton3 ? regular_tiling(precision, ft) : ft;
   return launch_generic(precision, fr, map, src, s.part, rc.n_total, rc.eps2, want_phi, pbc, grid_blocks, st);
+}
+
+// ----------------------------------------------------------------------------- allocation-free field
+// Workspace of lc_field_static: a file-scope device array of LC_FIELD_STATIC_MAX_BYTES that each
+// device holds for the life of the process.  On the host its name is only a stand-in for the
+// symbol: host code uses the device address hipGetSymbolAddress returns for the current device,
+// looked up once per device (each device has its own copy at its own address).
+namespace {
+static __device__ __align__(256) unsigned char scratch[LC_FIELD_STATIC_MAX_BYTES];
+constexpr int kScratchDevices = 64;
+}  // namespace
+
+hipError_t field_scratch(void** out) {
+  static std::mutex mu;
+  static void* ptr[kScratchDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p || ((uintptr_t)p & 255) != 0) return hipErrorInvalidSymbol;
+    ptr[dev] = p;
+  }
+  *out = ptr[dev];
+  return hipSuccess;
 }
 
 size_t field_workspace_bytes(int precision, int64_t n, const ForceTiling& ft) {

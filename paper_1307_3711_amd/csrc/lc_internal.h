@@ -265,6 +265,9 @@ hipError_t launch_refresh_sources(const DevState& s, const RunConst& rc, int pre
 hipError_t launch_field_standalone(int precision, int64_t n, const double* xyzq, double eps2, double* E,
                                    double* phi, void* work, const ForceTiling& ft, hipStream_t st);
 size_t field_workspace_bytes(int precision, int64_t n, const ForceTiling& ft);
+// Device address of the current device's lc_field_static workspace (LC_FIELD_STATIC_MAX_BYTES),
+// looked up on the first call per device.
+hipError_t field_scratch(void** out);
 
 int force_tile_targets(const ForceTiling& ft);
 int n3_block_size(const ForceTiling& ft);
