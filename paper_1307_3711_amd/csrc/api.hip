@@ -53,6 +53,9 @@ double a0_of(double intensity, double lambda_um) { return std::sqrt(intensity * 
 
 size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// Slots a cluster of capacity cap occupies: its capacity rounded up to a whole 64-slot group.
+int64_t slot_share(int64_t cap) { return (cap + kGroup - 1) / kGroup * kGroup; }
+
 // Pair-once partial rows: cluster c gets 3 M n3_round(cap_c) row elements.  With blocks of B
 // slots (128 to 512) and nb = ceil(cap / B) <= M blocks, row (K, m) of K, m < nb starts at
 // (K M + m) 3 B, so the rows end below 3 M nb B, and nb B = cap rounded up to a multiple of B
@@ -62,7 +65,7 @@ constexpr int kMaxPairBlocks = 32768;
 int64_t n3_round(int64_t cap) { return (cap + 511) / 512 * 512 + 512; }
 
 struct Layout {
-  size_t x, y, z, ux, uy, uz, wl, wc, wsp, kebar, pos4, posq, Z, cid, part, n3part, flag, ib_count, ib_off, ib_cluster;
+  size_t x, y, z, ux, uy, uz, wl, wc, wsp, kebar, pos4, posq, Z, gcl, part, n3part, flag, ib_count, ib_off, ib_cluster;
   size_t cp, dyn, order, tile_start, tile_total, queue, det_seen, det_counts, det_edges, ci_part, err, step, diag_part, records, total;
   int64_t n_total;
   int n_ion_blocks;
@@ -126,7 +129,7 @@ Layout make_layout(const lc_config* cfg, const lc_cluster* cl, int C) {
   int64_t NT = 0;
   int ib = 0;
   for (int c = 0; c < C; ++c) {
-    NT += cl[c].capacity;
+    NT += slot_share(cl[c].capacity);
     ib += (int)((cl[c].n_ion + kBlock - 1) / kBlock);
   }
   L.n_total = NT;
@@ -140,7 +143,7 @@ Layout make_layout(const lc_config* cfg, const lc_cluster* cl, int C) {
   L.pos4 = take(cfg->precision == LC_FP64 ? 0 : sizeof(float4) * (size_t)NT);
   L.posq = take(cfg->precision == LC_FP64 ? sizeof(double4) * (size_t)NT : 0);
   L.Z = take((size_t)NT);
-  L.cid = take(sizeof(int32_t) * (size_t)NT);
+  L.gcl = take(sizeof(int32_t) * (size_t)(NT / kGroup));
   L.part = take(sizeof(double) * (size_t)cfg->max_splits * kComp * (size_t)NT);
   int64_t n3_slots = 0;
   for (int c = 0; c < C; ++c) n3_slots += n3_round(cl[c].capacity);
@@ -224,6 +227,7 @@ struct lc_sim {
   ForceTiling ft;
   int S_eff = 1;                   // splits in use
   std::vector<int64_t> n_host;     // host view of counts (exact when ionization is off)
+  std::vector<int64_t> off;        // first global slot of each cluster (a multiple of 64)
   std::vector<int> inited;
   std::vector<int32_t> order;
   int64_t step = 0;
@@ -461,7 +465,7 @@ int lc_create(lc_sim** out, const lc_config* cfg, const lc_cluster* clusters, in
   d.wl = (double*)(b + L.wl); d.wc = (double*)(b + L.wc); d.wsp = (double*)(b + L.wsp);
   d.kebar = (double*)(b + L.kebar);
   d.pos4 = (float4*)(b + L.pos4); d.posq = (double4*)(b + L.posq);
-  d.Z = (int8_t*)(b + L.Z); d.cid = (int32_t*)(b + L.cid); d.part = (double*)(b + L.part);
+  d.Z = (int8_t*)(b + L.Z); d.gcl = (int32_t*)(b + L.gcl); d.part = (double*)(b + L.part);
   d.n3part = (void*)(b + L.n3part);
   d.flag = (int32_t*)(b + L.flag); d.ib_count = (int32_t*)(b + L.ib_count);
   d.ib_off = (int32_t*)(b + L.ib_off);
@@ -514,7 +518,8 @@ int lc_create(lc_sim** out, const lc_config* cfg, const lc_cluster* clusters, in
 
   // Per-cluster tables.
   std::vector<ClusterParams> cps(n_clusters);
-  std::vector<int32_t> cid(L.n_total), ibc(std::max(L.n_ion_blocks, 1), 0);
+  std::vector<int32_t> gcl(L.n_total / kGroup), ibc(std::max(L.n_ion_blocks, 1), 0);
+  s->off.assign(n_clusters, 0);
   int64_t off = 0, n3_off = 0;
   int ib0 = 0;
   for (int c = 0; c < n_clusters; ++c) {
@@ -578,9 +583,10 @@ int lc_create(lc_sim** out, const lc_config* cfg, const lc_cluster* clusters, in
     p.ion_block0 = ib0;
     p.n_ion_blocks = (int32_t)((k.n_ion + kBlock - 1) / kBlock);
     for (int q = 0; q < p.n_ion_blocks; ++q) ibc[ib0 + q] = c;
-    for (int64_t i = 0; i < k.capacity; ++i) cid[off + i] = c;
+    for (int64_t q = 0; q < slot_share(k.capacity) / kGroup; ++q) gcl[off / kGroup + q] = c;
+    s->off[c] = off;
     ib0 += p.n_ion_blocks;
-    off += k.capacity;
+    off += slot_share(k.capacity);
     cps[c] = p;
   }
   s->order.resize(n_clusters);
@@ -595,7 +601,7 @@ int lc_create(lc_sim** out, const lc_config* cfg, const lc_cluster* clusters, in
   int32_t zero32 = 0;
   if (e == hipSuccess) e = hipMemcpy(d.cp, cps.data(), sizeof(ClusterParams) * n_clusters, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d.dyn, dyn.data(), sizeof(ClusterDyn) * n_clusters, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(d.cid, cid.data(), sizeof(int32_t) * cid.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d.gcl, gcl.data(), sizeof(int32_t) * gcl.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d.ib_cluster, ibc.data(), sizeof(int32_t) * ibc.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d.order, s->order.data(), sizeof(int32_t) * n_clusters, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d.step, &zero64, sizeof(int64_t), hipMemcpyHostToDevice);
@@ -645,7 +651,7 @@ int lc_init_from_host(lc_sim* s, int32_t cluster, int64_t n, const double* x_nm,
   }
   for (int64_t i = 0; i < 3 * n; ++i)
     if (!std::isfinite(x_nm[i]) || (u && !std::isfinite(u[i]))) return fail(s, LC_E_NONFINITE, "non-finite input");
-  const int64_t off = [&] { int64_t o = 0; for (int c = 0; c < cluster; ++c) o += s->cl[c].capacity; return o; }();
+  const int64_t off = s->off[cluster];
   std::vector<double> buf(n);
   const double kn = 1e-9 * s->u.k;  // nm -> c/w
   double* dst[3] = {s->s.x, s->s.y, s->s.z};
@@ -863,8 +869,7 @@ int lc_read_particles(lc_sim* s, int32_t cluster, double* x, double* u, int8_t* 
   ClusterDyn d;
   e = hipMemcpy(&d, s->s.dyn + cluster, sizeof(ClusterDyn), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(s, e, "lc_read_particles");
-  int64_t off = 0;
-  for (int c = 0; c < cluster; ++c) off += s->cl[c].capacity;
+  const int64_t off = s->off[cluster];
   const int64_t n = std::min<int64_t>(d.n_cur, cap);
   std::vector<double> buf(std::max<int64_t>(n, 1));
   const double* src3[2][3] = {{s->s.x, s->s.y, s->s.z}, {s->s.ux, s->s.uy, s->s.uz}};
@@ -996,7 +1001,7 @@ namespace {
 __global__ void k_fold_partials(DevState s, RunConst rc, FieldLayout fl) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= rc.n_total) return;
-  const int c = s.cid[g];
+  const int c = slot_cluster(s, g);
   double e[3] = {0.0, 0.0, 0.0};
   if (g - s.cp[c].off < s.dyn[c].n_sched) field_sum(s, rc, fl, g, e[0], e[1], e[2]);
   for (int k = 0; k < 3; ++k) s.part[(int64_t)k * rc.n_total + g] = e[k];
@@ -1045,8 +1050,7 @@ extern "C" int lc_read_field(lc_sim* s, int32_t cluster, double* E, int64_t cap,
   e = schedule(s, ft, n3_pass(s, ft, is_diag_step(s, s->step)), false);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "lc_read_field");
-  int64_t off = 0;
-  for (int c = 0; c < cluster; ++c) off += s->cl[c].capacity;
+  const int64_t off = s->off[cluster];
   const int64_t NT = s->L.n_total;
   const int64_t n = std::min<int64_t>(d.n_cur, cap);
   for (int64_t i = 0; i < n; ++i)
@@ -1061,15 +1065,14 @@ double rel_diff(const std::vector<double>& a, const std::vector<double>& b, cons
   // normwise relative difference over live slots
   double num = 0.0, den = 0.0;
   const int64_t NT = s->L.n_total;
-  int64_t off = 0;
   for (int c = 0; c < s->C; ++c) {
+    const int64_t off = s->off[c];
     for (int64_t i = 0; i < s->n_host[c]; ++i)
       for (int k = 0; k < 3; ++k) {
         const double d = a[k * NT + off + i] - b[k * NT + off + i];
         num += d * d;
         den += b[k * NT + off + i] * b[k * NT + off + i];
       }
-    off += s->cl[c].capacity;
   }
   return den > 0.0 ? std::sqrt(num / den) : std::sqrt(num);
 }

@@ -794,9 +794,9 @@ __global__ __launch_bounds__(64 * kFoldWaves) void k_fold_n3(DevState s, RunCons
   double e0 = 0.0, e1 = 0.0, e2 = 0.0;
   bool live = false;
   if (g < rc.n_total) {
-    const int c = s.cid[g];
+    const int c = wave_cluster(s, (int64_t)blockIdx.x * 64);
     live = s.dyn[c].active && g - s.cp[c].off < s.dyn[c].n_sched;
-    if (live) n3_row_partial<Tr>(s, rc, B, g, w, kFoldWaves, e0, e1, e2);
+    if (live) n3_row_partial<Tr>(s, rc, B, g, c, w, kFoldWaves, e0, e1, e2);
   }
   if (w > 0) {
     red[w - 1][0][lane] = e0;

@@ -1,7 +1,9 @@
 // lc_internal.h -- device-side layout shared by the kernels and the host runtime of liblcmd.
 //
 // Every array lives in one caller-owned device allocation.  Particles of all clusters are
-// concatenated: cluster c owns global slots [off_c, off_c + cap_c); inside a cluster, ions
+// concatenated: cluster c owns global slots [off_c, off_c + cap_c), off_c a multiple of 64 (a
+// cluster's share is its capacity rounded up to 64, so every 64-slot group, the slots of one
+// wave, belongs to a single cluster); inside a cluster, ions
 // occupy local slots [0, n_ion) and electrons follow (initial ones, then spawned ones in
 // ascending parent order).  Per-particle arrays are structure-of-arrays FP64 except the
 // packed source records the Coulomb kernel reads (float4 or double4 {x, y, z, q}).
@@ -14,6 +16,7 @@
 namespace lc {
 
 constexpr int kBlock = 256;          // threads per block of the particle-parallel kernels
+constexpr int kGroup = 64;           // slots per group: clusters start on group boundaries
 constexpr int kDiagQ = 48;           // doubles per per-block diagnostic partial
 constexpr int kDiagBlocks = 64;      // blocks per cluster in the diagnostic reduction
 constexpr int kHist = 17;            // charge histogram bins 0..16
@@ -133,7 +136,7 @@ struct DevState {
   float4* pos4;         // FP32 source records (LC_FP32_*)
   double4* posq;        // FP64 source records (LC_FP64)
   int8_t* Z;
-  int32_t* cid;         // cluster of each slot
+  int32_t* gcl;         // cluster of each 64-slot group
   double* part;         // field partials [split][comp][slot]
   void* n3part;         // pair-once partial rows (float or double: the pair type), per cluster from cp.n3_off
   int32_t* flag;        // ionization flags [slot of ion]
@@ -173,10 +176,25 @@ struct FieldLayout {
 };
 
 
+// Cluster of global slot g (one table entry per 64-slot group).
+__device__ inline int slot_cluster(const DevState& s, int64_t g) { return s.gcl[g / kGroup]; }
+
+// Cluster of the wave whose 64 slots start at group boundary g0 (wave-uniform: the index goes
+// through readfirstlane, so the table and the cluster's parameters are read by scalar loads).
+__device__ inline int wave_cluster(const DevState& s, int64_t g0) {
+  return s.gcl[__builtin_amdgcn_readfirstlane((int)(g0 / kGroup))];
+}
+
 // Coulomb field of global slot g from the partials of the last field pass, summed over the
 // splits in split order (FP64).
 __device__ inline void field_sum(const DevState& s, const RunConst& rc, const FieldLayout& fl, int64_t g,
                                  double& ex, double& ey, double& ez) {
+  if (fl.S == 1) {  // one split (every pair-once step): plain loads, no loop
+    ex = s.part[g];
+    ey = s.part[rc.n_total + g];
+    ez = s.part[2 * rc.n_total + g];
+    return;
+  }
   ex = 0.0; ey = 0.0; ez = 0.0;
   for (int k = 0; k < fl.S; ++k) {
     const double* b = s.part + (int64_t)k * kComp * rc.n_total + g;
@@ -205,10 +223,9 @@ inline int fold_waves(const RunConst& rc, int B) {
 }
 
 template <typename Tr>
-__device__ inline void n3_row_partial(const DevState& s, const RunConst& rc, int B, int64_t g, int w, int ways,
-                                      double& e0, double& e1, double& e2) {
+__device__ inline void n3_row_partial(const DevState& s, const RunConst& rc, int B, int64_t g, int c, int w,
+                                      int ways, double& e0, double& e1, double& e2) {
   e0 = 0.0; e1 = 0.0; e2 = 0.0;
-  const int c = s.cid[g];
   const ClusterParams& cp = s.cp[c];
   const ClusterDyn& d = s.dyn[c];
   const int64_t l = g - cp.off;

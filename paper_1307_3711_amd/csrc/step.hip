@@ -5,6 +5,8 @@
 // All of these are HBM- or latency-bound; they are plain 1-thread-per-particle kernels with
 // coalesced FP64 structure-of-arrays access.  Reductions (diagnostics, spawn offsets) are
 // done in a fixed order so every run is bitwise reproducible.
+#include <algorithm>
+
 #include "lc_internal.h"
 
 namespace lc {
@@ -221,8 +223,15 @@ __device__ inline PState load_pstate(const DevState& s, const RunConst& rc, int6
   p.ux = s.ux[g]; p.uy = s.uy[g]; p.uz = s.uz[g];
   p.wl = s.wl[g]; p.wc = s.wc[g];
   p.zc = s.Z[g];
-  p.seen = rc.det_on ? s.det_seen[g] : 1;
+  p.seen = 1;  // the detector flag is loaded after the field (load_seen)
   return p;
+}
+
+// The detector flag of slot g, loaded after the particle state and the field: its test comes
+// first in the push, and loads complete in order, so loading it last keeps every load of the
+// push in flight at once.
+__device__ inline void load_seen(const DevState& s, const RunConst& rc, int64_t g, PState& p) {
+  if (rc.det_on) p.seen = s.det_seen[g];
 }
 
 // Ion detectors (Sec. III anisotropy study): an ion is counted once, when a push first takes it
@@ -312,41 +321,52 @@ __device__ inline void push_one(const DevState& s, const RunConst& rc, int64_t g
   if (!p.seen && zc > 0) detect_ion(s, rc, cp, c, g, x, y, z, M, unx, uny, unz);  // only ion slots hold Z > 0
 }
 
+// One wave per 64-slot group: the group's cluster comes from the group table through scalar
+// loads (its parameters and counters too), a retired cluster or a group past the live count
+// leaves the whole wave at once, and the particle loads follow without a per-lane lookup.
+// 5 waves per SIMD (at most 96 VGPRs) keep more loads in flight than the 4 the unconstrained
+// allocation (98 VGPRs) allows.
 template <int PREC>
-__global__ __launch_bounds__(kBlock) void k_push(DevState s, RunConst rc, FieldLayout fl, int64_t k, int diag) {
-  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (g >= rc.n_total) return;
-  const int c = s.cid[g];
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5)))
+void k_push(DevState s, RunConst rc, FieldLayout fl, int64_t k, int diag) {
+  const int64_t g0 = (int64_t)blockIdx.x * kBlock + kGroup * __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (g0 >= rc.n_total) return;
+  const int c = wave_cluster(s, g0);
   const ClusterDyn& d = s.dyn[c];
-  if (!d.active) return;
-  if (g - s.cp[c].off >= d.n_cur) return;
+  const int64_t l = g0 - s.cp[c].off + (threadIdx.x & 63);
+  if (!d.active || l >= d.n_cur) return;
+  const int64_t g = g0 + (threadIdx.x & 63);
+  // the particle state is loaded first so that its loads and those of the field are in flight
+  // together (one memory round trip instead of two)
+  PState ps = load_pstate(s, rc, g);
   double ecx, ecy, ecz;
   field_sum(s, rc, fl, g, ecx, ecy, ecz);
-  push_one<PREC>(s, rc, g, c, *s.step + k, diag, ecx, ecy, ecz, load_pstate(s, rc, g));
+  load_seen(s, rc, g, ps);
+  push_one<PREC>(s, rc, g, c, *s.step + k, diag, ecx, ecy, ecz, ps);
 }
 
-// Fold of the pair-once rows and push in one kernel: FW waves over 64 consecutive slots add
+// Fold of the pair-once rows and push in one kernel: FW waves over one 64-slot group add
 // their share of the rows, wave 0 combines them in order, keeps the field in split 0 (read by
 // the ionization check) and pushes.  Wave 0 loads the particle state before its rows so both
-// latencies overlap.
+// latencies overlap.  The group's cluster is uniform over the block (scalar loads).
 template <int PREC, int FW>
 __global__ __launch_bounds__(64 * FW) void k_fold_push(DevState s, RunConst rc, int B, int64_t k, int diag) {
   __shared__ double red[FW - 1][3][64];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t g = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t g0 = (int64_t)blockIdx.x * kGroup;
+  const int c = wave_cluster(s, g0);
+  const ClusterDyn& d = s.dyn[c];
+  const int64_t l0 = g0 - s.cp[c].off;
+  if (!d.active || l0 >= d.n_cur) return;  // the whole block: retired cluster or empty group
+  const int64_t g = g0 + lane;
+  const bool live = l0 + lane < d.n_cur;
   double e0 = 0.0, e1 = 0.0, e2 = 0.0;
-  bool live = false;
-  int c = 0;
   PState ps;
-  if (g < rc.n_total) {
-    c = s.cid[g];
-    live = s.dyn[c].active && g - s.cp[c].off < s.dyn[c].n_cur;
-    if (live) {
-      if (w == 0) ps = load_pstate(s, rc, g);
-      if (PREC == LC_FP64) n3_row_partial<double>(s, rc, B, g, w, FW, e0, e1, e2);
-      else n3_row_partial<float>(s, rc, B, g, w, FW, e0, e1, e2);
-    }
+  if (live) {
+    if (w == 0) ps = load_pstate(s, rc, g);
+    if (PREC == LC_FP64) n3_row_partial<double>(s, rc, B, g, c, w, FW, e0, e1, e2);
+    else n3_row_partial<float>(s, rc, B, g, c, w, FW, e0, e1, e2);
   }
   if (w > 0) {
     red[w - 1][0][lane] = e0;
@@ -363,6 +383,7 @@ __global__ __launch_bounds__(64 * FW) void k_fold_push(DevState s, RunConst rc, 
     s.part[g] = e0;
     s.part[rc.n_total + g] = e1;
     s.part[2 * rc.n_total + g] = e2;
+    load_seen(s, rc, g, ps);
     push_one<PREC>(s, rc, g, c, *s.step + k, diag, e0, e1, e2, ps);
   }
 }
@@ -373,7 +394,7 @@ __global__ __launch_bounds__(64 * FW) void k_fold_push(DevState s, RunConst rc, 
 __global__ __launch_bounds__(kBlock) void k_start_kick(DevState s, RunConst rc, FieldLayout fl) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (g >= rc.n_total) return;
-  const int c = s.cid[g];
+  const int c = slot_cluster(s, g);
   const ClusterParams& cp = s.cp[c];
   const ClusterDyn& d = s.dyn[c];
   if (g - cp.off >= d.n_cur) return;
@@ -694,40 +715,39 @@ __global__ __launch_bounds__(kBlock) void k_ionize_check(DevState s, RunConst rc
   if (threadIdx.x == 0) s.ib_count[ibk] = cnt;
 }
 
-// Exclusive prefix sum of the per-block flag counts over every ion block, in block order (one
-// workgroup, 1024 blocks per pass with a carry; wave scans by lane shuffles, then across the 16
-// waves).  A cluster's ion blocks are contiguous, so the rank base of its block b is
-// ib_off[ion_block0 + b] - ib_off[ion_block0].
+// Exclusive prefix sum of the per-block flag counts over every ion block, in block order, in one
+// workgroup and one pass: thread t takes the run of `per` consecutive blocks starting at t per,
+// the run totals are scanned across the workgroup (lane shuffles within each wave, then across
+// the 16 waves), and each thread writes its run's offsets.  A cluster's ion blocks are
+// contiguous, so the rank base of its block b is ib_off[ion_block0 + b] - ib_off[ion_block0].
 __global__ __launch_bounds__(1024) void k_ionize_scan(DevState s, int n_blocks) {
   __shared__ int32_t sh_w[16];
-  __shared__ int32_t sh_carry;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  if (tid == 0) sh_carry = 0;
+  const int per = (n_blocks + 1023) / 1024;
+  const int i0 = tid * per;
+  const int i1 = (i0 + per < n_blocks) ? i0 + per : n_blocks;
+  int32_t run = 0;
+  for (int i = i0; i < i1; ++i) run += s.ib_count[i];
+  int32_t x = run;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh_w[w] = x;
   __syncthreads();
-  for (int base = 0; base < n_blocks; base += 1024) {
-    const int i = base + tid;
-    const int32_t v = (i < n_blocks) ? s.ib_count[i] : 0;
-    int32_t x = v;
-    for (int o = 1; o < 64; o <<= 1) {
-      const int32_t y = __shfl_up(x, o, 64);
-      if (lane >= o) x += y;
+  if (w == 0) {
+    int32_t t = (lane < 16) ? sh_w[lane] : 0;
+    for (int o = 1; o < 16; o <<= 1) {
+      const int32_t y = __shfl_up(t, o, 64);
+      if (lane >= o) t += y;
     }
-    if (lane == 63) sh_w[w] = x;
-    __syncthreads();
-    if (w == 0) {
-      int32_t t = (lane < 16) ? sh_w[lane] : 0;
-      for (int o = 1; o < 16; o <<= 1) {
-        const int32_t y = __shfl_up(t, o, 64);
-        if (lane >= o) t += y;
-      }
-      if (lane < 16) sh_w[lane] = t;
-    }
-    __syncthreads();
-    const int32_t carry = sh_carry;
-    if (i < n_blocks) s.ib_off[i] = carry + (w > 0 ? sh_w[w - 1] : 0) + x - v;
-    __syncthreads();
-    if (tid == 0) sh_carry = carry + sh_w[15];
-    __syncthreads();
+    if (lane < 16) sh_w[lane] = t;
+  }
+  __syncthreads();
+  int32_t off = (w > 0 ? sh_w[w - 1] : 0) + x - run;
+  for (int i = i0; i < i1; ++i) {
+    s.ib_off[i] = off;
+    off += s.ib_count[i];
   }
 }
 
@@ -859,7 +879,7 @@ template <int PREC>
 __global__ __launch_bounds__(kBlock) void k_refresh_sources(DevState s, RunConst rc, int grid) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (g >= rc.n_total) return;
-  const int c = s.cid[g];
+  const int c = slot_cluster(s, g);
   const ClusterParams& cp = s.cp[c];
   if (g - cp.off >= s.dyn[c].n_cur) return;
   write_source(s, PREC, grid != 0, cp.box, g, s.x[g], s.y[g], s.z[g], cp.kw * (double)s.Z[g]);

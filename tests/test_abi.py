@@ -68,9 +68,12 @@ def test_state_bytes_scales_with_capacity():
     c2 = _binding.ClusterDesc.from_buffer_copy(_desc(c))
     c2.capacity = 2 * c.capacity
     b2 = _bytes(cfg, [c2])
-    # per-slot bytes: 10 FP64 arrays + double4 source + Z + cid + 8 splits x 4 FP64 partials + flag
-    per_slot = 10 * 8 + 32 + 1 + 4 + 8 * 4 * 8 + 4
-    assert abs((b2 - b1) - per_slot * c.capacity) <= 64 * 256
+    # per-slot bytes: 10 FP64 arrays + double4 source + Z + detector flag + 8 splits x 4 FP64
+    # partials + ionization flag, over a share of the capacity rounded up to 64 slots (plus a
+    # 4-byte cluster index per 64 slots)
+    per_slot = 10 * 8 + 32 + 1 + 1 + 8 * 4 * 8 + 4
+    share = lambda cap: -(-cap // 64) * 64
+    assert abs((b2 - b1) - per_slot * (share(2 * c.capacity) - share(c.capacity))) <= 64 * 256
     cfg32 = lc.make_config("fp32_acc64", max_splits=8)
     assert _bytes(cfg32, [_desc(c)]) < b1  # float4 sources instead of double4
     for mk in (ar_20k, xe_200k):
