@@ -137,7 +137,7 @@ def cpu_baseline(c, run, st, n, target_s=10.0):
     k, dt, x = _oracle_steps(c, run, st, target_s=target_s)
     out = {"value": k * n * n / dt / 1e9, "unit": "Gpair/s", "cores": oracle.threads(), "kind": "oracle",
            "sample": f"{k} steps of the same 20k-macroparticle state after 1 calibration step "
-                     f"(FP64, gcc -O2, {dt:.1f} s)"}
+                     f"(FP64, gcc -O2, {dt:.1f} s)", "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
     try:
         with tempfile.TemporaryDirectory() as d:
             with oracle.library(oracle.build_native(os.path.join(d, "liblc_oracle_native.so"))):
@@ -147,6 +147,17 @@ def cpu_baseline(c, run, st, n, target_s=10.0):
     except (OSError, subprocess.CalledProcessError) as e:
         out["native"] = {"value": None, "error": str(e)[:200]}
     return out
+
+
+def cpu_model():
+    """The host CPU's model name (/proc/cpuinfo), for the CPU-baseline record."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def ensemble_inputs(n_clusters, seed, steps_scale=1.0):
@@ -722,7 +733,7 @@ def main():
     ap.add_argument("--clusters", type=int, default=256)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--profile-steps", type=int, default=400)
     ap.add_argument("--graph", type=int, default=100)
@@ -790,33 +801,42 @@ def main():
     n = st["x_nm"].shape[0]
     pairs = float(n) * float(n)
 
+    # The timed window holds whole diagnostic periods (one record every diag_every steps, each
+    # step of a period replayed from one captured graph), starting on a period boundary: steps and
+    # warmup are rounded up to multiples of the period, so the work the workload prescribes,
+    # diagnostic passes included, is inside the window whatever counts are asked for.
+    period = max(run.diag_every, 1)
+    warmup = -(-args.warmup // period) * period
+    steps = -(-args.steps // period) * period
     log(f"bench: {n} macroparticles, fp32_acc64, autotune")
     sim, tuned = make_sim("fp32_acc64", c, run, st, args.graph, tiling, args.boundary)
-    log(f"bench: tiling {tuned}; warmup {args.warmup}")
-    sim.step(args.warmup)
+    log(f"bench: tiling {tuned}; warmup {warmup}")
+    sim.step(warmup)
     sim.stream.synchronize()
-    log(f"bench: timing {args.steps} steps")
-    wall = timed_steps(sim, args.steps)
+    log(f"bench: timing {steps} steps")
+    wall = timed_steps(sim, steps)
     log(f"bench: {wall:.3f} s; profiling {args.profile_steps} steps")
     prof = sim.profile_steps(args.profile_steps)
     rec32 = sim.diagnostics(0)
     force_ms, force_n = prof["field"]
     avg_force_s = force_ms / max(force_n, 1) * 1e-3
     achieved = FLOPS_PER_PAIR * pairs / avg_force_s / 1e12
-    value = args.steps * pairs / wall / 1e9
+    value = steps * pairs / wall / 1e9
     crec = counter_record(tuned, n, "fp32_acc64", args.boundary)
     evals = pair_evaluations(n, tuned)
     kname = "k_force_n3" if tuned.get("newton3") else "k_force_f32"
     out = {
         "metric": "G pair-interactions/s (FP32 pair math + FP64 accumulation), one Ar cluster",
-        "value": round(value, 3), "unit": "Gpair/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(wall / args.steps * 1e3, 5), "higher_is_better": True, "scaling": "weak",
+        "value": round(value, 3), "unit": "Gpair/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "steps_requested": args.steps, "warmup_requested": args.warmup,
+        "ms_per_step": round(wall / steps * 1e3, 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "fp32+fp64acc", "data": "synthetic",
         "config": {"workload": "Ar cluster R0=8nm, 20k macroparticles (10k Ar+ + 10k e-), 1e16 W/cm2, "
                                "30 fs Gaussian, dt=0.05, softening 0.1 nm, charges frozen"
                                + ("" if args.boundary == "open" else f", {args.boundary} boundaries (cube of 20 R0)"),
-                   "n_particles": n, "pairs_per_step": pairs, "tiling": tuned, "graph_steps": args.graph},
-        "cluster_steps_per_s": round(args.steps / wall, 2),
+                   "n_particles": n, "pairs_per_step": pairs, "tiling": tuned, "graph_steps": args.graph,
+                   "diagnostic_every": period},
+        "cluster_steps_per_s": round(steps / wall, 2),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                      "traffic": crec["traffic_bytes_per_launch"] if crec else None,
@@ -827,12 +847,12 @@ def main():
                                                / VALU_ISSUE_PER_S, 4) if crec else None)},
         "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 5) for k, v in prof.items() if v[1]},
     }
-    total_steps = args.warmup + args.steps + args.profile_steps
+    total_steps = warmup + steps + args.profile_steps
     if not args.no_fp64:
         log("bench: fp64 path on the same steps")
         sim64, tuned64 = make_sim("fp64", c, run, st, args.graph, tiling64, args.boundary)
-        sim64.step(args.warmup)
-        wall64 = timed_steps(sim64, args.steps)
+        sim64.step(warmup)
+        wall64 = timed_steps(sim64, steps)
         prof64 = sim64.profile_steps(args.profile_steps)
         rec64 = sim64.diagnostics(0)
         f64_ms, f64_n = prof64["field"]
@@ -847,8 +867,8 @@ def main():
         def rel(col):
             return float(abs(last32[col] - last64[col]) / max(abs(last64[col]), 1e-300))
 
-        out["fp64"] = {"value": round(args.steps * pairs / wall64 / 1e9, 3), "unit": "Gpair/s",
-                       "ms_per_step": round(wall64 / args.steps * 1e3, 5), "tiling": tuned64,
+        out["fp64"] = {"value": round(steps * pairs / wall64 / 1e9, 3), "unit": "Gpair/s",
+                       "ms_per_step": round(wall64 / steps * 1e3, 5), "tiling": tuned64,
                        "roofline": {"bound": "alu", "achieved": round(ach64, 3), "peak": FP64_PEAK_TFLOPS,
                                     "unit": "TFLOP/s", "frac": round(ach64 / FP64_PEAK_TFLOPS, 4),
                                     "traffic": crec64["traffic_bytes_per_launch"] if crec64 else None,
@@ -862,10 +882,43 @@ def main():
                                 "max_dx_over_R0": float(np.max(np.abs(p32["x"] - p64["x"])) / r0n),
                                 "rel_KE": rel(lc.R_KE_HALF), "rel_PE": rel(lc.R_PE),
                                 "rel_absorbed_eV_per_atom": rel(lc.R_ABS_EV)}
+        # both runs to the workload's end (4000 steps), record by record against the FP64
+        # oracle's records of the same run (tests/golden, written from the oracle alone)
+        if c.n_steps >= total_steps and args.boundary == "open":
+            log("bench: runs to the end, against the oracle's records")
+            out["error_vs_fp64_oracle"] = {
+                "fp32_acc64": oracle_record_errors(sim, c.n_steps - total_steps),
+                "fp64": oracle_record_errors(sim64, c.n_steps - total_steps)}
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(c, run, st, n)
     print(json.dumps(out), flush=True)
+
+
+def oracle_record_errors(sim, more_steps):
+    """Step a 20k argon run to the workload's end and compare its diagnostic records with the
+    FP64 oracle's (tests/golden/ar20k_oracle_records.json): the largest difference of KE, PE,
+    laser and Coulomb work over the run, relative to the energy scale |KE|+|PE|+|W_L|+|W_C| of
+    each record, and the absorbed energy per atom at the end, relative."""
+    import numpy as np
+    with open(os.path.join(ROOT, "tests", "golden", "ar20k_oracle_records.json")) as f:
+        gold = json.load(f)
+    cols = gold["columns"]
+    g = np.array(gold["records"])
+    sim.step(more_steps)
+    r = sim.diagnostics(0)
+    steps = list(r[:, 1])
+    idx = [steps.index(s) for s in g[:, cols.index("step")]]
+    r = r[idx]
+    col = lambda name: g[:, cols.index(name)]
+    scale = np.abs(col("KE_half")) + np.abs(col("PE")) + np.abs(col("W_laser")) + np.abs(col("W_coulomb"))
+    out = {"records": len(idx), "last_step": int(r[-1, 1])}
+    for name, c in (("KE", 5), ("PE", 7), ("W_laser", 8), ("W_coulomb", 9)):
+        key = {"KE": "KE_half"}.get(name, name)
+        out["max_rel_" + name] = float(np.max(np.abs(r[:, c] - col(key)) / scale))
+    a_g, a_o = float(r[-1, 19]), float(col("absorbed_eV_per_atom")[-1])
+    out["absorbed_eV_per_atom"] = {"gpu": a_g, "oracle": a_o, "rel": abs(a_g - a_o) / abs(a_o)}
+    return out
 
 
 if __name__ == "__main__":
