@@ -113,6 +113,7 @@ struct RunConst {
   double cap_slot_mean; // sum of capacity^2 over sum of capacity: the capacity of a typical slot's cluster
   double det_cos2;      // cos^2 of the detectors' acceptance half-angle
   double t_switch;      // LC_MIXED: first time (1/w) with open boundaries
+  int32_t max_ion_blocks;  // ion blocks (256 ions) of the largest cluster
 };
 
 // Periodic boundaries in force at time t (the step's t^n): always for LC_PERIODIC, before

@@ -716,46 +716,65 @@ __global__ __launch_bounds__(kBlock) void k_ionize_check(DevState s, RunConst rc
 }
 
 // Exclusive prefix sum of the per-block flag counts over every ion block, in block order, in one
-// workgroup and one pass: thread t takes the run of `per` consecutive blocks starting at t per,
-// the run totals are scanned across the workgroup (lane shuffles within each wave, then across
-// the 16 waves), and each thread writes its run's offsets.  A cluster's ion blocks are
-// contiguous, so the rank base of its block b is ib_off[ion_block0 + b] - ib_off[ion_block0].
+// workgroup: each pass covers 1024 x 16 blocks, thread t the run of 16 consecutive blocks at
+// 16 t (its loads issued together), the run totals are scanned across the workgroup (lane
+// shuffles within each wave, then across the 16 waves) with the carry of earlier passes, and
+// each thread writes its run's offsets.  A cluster's ion blocks are contiguous, so the rank base
+// of its block b is ib_off[ion_block0 + b] - ib_off[ion_block0].
+constexpr int kScanRun = 16;
 __global__ __launch_bounds__(1024) void k_ionize_scan(DevState s, int n_blocks) {
   __shared__ int32_t sh_w[16];
+  __shared__ int32_t sh_carry;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int per = (n_blocks + 1023) / 1024;
-  const int i0 = tid * per;
-  const int i1 = (i0 + per < n_blocks) ? i0 + per : n_blocks;
-  int32_t run = 0;
-  for (int i = i0; i < i1; ++i) run += s.ib_count[i];
-  int32_t x = run;
-  for (int o = 1; o < 64; o <<= 1) {
-    const int32_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) sh_w[w] = x;
-  __syncthreads();
-  if (w == 0) {
-    int32_t t = (lane < 16) ? sh_w[lane] : 0;
-    for (int o = 1; o < 16; o <<= 1) {
-      const int32_t y = __shfl_up(t, o, 64);
-      if (lane >= o) t += y;
+  if (tid == 0) sh_carry = 0;
+  for (int base = 0; base < n_blocks; base += 1024 * kScanRun) {
+    const int i0 = base + tid * kScanRun;
+    int32_t v[kScanRun];
+#pragma unroll
+    for (int k = 0; k < kScanRun; ++k) v[k] = (i0 + k < n_blocks) ? s.ib_count[i0 + k] : 0;
+    int32_t run = 0;
+#pragma unroll
+    for (int k = 0; k < kScanRun; ++k) run += v[k];
+    int32_t x = run;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
     }
-    if (lane < 16) sh_w[lane] = t;
-  }
-  __syncthreads();
-  int32_t off = (w > 0 ? sh_w[w - 1] : 0) + x - run;
-  for (int i = i0; i < i1; ++i) {
-    s.ib_off[i] = off;
-    off += s.ib_count[i];
+    __syncthreads();  // the previous pass's readers of sh_w and sh_carry are done
+    if (lane == 63) sh_w[w] = x;
+    __syncthreads();
+    if (w == 0) {
+      int32_t t = (lane < 16) ? sh_w[lane] : 0;
+      for (int o = 1; o < 16; o <<= 1) {
+        const int32_t y = __shfl_up(t, o, 64);
+        if (lane >= o) t += y;
+      }
+      if (lane < 16) sh_w[lane] = t;
+    }
+    __syncthreads();
+    const int32_t carry = sh_carry;
+    int32_t off = carry + (w > 0 ? sh_w[w - 1] : 0) + x - run;
+#pragma unroll
+    for (int k = 0; k < kScanRun; ++k) {
+      if (i0 + k < n_blocks) s.ib_off[i0 + k] = off;
+      off += v[k];
+    }
+    __syncthreads();
+    if (tid == 0) sh_carry = carry + sh_w[15];
   }
 }
 
 // Spawn one electron per flagged ion at slot n_base + (rank of the ion among this step's
 // flagged ions, ascending ion index), next to the ion's new position with its momentum.
+// The rank base of a block (flags of the cluster's earlier blocks) comes from the scan kernel
+// when some cluster has more than kSpawnDirect ion blocks; otherwise every block adds up the
+// counts of its cluster's earlier blocks itself, in parallel (integer sums: exact in any order),
+// which saves the scan's launch and its latency.
+constexpr int kSpawnDirect = 1024;
 template <int PREC>
-__global__ __launch_bounds__(kBlock) void k_ionize_spawn(DevState s, RunConst rc, int64_t k) {
+__global__ __launch_bounds__(kBlock) void k_ionize_spawn(DevState s, RunConst rc, int64_t k, int scanned) {
   __shared__ int32_t sh_wave[4];
+  __shared__ int32_t sh_pre[4];
   const int ibk = blockIdx.x;
   const int c = s.ib_cluster[ibk];
   const ClusterParams& cp = s.cp[c];
@@ -763,7 +782,17 @@ __global__ __launch_bounds__(kBlock) void k_ionize_spawn(DevState s, RunConst rc
   const int b = ibk - cp.ion_block0;
   const int64_t li = (int64_t)b * kBlock + threadIdx.x;
   if (!d.active) return;
-  const int64_t base = (int64_t)s.ib_off[ibk] - (int64_t)s.ib_off[cp.ion_block0];
+  int64_t base;
+  if (scanned) {
+    base = (int64_t)s.ib_off[ibk] - (int64_t)s.ib_off[cp.ion_block0];
+  } else {
+    int32_t pre = 0;
+    for (int q = threadIdx.x; q < b; q += kBlock) pre += s.ib_count[cp.ion_block0 + q];
+    for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o, 64);
+    if ((threadIdx.x & 63) == 0) sh_pre[threadIdx.x >> 6] = pre;
+    __syncthreads();
+    base = (int64_t)sh_pre[0] + sh_pre[1] + sh_pre[2] + sh_pre[3];
+  }
   const int flag = (li < cp.n_ion) ? s.flag[cp.off + li] : 0;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint64_t ball = __ballot(flag);
@@ -944,13 +973,13 @@ hipError_t launch_ionize(const DevState& s, const RunConst& rc, int precision, c
   }
   if (precision == LC_FP64) {
     k_ionize_check<LC_FP64><<<n_ion_blocks, kBlock, 0, st>>>(s, rc, fl, k);
-    k_ionize_scan<<<1, 1024, 0, st>>>(s, n_ion_blocks);
-    k_ionize_spawn<LC_FP64><<<n_ion_blocks, kBlock, 0, st>>>(s, rc, k);
   } else {
     k_ionize_check<LC_FP32_ACC64><<<n_ion_blocks, kBlock, 0, st>>>(s, rc, fl, k);
-    k_ionize_scan<<<1, 1024, 0, st>>>(s, n_ion_blocks);
-    k_ionize_spawn<LC_FP32_ACC64><<<n_ion_blocks, kBlock, 0, st>>>(s, rc, k);
   }
+  const int scanned = rc.max_ion_blocks > kSpawnDirect ? 1 : 0;
+  if (scanned) k_ionize_scan<<<1, 1024, 0, st>>>(s, n_ion_blocks);
+  if (precision == LC_FP64) k_ionize_spawn<LC_FP64><<<n_ion_blocks, kBlock, 0, st>>>(s, rc, k, scanned);
+  else k_ionize_spawn<LC_FP32_ACC64><<<n_ion_blocks, kBlock, 0, st>>>(s, rc, k, scanned);
   return hipGetLastError();
 }
 
