@@ -160,12 +160,12 @@ def cpu_model():
     return None
 
 
-def ensemble_inputs(n_clusters, seed, steps_scale=1.0):
+def ensemble_inputs(n_clusters, seed, steps_scale=1.0, capacity_rule="random"):
     """Descriptions and initial states of one seeded ensemble of uneven Ar/Xe clusters."""
     import paper_1307_3711_amd as lc
     from workloads import ensemble, initial_state
     from workloads.species import SPECIES
-    cl = ensemble(n_clusters, seed=seed)
+    cl = ensemble(n_clusters, seed=seed, capacity_rule=capacity_rule)
     descs, states = [], []
     for i, c in enumerate(cl):
         d = lc.make_cluster(SPECIES[c.species], c.r0_nm, c.n_ion, c.capacity, c.laser.intensity_wcm2,
@@ -571,18 +571,24 @@ def bench_lumping(args):
     r0 = SPECIES["D"]["rw_angstrom"] * 8007 ** (1.0 / 3.0) / 10.0
     laser = Laser(lambda_um=lam, intensity_wcm2=5e16, envelope="gauss_field", fwhm_fs=25.0)
     counts = [40, 60, 80, 120, 160, 200, 300, 400, 500]
-    copies = 4
+    copies = args.copies
     t_end_fs = 300.0
+    dt, soft = args.dt, args.softening
     w_fs = 2.0 * math.pi * 299792458.0 / (lam * 1e-6) * 1e-15
-    steps = args.steps if args.steps_given else int(math.ceil(t_end_fs * w_fs / 0.05))
+    steps = args.steps if args.steps_given else int(math.ceil(t_end_fs * w_fs / dt))
     cl = [Cluster(species="D", r0_nm=r0, n_ion=n, capacity=2 * n, z_init=1, z_max=1, laser=laser, n_steps=steps)
           for n in counts for _ in range(copies)]
     descs = [lc.make_cluster(SPECIES["D"], c.r0_nm, c.n_ion, c.capacity, laser.intensity_wcm2, envelope=laser.envelope,
                              fwhm_fs=laser.fwhm_fs, z_max=1, n_steps=steps) for c in cl]
     states = [initial_state(c, args.seed, i) for i, c in enumerate(cl)]
     log(f"lumping: D_8007 (R0 = {r0:.3f} nm) at {counts} ion macroparticles x {copies} placements, {steps} steps")
-    out = run_ensemble(descs, states, "fp64", lambda_um=lam, seed=args.seed, diag_every=1000, autotune=False,
-                       keep_particles=True)
+    out = run_ensemble(descs, states, "fp64", dt=dt, softening_nm=soft, lambda_um=lam, seed=args.seed,
+                       diag_every=1000, autotune=False, keep_particles=True)
+    # angular frequency of an electron bound at rest inside the softening core of its ion of
+    # charge w (w real deuterons per macro-ion): omega_b = (kappa w / eps^3)^(1/2) in units of the
+    # laser frequency; the leap-frog is stable for omega_b dt < 2
+    u = lc.units(lam)
+    eps = soft * u["k_per_nm"]
     mass = SPECIES["D"]["mass_u"] * 931494102.42  # eV
     rows = []
     for k, n in enumerate(counts):
@@ -594,6 +600,7 @@ def bench_lumping(args):
             means.append(ke.mean() / 1e3)
             ratios.append(ke.mean() / ke.max())
         rows.append({"n_macro_ions": n, "n_atoms_per_macro": round(8007 / n, 2),
+                     "omega_bound_dt": round(math.sqrt(u["kappa"] * (8007 / n) / eps ** 3) * dt, 3),
                      "mean_keV": round(float(np.mean(means)), 4), "mean_keV_std": round(float(np.std(means)), 4),
                      "mean_over_max": round(float(np.mean(ratios)), 4)})
     m = np.array([r["mean_keV"] for r in rows])
@@ -602,7 +609,8 @@ def bench_lumping(args):
            "ms_per_step": round(out["wall_s"] / steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"D_8007 (R0 {r0:.3f} nm), 857 nm, 5e16 W/cm2, 25 fs Gaussian, {t_end_fs:.0f} fs, "
-                                  f"lumped into {counts[0]}..{counts[-1]} ion macroparticles, {copies} placements each"},
+                                  f"lumped into {counts[0]}..{counts[-1]} ion macroparticles, {copies} placements each",
+                      "dt": dt, "softening_nm": soft},
            "lumpings": rows,
            "mean_energy_spread": round(float((m.max() - m.min()) / m.mean()), 4),
            "mean_energy_40_vs_500": round(float(abs(rows[0]["mean_keV"] - rows[-1]["mean_keV"]) / rows[-1]["mean_keV"]), 4),
@@ -634,8 +642,12 @@ def bench_surrogate(args):
 
     Xl, Yl = [], []
     md_wall = md_runs = md_cs = 0
-    for b in range(args.batches):
-        cl, descs, states = ensemble_inputs(256, b)
+    if args.load_data:  # an earlier run's MD training set (and its MD rate), to try training settings
+        d = np.load(args.load_data)
+        Xl, Yl = [d["X"]], [d["Y"]]
+        md_wall, md_runs, md_cs = float(d["md_wall"]), int(d["md_runs"]), float(d["md_cs"])
+    for b in range(0 if args.load_data else args.batches):
+        cl, descs, states = ensemble_inputs(256, b, capacity_rule=args.lumping)
         r = run_ensemble(descs, states, "fp32_acc64", seed=b, progress=lambda d, t: log(f"  batch {b}: {d}/{t}"))
         md_wall += r["wall_s"]
         md_runs += len(cl)
@@ -646,7 +658,7 @@ def bench_surrogate(args):
     X = np.concatenate(Xl)
     Y = np.concatenate(Yl)
     if args.save_data:
-        np.savez(args.save_data, X=X, Y=Y)
+        np.savez(args.save_data, X=X, Y=Y, md_wall=md_wall, md_runs=md_runs, md_cs=md_cs)
     n = X.shape[0]
     perm = np.random.Generator(np.random.Philox(key=[0, 77])).permutation(n)
     n_tr = int(0.9 * n)
@@ -683,7 +695,7 @@ def bench_surrogate(args):
     inf_s = (time.perf_counter() - t0) / reps
 
     # held-out clusters (ensemble seed 200) re-run by the MD with 4 seeds
-    cl, descs, _ = ensemble_inputs(64, 200)
+    cl, descs, _ = ensemble_inputs(64, 200, capacity_rule=args.lumping)
     ph = net.infer(torch.from_numpy(_features_of(cl)).cuda()).cpu().numpy()
     md = []
     for sd in (200, 201, 202, 203):
@@ -691,6 +703,25 @@ def bench_surrogate(args):
         r = run_ensemble(descs, states, "fp32_acc64", seed=sd)
         md.append(targets(r["last"]))
     md = np.array(md)
+    # the same held-out clusters lumped differently: capacities (hence ion macroparticle counts)
+    # drawn again log-uniformly, physics unchanged; their spread is what the lumping alone does to
+    # the MD's outcome, which the network's inputs cannot tell apart
+    lump = []
+    if args.lumping == "random":
+        from dataclasses import replace as dc_replace
+        for k in range(3):
+            rng = np.random.Generator(np.random.Philox(key=[300 + k, 5]))
+            cl2 = []
+            for c in cl:
+                cap = int(round(math.exp(rng.uniform(math.log(1000), math.log(16000)))))
+                n_atoms = int(math.floor((c.r0_nm * 10.0 / SPECIES[c.species]["rw_angstrom"]) ** 3))
+                cl2.append(dc_replace(c, capacity=cap, n_ion=max(1, min(cap // 9, n_atoms))))
+            d2 = [lc.make_cluster(SPECIES[c.species], c.r0_nm, c.n_ion, c.capacity, c.laser.intensity_wcm2,
+                                  envelope=c.laser.envelope, fwhm_fs=c.laser.fwhm_fs, z_max=c.z_max,
+                                  electron_offset_nm=c.electron_offset_nm, n_steps=c.n_steps) for c in cl2]
+            st2 = [initial_state(c, 200, i) for i, c in enumerate(cl2)]
+            lump.append(targets(run_ensemble(d2, st2, "fp32_acc64", seed=200)["last"]))
+    rmse_lump = (np.sqrt(np.mean((np.array(lump) - md[0][None]) ** 2, axis=(0, 1))) if lump else None)
     rmse_sur = np.sqrt(np.mean((ph - md[0]) ** 2, axis=0))
     rmse_md = np.sqrt(np.mean((md[1:] - md[0][None]) ** 2, axis=(0, 1)))
     med_sur = np.median(np.abs(ph - md[0]), axis=0)
@@ -704,25 +735,31 @@ def bench_surrogate(args):
            "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (fp32 accumulate)", "data": "synthetic",
            "config": {"workload": f"{md_runs} ensemble MD runs ({args.batches} x 256 clusters), 90/10 split, "
                                   "batch 256, Adam; 1M-point inference; 64 held-out clusters re-run by MD",
-                      "lr": args.lr},
+                      "lr": args.lr, "lumping": args.lumping},
            "md_runs_per_s": round(md_runs_per_s, 3), "md_cluster_steps_per_s": round(md_cs / md_wall, 1),
            "speedup_vs_md": round((1e6 / inf_s) / md_runs_per_s, 1), "train_s": round(train_s, 3),
            "final_train_loss": float(losses[-50:].mean().cpu()),
-           "val_rmse": {"log_absorbed_eV": float(val_rmse[0]), "mean_charge": float(val_rmse[1])},
-           "heldout_rmse_vs_md": {"log_absorbed_eV": float(rmse_sur[0]), "mean_charge": float(rmse_sur[1])},
-           "md_seed_spread_rmse": {"log_absorbed_eV": float(rmse_md[0]), "mean_charge": float(rmse_md[1])},
-           "heldout_median_abs_err": {"log_absorbed_eV": float(med_sur[0]), "mean_charge": float(med_sur[1])},
-           "md_seed_spread_median_abs": {"log_absorbed_eV": float(med_md[0]), "mean_charge": float(med_md[1])},
-           "train_mean_predictor_rmse": {"log_absorbed_eV": float(rmse_mean[0]), "mean_charge": float(rmse_mean[1])}}
+           "targets": "asinh(absorbed eV per atom), mean ion charge",
+           "val_rmse": {"asinh_absorbed_eV": float(val_rmse[0]), "mean_charge": float(val_rmse[1])},
+           "heldout_rmse_vs_md": {"asinh_absorbed_eV": float(rmse_sur[0]), "mean_charge": float(rmse_sur[1])},
+           "md_seed_spread_rmse": {"asinh_absorbed_eV": float(rmse_md[0]), "mean_charge": float(rmse_md[1])},
+           "heldout_median_abs_err": {"asinh_absorbed_eV": float(med_sur[0]), "mean_charge": float(med_sur[1])},
+           "md_seed_spread_median_abs": {"asinh_absorbed_eV": float(med_md[0]), "mean_charge": float(med_md[1])},
+           "train_mean_predictor_rmse": {"asinh_absorbed_eV": float(rmse_mean[0]), "mean_charge": float(rmse_mean[1])}}
+    if rmse_lump is not None:
+        out["md_lumping_spread_rmse"] = {"asinh_absorbed_eV": float(rmse_lump[0]), "mean_charge": float(rmse_lump[1])}
     print(json.dumps(out), flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--batches", type=int, default=16, help="surrogate: 256-cluster ensembles of training data")
-    ap.add_argument("--train-steps", type=int, default=6000)
-    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--train-steps", type=int, default=48000)
+    ap.add_argument("--lr", type=float, default=1e-2)
+    ap.add_argument("--lumping", default="radius", choices=["random", "radius"],
+                    help="surrogate: capacity (lumping) drawn at random (the ensemble recipe) or fixed by R0")
     ap.add_argument("--save-data", default="", help="surrogate: write the MD training set (npz) here")
+    ap.add_argument("--load-data", default="", help="surrogate: train on a saved MD training set instead")
     ap.add_argument("--fp64-steps", type=int, default=2000, help="xe200k: steps of the FP64 comparison run")
     ap.add_argument("--workload", default="ar20k", choices=["ar20k", "ensemble", "surrogate", "particles", "xe200k", "iedf",
                                                             "lumping",
@@ -730,6 +767,9 @@ def main():
     ap.add_argument("--sizes", default="20000,30000,40000,60000,100000",
                     help="particle counts of the scan workload")
     ap.add_argument("--reps", type=int, default=50)
+    ap.add_argument("--dt", type=float, default=0.05, help="lumping: time step (1/w)")
+    ap.add_argument("--softening", type=float, default=0.1, help="lumping: softening length (nm)")
+    ap.add_argument("--copies", type=int, default=4, help="lumping: random placements per lumping")
     ap.add_argument("--clusters", type=int, default=256)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--gpus", type=int, default=1)

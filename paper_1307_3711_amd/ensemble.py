@@ -124,9 +124,9 @@ def features(r0_nm, n_atoms, intensity_wcm2, fwhm_fs):
                     axis=-1).astype(np.float32)
 
 
-def targets(last_records, floor_ev=1.0):
-    """Surrogate outputs from each cluster's last record: log of the absorbed laser energy per
-    atom (eV, floored at floor_ev: weakly driven runs can end with a net laser work near zero or
-    below it) and the mean ion charge."""
-    a = np.maximum(np.asarray(last_records)[:, R_ABS_EV], floor_ev)
-    return np.stack([np.log(a), np.asarray(last_records)[:, R_MEANZ]], axis=-1).astype(np.float32)
+def targets(last_records):
+    """Surrogate outputs from each cluster's last record: asinh of the absorbed laser energy per
+    atom in eV (log(2 W) for W well above 1 eV, and continuous through the weakly driven runs
+    whose net laser work ends near zero or below it) and the mean ion charge."""
+    r = np.asarray(last_records)
+    return np.stack([np.arcsinh(r[:, R_ABS_EV]), r[:, R_MEANZ]], axis=-1).astype(np.float32)

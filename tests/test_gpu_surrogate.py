@@ -2,9 +2,12 @@
 
 MD runs of uneven clusters (the ensemble path) produce training data; the network is trained
 on the GPU by the library's own kernels and then judged on held-out clusters re-run by the MD:
-it must predict the mean ion charge better than the best constant (the training mean, which is
-all one has without a model or a new MD run) and answer many orders of magnitude faster than
-the MD produces a run.
+it must predict both outputs (asinh of the absorbed energy per atom, mean ion charge) better than
+the best constant (the training mean, which is all one has without a model or a new MD run) and
+answer many orders of magnitude faster than the MD produces a run.  The capacities (hence the
+lumping N_atoms / n_ion) follow the radius, so the MD's outcome is a function of the network's
+inputs up to the Monte-Carlo and placement noise, whose size (a second MD run of the held-out
+clusters with other seeds) is printed beside the errors.
 """
 import time
 
@@ -16,17 +19,18 @@ from _helpers import gpu_available
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
 
 
-def _runs(n, seed, scale=1.0):
+def _runs(n, seed, scale=1.0, place_seed=None):
     import paper_1307_3711_amd as lc
     from paper_1307_3711_amd.ensemble import features, run_ensemble, targets
     from workloads import ensemble, initial_state
     from workloads.species import SPECIES
-    cl = ensemble(n, seed=seed, cap_lo=300, cap_hi=900)
+    cl = ensemble(n, seed=seed, cap_lo=300, cap_hi=900, capacity_rule="radius")
     descs = [lc.make_cluster(SPECIES[c.species], c.r0_nm, c.n_ion, c.capacity, c.laser.intensity_wcm2,
                              envelope=c.laser.envelope, fwhm_fs=c.laser.fwhm_fs, z_max=c.z_max,
                              n_steps=max(1, int(c.n_steps * scale))) for c in cl]
-    states = [initial_state(c, seed, i) for i, c in enumerate(cl)]
-    r = run_ensemble(descs, states, "fp32_acc64", seed=seed, autotune=False)
+    ps = seed if place_seed is None else place_seed
+    states = [initial_state(c, ps, i) for i, c in enumerate(cl)]
+    r = run_ensemble(descs, states, "fp32_acc64", seed=ps, autotune=False)
     na = np.array([(c.r0_nm * 10.0 / SPECIES[c.species]["rw_angstrom"]) ** 3 for c in cl])
     X = features(np.array([c.r0_nm for c in cl]), na, np.array([c.laser.intensity_wcm2 for c in cl]),
                  np.array([c.laser.fwhm_fs for c in cl]))
@@ -37,21 +41,27 @@ def test_surrogate_beats_constant_and_md_speed():
     import torch
     import paper_1307_3711_amd as lc
     from workloads.surrogate import init_params, row_order
-    X, Y, md_wall = _runs(160, 5)
+    X, Y, md_wall = _runs(320, 5)
     Xh, Yh, _ = _runs(40, 6)
     net = lc.Surrogate(init_params(3))
     Xd, Yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
     net.fit_scaler(Xd, Yd)
-    steps, batch = 3000, 32
+    steps, batch = 3000, 64
     rows = torch.from_numpy(row_order(X.shape[0], batch, steps, 4)).cuda()
     q = steps // 3
     for k, lr in enumerate((3e-3, 1e-3, 3e-4)):
         net.train(Xd, Yd, rows[k * q * batch:], batch, q, lr)
     pred = net.infer(torch.from_numpy(Xh).cuda()).cpu().numpy()
-    rmse_net = np.sqrt(np.mean((pred[:, 1] - Yh[:, 1]) ** 2))
-    rmse_const = np.sqrt(np.mean((Y[:, 1].mean() - Yh[:, 1]) ** 2))
-    print(f"mean charge on held-out clusters: network RMSE {rmse_net:.3f}, constant {rmse_const:.3f}", flush=True)
-    assert rmse_net < 0.7 * rmse_const
+    _, Yh2, _ = _runs(40, 6, place_seed=16)
+    rmse_net = np.sqrt(np.mean((pred - Yh) ** 2, axis=0))
+    rmse_const = np.sqrt(np.mean((Y.mean(axis=0)[None] - Yh) ** 2, axis=0))
+    spread = np.sqrt(np.mean((Yh2 - Yh) ** 2, axis=0))
+    for k, name in enumerate(("asinh absorbed eV/atom", "mean charge")):
+        print(f"{name} on held-out clusters: network RMSE {rmse_net[k]:.3f}, constant {rmse_const[k]:.3f}, "
+              f"MD seed spread {spread[k]:.3f}", flush=True)
+    # the absorbed energy of clusters this small is noisy (the MD's own seed spread is a fifth of
+    # the constant's error): the network must still take off a fifth of the constant's error
+    assert rmse_net[0] < 0.8 * rmse_const[0] and rmse_net[1] < 0.5 * rmse_const[1]
     Xq = torch.from_numpy(np.repeat(Xh, 4096, axis=0)).cuda()
     net.infer(Xq)
     net.stream.synchronize()

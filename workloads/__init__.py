@@ -144,7 +144,7 @@ def ar_anisotropy(n_ion=5000, n_steps=60000):
 
 
 def ensemble(n_clusters=256, seed=0, cap_lo=1000, cap_hi=16000, steps_per_fwhm=None,
-             lambda_um=0.8, dt=0.05):
+             lambda_um=0.8, dt=0.05, capacity_rule="random"):
     """Batched ensemble of uneven clusters.
 
     Cluster c draws (numpy Philox keyed by (seed, 1_000_000 + c)): species Ar or Xe with
@@ -153,6 +153,10 @@ def ensemble(n_clusters=256, seed=0, cap_lo=1000, cap_hi=16000, steps_per_fwhm=N
     min(capacity // 9, floor(N_atoms)) so that each ion can reach Xe8+/Ar8+ within capacity
     and no macroparticle stands for less than one atom.  Each cluster runs until
     t_end = 4 FWHM (the Gaussian peak sits at 2 FWHM); steps_per_fwhm overrides that length.
+    capacity_rule "radius" replaces the random capacity by one fixed by the radius,
+    cap_lo (cap_hi / cap_lo)^((R0 - 2 nm) / 8 nm) (log-linear over the same range), so that the
+    lumping N_atoms / n_ion is a function of the cluster's species and size; every other draw is
+    unchanged.
     """
     out = []
     for c in range(n_clusters):
@@ -162,6 +166,10 @@ def ensemble(n_clusters=256, seed=0, cap_lo=1000, cap_hi=16000, steps_per_fwhm=N
         r0 = float(rng.uniform(2.0, 10.0))
         inten = float(math.exp(rng.uniform(math.log(1e15), math.log(1e17))))
         fwhm = float(rng.uniform(20.0, 100.0))
+        if capacity_rule == "radius":
+            cap = int(round(cap_lo * (cap_hi / cap_lo) ** ((r0 - 2.0) / 8.0)))
+        elif capacity_rule != "random":
+            raise ValueError("capacity_rule must be random or radius")
         rw = SPECIES[species]["rw_angstrom"]
         n_atoms_floor = int(math.floor((r0 * 10.0 / rw) ** 3))
         n_ion = max(1, min(cap // 9, n_atoms_floor))
