@@ -768,7 +768,8 @@ def main():
                     help="particle counts of the scan workload")
     ap.add_argument("--reps", type=int, default=50)
     ap.add_argument("--dt", type=float, default=0.05, help="lumping: time step (1/w)")
-    ap.add_argument("--softening", type=float, default=0.1, help="lumping: softening length (nm)")
+    ap.add_argument("--softening", type=float, default=0.4,
+                    help="lumping: softening length (nm); 0.4 nm resolves the lumped electron-ion pairs")
     ap.add_argument("--copies", type=int, default=4, help="lumping: random placements per lumping")
     ap.add_argument("--clusters", type=int, default=256)
     ap.add_argument("--seed", type=int, default=0)
