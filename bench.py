@@ -780,6 +780,8 @@ def main():
     ap.add_argument("--graph", type=int, default=100)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-records", action="store_true",
+                    help="ar20k: skip running both paths to step 4000 against the oracle's records")
     ap.add_argument("--tiling", default="", help="R,WJ,T,S,persistent[,scalar[,newton3]]: skip the autotuner")
     ap.add_argument("--tiling-fp64", default="", help="the same for the FP64 comparison run")
     ap.add_argument("--polarization", default="linear_x", choices=["linear_x", "circular"],
@@ -925,7 +927,7 @@ def main():
                                 "rel_absorbed_eV_per_atom": rel(lc.R_ABS_EV)}
         # both runs to the workload's end (4000 steps), record by record against the FP64
         # oracle's records of the same run (tests/golden, written from the oracle alone)
-        if c.n_steps >= total_steps and args.boundary == "open":
+        if c.n_steps >= total_steps and args.boundary == "open" and not args.no_oracle_records:
             log("bench: runs to the end, against the oracle's records")
             out["error_vs_fp64_oracle"] = {
                 "fp32_acc64": oracle_record_errors(sim, c.n_steps - total_steps),
