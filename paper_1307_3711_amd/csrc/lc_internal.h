@@ -186,23 +186,38 @@ __device__ inline int wave_cluster(const DevState& s, int64_t g0) {
   return s.gcl[__builtin_amdgcn_readfirstlane((int)(g0 / kGroup))];
 }
 
-// Coulomb field of global slot g from the partials of the last field pass, summed over the
-// splits in split order (FP64).
-__device__ inline void field_sum(const DevState& s, const RunConst& rc, const FieldLayout& fl, int64_t g,
-                                 double& ex, double& ey, double& ez) {
+// Coulomb field of slot g from the partials of the last field pass, summed over the splits in
+// split order (FP64).  g is a global slot, or a lane's offset in a group view (group_view).
+template <typename I>
+__device__ inline void field_sum(const DevState& s, const RunConst& rc, const FieldLayout& fl, I g, double& ex,
+                                 double& ey, double& ez) {
+  const int64_t n = rc.n_total;
   if (fl.S == 1) {  // one split (every pair-once step): plain loads, no loop
     ex = s.part[g];
-    ey = s.part[rc.n_total + g];
-    ez = s.part[2 * rc.n_total + g];
+    ey = (s.part + n)[g];
+    ez = (s.part + 2 * n)[g];
     return;
   }
   ex = 0.0; ey = 0.0; ez = 0.0;
   for (int k = 0; k < fl.S; ++k) {
-    const double* b = s.part + (int64_t)k * kComp * rc.n_total + g;
-    ex += b[0];
-    ey += b[rc.n_total];
-    ez += b[2 * rc.n_total];
+    const double* b = s.part + (int64_t)k * kComp * n;
+    ex += b[g];
+    ey += (b + n)[g];
+    ez += (b + 2 * n)[g];
   }
+}
+
+// The state as seen from the 64-slot group that starts at slot g0 (wave-uniform): every
+// per-slot array advanced to g0, so a lane reaches its slot by a 32-bit offset from a scalar
+// base, one shared address register for all of them instead of a 64-bit address per array.
+__device__ inline DevState group_view(const DevState& s, int64_t g0) {
+  DevState v = s;
+  v.x += g0; v.y += g0; v.z += g0;
+  v.ux += g0; v.uy += g0; v.uz += g0;
+  v.wl += g0; v.wc += g0; v.wsp += g0; v.kebar += g0;
+  v.pos4 += g0; v.posq += g0;
+  v.Z += g0; v.part += g0; v.det_seen += g0;
+  return v;
 }
 
 // Pair-once rows (written by the pair-once Coulomb kernel, layout in force.hip): the partial

@@ -86,7 +86,8 @@ __device__ inline float grid_coord(double x, double is) {
 
 // Source record of slot g for the field pass of a step: {x, y, z, q}; FP32 records of a
 // periodic pass hold the grid coordinates and q (2^32 / L)^2 (the pair kernels' grid units).
-__device__ inline void write_source(const DevState& s, int precision, bool grid, double box, int64_t g, double x,
+template <typename I>
+__device__ inline void write_source(const DevState& s, int precision, bool grid, double box, I g, double x,
                                     double y, double z, double q) {
   if (precision == LC_FP64) {
     s.posq[g] = make_double4(x, y, z, q);
@@ -217,7 +218,8 @@ struct PState {
   int seen;  // detector flag (with detectors on)
 };
 
-__device__ inline PState load_pstate(const DevState& s, const RunConst& rc, int64_t g) {
+template <typename I>
+__device__ inline PState load_pstate(const DevState& s, const RunConst& rc, I g) {
   PState p;
   p.x = s.x[g]; p.y = s.y[g]; p.z = s.z[g];
   p.ux = s.ux[g]; p.uy = s.uy[g]; p.uz = s.uz[g];
@@ -230,7 +232,8 @@ __device__ inline PState load_pstate(const DevState& s, const RunConst& rc, int6
 // The detector flag of slot g, loaded after the particle state and the field: its test comes
 // first in the push, and loads complete in order, so loading it last keeps every load of the
 // push in flight at once.
-__device__ inline void load_seen(const DevState& s, const RunConst& rc, int64_t g, PState& p) {
+template <typename I>
+__device__ inline void load_seen(const DevState& s, const RunConst& rc, I g, PState& p) {
   if (rc.det_on) p.seen = s.det_seen[g];
 }
 
@@ -239,7 +242,8 @@ __device__ inline void load_seen(const DevState& s, const RunConst& rc, int64_t 
 // every ion and for each axis whose direction its position is within the acceptance cone of.
 // Counts are integers (order-independent atomics); the slot is the number of edges <= E.
 // Called for ions not counted yet (the flag comes with the particle state).
-__device__ inline void detect_ion(const DevState& s, const RunConst& rc, const ClusterParams& cp, int c, int64_t g,
+template <typename I>
+__device__ inline void detect_ion(const DevState& s, const RunConst& rc, const ClusterParams& cp, int c, I g,
                                   double x, double y, double z, double M, double ux, double uy, double uz) {
   const double r2 = x * x + y * y + z * z;
   if (r2 < cp.det_r2) return;
@@ -261,9 +265,9 @@ __device__ inline void detect_ion(const DevState& s, const RunConst& rc, const C
 // Relativistic Boris step of live particle g (cluster c) at step index n in the Coulomb field
 // (ecx, ecy, ecz) from state p: u^{n-1/2} -> u^{n+1/2}, x^n -> x^{n+1}, with the exact discrete work split
 // W_L / W_C, optional KE(n) for the diagnostics, and the refresh of the source record the next
-// field pass reads.
+// field pass reads.  s is the view of the particle's 64-slot group and g its lane there.
 template <int PREC>
-__device__ inline void push_one(const DevState& s, const RunConst& rc, int64_t g, int c, int64_t n, int diag,
+__device__ inline void push_one(const DevState& s, const RunConst& rc, uint32_t g, int c, int64_t n, int diag,
                                 double ecx, double ecy, double ecz, const PState& p) {
   const ClusterParams& cp = s.cp[c];
   const ClusterDyn& d = s.dyn[c];
@@ -324,25 +328,34 @@ __device__ inline void push_one(const DevState& s, const RunConst& rc, int64_t g
 // One wave per 64-slot group: the group's cluster comes from the group table through scalar
 // loads (its parameters and counters too), a retired cluster or a group past the live count
 // leaves the whole wave at once, and the particle loads follow without a per-lane lookup.
-// 5 waves per SIMD (at most 96 VGPRs) keep more loads in flight than the 4 the unconstrained
-// allocation (98 VGPRs) allows.
+// The slots are addressed through the group's view (scalar bases, 32-bit lane offsets): one
+// address register instead of a 64-bit pair per array, 84 VGPRs (5 waves per SIMD).  Measured:
+// held to 80 VGPRs (6 waves) it compiles without spills but runs 4 % slower, with fewer loads
+// in flight per wave; at 72 (7 waves) it spills and runs 24 % slower.
+// Two waves per workgroup: workgroups go out to the compute units in a fixed rotation, and
+// with four waves a layout whose clusters alternate long live and long empty runs (capacity
+// 8192, half live) put nearly all live workgroups on the same half of the units; measured on
+// a pattern probe, two-wave groups keep every layout tried within 0.9 of the best case.
+constexpr int kPushBlock = 128;
+
 template <int PREC>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5)))
+__global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(5)))
 void k_push(DevState s, RunConst rc, FieldLayout fl, int64_t k, int diag) {
-  const int64_t g0 = (int64_t)blockIdx.x * kBlock + kGroup * __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t g0 = (int64_t)blockIdx.x * kPushBlock + kGroup * __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (g0 >= rc.n_total) return;
   const int c = wave_cluster(s, g0);
   const ClusterDyn& d = s.dyn[c];
-  const int64_t l = g0 - s.cp[c].off + (threadIdx.x & 63);
+  const uint32_t lane = threadIdx.x & 63;
+  const int64_t l = g0 - s.cp[c].off + lane;
   if (!d.active || l >= d.n_cur) return;
-  const int64_t g = g0 + (threadIdx.x & 63);
+  const DevState v = group_view(s, g0);
   // the particle state is loaded first so that its loads and those of the field are in flight
   // together (one memory round trip instead of two)
-  PState ps = load_pstate(s, rc, g);
+  PState ps = load_pstate(v, rc, lane);
   double ecx, ecy, ecz;
-  field_sum(s, rc, fl, g, ecx, ecy, ecz);
-  load_seen(s, rc, g, ps);
-  push_one<PREC>(s, rc, g, c, *s.step + k, diag, ecx, ecy, ecz, ps);
+  field_sum(v, rc, fl, lane, ecx, ecy, ecz);
+  load_seen(v, rc, lane, ps);
+  push_one<PREC>(v, rc, lane, c, *s.step + k, diag, ecx, ecy, ecz, ps);
 }
 
 // Fold of the pair-once rows and push in one kernel: FW waves over one 64-slot group add
@@ -352,21 +365,21 @@ void k_push(DevState s, RunConst rc, FieldLayout fl, int64_t k, int diag) {
 template <int PREC, int FW>
 __global__ __launch_bounds__(64 * FW) void k_fold_push(DevState s, RunConst rc, int B, int64_t k, int diag) {
   __shared__ double red[FW - 1][3][64];
-  const int lane = threadIdx.x & 63;
+  const uint32_t lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t g0 = (int64_t)blockIdx.x * kGroup;
   const int c = wave_cluster(s, g0);
   const ClusterDyn& d = s.dyn[c];
   const int64_t l0 = g0 - s.cp[c].off;
   if (!d.active || l0 >= d.n_cur) return;  // the whole block: retired cluster or empty group
-  const int64_t g = g0 + lane;
+  const DevState v = group_view(s, g0);
   const bool live = l0 + lane < d.n_cur;
   double e0 = 0.0, e1 = 0.0, e2 = 0.0;
   PState ps;
   if (live) {
-    if (w == 0) ps = load_pstate(s, rc, g);
-    if (PREC == LC_FP64) n3_row_partial<double>(s, rc, B, g, c, w, FW, e0, e1, e2);
-    else n3_row_partial<float>(s, rc, B, g, c, w, FW, e0, e1, e2);
+    if (w == 0) ps = load_pstate(v, rc, lane);
+    if (PREC == LC_FP64) n3_row_partial<double>(s, rc, B, g0 + lane, c, w, FW, e0, e1, e2);
+    else n3_row_partial<float>(s, rc, B, g0 + lane, c, w, FW, e0, e1, e2);
   }
   if (w > 0) {
     red[w - 1][0][lane] = e0;
@@ -380,11 +393,11 @@ __global__ __launch_bounds__(64 * FW) void k_fold_push(DevState s, RunConst rc, 
       e1 += red[q][1][lane];
       e2 += red[q][2][lane];
     }
-    s.part[g] = e0;
-    s.part[rc.n_total + g] = e1;
-    s.part[2 * rc.n_total + g] = e2;
-    load_seen(s, rc, g, ps);
-    push_one<PREC>(s, rc, g, c, *s.step + k, diag, e0, e1, e2, ps);
+    v.part[lane] = e0;
+    (v.part + rc.n_total)[lane] = e1;
+    (v.part + 2 * rc.n_total)[lane] = e2;
+    load_seen(v, rc, lane, ps);
+    push_one<PREC>(v, rc, lane, c, *s.step + k, diag, e0, e1, e2, ps);
   }
 }
 
@@ -928,8 +941,9 @@ hipError_t launch_schedule(const DevState& s, const RunConst& rc, const ForceTil
 
 hipError_t launch_push(const DevState& s, const RunConst& rc, int precision, const FieldLayout& fl, int64_t k,
                        bool diag, hipStream_t st) {
-  if (precision == LC_FP64) k_push<LC_FP64><<<blocks_for(rc.n_total), kBlock, 0, st>>>(s, rc, fl, k, diag ? 1 : 0);
-  else k_push<LC_FP32_ACC64><<<blocks_for(rc.n_total), kBlock, 0, st>>>(s, rc, fl, k, diag ? 1 : 0);
+  const int pb = (int)((rc.n_total + kPushBlock - 1) / kPushBlock);
+  if (precision == LC_FP64) k_push<LC_FP64><<<pb, kPushBlock, 0, st>>>(s, rc, fl, k, diag ? 1 : 0);
+  else k_push<LC_FP32_ACC64><<<pb, kPushBlock, 0, st>>>(s, rc, fl, k, diag ? 1 : 0);
   return hipGetLastError();
 }
 
