@@ -240,12 +240,22 @@ int lc_start(lc_sim* sim);
 int lc_step(lc_sim* sim, int64_t n_steps);
 
 /* Capture steps_per_graph steps into one hipGraph that lc_step replays (0 turns graph
- * replay off).  Replays are used only where they line up with the diagnostic cadence. */
+ * replay off).  Replays are used only where they line up with the diagnostic cadence.
+ * No passage of the paper defines this call: its performance study (Sec. III, execution time
+ * against cores and against macroparticle count, the N_part^2 law) counts whole time steps;
+ * a step of a small cluster is a few short launches, and replaying many steps as one graph
+ * removes the per-launch cost without changing any result (replays are bitwise identical to
+ * direct launches).  Returns LC_E_INVALID for a negative count. */
 int lc_set_graph(lc_sim* sim, int32_t steps_per_graph);
 
-/* Copy up to max_records diagnostic records (LC_REC doubles each, oldest first) of one
- * cluster to host memory; synchronizes the stream.  Returns a latched device error
- * (LC_E_CAPACITY, LC_E_NONFINITE) if one occurred.  Record layout:
+/* Copy the latest max_records diagnostic records (LC_REC doubles each, in time order) of one
+ * cluster to host memory; synchronizes the stream.  The records hold the observables the
+ * paper reports as functions of time (Sec. III: average kinetic energy, as in the lumping
+ * study of the deuterium cluster; the population of each ion charge state, as in the argon
+ * charge-state fractions; absorbed energy) and the energy budget of the Sec. II model (laser
+ * work on the particles, Coulomb potential energy).  records must hold max_records * LC_REC
+ * doubles (caller-owned host memory); *n_out receives the number written.  Returns a latched
+ * device error (LC_E_CAPACITY, LC_E_NONFINITE) if one occurred.  Record layout:
  *  0 t  1 step  2 N  3 N_ion  4 N_electron  5 KE(n+1/2)  6 KE(n)  7 PE(n)
  *  8 W_laser  9 W_coulomb  10 spawn KE  11-13 momentum  14-16 sum w Z E_C  17 sum w|Z||E_C|
  *  18 mean ion charge  19 absorbed eV per atom  20 dropped spawns  21 ionizations

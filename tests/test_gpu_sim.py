@@ -68,6 +68,39 @@ def test_small_ar_fp64_200_steps(tiling):
     assert rg[0, 23] == pytest.approx(osim.ke_start, rel=1e-12, abs=1e-300)
 
 
+@pytest.mark.parametrize("envelope,other", [("gauss_intensity", "gauss_field"), ("gauss_field", "gauss_intensity")])
+def test_gaussian_envelopes_fp64(envelope, other):
+    """Eq.(3) on the device in both width readings (field FWHM with the printed constant, and
+    the intensity-FWHM variant with half the exponent): a 2 fs pulse centred at 2 tau peaks
+    inside the 200 steps.  FP64 against the oracle at the bar of the sin^2 case, the envelope
+    column a(t) to rounding; the oracle's laser work under the other reading differs by far
+    more than that bar, so a device that took the wrong constant fails."""
+    import paper_1307_3711_amd as lc
+    laser = Laser(intensity_wcm2=1e16, envelope=envelope, fwhm_fs=2.0)
+    c = Cluster(species="Ar", r0_nm=2.5, n_ion=500, capacity=4500, z_init=1, z_max=8, laser=laser, n_steps=200)
+    run = Run(dt=0.05, ionize=True, diag_every=10, seed=0)
+    sim, states = gpu_run([c], run, "fp64")
+    osim = oracle_run(c, run, states[0])
+    print(f"{envelope}: 200 steps", flush=True)
+    sim.step(200)
+    rg = sim.diagnostics(0)
+    ro = osim.run(200)
+    r0n = units.nm_to_norm(c.r0_nm, 0.8)
+    dx, du = _compare_state(sim, osim, r0n, 1e-9, 1e-9)
+    print(f"max|dx|/R0 = {dx:.3e}  max|du|/max|u| = {du:.3e}  events gpu={rg[-1][21]} oracle={ro[-1][21]}")
+    assert dx <= 1e-9 and du <= 1e-9
+    _compare_records(rg, ro, ENERGY_COLS, 1e-10)
+    _compare_records(rg, ro, [22], 1e-13)
+    assert np.array_equal(rg[:, 21], ro[:, 21]) and np.array_equal(rg[:, 24:41], ro[:, 24:41])
+    assert np.max(ro[:, 22]) > 0.99 * oracle.make_params(c, run).a0  # the peak lies inside the run
+    c2 = Cluster(species="Ar", r0_nm=2.5, n_ion=500, capacity=4500, z_init=1, z_max=8,
+                 laser=Laser(intensity_wcm2=1e16, envelope=other, fwhm_fs=2.0), n_steps=200)
+    ro2 = oracle_run(c2, run, states[0]).run(200)
+    sep = np.max(np.abs(ro2[:, 8] - ro[:, 8])) / np.max(np.abs(ro[:, 8]))
+    print(f"laser work, {other} against {envelope}: {sep:.3e} relative")
+    assert sep > 1e-3
+
+
 # Pair-once tilings (each unordered pair evaluated once for both particles on steps without
 # a diagnostic record); the diagnostic steps take the one-sided kernels with the other fields.
 N3 = dict(R=4, WJ=4, T=1024, S=8, scalar=1, newton3=1)
