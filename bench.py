@@ -392,6 +392,7 @@ def bench_xe(args):
         # the FP64 oracle on 20 steps from the same start (44,444 macroparticles); its cost per
         # step is a N^2, so its pair rate gives its time for the run's pair count
         import oracle
+        from oracle import units
         osim = oracle.Sim.from_workload(c, run, st)
         osim.start()
         n0 = float(osim.N)
@@ -399,11 +400,30 @@ def bench_xe(args):
         osim.run(20)
         dt = time.perf_counter() - t0
         rate = 20 * n0 * n0 / dt
-        out["cpu_baseline"] = {"value": round(rate / 1e9, 3), "unit": "Gpair/s", "cores": oracle.threads(),
-                               "kind": "oracle",
-                               "sample": f"20 steps at the start ({int(n0)} macroparticles, {dt:.1f} s); the run's "
-                                         f"{r32['counters']['pairs']:.3g} pair interactions at this rate: "
-                                         f"{r32['counters']['pairs'] / rate / 3600:.1f} h"}
+        # one field pass each on synthetic states of 100k and 200k macroparticles (the oracle's
+        # own placement in the same sphere, one electron per ion), sizes the run grows through;
+        # the run's time on the oracle is then the sum over its steps of N^2 / rate(N), the rate
+        # interpolated linearly in N between the three samples
+        sizes, rates = [n0], [rate]
+        r0n = units.nm_to_norm(c.r0_nm, c.laser.lambda_um)
+        eps2 = units.nm_to_norm(run.softening_nm, c.laser.lambda_um) ** 2
+        for m in (100_000, 200_000):
+            xs, zs = oracle.init_cluster(seed=99, cluster_index=0, n_ion=m // 2, z_init=1, r0=r0n, delta=r0n * 1e-3)
+            t1 = time.perf_counter()
+            oracle.coulomb_field(xs, zs.astype(np.float64), eps2, want_phi=False)
+            sizes.append(float(m))
+            rates.append(float(m) * m / (time.perf_counter() - t1))
+        nrec = rec[:, 2]
+        steps_per_rec = np.diff(np.concatenate([[0.0], rec[:, 1]]))
+        t_run = float(np.sum(steps_per_rec * nrec * nrec / np.interp(nrec, sizes, rates)))
+        value = float(r32["counters"]["pairs"]) / t_run
+        out["cpu_baseline"] = {"value": round(value / 1e9, 3), "unit": "Gpair/s", "cores": oracle.threads(),
+                               "kind": "oracle", "cpu": cpu_model(),
+                               "rates_by_size": {str(int(n)): round(r / 1e9, 3) for n, r in zip(sizes, rates)},
+                               "sample": f"20 steps at the start ({int(n0)} macroparticles, {dt:.1f} s) and one "
+                                         f"field pass each at 100k and 200k; the run's "
+                                         f"{r32['counters']['pairs']:.3g} pair interactions at these rates "
+                                         f"(extrapolated over the run's N(t) records): {t_run / 3600:.1f} h"}
     if not args.no_fp64:
         n64 = min(args.fp64_steps, steps)
         r64 = _xe_run("fp64", c, run, st, n64)
