@@ -13,7 +13,7 @@ and within 1 % at the end.  The absorbed energy is not held to 1 % of its own va
 explosion: there it rises by three orders of magnitude within a few hundred steps and the FP64
 GPU path, whose arithmetic differs from the oracle's only in the order of the field sums,
 already differs from the oracle by 1.1 % of its value at the steepest point.  The divergence
-curve of each run is printed and written to gpurun_out/.
+curve of each run is printed, and written as JSON into the directory LC_TEST_OUT names (if set).
 """
 import json
 import os
@@ -64,10 +64,11 @@ def test_ar20k_records_against_oracle(precision, tiling):
             curve[name + "_own"] = (d / (np.abs(g[name]) + 1e-300)).tolist()
             worst[name] = float(np.max(d) / abs(g[name][-1]))
             worst["absorbed_final"] = float(d[-1] / abs(g[name][-1]))
-    out = os.path.join(os.path.dirname(HERE), "gpurun_out")
-    os.makedirs(out, exist_ok=True)
-    with open(os.path.join(out, f"ar20k_divergence_{precision}.json"), "w") as f:
-        json.dump(curve, f)
+    out = os.environ.get("LC_TEST_OUT")
+    if out:
+        os.makedirs(out, exist_ok=True)
+        with open(os.path.join(out, f"ar20k_divergence_{precision}.json"), "w") as f:
+            json.dump(curve, f)
     for k in range(0, len(g["t"]), 4):
         print(f"t={g['t'][k]:6.1f} " + " ".join(f"{n}={curve[n][k]:.2e}" for n in COLS), flush=True)
     print(f"ar20k {precision}: worst {worst}; absorbed gpu {r[-1, 19]:.6g} oracle {g['absorbed_eV_per_atom'][-1]:.6g}",
