@@ -66,9 +66,11 @@ int64_t n3_round(int64_t cap) { return (cap + 511) / 512 * 512 + 512; }
 
 struct Layout {
   size_t x, y, z, ux, uy, uz, wl, wc, wsp, kebar, pos4, posq, Z, gcl, part, n3part, flag, ib_count, ib_off, ib_cluster;
-  size_t cp, dyn, order, tile_start, tile_total, queue, det_seen, det_counts, det_edges, ci_part, err, step, diag_part, records, total;
+  size_t cp, dyn, order, tile_start, tile_total, queue, det_seen, det_counts, det_edges, ci_part, err, step, diag_part, records;
+  size_t laser_tab, laser_tab0, total;
   int64_t n_total;
   int n_ion_blocks;
+  bool has_laser_tab;
 };
 
 bool valid_config(const lc_config* cfg, std::string* why) {
@@ -168,6 +170,11 @@ Layout make_layout(const lc_config* cfg, const lc_cluster* cl, int C) {
   L.diag_part = take(sizeof(double) * (size_t)C * kDiagBlocks * kDiagQ);
   const int mr = cfg->diag_every > 0 ? cfg->max_records : 1;
   L.records = take(sizeof(double) * (size_t)C * mr * LC_REC);
+  // without ionization no particle count changes, and groups of pair-once steps can leave the
+  // schedule out if the laser values of their steps are ready in a table
+  L.has_laser_tab = !cfg->ionize && C <= kLaserTabClusters;
+  L.laser_tab = take(L.has_laser_tab ? sizeof(double) * 3 * (size_t)kLaserTabSteps * C : 0);
+  L.laser_tab0 = take(L.has_laser_tab ? sizeof(int64_t) : 0);
   L.total = p;
   return L;
 }
@@ -335,13 +342,21 @@ hipError_t enqueue_steps(lc_sim* s, int count, int64_t first_step) {
   ForceTiling ft = s->ft;
   ft.S = s->S_eff;
   // The tables of the first step were built by the previous step's closing schedule (or by
-  // lc_start / a tiling change); every step ends with the schedule of the next one.
+  // lc_start / a tiling change); every step ends with the schedule of the next one, except
+  // inside a group of steps where nothing can change the tables (begin below).
+  const bool tab = s->s.laser_tab && !s->cfg.ionize && ft.newton3 && !ft.persistent && count > 1;
+  const int tab_steps = std::min(count, kLaserTabSteps);
+  if (tab) {
+    hipError_t e = launch_laser_table(s->s, s->rc, tab_steps, s->stream);
+    if (e != hipSuccess) return e;
+  }
+  bool begin = false;
   for (int k = 0; k < count; ++k) {
     const bool diag = is_diag_step(s, first_step + k);
     const bool n3 = n3_pass(s, ft, diag);
     const FieldLayout fl = field_layout(ft, n3);
     hipError_t e = launch_force(s->s, s->rc, s->cfg.precision, ft, diag, pbc_step(s, first_step + k),
-                                force_grid(s, ft, n3), s->stream, false);
+                                force_grid(s, ft, n3), s->stream, false, begin);
     if (e != hipSuccess) return e;
     e = n3 ? launch_fold_push(s->s, s->rc, s->cfg.precision, n3_block_size(ft), 0, diag, s->stream)
            : launch_push(s->s, s->rc, s->cfg.precision, fl, 0, diag, s->stream);
@@ -355,8 +370,18 @@ hipError_t enqueue_steps(lc_sim* s, int count, int64_t first_step) {
       if (e != hipSuccess) return e;
     }
     const bool n3_next = n3_pass(s, ft, is_diag_step(s, first_step + k + 1));
-    e = schedule(s, ft, n3_next, true);
-    if (e != hipSuccess) return e;
+    // Without ionization no particle count changes, so between two pair-once steps of this
+    // group the tile tables stay as they are: the schedule is left out and the next step's
+    // force launch does its bookkeeping (step count, active flags, step index, and the laser
+    // value from the table filled at the group's start).
+    // A cluster that retires there keeps its tiles until the group's last schedule; its rows
+    // are computed but not read (its push is off).  The group's last step always schedules,
+    // so the device state between calls is the same as with a schedule after every step.
+    begin = tab && n3 && n3_next && k + 1 < tab_steps;
+    if (!begin) {
+      e = schedule(s, ft, n3_next, true);
+      if (e != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }
@@ -479,6 +504,8 @@ int lc_create(lc_sim** out, const lc_config* cfg, const lc_cluster* clusters, in
   d.ci_part = (double*)(b + L.ci_part);
   d.err = (int32_t*)(b + L.err); d.step = (int64_t*)(b + L.step);
   d.diag_part = (double*)(b + L.diag_part); d.records = (double*)(b + L.records);
+  d.laser_tab = L.has_laser_tab ? (double*)(b + L.laser_tab) : nullptr;
+  d.laser_tab0 = L.has_laser_tab ? (int64_t*)(b + L.laser_tab0) : nullptr;
 
   RunConst& rc = s->rc;
   rc.dt = cfg->dt;

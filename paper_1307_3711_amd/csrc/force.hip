@@ -475,6 +475,34 @@ template <> struct N3Type<double> {
   static constexpr double kFar = 1e150;
 };
 
+// Step bookkeeping a pair-once launch takes over when no schedule launch precedes it (the
+// tile tables of the step before still hold): the first wave of block 0 counts the step just
+// taken and sets the next step's index and laser value (from the laser table, so that no
+// transcendental function enters this kernel), fields no tile of the launch reads.
+struct StepBegin {
+  ClusterDyn* dyn;
+  const ClusterParams* cp;
+  int64_t* step;
+  const double* tab;
+  const int64_t* tab0;
+  int n_clusters;
+  int on;
+};
+
+// One wave: every lane loads the step index before lane 0 stores the next one.
+__device__ inline void begin_step_wave(const StepBegin& b) {
+  const int64_t n = *b.step + 1;
+  const double* row = b.tab + 3 * (n - *b.tab0) * b.n_clusters;
+  for (int c = threadIdx.x; c < b.n_clusters; c += 64) {
+    ClusterDyn& d = b.dyn[c];
+    begin_step_counts(b.cp[c], d, 1, n);
+    d.env = row[3 * c];
+    d.laser_e = row[3 * c + 1];
+    d.laser_ey = row[3 * c + 2];
+  }
+  if (threadIdx.x == 0) *b.step = n;
+}
+
 template <typename T>
 struct N3Args {
   const typename N3Type<T>::V4* src;  // source records, global slot indexed
@@ -483,6 +511,7 @@ struct N3Args {
   double eps2;
   int persistent;
   TileMap map;
+  StepBegin begin;
 };
 
 __device__ inline float n3_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -825,6 +854,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? (R >= 5 ? 2 : 3) : (R >= 6 ?
 void k_force_n3(N3Args<T> a) {
   extern __shared__ __align__(16) unsigned char lds_n3_raw[];
   T* lds_n3 = reinterpret_cast<T*>(lds_n3_raw);
+  if (a.begin.on && blockIdx.x == 0 && threadIdx.x < 64) begin_step_wave(a.begin);
   const int total = *a.map.tile_total;
   if (!a.persistent) {
     // one tile per block when the grid covers the tiles, else a block-strided walk over them
@@ -1179,19 +1209,21 @@ bool force_tiling_valid(int precision, const ForceTiling& ft) {
 }
 
 hipError_t launch_force(const DevState& s, const RunConst& rc, int precision, const ForceTiling& ft,
-                        bool want_phi, bool pbc, int grid_blocks, hipStream_t st, bool fold_n3) {
+                        bool want_phi, bool pbc, int grid_blocks, hipStream_t st, bool fold_n3, bool begin_step) {
   TileMap map{s.tile_start, s.order, s.cp, s.dyn, s.tile_total, s.queue, rc.n_clusters};
+  if (begin_step && (!ft.newton3 || want_phi || ft.persistent || !s.laser_tab)) return hipErrorInvalidValue;
   if (ft.newton3 && !want_phi) {
     if (precision == LC_FP32_KAHAN || rc.n3_rows <= 0) return hipErrorInvalidValue;
     hipError_t e;
     const int fb = (int)((rc.n_total + 63) / 64);
+    const StepBegin sb{s.dyn, s.cp, s.step, s.laser_tab, s.laser_tab0, rc.n_clusters, begin_step ? 1 : 0};
     if (precision == LC_FP64) {
-      N3Args<double> a{s.posq, (double*)s.n3part, rc.n3_rows, rc.eps2, ft.persistent, map};
+      N3Args<double> a{s.posq, (double*)s.n3part, rc.n3_rows, rc.eps2, ft.persistent, map, sb};
       e = launch_n3(ft, a, grid_blocks, pbc, st);
       if (e != hipSuccess || !fold_n3) return e;
       k_fold_n3<double><<<fb, 64 * kFoldWaves, 0, st>>>(s, rc, n3_block(ft.R, ft.WJ));
     } else {
-      N3Args<float> a{s.pos4, (float*)s.n3part, rc.n3_rows, rc.eps2, ft.persistent, map};
+      N3Args<float> a{s.pos4, (float*)s.n3part, rc.n3_rows, rc.eps2, ft.persistent, map, sb};
       e = launch_n3(ft, a, grid_blocks, pbc, st);
       if (e != hipSuccess || !fold_n3) return e;
       k_fold_n3<float><<<fb, 64 * kFoldWaves, 0, st>>>(s, rc, n3_block(ft.R, ft.WJ));
@@ -1271,12 +1303,12 @@ hipError_t launch_field_standalone(int precision, int64_t n, const double* xyzq,
   if (ft.newton3) {
     if (phi) return hipErrorInvalidValue;
     if (precision == LC_FP64) {
-      N3Args<double> a{(const double4*)w.src, (double*)w.part, ib, eps2, ft.persistent, map};
+      N3Args<double> a{(const double4*)w.src, (double*)w.part, ib, eps2, ft.persistent, map, StepBegin{}};
       e = launch_n3(ft, a, grid, false, st);
       if (e != hipSuccess) return e;
       k_sum_n3<double><<<pb, kBlock, 0, st>>>((const double*)w.part, n, TI, E);
     } else {
-      N3Args<float> a{(const float4*)w.src, (float*)w.part, ib, eps2, ft.persistent, map};
+      N3Args<float> a{(const float4*)w.src, (float*)w.part, ib, eps2, ft.persistent, map, StepBegin{}};
       e = launch_n3(ft, a, grid, false, st);
       if (e != hipSuccess) return e;
       k_sum_n3<float><<<pb, kBlock, 0, st>>>((const float*)w.part, n, TI, E);

@@ -158,7 +158,14 @@ struct DevState {
   double* diag_part;    // [cluster][kDiagBlocks][kDiagQ]
   double* ci_part;      // [cluster][kDiagBlocks][2] electron count and kinetic energy in the sphere
   double* records;      // [cluster][max_records][LC_REC]
+  double* laser_tab;    // [step - *laser_tab0][cluster][3]: a(t), E_x, E_y of the steps of a group
+  int64_t* laser_tab0;  // step index of the table's first row
 };
+
+// Steps a laser table covers (runs whose schedule can be left out inside a group of steps).
+constexpr int kLaserTabSteps = 256;
+// Clusters up to which runs without ionization keep a laser table.
+constexpr int kLaserTabClusters = 64;
 
 struct ForceTiling {
   int R;
@@ -176,6 +183,59 @@ struct FieldLayout {
   int S;
 };
 
+
+// Envelope a(t) of the laser field amplitude (Eq.(3) and the test envelopes).
+__device__ inline double envelope(const ClusterParams& cp, double t) {
+  switch (cp.envelope) {
+    case LC_GAUSS_FIELD: {
+      const double d = t - 2.0 * cp.tau;
+      return cp.a0 * exp(-2.77 * d * d / (cp.tau * cp.tau));
+    }
+    case LC_GAUSS_INTENSITY: {
+      const double d = t - 2.0 * cp.tau;
+      return cp.a0 * exp(-1.385 * d * d / (cp.tau * cp.tau));
+    }
+    case LC_SIN2: {
+      if (t <= 0.0 || t >= cp.t_sin2) return 0.0;
+      const double s = sin(M_PI * t / cp.t_sin2);
+      return cp.a0 * s * s;
+    }
+    default:
+      return cp.a0;
+  }
+}
+
+// Envelope and dipole laser field (E_x, E_y) of a cluster at time t (Eqs.(3)-(9), psi = t);
+// the magnetic field follows as z^ x E.
+__device__ inline void laser_values(const ClusterParams& cp, double t, double& env, double& ex, double& ey) {
+  env = envelope(cp, t);
+  ex = env * sin(t);
+  ey = (cp.polarization == LC_CIRCULAR) ? -(env * cos(t)) : 0.0;
+}
+
+// Counters of one cluster as step n begins: with advance, the step just taken is counted
+// (n_sched^2 pair interactions, if the cluster was active); then the active flag and the live
+// count this step's field pass covers.
+__device__ inline void begin_step_counts(const ClusterParams& cp, ClusterDyn& d, int advance, int64_t n) {
+  if (advance && d.active) {
+    d.pairs += (double)d.n_sched * (double)d.n_sched;
+    d.steps_done += 1;
+  }
+  d.active = (n < cp.n_steps) ? 1 : 0;
+  d.n_sched = d.n_cur;
+}
+
+// Bookkeeping of one cluster as step n (time t) begins: its counters and the laser value of
+// step n.  The tile tables are the caller's business.
+__device__ inline void begin_step_cluster(const ClusterParams& cp, ClusterDyn& d, int advance, int64_t n,
+                                          double t) {
+  begin_step_counts(cp, d, advance, n);
+  double env, ex, ey;
+  laser_values(cp, t, env, ex, ey);
+  d.env = env;
+  d.laser_e = ex;
+  d.laser_ey = ey;
+}
 
 // Cluster of global slot g (one table entry per 64-slot group).
 __device__ inline int slot_cluster(const DevState& s, int64_t g) { return s.gcl[g / kGroup]; }
@@ -269,13 +329,19 @@ __device__ inline void n3_row_partial(const DevState& s, const RunConst& rc, int
 
 // Host launchers (defined in force.hip / step.hip).
 // A pass without the potential takes the pair-once kernel when ft.newton3 is set.
-// fold_n3 = false leaves the rows unsummed for launch_fold_push.
+// fold_n3 = false leaves the rows unsummed for launch_fold_push.  begin_step (pair-once,
+// non-persistent passes only): the launch also does the step bookkeeping of the schedule that
+// was left out before it (the tile tables of the step before must still hold).
 hipError_t launch_force(const DevState& s, const RunConst& rc, int precision, const ForceTiling& ft,
-                        bool want_phi, bool pbc, int grid_blocks, hipStream_t st, bool fold_n3 = true);
+                        bool want_phi, bool pbc, int grid_blocks, hipStream_t st, bool fold_n3 = true,
+                        bool begin_step = false);
 // n3: build the pair-once tile tables (blocks of n3_block_size(ft)) instead of target blocks
 // times splits.
 hipError_t launch_schedule(const DevState& s, const RunConst& rc, const ForceTiling& ft, bool n3, bool advance,
                            hipStream_t st);
+// Laser values of steps *step + 1 .. *step + steps - 1 of every cluster into the laser table
+// (steps <= kLaserTabSteps), for force launches that take over the schedule's bookkeeping.
+hipError_t launch_laser_table(const DevState& s, const RunConst& rc, int steps, hipStream_t st);
 hipError_t launch_push(const DevState& s, const RunConst& rc, int precision, const FieldLayout& fl, int64_t k,
                        bool diag, hipStream_t st);
 // Push after a pair-once pass whose rows were not folded: the fold and the push in one kernel

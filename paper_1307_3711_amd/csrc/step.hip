@@ -21,27 +21,6 @@ __device__ inline double gm1(double ux, double uy, double uz) {
   return u2 / (1.0 + sqrt(1.0 + u2));
 }
 
-// Envelope a(t) of the laser field amplitude (Eq.(3) and the test envelopes).
-__device__ inline double envelope(const ClusterParams& cp, double t) {
-  switch (cp.envelope) {
-    case LC_GAUSS_FIELD: {
-      const double d = t - 2.0 * cp.tau;
-      return cp.a0 * exp(-2.77 * d * d / (cp.tau * cp.tau));
-    }
-    case LC_GAUSS_INTENSITY: {
-      const double d = t - 2.0 * cp.tau;
-      return cp.a0 * exp(-1.385 * d * d / (cp.tau * cp.tau));
-    }
-    case LC_SIN2: {
-      if (t <= 0.0 || t >= cp.t_sin2) return 0.0;
-      const double s = sin(M_PI * t / cp.t_sin2);
-      return cp.a0 * s * s;
-    }
-    default:
-      return cp.a0;
-  }
-}
-
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): two 64x64->128 multiplies per round,
 // Weyl key schedule between rounds.
 struct U64x4 {
@@ -129,23 +108,32 @@ __device__ inline int32_t schedule_cluster(const DevState& s, int p, int TI, int
   const int c = s.order[p];
   const ClusterParams& cp = s.cp[c];
   ClusterDyn& d = s.dyn[c];
-  if (advance && d.active) {
-    d.pairs += (double)d.n_sched * (double)d.n_sched;
-    d.steps_done += 1;
-  }
-  const int active = (n < cp.n_steps) ? 1 : 0;
-  const int64_t ncur = d.n_cur;
-  d.n_sched = ncur;
-  const int ib = active ? (int)((ncur + TI - 1) / TI) : 0;
+  begin_step_cluster(cp, d, advance, n, t);
+  const int ib = d.active ? (int)((d.n_sched + TI - 1) / TI) : 0;
   const int32_t tiles = n3 ? (int32_t)((int64_t)ib * (ib + 1) / 2) : ib * S;
-  const double env = envelope(cp, t);
-  d.env = env;
-  d.laser_e = env * sin(t);
-  d.laser_ey = (cp.polarization == LC_CIRCULAR) ? -(env * cos(t)) : 0.0;
-  d.active = active;
   d.i_blocks = ib;
   d.n_tiles = tiles;
   return tiles;
+}
+
+// Laser values of the steps n0 + 1 .. n0 + steps - 1 (n0: the current step index) of every
+// cluster, with the schedule's arithmetic, for the force launches that take over the step
+// bookkeeping inside a group of steps.  Row j holds step n0 + j (row 0 is not used).
+__global__ __launch_bounds__(kBlock) void k_laser_table(DevState s, RunConst rc, int steps) {
+  const int64_t n0 = *s.step;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i == 0) *s.laser_tab0 = n0;
+  const int64_t j = i / rc.n_clusters;
+  const int c = (int)(i - j * rc.n_clusters);
+  if (j < 1 || j >= steps) return;
+  const int64_t n = n0 + j;
+  const double t = rc.t0 + (double)n * rc.dt;
+  double env, ex, ey;
+  laser_values(s.cp[c], t, env, ex, ey);
+  double* row = s.laser_tab + 3 * (j * rc.n_clusters + c);
+  row[0] = env;
+  row[1] = ex;
+  row[2] = ey;
 }
 
 // Up to 64 clusters: one wave, the scan across its lanes without barriers.
@@ -936,6 +924,13 @@ hipError_t launch_schedule(const DevState& s, const RunConst& rc, const ForceTil
   const int TI = n3 ? n3_block_size(ft) : force_tile_targets(ft);
   if (rc.n_clusters <= 64) k_schedule_wave<<<1, 64, 0, st>>>(s, rc, TI, ft.S, n3 ? 1 : 0, advance ? 1 : 0);
   else k_schedule<<<1, kBlock, 0, st>>>(s, rc, TI, ft.S, n3 ? 1 : 0, advance ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_laser_table(const DevState& s, const RunConst& rc, int steps, hipStream_t st) {
+  if (!s.laser_tab || steps < 1 || steps > kLaserTabSteps || rc.n_clusters > kLaserTabClusters) return hipErrorInvalidValue;
+  const int64_t n = (int64_t)steps * rc.n_clusters;
+  k_laser_table<<<(int)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(s, rc, steps);
   return hipGetLastError();
 }
 

@@ -199,6 +199,38 @@ def test_determinism_and_graph_replay_bitwise(tiling):
         assert np.array_equal(r, out[0][1])
 
 
+@pytest.mark.parametrize("precision", ["fp32_acc64", "fp64"])
+def test_schedule_left_out_without_ionization_bitwise(precision):
+    """Without ionization a captured group of pair-once steps leaves the schedule out between
+    its steps and the next force launch does the step bookkeeping; stepping one step at a time
+    schedules after every step.  Two clusters, one retiring inside a group (its tiles stay until
+    the group's last schedule, its state must not move): positions, momenta, records, counted
+    steps and pair interactions bitwise identical either way."""
+    import paper_1307_3711_amd as lc
+    laser = Laser(intensity_wcm2=1e16, envelope="flat")
+    cl = [Cluster(species="Ar", r0_nm=2.0, n_ion=300, capacity=600, z_init=1, z_max=8, laser=laser),
+          Cluster(species="Ar", r0_nm=1.5, n_ion=100, capacity=200, z_init=1, z_max=8, laser=laser)]
+    run = Run(dt=0.05, ionize=False, diag_every=10, seed=2)
+    states = [initial_state(c, run.seed, i) for i, c in enumerate(cl)]
+    mpb = lc.pair_blocks_for([c.capacity for c in cl])
+    out = []
+    for graph in (0, 20):
+        tiling = N3 if precision == "fp32_acc64" else dict(R=4, WJ=4, newton3=1)
+        sim, _ = gpu_run(cl, run, precision, states=states, n_steps_per_cluster=[0, 33], tuning=tiling,
+                         max_pair_blocks=mpb)
+        if graph:
+            sim.set_graph(graph)
+        print(f"{precision} graph={graph}: 60 steps", flush=True)
+        sim.step(60)
+        out.append([(sim.particles(i), sim.diagnostics(i), sim.counters(i)) for i in range(len(cl))])
+        sim.close()
+    for (g0, r0, c0), (g1, r1, c1) in zip(out[0], out[1]):
+        assert np.array_equal(g0["x"], g1["x"]) and np.array_equal(g0["u"], g1["u"])
+        assert np.array_equal(r0, r1)
+        assert c0 == c1, (c0, c1)
+    assert out[1][1][2]["steps"] == 33 and out[1][0][2]["steps"] == 60
+
+
 def test_checkpoint_resume_bitwise():
     c, run = small_ar()
     sim, states = gpu_run([c], run, "fp64")
