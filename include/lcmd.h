@@ -245,7 +245,9 @@ int lc_step(lc_sim* sim, int64_t n_steps);
  * against cores and against macroparticle count, the N_part^2 law) counts whole time steps;
  * a step of a small cluster is a few short launches, and replaying many steps as one graph
  * removes the per-launch cost without changing any result (replays are bitwise identical to
- * direct launches).  Returns LC_E_INVALID for a negative count. */
+ * direct launches).  In a run without ionization the captured pair-once steps also leave out
+ * the per-step tile schedule (no particle count can change); the next field pass does its
+ * bookkeeping, with the same results.  Returns LC_E_INVALID for a negative count. */
 int lc_set_graph(lc_sim* sim, int32_t steps_per_graph);
 
 /* Copy the latest max_records diagnostic records (LC_REC doubles each, in time order) of one
