@@ -27,13 +27,26 @@ struct U64x4 {
   uint64_t v[4];
 };
 
+// 64 x 64 -> 128-bit product from four 32 x 32 -> 64-bit products with carries folded into
+// their additions (each term stays below 2^64), both halves from the same partial products.
+__device__ inline void mul64x64(uint64_t a, uint64_t b, uint64_t& hi, uint64_t& lo) {
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+  const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+  const uint64_t p00 = (uint64_t)a0 * b0;
+  const uint64_t t = (uint64_t)a1 * b0 + (p00 >> 32);
+  const uint64_t u = (uint64_t)a0 * b1 + (uint32_t)t;
+  hi = (uint64_t)a1 * b1 + (t >> 32) + (u >> 32);
+  lo = (u << 32) | (uint32_t)p00;
+}
+
 __device__ inline U64x4 philox(uint64_t k0, uint64_t k1, uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3) {
   const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
   const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
-    const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+    uint64_t hi0, lo0, hi1, lo1;
+    mul64x64(M0, c0, hi0, lo0);
+    mul64x64(M1, c2, hi1, lo1);
     const uint64_t n0 = hi1 ^ c1 ^ k0;
     const uint64_t n2 = hi0 ^ c3 ^ k1;
     c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
