@@ -150,14 +150,23 @@ def cpu_baseline(c, run, st, n, target_s=10.0):
 
 
 def cpu_model():
-    """The host CPU's model name (/proc/cpuinfo), for the CPU-baseline record."""
+    """The host CPU's model name with its family / model / stepping numbers (/proc/cpuinfo;
+    a virtual machine may report only a short name), for the CPU-baseline record."""
+    info = {}
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+            if ":" in line:
+                k, v = (x.strip() for x in line.split(":", 1))
+                if k in ("model name", "cpu family", "model", "stepping") and k not in info:
+                    info[k] = v
+            elif info:
+                break
     except OSError:
-        pass
-    return None
+        return None
+    if "model name" not in info:
+        return None
+    ids = ", ".join(f"{k} {info[k]}" for k in ("cpu family", "model", "stepping") if k in info)
+    return info["model name"] + (f" ({ids})" if ids else "")
 
 
 def ensemble_inputs(n_clusters, seed, steps_scale=1.0, capacity_rule="random"):
