@@ -325,8 +325,9 @@ int lc_autotune(lc_sim* sim, const char* cache_json, lc_tuning* chosen);
  * number of launches: index 0 the Coulomb kernel, 1 push, 2 diagnostics, 3 ionization.
  * With a pair-once tiling, group 0 holds the pair-once passes only: the one-sided pass of a
  * diagnostic step (which also computes the potential) is added to group 2, and the push
- * group includes the fold of the pair-once rows.  Advances the simulation like lc_step.
- * Synchronizes the stream. */
+ * group includes the fold of the pair-once rows.  A pair-once dispatch records its events
+ * itself (its own start and end); the other groups are bracketed by events on the stream.
+ * Advances the simulation like lc_step.  Synchronizes the stream. */
 int lc_profile_steps(lc_sim* sim, int64_t n_steps, double out_ms[4], int64_t out_launches[4]);
 
 /* Write the whole device state and step index to a file / restore it into a handle

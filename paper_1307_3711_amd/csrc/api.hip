@@ -1252,11 +1252,17 @@ extern "C" int lc_profile_steps(lc_sim* s, int64_t n_steps, double* out_ms, int6
       const bool n3 = n3_pass(s, ft, diag);
       const FieldLayout fl = field_layout(ft, n3);
       hipEvent_t* E = &ev[8 * k];
-      e = hipEventRecord(E[0], s->stream);
-      if (e == hipSuccess)
+      if (n3) {
+        // the pair-once dispatch records its own start and end
         e = launch_force(s->s, s->rc, s->cfg.precision, ft, diag, pbc_step(s, s->step), force_grid(s, ft, n3),
-                         s->stream, false);
-      if (e == hipSuccess) e = hipEventRecord(E[1], s->stream);
+                         s->stream, false, false, E[0], E[1]);
+      } else {
+        e = hipEventRecord(E[0], s->stream);
+        if (e == hipSuccess)
+          e = launch_force(s->s, s->rc, s->cfg.precision, ft, diag, pbc_step(s, s->step), force_grid(s, ft, n3),
+                           s->stream, false);
+        if (e == hipSuccess) e = hipEventRecord(E[1], s->stream);
+      }
       used[4 * k + 0] = 1;
       // with a pair-once tiling the one-sided pass of a diagnostic step (potential included)
       // is diagnostic work: it goes to that group, so group 0 times the pair-once kernel alone

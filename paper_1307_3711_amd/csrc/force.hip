@@ -27,6 +27,8 @@
 #include <limits>
 #include <mutex>
 
+#include <hip/hip_ext.h>
+
 #include "lc_internal.h"
 
 namespace lc {
@@ -1016,15 +1018,25 @@ int n3_resident_per_cu(int precision, const ForceTiling& ft) {
   return v;
 }
 
+// A launch, with start and stop events recorded by the dispatch itself when given (the
+// kernel's own duration, without the gaps that separately recorded events add).
+template <typename A>
+void launch_timed(void (*kern)(A), int grid, int threads, size_t lds, hipStream_t st, hipEvent_t e0,
+                  hipEvent_t e1, const A& a) {
+  if (e0) hipExtLaunchKernelGGL(kern, dim3(grid), dim3(threads), (std::uint32_t)lds, st, e0, e1, 0u, a);
+  else hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, st, a);
+}
+
 template <typename T>
-hipError_t launch_n3(const ForceTiling& ft, const N3Args<T>& a, int grid, bool pbc, hipStream_t st) {
+hipError_t launch_n3(const ForceTiling& ft, const N3Args<T>& a, int grid, bool pbc, hipStream_t st,
+                     hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   const size_t lds = n3_lds_bytes(ft, sizeof(T));
   const int threads = 64 * n3_waves(ft.R, ft.WJ);
   switch (ft.WJ * 16 + ft.R) {
-#define LC_N3_LAUNCH(R_, WJ_)                                                     \
-  case WJ_ * 16 + R_:                                                             \
-    if (pbc) k_force_n3<T, R_, WJ_, true><<<grid, threads, lds, st>>>(a);        \
-    else k_force_n3<T, R_, WJ_, false><<<grid, threads, lds, st>>>(a);           \
+#define LC_N3_LAUNCH(R_, WJ_)                                                            \
+  case WJ_ * 16 + R_:                                                                    \
+    if (pbc) launch_timed(k_force_n3<T, R_, WJ_, true>, grid, threads, lds, st, e0, e1, a); \
+    else launch_timed(k_force_n3<T, R_, WJ_, false>, grid, threads, lds, st, e0, e1, a);   \
     break;
     LC_N3_SHAPES(LC_N3_LAUNCH)
 #undef LC_N3_LAUNCH
@@ -1209,7 +1221,8 @@ bool force_tiling_valid(int precision, const ForceTiling& ft) {
 }
 
 hipError_t launch_force(const DevState& s, const RunConst& rc, int precision, const ForceTiling& ft,
-                        bool want_phi, bool pbc, int grid_blocks, hipStream_t st, bool fold_n3, bool begin_step) {
+                        bool want_phi, bool pbc, int grid_blocks, hipStream_t st, bool fold_n3, bool begin_step,
+                        hipEvent_t e0, hipEvent_t e1) {
   TileMap map{s.tile_start, s.order, s.cp, s.dyn, s.tile_total, s.queue, rc.n_clusters};
   if (begin_step && (!ft.newton3 || want_phi || ft.persistent || !s.laser_tab)) return hipErrorInvalidValue;
   if (ft.newton3 && !want_phi) {
@@ -1219,12 +1232,12 @@ hipError_t launch_force(const DevState& s, const RunConst& rc, int precision, co
     const StepBegin sb{s.dyn, s.cp, s.step, s.laser_tab, s.laser_tab0, rc.n_clusters, begin_step ? 1 : 0};
     if (precision == LC_FP64) {
       N3Args<double> a{s.posq, (double*)s.n3part, rc.n3_rows, rc.eps2, ft.persistent, map, sb};
-      e = launch_n3(ft, a, grid_blocks, pbc, st);
+      e = launch_n3(ft, a, grid_blocks, pbc, st, e0, e1);
       if (e != hipSuccess || !fold_n3) return e;
       k_fold_n3<double><<<fb, 64 * kFoldWaves, 0, st>>>(s, rc, n3_block(ft.R, ft.WJ));
     } else {
       N3Args<float> a{s.pos4, (float*)s.n3part, rc.n3_rows, rc.eps2, ft.persistent, map, sb};
-      e = launch_n3(ft, a, grid_blocks, pbc, st);
+      e = launch_n3(ft, a, grid_blocks, pbc, st, e0, e1);
       if (e != hipSuccess || !fold_n3) return e;
       k_fold_n3<float><<<fb, 64 * kFoldWaves, 0, st>>>(s, rc, n3_block(ft.R, ft.WJ));
     }

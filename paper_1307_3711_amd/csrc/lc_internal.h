@@ -331,10 +331,11 @@ __device__ inline void n3_row_partial(const DevState& s, const RunConst& rc, int
 // A pass without the potential takes the pair-once kernel when ft.newton3 is set.
 // fold_n3 = false leaves the rows unsummed for launch_fold_push.  begin_step (pair-once,
 // non-persistent passes only): the launch also does the step bookkeeping of the schedule that
-// was left out before it (the tile tables of the step before must still hold).
+// was left out before it (the tile tables of the step before must still hold).  e0, e1: events
+// the pair-once kernel's dispatch records at its start and end (timing; nullptr: none).
 hipError_t launch_force(const DevState& s, const RunConst& rc, int precision, const ForceTiling& ft,
                         bool want_phi, bool pbc, int grid_blocks, hipStream_t st, bool fold_n3 = true,
-                        bool begin_step = false);
+                        bool begin_step = false, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // n3: build the pair-once tile tables (blocks of n3_block_size(ft)) instead of target blocks
 // times splits.
 hipError_t launch_schedule(const DevState& s, const RunConst& rc, const ForceTiling& ft, bool n3, bool advance,
