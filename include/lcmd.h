@@ -301,8 +301,10 @@ int64_t lc_step_index(const lc_sim* sim);
 
 /* Average device time (ms) of the push kernel (out_ms[0]) and of the ionization kernels
  * (out_ms[1], 0 when ionization is off) over reps back-to-back launches on the current state,
- * without field passes in between (the push reuses the last field).  The state advances as if
- * stepped.  A bandwidth probe of the particle-parallel kernels; synchronizes the stream. */
+ * without field passes in between (the push reuses the last field).  Each push dispatch records
+ * its own start and end; the ionization group (check, spawn) is bracketed by events on the
+ * stream.  The state advances as if stepped.  A bandwidth probe of the particle-parallel
+ * kernels; synchronizes the stream. */
 int lc_time_particle_kernels(lc_sim* sim, int32_t reps, double out_ms[2]);
 
 /* Work counters of one cluster: out[0] steps taken (a cluster stops at its n_steps),

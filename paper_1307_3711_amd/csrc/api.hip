@@ -816,18 +816,27 @@ int lc_time_particle_kernels(lc_sim* s, int32_t reps, double out_ms[2]) {
   const bool n3 = n3_pass(s, ft, is_diag_step(s, s->step));
   const FieldLayout fl = field_layout(ft, n3);
   hipError_t e = schedule(s, ft, n3, false);
-  if (e == hipSuccess) e = hipEventRecord(ev[0], s->stream);
-  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_push(s->s, s->rc, s->cfg.precision, fl, 0, false, s->stream);
-  if (e == hipSuccess) e = hipEventRecord(ev[1], s->stream);
+  // each push dispatch records its own start and end (the kernel's duration, summed over reps)
+  std::vector<hipEvent_t> pe(2 * (size_t)reps, nullptr);
+  for (auto& x : pe)
+    if (e == hipSuccess) e = hipEventCreate(&x);
+  for (int r = 0; r < reps && e == hipSuccess; ++r)
+    e = launch_push(s->s, s->rc, s->cfg.precision, fl, 0, false, s->stream, pe[2 * r], pe[2 * r + 1]);
   if (e == hipSuccess) e = hipEventRecord(ev[2], s->stream);
   for (int r = 0; r < reps && e == hipSuccess && s->cfg.ionize; ++r)
     e = launch_ionize(s->s, s->rc, s->cfg.precision, fl, 0, s->L.n_ion_blocks, s->stream);
   if (e == hipSuccess) e = hipEventRecord(ev[3], s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   float a = 0.f, b = 0.f;
-  if (e == hipSuccess) e = hipEventElapsedTime(&a, ev[0], ev[1]);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) {
+    float m = 0.f;
+    e = hipEventElapsedTime(&m, pe[2 * r], pe[2 * r + 1]);
+    a += m;
+  }
   if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[2], ev[3]);
   for (auto& x : ev) (void)hipEventDestroy(x);
+  for (auto& x : pe)
+    if (x) (void)hipEventDestroy(x);
   if (e != hipSuccess) return hip_fail(s, e, "lc_time_particle_kernels");
   out_ms[0] = a / reps;
   out_ms[1] = s->cfg.ionize ? b / reps : 0.0;

@@ -27,8 +27,6 @@
 #include <limits>
 #include <mutex>
 
-#include <hip/hip_ext.h>
-
 #include "lc_internal.h"
 
 namespace lc {
@@ -1018,15 +1016,6 @@ int n3_resident_per_cu(int precision, const ForceTiling& ft) {
   return v;
 }
 
-// A launch, with start and stop events recorded by the dispatch itself when given (the
-// kernel's own duration, without the gaps that separately recorded events add).
-template <typename A>
-void launch_timed(void (*kern)(A), int grid, int threads, size_t lds, hipStream_t st, hipEvent_t e0,
-                  hipEvent_t e1, const A& a) {
-  if (e0) hipExtLaunchKernelGGL(kern, dim3(grid), dim3(threads), (std::uint32_t)lds, st, e0, e1, 0u, a);
-  else hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, st, a);
-}
-
 template <typename T>
 hipError_t launch_n3(const ForceTiling& ft, const N3Args<T>& a, int grid, bool pbc, hipStream_t st,
                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
@@ -1035,8 +1024,8 @@ hipError_t launch_n3(const ForceTiling& ft, const N3Args<T>& a, int grid, bool p
   switch (ft.WJ * 16 + ft.R) {
 #define LC_N3_LAUNCH(R_, WJ_)                                                            \
   case WJ_ * 16 + R_:                                                                    \
-    if (pbc) launch_timed(k_force_n3<T, R_, WJ_, true>, grid, threads, lds, st, e0, e1, a); \
-    else launch_timed(k_force_n3<T, R_, WJ_, false>, grid, threads, lds, st, e0, e1, a);   \
+    if (pbc) launch_timed(k_force_n3<T, R_, WJ_, true>, dim3(grid), dim3(threads), lds, st, e0, e1, a); \
+    else launch_timed(k_force_n3<T, R_, WJ_, false>, dim3(grid), dim3(threads), lds, st, e0, e1, a);   \
     break;
     LC_N3_SHAPES(LC_N3_LAUNCH)
 #undef LC_N3_LAUNCH

@@ -8,8 +8,12 @@
 // ascending parent order).  Per-particle arrays are structure-of-arrays FP64 except the
 // packed source records the Coulomb kernel reads (float4 or double4 {x, y, z, q}).
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <cstdint>
+#include <utility>
 
 #include "../../include/lcmd.h"
 
@@ -327,6 +331,15 @@ __device__ inline void n3_row_partial(const DevState& s, const RunConst& rc, int
   }
 }
 
+// A kernel launch whose dispatch records start and end events when e0 is given (the kernel's
+// own duration, without the gaps that events recorded separately on the stream add).
+template <typename... P, typename... A>
+inline void launch_timed(void (*kern)(P...), dim3 grid, dim3 block, size_t lds, hipStream_t st, hipEvent_t e0,
+                         hipEvent_t e1, A&&... args) {
+  if (e0) hipExtLaunchKernelGGL(kern, grid, block, (std::uint32_t)lds, st, e0, e1, 0u, std::forward<A>(args)...);
+  else hipLaunchKernelGGL(kern, grid, block, lds, st, std::forward<A>(args)...);
+}
+
 // Host launchers (defined in force.hip / step.hip).
 // A pass without the potential takes the pair-once kernel when ft.newton3 is set.
 // fold_n3 = false leaves the rows unsummed for launch_fold_push.  begin_step (pair-once,
@@ -343,8 +356,9 @@ hipError_t launch_schedule(const DevState& s, const RunConst& rc, const ForceTil
 // Laser values of steps *step + 1 .. *step + steps - 1 of every cluster into the laser table
 // (steps <= kLaserTabSteps), for force launches that take over the schedule's bookkeeping.
 hipError_t launch_laser_table(const DevState& s, const RunConst& rc, int steps, hipStream_t st);
+// e0, e1: events the push's dispatch records at its start and end (timing; nullptr: none).
 hipError_t launch_push(const DevState& s, const RunConst& rc, int precision, const FieldLayout& fl, int64_t k,
-                       bool diag, hipStream_t st);
+                       bool diag, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // Push after a pair-once pass whose rows were not folded: the fold and the push in one kernel
 // (the field is also left in split 0 for the ionization check).
 hipError_t launch_fold_push(const DevState& s, const RunConst& rc, int precision, int B, int64_t k, bool diag,

@@ -948,10 +948,11 @@ hipError_t launch_laser_table(const DevState& s, const RunConst& rc, int steps, 
 }
 
 hipError_t launch_push(const DevState& s, const RunConst& rc, int precision, const FieldLayout& fl, int64_t k,
-                       bool diag, hipStream_t st) {
-  const int pb = (int)((rc.n_total + kPushBlock - 1) / kPushBlock);
-  if (precision == LC_FP64) k_push<LC_FP64><<<pb, kPushBlock, 0, st>>>(s, rc, fl, k, diag ? 1 : 0);
-  else k_push<LC_FP32_ACC64><<<pb, kPushBlock, 0, st>>>(s, rc, fl, k, diag ? 1 : 0);
+                       bool diag, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  const dim3 pb((unsigned)((rc.n_total + kPushBlock - 1) / kPushBlock));
+  const int dg = diag ? 1 : 0;
+  if (precision == LC_FP64) launch_timed(k_push<LC_FP64>, pb, dim3(kPushBlock), 0, st, e0, e1, s, rc, fl, k, dg);
+  else launch_timed(k_push<LC_FP32_ACC64>, pb, dim3(kPushBlock), 0, st, e0, e1, s, rc, fl, k, dg);
   return hipGetLastError();
 }
 
