@@ -253,6 +253,84 @@ def test_circular_dipole_orbit_second_order(a):
     assert errs[2][0] < 2e-4 * max(a, 1.0) and errs[2][1] < 1e-3
 
 
+def _dipole_reference(a, u0, t0, t1):
+    """Electron in the linearly polarized dipole field E = (a sin t, 0, 0), B = (0, a sin t, 0)
+    from momentum u0 at the origin: du/dt = -(E + v x B), dx/dt = v, v = u / gamma, by an
+    independent eighth-order Runge-Kutta integration at tight tolerance."""
+    from scipy.integrate import solve_ivp
+
+    def rhs(t, y):
+        u = y[:3]
+        g = math.sqrt(1.0 + u @ u)
+        v = u / g
+        f = a * math.sin(t)
+        E = np.array([f, 0.0, 0.0])
+        B = np.array([0.0, f, 0.0])
+        return np.concatenate([-(E + np.cross(v, B)), v])
+
+    out = solve_ivp(rhs, (t0, t1), np.concatenate([u0, np.zeros(3)]), method="DOP853", rtol=1e-13,
+                    atol=1e-15, dense_output=True)
+    return out.sol
+
+
+def test_dipole_orbit_with_initial_momentum_second_order():
+    """An electron that starts with momentum across the magnetic field (so the start's backward
+    half kick has a v x B part) in the relativistic dipole field (a = 1): momenta at the last
+    half step and positions at the last step against an independent high-order integration of
+    the same equations of motion, converging at second order in dt (a first-order slip in the
+    start or in the position update would show as a ratio near 2)."""
+    a, t0 = 1.0, 0.3
+    u0 = np.array([0.3, 0.2, 0.4])
+    c = Cluster(species="Ar", r0_nm=1.0, n_ion=0, capacity=1, laser=Laser(envelope="flat"))
+    errs = []
+    for dt in (0.1, 0.05, 0.025):
+        run = Run(dt=dt, t0=t0, ionize=False, diag_every=0)
+        p = oracle.make_params(c, run, weight=1.0)
+        p.a0 = a
+        sim = oracle.Sim(p, 1, np.zeros((1, 3)), u0[None, :].copy(), np.array([-1], np.int8))
+        sim.start()
+        nst = int(round(10.0 / dt))
+        sim.run(nst)
+        t = t0 + nst * dt
+        ref = _dipole_reference(a, u0, t0, t)
+        eu = np.max(np.abs(sim.momenta()[0] - ref(t - dt / 2)[:3]))
+        ex = np.max(np.abs(sim.positions()[0] - ref(t)[3:]))
+        errs.append((eu, ex))
+    for k in range(2):
+        for m in range(2):
+            assert 3.4 < errs[k][m] / errs[k + 1][m] < 4.6, (k, m, errs)
+    assert errs[2][0] < 1e-3 and errs[2][1] < 1e-3
+
+
+def test_ionization_survival_at_high_rate():
+    """The check takes P = 1 - exp(-nu dt), not its first-order expansion: with the field set
+    so that nu dt = 1 (circular polarization, flat envelope, so the rate is constant), one
+    check leaves exp(-1) = 0.37 of the ions unionized (binomial count, 4.5 sigma)."""
+    n_ion = 3000
+    c = Cluster(species="Ar", r0_nm=20.0, n_ion=n_ion, capacity=3 * n_ion, z_init=1, z_max=2,
+                laser=Laser(intensity_wcm2=1e15, envelope="flat", polarization="circular"))
+    run = Run(dt=0.05, ionize=True, diag_every=0, seed=23)
+    sim = oracle.Sim.from_workload(c, run, initial_state(c, 23))
+    p = sim.p
+    p.kappa = 0.0
+    lo, hi = 1e-4, 10.0  # a0 with nu(a0) dt = 1, by bisection in log space
+    for _ in range(200):
+        mid = math.sqrt(lo * hi)
+        if oracle.adk_rate(p.ip_au[1], 2.0, mid * p.field_au) * p.rate_scale * p.dt < 1.0:
+            lo = mid
+        else:
+            hi = mid
+    p.a0 = hi
+    nu_dt = oracle.adk_rate(p.ip_au[1], 2.0, p.a0 * p.field_au) * p.rate_scale * p.dt
+    assert abs(nu_dt - 1.0) < 1e-9
+    sim.start()
+    sim.run(1)
+    surv = np.mean(sim.charges()[:n_ion] == 1)
+    expect = math.exp(-1.0)
+    sigma = math.sqrt(expect * (1 - expect) / n_ion)
+    assert abs(surv - expect) < 4.5 * sigma, (surv, expect)
+
+
 def test_ionization_survival_law_circular():
     """Circular polarization with a flat envelope keeps |E_L| = a0 at every phase, so the
     laser-only ADK rate nu is constant and an ion that may ionize once survives n checks with
