@@ -344,7 +344,7 @@ hipError_t enqueue_steps(lc_sim* s, int count, int64_t first_step) {
   // The tables of the first step were built by the previous step's closing schedule (or by
   // lc_start / a tiling change); every step ends with the schedule of the next one, except
   // inside a group of steps where nothing can change the tables (begin below).
-  const bool tab = s->s.laser_tab && !s->cfg.ionize && ft.newton3 && !ft.persistent && count > 1;
+  const bool tab = s->s.laser_tab && !s->cfg.ionize && count > 1;
   const int tab_steps = std::min(count, kLaserTabSteps);
   if (tab) {
     hipError_t e = launch_laser_table(s->s, s->rc, tab_steps, s->stream);
@@ -370,14 +370,15 @@ hipError_t enqueue_steps(lc_sim* s, int count, int64_t first_step) {
       if (e != hipSuccess) return e;
     }
     const bool n3_next = n3_pass(s, ft, is_diag_step(s, first_step + k + 1));
-    // Without ionization no particle count changes, so between two pair-once steps of this
-    // group the tile tables stay as they are: the schedule is left out and the next step's
-    // force launch does its bookkeeping (step count, active flags, step index, and the laser
-    // value from the table filled at the group's start).
-    // A cluster that retires there keeps its tiles until the group's last schedule; its rows
-    // are computed but not read (its push is off).  The group's last step always schedules,
-    // so the device state between calls is the same as with a schedule after every step.
-    begin = tab && n3 && n3_next && k + 1 < tab_steps;
+    // Without ionization no particle count changes, so between two steps of this group that
+    // take the same kind of pass (pair-once, or one-sided) the tile tables stay as they are:
+    // the schedule is left out and the next step's force launch does its bookkeeping (step
+    // count, active flags, step index, and the laser value from the table filled at the
+    // group's start).  A cluster that retires there keeps its tiles until the group's last
+    // schedule; its field is computed but not used (its push is off).  The group's last step
+    // always schedules, so the device state between calls is the same as with a schedule
+    // after every step.
+    begin = tab && n3 == n3_next && !pass_tiling(s, ft, n3).persistent && k + 1 < tab_steps;
     if (!begin) {
       e = schedule(s, ft, n3_next, true);
       if (e != hipSuccess) return e;
@@ -1149,11 +1150,11 @@ extern "C" int lc_autotune(lc_sim* s, const char* cache_json, lc_tuning* chosen)
   int64_t nmax = 0;
   for (int c = 0; c < s->C; ++c) nmax = std::max(nmax, s->n_host[c]);
   // average of `reps` field passes (schedule + Coulomb kernel), after one untimed pass; a
-  // non-persistent pair-once pass of a run whose steps leave the schedule out inside graph
-  // groups (no ionization, a laser table) is timed without it, as those steps run
+  // non-persistent pass of a run whose steps leave the schedule out inside graph groups (no
+  // ionization, a laser table) is timed without it, as those steps run
   auto time_pass = [&](const ForceTiling& ft, int reps, float* ms) {
     const bool n3 = ft.newton3 != 0;
-    const bool sched = !(n3 && !ft.persistent && s->s.laser_tab && !s->cfg.ionize);
+    const bool sched = !(!ft.persistent && s->s.laser_tab && !s->cfg.ionize);
     const int grid = force_grid(s, ft, n3);
     hipError_t e = schedule(s, ft, n3, false);
     const bool pbc = pbc_step(s, s->step);

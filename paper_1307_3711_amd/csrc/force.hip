@@ -45,6 +45,34 @@ struct TileMap {
   int n_clusters;
 };
 
+// Step bookkeeping a Coulomb launch takes over when no schedule launch precedes it (the tile
+// tables of the step before still hold): the first wave of block 0 counts the step just taken
+// and sets the next step's index and laser value (from the laser table, so that no
+// transcendental function enters these kernels), fields no tile of the launch reads.
+struct StepBegin {
+  ClusterDyn* dyn;
+  const ClusterParams* cp;
+  int64_t* step;
+  const double* tab;
+  const int64_t* tab0;
+  int n_clusters;
+  int on;
+};
+
+// One wave: every lane loads the step index before lane 0 stores the next one.
+__device__ inline void begin_step_wave(const StepBegin& b) {
+  const int64_t n = *b.step + 1;
+  const double* row = b.tab + 3 * (n - *b.tab0) * b.n_clusters;
+  for (int c = threadIdx.x; c < b.n_clusters; c += 64) {
+    ClusterDyn& d = b.dyn[c];
+    begin_step_counts(b.cp[c], d, 1, n);
+    d.env = row[3 * c];
+    d.laser_e = row[3 * c + 1];
+    d.laser_ey = row[3 * c + 2];
+  }
+  if (threadIdx.x == 0) *b.step = n;
+}
+
 template <typename Src>
 struct ForceArgs {
   const Src* src;      // source/target records, global slot indexed
@@ -55,6 +83,7 @@ struct ForceArgs {
   int S;               // splits
   int persistent;
   TileMap map;
+  StepBegin begin;
 };
 
 __device__ inline void decode_tile(const TileMap& m, int t, int S, int& c, int& ib, int& s) {
@@ -475,34 +504,6 @@ template <> struct N3Type<double> {
   static constexpr double kFar = 1e150;
 };
 
-// Step bookkeeping a pair-once launch takes over when no schedule launch precedes it (the
-// tile tables of the step before still hold): the first wave of block 0 counts the step just
-// taken and sets the next step's index and laser value (from the laser table, so that no
-// transcendental function enters this kernel), fields no tile of the launch reads.
-struct StepBegin {
-  ClusterDyn* dyn;
-  const ClusterParams* cp;
-  int64_t* step;
-  const double* tab;
-  const int64_t* tab0;
-  int n_clusters;
-  int on;
-};
-
-// One wave: every lane loads the step index before lane 0 stores the next one.
-__device__ inline void begin_step_wave(const StepBegin& b) {
-  const int64_t n = *b.step + 1;
-  const double* row = b.tab + 3 * (n - *b.tab0) * b.n_clusters;
-  for (int c = threadIdx.x; c < b.n_clusters; c += 64) {
-    ClusterDyn& d = b.dyn[c];
-    begin_step_counts(b.cp[c], d, 1, n);
-    d.env = row[3 * c];
-    d.laser_e = row[3 * c + 1];
-    d.laser_ey = row[3 * c + 2];
-  }
-  if (threadIdx.x == 0) *b.step = n;
-}
-
 template <typename T>
 struct N3Args {
   const typename N3Type<T>::V4* src;  // source records, global slot indexed
@@ -878,6 +879,7 @@ void k_force_n3(N3Args<T> a) {
 template <int R, int WJ, bool PHI, bool KAHAN, bool SCALAR, bool PBC>
 __global__ __launch_bounds__(kBlock) void k_force_f32(ForceArgs<float4> a, const float4* __restrict__ gsrc) {
   extern __shared__ float4 lds32[];
+  if (a.begin.on && blockIdx.x == 0 && threadIdx.x < 64) begin_step_wave(a.begin);
   const int total = *a.map.tile_total;
   if (!a.persistent) {
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
@@ -900,6 +902,7 @@ __global__ __launch_bounds__(kBlock) void k_force_f32(ForceArgs<float4> a, const
 template <int R, int WJ, bool PHI, bool PBC>
 __global__ __launch_bounds__(kBlock) void k_force_f64(ForceArgs<double4> a) {
   extern __shared__ double4 lds64[];
+  if (a.begin.on && blockIdx.x == 0 && threadIdx.x < 64) begin_step_wave(a.begin);
   const int total = *a.map.tile_total;
   if (!a.persistent) {
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
@@ -1043,10 +1046,11 @@ hipError_t launch_n3(const ForceTiling& ft, const N3Args<T>& a, int grid, bool p
   }
 
 hipError_t launch_generic(int precision, const ForceTiling& ft, const TileMap& map, const void* src,
-                          double* part, int64_t stride, double eps2, bool phi, bool pbc, int grid, hipStream_t st) {
+                          double* part, int64_t stride, double eps2, bool phi, bool pbc, int grid, hipStream_t st,
+                          const StepBegin& sb = StepBegin{}) {
   const size_t lds = force_lds_bytes(precision, ft, phi);
   if (precision == LC_FP64) {
-    ForceArgs<double4> a{(const double4*)src, part, stride, eps2, ft.T, ft.S, ft.persistent, map};
+    ForceArgs<double4> a{(const double4*)src, part, stride, eps2, ft.T, ft.S, ft.persistent, map, sb};
     switch (ft.R) {
       case 1: LC_WJ_SWITCH(1, dispatch_f64, a, phi, pbc, grid, lds, st)
       case 2: LC_WJ_SWITCH(2, dispatch_f64, a, phi, pbc, grid, lds, st)
@@ -1054,7 +1058,7 @@ hipError_t launch_generic(int precision, const ForceTiling& ft, const TileMap& m
       default: return hipErrorInvalidValue;
     }
   }
-  ForceArgs<float4> a{(const float4*)src, part, stride, eps2, ft.T, ft.S, ft.persistent, map};
+  ForceArgs<float4> a{(const float4*)src, part, stride, eps2, ft.T, ft.S, ft.persistent, map, sb};
   const int kahan = (precision == LC_FP32_KAHAN);
   switch (ft.R) {
     case 1: LC_WJ_SWITCH(1, dispatch_f32, a, phi, kahan, ft.scalar_src, pbc, grid, lds, st)
@@ -1213,12 +1217,12 @@ hipError_t launch_force(const DevState& s, const RunConst& rc, int precision, co
                         bool want_phi, bool pbc, int grid_blocks, hipStream_t st, bool fold_n3, bool begin_step,
                         hipEvent_t e0, hipEvent_t e1) {
   TileMap map{s.tile_start, s.order, s.cp, s.dyn, s.tile_total, s.queue, rc.n_clusters};
-  if (begin_step && (!ft.newton3 || want_phi || ft.persistent || !s.laser_tab)) return hipErrorInvalidValue;
+  if (begin_step && (ft.persistent || !s.laser_tab)) return hipErrorInvalidValue;
+  const StepBegin sb{s.dyn, s.cp, s.step, s.laser_tab, s.laser_tab0, rc.n_clusters, begin_step ? 1 : 0};
   if (ft.newton3 && !want_phi) {
     if (precision == LC_FP32_KAHAN || rc.n3_rows <= 0) return hipErrorInvalidValue;
     hipError_t e;
     const int fb = (int)((rc.n_total + 63) / 64);
-    const StepBegin sb{s.dyn, s.cp, s.step, s.laser_tab, s.laser_tab0, rc.n_clusters, begin_step ? 1 : 0};
     if (precision == LC_FP64) {
       N3Args<double> a{s.posq, (double*)s.n3part, rc.n3_rows, rc.eps2, ft.persistent, map, sb};
       e = launch_n3(ft, a, grid_blocks, pbc, st, e0, e1);
@@ -1234,7 +1238,8 @@ hipError_t launch_force(const DevState& s, const RunConst& rc, int precision, co
   }
   const void* src = (precision == LC_FP64) ? (const void*)s.posq : (const void*)s.pos4;
   const ForceTiling fr = ft.newton3 ? regular_tiling(precision, ft) : ft;
-  return launch_generic(precision, fr, map, src, s.part, rc.n_total, rc.eps2, want_phi, pbc, grid_blocks, st);
+  if (begin_step && fr.persistent) return hipErrorInvalidValue;
+  return launch_generic(precision, fr, map, src, s.part, rc.n_total, rc.eps2, want_phi, pbc, grid_blocks, st, sb);
 }
 
 // ----------------------------------------------------------------------------- allocation-free field

@@ -200,12 +200,14 @@ def test_determinism_and_graph_replay_bitwise(tiling):
 
 
 @pytest.mark.parametrize("precision", ["fp32_acc64", "fp64"])
-def test_schedule_left_out_without_ionization_bitwise(precision):
-    """Without ionization a captured group of pair-once steps leaves the schedule out between
-    its steps and the next force launch does the step bookkeeping; stepping one step at a time
-    schedules after every step.  Two clusters, one retiring inside a group (its tiles stay until
-    the group's last schedule, its state must not move): positions, momenta, records, counted
-    steps and pair interactions bitwise identical either way."""
+@pytest.mark.parametrize("pair_once", [True, False])
+def test_schedule_left_out_without_ionization_bitwise(precision, pair_once):
+    """Without ionization a captured group of steps leaves the schedule out between its steps
+    of the same kind of pass (pair-once, or one-sided, diagnostic steps included) and the next
+    force launch does the step bookkeeping; stepping one step at a time schedules after every
+    step.  Two clusters, one retiring inside a group (its tiles stay until the group's last
+    schedule, its state must not move): positions, momenta, records, counted steps and pair
+    interactions bitwise identical either way."""
     import paper_1307_3711_amd as lc
     laser = Laser(intensity_wcm2=1e16, envelope="flat")
     cl = [Cluster(species="Ar", r0_nm=2.0, n_ion=300, capacity=600, z_init=1, z_max=8, laser=laser),
@@ -215,7 +217,10 @@ def test_schedule_left_out_without_ionization_bitwise(precision):
     mpb = lc.pair_blocks_for([c.capacity for c in cl])
     out = []
     for graph in (0, 20):
-        tiling = N3 if precision == "fp32_acc64" else dict(R=4, WJ=4, newton3=1)
+        if pair_once:
+            tiling = N3 if precision == "fp32_acc64" else dict(R=4, WJ=4, newton3=1)
+        else:
+            tiling = dict(R=2, WJ=2, S=2) if precision == "fp64" else dict(R=4, WJ=1, S=4)
         sim, _ = gpu_run(cl, run, precision, states=states, n_steps_per_cluster=[0, 33], tuning=tiling,
                          max_pair_blocks=mpb)
         if graph:
