@@ -5,6 +5,7 @@ arguments and lends PyTorch device memory and streams to the library.
 """
 from ._binding import (  # noqa: F401
     LC_MAX_Z, LC_REC, LC_DET_BINS, LC_DET_SLOTS, LC_FIELD_STATIC_MAX_BYTES, LcError, Simulation, Surrogate, field,
+    LC_OK, LC_E_INVALID, LC_E_CAPACITY, LC_E_NONFINITE, LC_E_HIP, LC_E_STATE, LC_E_UNSUPPORTED,
     field_static, lib, make_cluster,
     make_config, make_tuning, pair_blocks_for, units,
     PRECISIONS, ENVELOPES, PHASES, OFI, POLARIZATIONS, BOUNDARIES,
