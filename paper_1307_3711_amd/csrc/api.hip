@@ -538,6 +538,7 @@ int lc_create(lc_sim** out, const lc_config* cfg, const lc_cluster* clusters, in
     int64_t cap_max = 1;
     for (int c = 0; c < n_clusters; ++c) cap_max = std::max<int64_t>(cap_max, clusters[c].capacity);
     rc.ci_blocks = (int32_t)std::min<int64_t>(kDiagBlocks, (cap_max + 2047) / 2048);
+    rc.diag_blocks = diag_blocks_for(cap_max);
     int64_t ib_max = 0;
     for (int c = 0; c < n_clusters; ++c) ib_max = std::max<int64_t>(ib_max, (clusters[c].n_ion + kBlock - 1) / kBlock);
     rc.max_ion_blocks = (int32_t)ib_max;

@@ -22,7 +22,8 @@ namespace lc {
 constexpr int kBlock = 256;          // threads per block of the particle-parallel kernels
 constexpr int kGroup = 64;           // slots per group: clusters start on group boundaries
 constexpr int kDiagQ = 48;           // doubles per per-block diagnostic partial
-constexpr int kDiagBlocks = 64;      // blocks per cluster in the diagnostic reduction
+constexpr int kDiagBlocks = 64;      // at most this many blocks per cluster in the diagnostic reduction
+constexpr int kDiagSlots = 512;      // slots per block of the diagnostic reduction (up to kDiagBlocks)
 constexpr int kHist = 17;            // charge histogram bins 0..16
 
 // Field partial components written per source split: Ex, Ey, Ez, phi.
@@ -118,7 +119,15 @@ struct RunConst {
   double det_cos2;      // cos^2 of the detectors' acceptance half-angle
   double t_switch;      // LC_MIXED: first time (1/w) with open boundaries
   int32_t max_ion_blocks;  // ion blocks (256 ions) of the largest cluster
+  int32_t diag_blocks;     // diag_blocks_for() of the largest cluster: the diagnostic grid's width
 };
+
+// Blocks of the diagnostic reduction of a cluster with cap slots.  A function of the cluster's
+// own capacity only, so a cluster's records do not depend on the rest of the ensemble.
+__host__ __device__ inline int diag_blocks_for(int64_t cap) {
+  const int64_t b = (cap + kDiagSlots - 1) / kDiagSlots;
+  return (int)(b < 1 ? 1 : (b > kDiagBlocks ? kDiagBlocks : b));
+}
 
 // Periodic boundaries in force at time t (the step's t^n): always for LC_PERIODIC, before
 // t_switch for LC_MIXED, never for LC_OPEN.  Host and device take the same decision.

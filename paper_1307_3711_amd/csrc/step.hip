@@ -453,12 +453,22 @@ __global__ __launch_bounds__(kBlock) void k_sum_kestart(DevState s) {
 }
 
 // ----------------------------------------------------------------------------- diagnostics (S5)
-// Partial sums per (cluster, block); quantity layout:
+// Partial sums per (cluster, block), diag_blocks_for(capacity) blocks per cluster each taking
+// every nb-th run of 256 slots; quantity layout:
 //  0 KE(n+1/2)  1 KE(n)  2 PE  3 W_L  4 W_C  5 spawn KE  6-8 momentum  9-11 sum w Z E_C
 //  12 sum w|Z||E_C|  13 ions  14 electrons  15 sum of ion charges  16..32 charge histogram
+// Quantities 0-12 are FP64 sums per lane, added over the wave in a fixed order; 13-32 are
+// integer tallies (wave ballots for the counts, a per-lane sum for the charges), exact in any order.
 constexpr int kQ = 33;
+constexpr int kQf = 13;  // floating-point quantities
 
 __device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ inline int wave_sum_int(int v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
@@ -469,47 +479,63 @@ __global__ __launch_bounds__(kBlock) void k_diag_partial(DevState s, RunConst rc
   const int c = blockIdx.y;
   const ClusterParams& cp = s.cp[c];
   const ClusterDyn& d = s.dyn[c];
-  if (!d.active) return;
-  double q[kQ];
+  const int nb = diag_blocks_for(cp.cap);
+  if (!d.active || (int)blockIdx.x >= nb) return;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  double q[kQf];
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) q[i] = 0.0;
-  for (int64_t li = (int64_t)blockIdx.x * kBlock + threadIdx.x; li < d.n_cur; li += (int64_t)kDiagBlocks * kBlock) {
-    const int64_t g = cp.off + li;
-    const int zc = s.Z[g];
-    const double M = (zc < 0) ? 1.0 : cp.mass_ion;
-    const double w = cp.weight;
-    const double ux = s.ux[g], uy = s.uy[g], uz = s.uz[g];
-    double ex, ey, ez;
-    field_sum(s, rc, fl, g, ex, ey, ez);
-    double phi = 0.0;
-    for (int k = 0; k < fl.S; ++k) phi += s.part[((int64_t)k * kComp + 3) * rc.n_total + g];
-    q[0] += w * M * gm1(ux, uy, uz);
-    q[1] += s.kebar[g];
-    q[2] += 0.5 * w * (double)zc * phi;
-    q[3] += s.wl[g];
-    q[4] += s.wc[g];
-    q[5] += s.wsp[g];
-    q[6] += w * M * ux;
-    q[7] += w * M * uy;
-    q[8] += w * M * uz;
-    q[9] += w * (double)zc * ex;
-    q[10] += w * (double)zc * ey;
-    q[11] += w * (double)zc * ez;
-    q[12] += w * fabs((double)zc) * sqrt(ex * ex + ey * ey + ez * ez);
-    if (zc < 0) {
-      q[14] += 1.0;
-    } else {
-      q[13] += 1.0;
-      q[15] += (double)zc;
+  for (int i = 0; i < kQf; ++i) q[i] = 0.0;
+  int zsum = 0;                            // this lane's sum of ion charges
+  int n_ion = 0, n_el = 0, hist[kHist];    // the wave's counts (the same in every lane)
 #pragma unroll
-      for (int b = 0; b < kHist; ++b) q[16 + b] += (zc == b) ? 1.0 : 0.0;
+  for (int b = 0; b < kHist; ++b) hist[b] = 0;
+  // every lane of a wave runs the same iterations, so every ballot sees the whole wave
+  for (int64_t base = (int64_t)blockIdx.x * kBlock + kGroup * wv; base < d.n_cur; base += (int64_t)nb * kBlock) {
+    const int64_t li = base + lane;
+    const bool ok = li < d.n_cur;
+    int zc = 0;
+    if (ok) {
+      const int64_t g = cp.off + li;
+      zc = s.Z[g];
+      const double M = (zc < 0) ? 1.0 : cp.mass_ion;
+      const double w = cp.weight;
+      const double ux = s.ux[g], uy = s.uy[g], uz = s.uz[g];
+      double ex, ey, ez;
+      field_sum(s, rc, fl, g, ex, ey, ez);
+      double phi = 0.0;
+      for (int k = 0; k < fl.S; ++k) phi += s.part[((int64_t)k * kComp + 3) * rc.n_total + g];
+      q[0] += w * M * gm1(ux, uy, uz);
+      q[1] += s.kebar[g];
+      q[2] += 0.5 * w * (double)zc * phi;
+      q[3] += s.wl[g];
+      q[4] += s.wc[g];
+      q[5] += s.wsp[g];
+      q[6] += w * M * ux;
+      q[7] += w * M * uy;
+      q[8] += w * M * uz;
+      q[9] += w * (double)zc * ex;
+      q[10] += w * (double)zc * ey;
+      q[11] += w * (double)zc * ez;
+      q[12] += w * fabs((double)zc) * sqrt(ex * ex + ey * ey + ez * ez);
+      if (zc >= 0) zsum += zc;
     }
-  }
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    n_el += __popcll(__ballot(ok && zc < 0));
+    n_ion += __popcll(__ballot(ok && zc >= 0));
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) {
+    for (int b = 0; b < kHist; ++b) hist[b] += __popcll(__ballot(ok && zc == b));
+  }
+#pragma unroll
+  for (int i = 0; i < kQf; ++i) {
     const double v = wave_sum(q[i]);
     if (lane == 0) sh[wv][i] = v;
+  }
+  zsum = wave_sum_int(zsum);
+  if (lane == 0) {
+    sh[wv][13] = (double)n_ion;
+    sh[wv][14] = (double)n_el;
+    sh[wv][15] = (double)zsum;
+#pragma unroll
+    for (int b = 0; b < kHist; ++b) sh[wv][16 + b] = (double)hist[b];
   }
   __syncthreads();
   if (threadIdx.x < kQ) {
@@ -527,7 +553,9 @@ __global__ __launch_bounds__(64) void k_diag_final(DevState s, RunConst rc, int6
   if (!d.active) return;
   if (threadIdx.x < kQ) {
     double v = 0.0;
-    for (int b = 0; b < kDiagBlocks; ++b) v += s.diag_part[((int64_t)c * kDiagBlocks + b) * kDiagQ + threadIdx.x];
+    const int nb = diag_blocks_for(cp.cap);
+#pragma unroll 8
+    for (int b = 0; b < nb; ++b) v += s.diag_part[((int64_t)c * kDiagBlocks + b) * kDiagQ + threadIdx.x];
     tot[threadIdx.x] = v;
   }
   __syncthreads();
@@ -982,7 +1010,7 @@ hipError_t launch_start_kick(const DevState& s, const RunConst& rc, int precisio
 }
 
 hipError_t launch_diag(const DevState& s, const RunConst& rc, const FieldLayout& fl, int64_t k, hipStream_t st) {
-  k_diag_partial<<<dim3(kDiagBlocks, rc.n_clusters), kBlock, 0, st>>>(s, rc, fl);
+  k_diag_partial<<<dim3(rc.diag_blocks, rc.n_clusters), kBlock, 0, st>>>(s, rc, fl);
   k_diag_final<<<rc.n_clusters, 64, 0, st>>>(s, rc, k);
   return hipGetLastError();
 }
