@@ -2,7 +2,8 @@
 
 Element by element on seeded cluster states spanning several LDS tiles, target blocks and a
 ragged tail, for every precision and a range of tilings; then sampled targets of the full
-20k-macroparticle argon state in the tiling the benchmark uses.
+20k-macroparticle argon state in the tiling the benchmark uses, and of a cluster of a million
+macroparticles (pair-once rows beyond 32-bit offsets).
 
 Tolerances (fixed before measuring):
   FP64: per target |dE| <= 1e-12 * S1_i and |dphi| <= 1e-12 * S0_i, where
@@ -227,6 +228,43 @@ def test_field_full_20k_sampled(precision, tiling):
     assert np.all(np.abs(Eg[idx] - Eo) <= tol * s1[:, None])
     if phi:
         assert np.all(np.abs(Pg[idx] - Po) <= tol * s0)
+
+
+@pytest.mark.skipif(not gpu_available(), reason="needs a GPU")
+@pytest.mark.parametrize("precision,tiling", [("fp32_acc64", None), ("fp32_acc64", dict(R=4, WJ=4, newton3=1)),
+                                              ("fp32_acc64", dict(R=4, WJ=4, S=64, persistent=1)),
+                                              ("fp64", dict(S=16)), ("fp64", dict(R=4, WJ=4, newton3=1))])
+def test_field_one_million_sampled(precision, tiling):
+    """One cluster of a million macroparticles (500k Ar+ + 500k e-, R0 = 30 nm, the density of
+    the 20k state): 3907 blocks of 256 targets, 7.6M pair-once tiles whose rows (47 GB in FP32,
+    94 GB in FP64) sit far beyond 32-bit element offsets.  Sampled targets (first and last
+    slots, both sides of block and ion/electron boundaries) against the oracle target by
+    target, at the bars of the 20k test."""
+    n_ion = 500_000
+    c = Cluster(species="Ar", r0_nm=30.0, n_ion=n_ion, capacity=2 * n_ion, z_init=1)
+    st = initial_state(c, 3)
+    x = units.nm_to_norm(st["x_nm"], 0.8)
+    q = units.kappa(0.8) * (units.n_atoms(30.0, 2.4) / n_ion) * st["Z"].astype(np.float64)
+    n = x.shape[0]
+    idx = np.array([0, 1, 255, 256, 257, 65535, 65536, 262143, 262144, n_ion - 1, n_ion, n_ion + 1, 777_777,
+                    n - 257, n - 256, n - 2, n - 1])
+    print(f"{precision} {tiling}: n={n}", flush=True)
+    Eg, _ = _gpu_field(x, q, EPS2, precision, tiling, phi=False)
+    import torch
+    torch.cuda.empty_cache()  # hand the workspace back before the next case
+    if precision == "fp64":
+        Eo, _ = oracle.coulomb_field_at(x, q, EPS2, idx, want_phi=False)
+        tol = 1e-12
+    else:
+        xr = x.astype(np.float32).astype(np.float64)
+        qr = q.astype(np.float32).astype(np.float64)
+        Eo, _ = oracle.coulomb_field_at(xr, qr, float(np.float32(EPS2)), idx, want_phi=False)
+        tol = 64 * U32
+    s1, _ = _scales(x, q, EPS2, idx)
+    err = np.max(np.abs(Eg[idx] - Eo) / s1[:, None])
+    print(f"max error / S1 = {err:.2e}", flush=True)
+    assert err <= tol
+    assert np.all(np.isfinite(Eg))
 
 
 def _s3(x, q, eps2, idx):
