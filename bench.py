@@ -660,7 +660,7 @@ def _features_of(cl):
 
 
 def bench_surrogate(args):
-    """Train the 4-64-64-2 surrogate on ensemble MD runs, time 1M-point inference, and judge it
+    """Train the 4-64-64-2 surrogate on ensemble MD runs, time 1M-point inference, and score it
     on held-out clusters re-run by the MD (three extra seeds give the MD's own spread)."""
     import numpy as np
     import torch
@@ -843,7 +843,7 @@ def main():
     tiling = parse_tiling(args.tiling)
     tiling64 = parse_tiling(args.tiling_fp64)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
 

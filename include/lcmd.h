@@ -51,7 +51,7 @@ typedef enum {
   LC_E_NONFINITE = -3,    /* a position or momentum became NaN/Inf                       */
   LC_E_HIP = -4,          /* a HIP runtime call failed                                   */
   LC_E_STATE = -5,        /* call out of order (e.g. step before start)                  */
-  LC_E_UNSUPPORTED = -6   /* valid request this build does not implement                 */
+  LC_E_UNSUPPORTED = -6   /* valid request the library does not implement                */
 } lc_status;
 
 /* Pair arithmetic of the Coulomb direct sum. */
