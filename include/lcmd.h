@@ -341,7 +341,11 @@ void lc_destroy(lc_sim* sim);
 
 /* ---------------------------------------------------------------- the field alone */
 
-/* Workspace bytes for lc_field with n particles, a precision and a tiling (NULL: default). */
+/* Workspace bytes for lc_field with n particles, a precision and a tiling (NULL: default);
+ * 0 for an invalid precision, tiling or n < 0.  One-sided tilings need S * 32 bytes per
+ * particle plus the source records; a pair-once tiling (newton3 = 1, blocks of B slots) keeps
+ * 3 n ceil(n / B) partial sums in the pair type, about 12 n^2 / B bytes in FP32 (47 GB at
+ * n = 1M, B = 256) and twice that in FP64. */
 size_t lc_field_workspace_bytes(int32_t precision, int64_t n, const lc_tuning* t);
 
 /* Softened Coulomb field of n point sources on themselves (Sec. II force from every other
@@ -352,7 +356,9 @@ size_t lc_field_workspace_bytes(int32_t precision, int64_t n, const lc_tuning* t
  * d_E: device, 3 n doubles out, laid out Ex[n], Ey[n], Ez[n].  d_work: caller-owned device
  * workspace of at least lc_field_workspace_bytes().  Asynchronous on hip_stream.
  * A tiling with newton3 = 1 computes E only (d_phi must be NULL).
- * LC_E_INVALID for n < 0, eps2 <= 0, a too small workspace or an unknown tiling. */
+ * LC_E_INVALID for n < 0, n > 2^30, eps2 <= 0, a workspace that is too small or not 256-byte
+ * aligned, or an unknown tiling; LC_E_HIP when a launch fails (also for a request of more than
+ * 2^31 - 1 tiles). */
 int lc_field(int32_t precision, int64_t n, const double* d_xyzq, double eps2, double* d_E,
              double* d_phi, void* d_work, size_t work_bytes, const lc_tuning* t, void* hip_stream);
 
