@@ -964,7 +964,7 @@ def main():
                 "fp64": oracle_record_errors(sim64, c.n_steps - total_steps)}
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(c, run, st, n)
+        out["cpu_baseline"] = cpu_baseline(c, run, st, n, target_s=13.0)
     print(json.dumps(out), flush=True)
 
 
