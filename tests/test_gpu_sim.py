@@ -236,6 +236,36 @@ def test_schedule_left_out_without_ionization_bitwise(precision, pair_once):
     assert out[1][1][2]["steps"] == 33 and out[1][0][2]["steps"] == 60
 
 
+@pytest.mark.parametrize("precision,pair_once", [("fp32_acc64", True), ("fp64", False)])
+def test_schedule_left_out_in_groups_longer_than_the_laser_table(precision, pair_once):
+    """Groups of 300 captured steps: the laser table covers the first 256 steps of a group, after
+    which every step schedules again; a cluster retires inside the second group.  Bitwise equal
+    to stepping one step at a time."""
+    import paper_1307_3711_amd as lc
+    laser = Laser(intensity_wcm2=1e16, envelope="flat")
+    cl = [Cluster(species="Ar", r0_nm=2.0, n_ion=150, capacity=300, z_init=1, z_max=8, laser=laser),
+          Cluster(species="Ar", r0_nm=1.5, n_ion=50, capacity=100, z_init=1, z_max=8, laser=laser)]
+    run = Run(dt=0.05, ionize=False, diag_every=50, seed=4)
+    states = [initial_state(c, run.seed, i) for i, c in enumerate(cl)]
+    mpb = lc.pair_blocks_for([c.capacity for c in cl])
+    tiling = N3 if pair_once else dict(R=2, WJ=2, S=2)
+    out = []
+    for graph in (0, 300):
+        sim, _ = gpu_run(cl, run, precision, states=states, n_steps_per_cluster=[0, 450], tuning=tiling,
+                         max_pair_blocks=mpb)
+        if graph:
+            sim.set_graph(graph)
+        print(f"{precision} graph={graph}: 600 steps", flush=True)
+        sim.step(600)
+        out.append([(sim.particles(i), sim.diagnostics(i), sim.counters(i)) for i in range(len(cl))])
+        sim.close()
+    for (g0, r0, c0), (g1, r1, c1) in zip(out[0], out[1]):
+        assert np.array_equal(g0["x"], g1["x"]) and np.array_equal(g0["u"], g1["u"])
+        assert np.array_equal(r0, r1)
+        assert c0 == c1, (c0, c1)
+    assert out[1][1][2]["steps"] == 450 and out[1][0][2]["steps"] == 600
+
+
 def test_checkpoint_resume_bitwise():
     c, run = small_ar()
     sim, states = gpu_run([c], run, "fp64")
