@@ -259,13 +259,16 @@ ION_BYTES = 9        # per ion: read Z (1), write + read the ionization flag (8)
 def bench_scan(args):
     """Coulomb-kernel rate against N: argon clusters at the density of the 20k workload
     (R0 = 8 nm (N / 20000)^(1/3), Ar+ and e- pairs, charges frozen), one-sided scalar-source
-    tiling and pair-once tiling, each timed with HIP events around its field passes."""
+    tiling and pair-once tiling in FP32 pairs with FP64 accumulation, and the one-sided tiling
+    with Kahan-compensated FP32 sums, each timed with HIP events around its field passes."""
     import paper_1307_3711_amd as lc
     from workloads import Cluster, Laser, Run, initial_state
     from workloads.species import SPECIES
     sizes = [int(v) for v in args.sizes.split(",")]
     tilings = {"one_sided": dict(R=1, WJ=4, T=1024, S=16, scalar=1),
-               "pair_once": dict(R=4, WJ=4, T=1024, S=16, scalar=1, newton3=1)}
+               "pair_once": dict(R=4, WJ=4, T=1024, S=16, scalar=1, newton3=1),
+               "kahan_one_sided": dict(R=1, WJ=4, T=1024, S=16, scalar=1)}
+    precisions = {"one_sided": "fp32_acc64", "pair_once": "fp32_acc64", "kahan_one_sided": "fp32_kahan"}
     res = []
     for n in sizes:
         r0 = 8.0 * (n / 20000.0) ** (1.0 / 3.0)
@@ -275,7 +278,7 @@ def bench_scan(args):
         st = initial_state(c, run.seed)
         row = {"n": n, "r0_nm": round(r0, 3)}
         for name, til in tilings.items():
-            sim, _ = make_sim("fp32_acc64", c, run, st, 0, til)
+            sim, _ = make_sim(precisions[name], c, run, st, 0, til)
             sim.profile_steps(max(20, args.reps))  # warm-up at steady clocks, same launches
             prof = sim.profile_steps(args.reps)
             ms, cnt = prof["field"]
@@ -290,7 +293,7 @@ def bench_scan(args):
            "ms_per_step": res[-1]["pair_once"]["us_per_pass"] / 1e3, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "fp32+fp64acc", "data": "synthetic",
            "config": {"workload": "Ar clusters at the 20k workload's density, sizes " + args.sizes,
-                      "tilings": tilings},
+                      "tilings": tilings, "precisions": precisions},
            "scan": res}
     print(json.dumps(out), flush=True)
 
