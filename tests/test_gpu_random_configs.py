@@ -1,8 +1,8 @@
 """Seeded random configurations against the oracle: ensembles of one to four clusters with
 random species, radius, ion count (edge counts 0, 1, 63, 64, 65 among them), initial charge,
 charge cap, capacity slack, intensity, envelope, polarization and start time, each run in a
-random precision, tiling (one-sided or pair-once, plain or persistent, LDS or scalar sources)
-and boundary mode, with device placement (lc_init_generate) against the oracle's own, for 10
+random precision, tiling (one-sided or pair-once, plain or persistent, LDS or scalar sources),
+boundary mode and (FP64) tunnelling field and collisional rate, with device placement (lc_init_generate) against the oracle's own, for 10
 steps with diagnostics every 2-5 steps.
 
 Bar: identical particle counts, charge arrays, ionization events and charge histograms
@@ -61,8 +61,12 @@ def _case(k):
         w32 = float(rng.uniform(0.5, 1.5))
         weights.append(w32 if precision != "fp64" else (1.0 if n_ion == 0 else None))
         z0s.append(z0)
+    # FP64 cases also draw the local-field tunnelling rate and the collisional rate (both sides
+    # take every ionization decision in FP64, so the events stay identical)
+    ofi = "local" if (precision == "fp64" and rng.random() < 0.3) else "laser_only"
+    collisional = bool(precision == "fp64" and rng.random() < 0.3)
     run = Run(dt=0.05, t0=float(rng.uniform(0.0, 60.0)), ionize=True, diag_every=int(rng.choice([2, 3, 5])),
-              seed=int(rng.integers(1000)), boundary=boundary)
+              seed=int(rng.integers(1000)), boundary=boundary, ofi_field=ofi, collisional=collisional)
     return precision, tiling, run, clusters, weights, z0s
 
 
@@ -72,13 +76,15 @@ def _case(k):
 def test_random_configuration_against_oracle(k):
     import paper_1307_3711_amd as lc
     precision, tiling, run, clusters, weights, z0s = _case(k)
-    print(f"case {k}: {precision} {tiling} {run.boundary} t0={run.t0:.1f} diag_every={run.diag_every} "
+    print(f"case {k}: {precision} {tiling} {run.boundary} {run.ofi_field} collisional={run.collisional} "
+          f"t0={run.t0:.1f} diag_every={run.diag_every} "
           f"clusters {[(c.species, c.n_ion, c.capacity, c.z_init, c.z_max) for c in clusters]}", flush=True)
     pair_once = tiling.get("newton3", 0) == 1
     mpb = lc.pair_blocks_for([c.capacity for c in clusters]) if pair_once else 0
     cfg = lc.make_config(precision, ionize=True, dt=run.dt, t0=run.t0, softening_nm=run.softening_nm,
                          diag_every=run.diag_every, max_records=16, max_splits=8, seed=run.seed,
-                         max_pair_blocks=mpb, boundary=run.boundary, box_r0=run.box_r0)
+                         max_pair_blocks=mpb, boundary=run.boundary, box_r0=run.box_r0, ofi_field=run.ofi_field,
+                         collisional=run.collisional)
     ds = descs(clusters)
     for d, w in zip(ds, weights):
         if w is not None:
@@ -123,6 +129,7 @@ def test_cases_cover_the_edges():
     assert {p for p, *_ in cases} == {"fp64", "fp32_acc64"}
     assert any(t.get("newton3") for _, t, *_ in cases) and any(not t.get("newton3") for _, t, *_ in cases)
     assert any(r.boundary == "periodic" for _, _, r, *_ in cases)
+    assert any(r.ofi_field == "local" for _, _, r, *_ in cases) and any(r.collisional for _, _, r, *_ in cases)
     cl = [c for *_, cs, _, _ in cases for c in cs]
     assert any(c.laser.polarization == "circular" for c in cl)
     assert {c.n_ion for c in cl} >= set(EDGE_IONS), sorted({c.n_ion for c in cl} & set(EDGE_IONS))
