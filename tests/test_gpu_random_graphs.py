@@ -71,6 +71,46 @@ def test_graph_groups_match_single_steps(k):
         assert c0["steps"] == min(steps, n_steps[i]), (i, c0)
 
 
+@pytest.mark.gpu
+@pytest.mark.skipif(not gpu_available(), reason="needs a GPU")
+@pytest.mark.parametrize("k", [1, 2, 5, 6, 9, 10])
+def test_checkpoint_mid_run_resumes_bitwise(k, tmp_path):
+    """Six of the random runs (both precisions, with and without ionization, every boundary
+    mode) with captured groups, saved part way (between groups or inside one, wherever the
+    split falls) and resumed in a fresh handle: identical to the unbroken run."""
+    import paper_1307_3711_amd as lc
+    precision, tiling, run, clusters, n_steps, steps, graph = _case(k)
+    split = steps // 2 + k
+    print(f"case {k}: {precision} ionize={run.ionize} {run.boundary}: save at step {split} of {steps}", flush=True)
+    states = [initial_state(c, run.seed, i) for i, c in enumerate(clusters)]
+    mpb = lc.pair_blocks_for([c.capacity for c in clusters]) if tiling.get("newton3") else 0
+
+    def make():
+        sim, _ = gpu_run(clusters, run, precision, states=states, max_records=64, n_steps_per_cluster=n_steps,
+                         tuning=tiling, max_pair_blocks=mpb)
+        sim.set_graph(graph)
+        return sim
+
+    ref = make()
+    ref.step(steps)
+    a = make()
+    a.step(split)
+    path = str(tmp_path / "ck.bin")
+    a.save(path)
+    a.close()
+    b = make()
+    b.load(path)
+    assert b.step_index == split
+    b.step(steps - split)
+    for i in range(len(clusters)):
+        p0, p1 = ref.particles(i), b.particles(i)
+        for key in ("x", "u", "Z", "wl", "wc"):
+            assert np.array_equal(p0[key], p1[key]), (i, key)
+        assert np.array_equal(ref.diagnostics(i), b.diagnostics(i)) and ref.counters(i) == b.counters(i), i
+    ref.close()
+    b.close()
+
+
 def test_graph_cases_cover_the_modes():
     cases = [_case(k) for k in range(12)]
     assert {c[0] for c in cases} == {"fp64", "fp32_acc64"}
