@@ -174,9 +174,10 @@ __global__ __launch_bounds__(64) void k_schedule_wave(DevState s, RunConst rc, i
 
 __global__ __launch_bounds__(kBlock) void k_schedule(DevState s, RunConst rc, int TI, int S, int n3,
                                                      int advance) {
-  __shared__ int32_t sh_scan[kBlock];
+  constexpr int kWaves = kBlock / 64;
+  __shared__ int32_t sh_wave[kWaves];
   __shared__ int32_t sh_carry;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t n = *s.step + advance;
   const double t = rc.t0 + (double)n * rc.dt;
   if (tid == 0) sh_carry = 0;
@@ -184,22 +185,22 @@ __global__ __launch_bounds__(kBlock) void k_schedule(DevState s, RunConst rc, in
   for (int base = 0; base < rc.n_clusters; base += kBlock) {
     const int p = base + tid;
     const int32_t tiles = (p < rc.n_clusters) ? schedule_cluster(s, p, TI, S, n3, advance, n, t) : 0;
-    sh_scan[tid] = tiles;
-    __syncthreads();
-    for (int o = 1; o < kBlock; o <<= 1) {  // Hillis-Steele inclusive scan
-      const int32_t v = (tid >= o) ? sh_scan[tid - o] : 0;
-      __syncthreads();
-      sh_scan[tid] += v;
-      __syncthreads();
+    int32_t v = tiles;
+    for (int o = 1; o < 64; o <<= 1) {  // inclusive scan across the wave's lanes
+      const int32_t u = __shfl_up(v, o, 64);
+      if (lane >= o) v += u;
     }
-    const int32_t carry = sh_carry;
+    if (lane == 63) sh_wave[wv] = v;
+    __syncthreads();
+    int32_t off = sh_carry;  // tiles of earlier passes and earlier waves of this pass
+    for (int q = 0; q < wv; ++q) off += sh_wave[q];
     if (p < rc.n_clusters) {
-      const int32_t excl = carry + sh_scan[tid] - tiles;
+      const int32_t excl = off + v - tiles;
       s.tile_start[p] = excl;
       s.dyn[s.order[p]].tile0 = excl;
     }
-    __syncthreads();
-    if (tid == kBlock - 1) sh_carry = carry + sh_scan[kBlock - 1];
+    __syncthreads();  // every wave has read sh_carry and sh_wave
+    if (tid == kBlock - 1) sh_carry = off + v;  // the last lane of the last wave: the pass total
     __syncthreads();
   }
   if (tid == 0) {
