@@ -185,11 +185,12 @@ def ensemble_inputs(n_clusters, seed, steps_scale=1.0, capacity_rule="random"):
     return cl, descs, states
 
 
-def ensemble_cpu_baseline(cl, states, r32, n_sample=8, steps=200):
+def ensemble_cpu_baseline(cl, states, r32, n_sample=8, steps=3000):
     """The FP64 oracle on a stratified sample of the ensemble (every len/n_sample-th cluster
-    by capacity, `steps` steps each): its cost per step is a N^2, so its pair rate on the
-    sample, applied to the pair count the GPU run evaluated, gives the oracle's time for the
-    whole run and its cluster-steps/s."""
+    by capacity, `steps` steps each, about 10-30 s of CPU work): its cost per step is a N^2,
+    so its pair rate on the sample (N^2 counted at the start of every step, as the GPU counts),
+    applied to the pair count the GPU run evaluated, gives the oracle's time for the whole run
+    and its cluster-steps/s."""
     import oracle
     from workloads import Run
     order = sorted(range(len(cl)), key=lambda i: cl[i].capacity)
@@ -200,9 +201,9 @@ def ensemble_cpu_baseline(cl, states, r32, n_sample=8, steps=200):
         osim = oracle.Sim.from_workload(cl[i], run, states[i], i)
         osim.start()
         t0 = time.perf_counter()
-        for _ in range(steps // 50):
-            pairs += 50.0 * float(osim.N) ** 2  # the count at the start of each stretch
-            osim.run(50)
+        for _ in range(steps):
+            pairs += float(osim.N) ** 2
+            osim.run(1)
         secs += time.perf_counter() - t0
     rate = pairs / secs
     cpu_wall = r32["pairs"] / rate
