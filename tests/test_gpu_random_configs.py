@@ -15,8 +15,6 @@ radians per step (dt = 0.05 in 1/w), and with tens of atoms per macroparticle th
 leap-frog's stability limit of 2, where the FP32 rounding of the pair differences (about 200 u
 of the bound pair's separation) grows by orders of magnitude within ten steps (the FP64 path's
 1e-16 grows too, but stays far below its bar)."""
-import dataclasses
-
 import numpy as np
 import pytest
 
@@ -133,4 +131,3 @@ def test_cases_cover_the_edges():
     cl = [c for *_, cs, _, _ in cases for c in cs]
     assert any(c.laser.polarization == "circular" for c in cl)
     assert {c.n_ion for c in cl} >= set(EDGE_IONS), sorted({c.n_ion for c in cl} & set(EDGE_IONS))
-    assert dataclasses.is_dataclass(cl[0])

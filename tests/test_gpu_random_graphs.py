@@ -4,8 +4,6 @@ is left out between steps of a group and the force launches do the step bookkeep
 cluster mixes with random retirement steps, precision, tiling, ionization, boundary mode
 (open, periodic, or periodic switching to open inside the run), diagnostic interval and group
 length.  Particles, diagnostic records and per-cluster counters must be identical."""
-import dataclasses
-
 import numpy as np
 import pytest
 
@@ -119,4 +117,3 @@ def test_graph_cases_cover_the_modes():
     assert any(c[1].get("newton3") for c in cases) and any(not c[1].get("newton3") for c in cases)
     # some cluster retires inside the run
     assert any(min(c[4]) < c[5] for c in cases)
-    assert dataclasses.is_dataclass(cases[0][2])
