@@ -808,8 +808,10 @@ def main():
     ap.add_argument("--clusters", type=int, default=256)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (ar20k: diagnostic periods of 100 MD steps, default 30; others: 1000)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps before them (ar20k: periods, default 5; others: 100)")
     ap.add_argument("--profile-steps", type=int, default=400)
     ap.add_argument("--graph", type=int, default=100)
     ap.add_argument("--no-fp64", action="store_true")
@@ -828,7 +830,14 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB buffer 3 times (HBM counter calibration for rocprofv3)")
     args = ap.parse_args()
-    args.steps_given = any(a.startswith("--steps") for a in sys.argv[1:])
+    args.steps_given = args.steps is not None
+    if args.steps is None:
+        args.steps = 30 if args.workload == "ar20k" else 1000
+    if args.warmup is None:
+        args.warmup = 5 if args.workload == "ar20k" else 100
+    if args.steps < 1 or args.warmup < 0:
+        print("bench.py: --steps must be at least 1 and --warmup at least 0", file=sys.stderr)
+        sys.exit(2)
     if args.copy_probe:
         import torch
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -878,42 +887,44 @@ def main():
     n = st["x_nm"].shape[0]
     pairs = float(n) * float(n)
 
-    # The timed window holds whole diagnostic periods (one record every diag_every steps, each
-    # step of a period replayed from one captured graph), starting on a period boundary: steps and
-    # warmup are rounded up to multiples of the period, so the work the workload prescribes,
-    # diagnostic passes included, is inside the window whatever counts are asked for.
+    # One benchmark step is one diagnostic period: diag_every MD steps (one captured graph
+    # replay) whose last one carries the diagnostic pass, so that the timed window of exactly
+    # --steps steps holds the work the workload prescribes, diagnostics included, starting on a
+    # period boundary after --warmup such steps.
     period = max(run.diag_every, 1)
-    warmup = -(-args.warmup // period) * period
-    steps = -(-args.steps // period) * period
+    warmup_md = args.warmup * period
+    steps_md = args.steps * period
     log(f"bench: {n} macroparticles, fp32_acc64, autotune")
     sim, tuned = make_sim("fp32_acc64", c, run, st, args.graph, tiling, args.boundary)
-    log(f"bench: tiling {tuned}; warmup {warmup}")
-    sim.step(warmup)
+    log(f"bench: tiling {tuned}; warmup {args.warmup} x {period} MD steps")
+    sim.step(warmup_md)
     sim.stream.synchronize()
-    log(f"bench: timing {steps} steps")
-    wall = timed_steps(sim, steps)
-    log(f"bench: {wall:.3f} s; profiling {args.profile_steps} steps")
+    log(f"bench: timing {args.steps} x {period} MD steps")
+    wall = timed_steps(sim, steps_md)
+    log(f"bench: {wall:.3f} s; profiling {args.profile_steps} MD steps")
     prof = sim.profile_steps(args.profile_steps)
     rec32 = sim.diagnostics(0)
     force_ms, force_n = prof["field"]
     avg_force_s = force_ms / max(force_n, 1) * 1e-3
     achieved = FLOPS_PER_PAIR * pairs / avg_force_s / 1e12
-    value = steps * pairs / wall / 1e9
+    value = steps_md * pairs / wall / 1e9
     crec = counter_record(tuned, n, "fp32_acc64", args.boundary)
     evals = pair_evaluations(n, tuned)
     kname = "k_force_n3" if tuned.get("newton3") else "k_force_f32"
     out = {
         "metric": "G pair-interactions/s (FP32 pair math + FP64 accumulation), one Ar cluster",
-        "value": round(value, 3), "unit": "Gpair/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
-        "steps_requested": args.steps, "warmup_requested": args.warmup,
-        "ms_per_step": round(wall / steps * 1e3, 5), "higher_is_better": True, "scaling": "weak",
+        "value": round(value, 3), "unit": "Gpair/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "fp32+fp64acc", "data": "synthetic",
         "config": {"workload": "Ar cluster R0=8nm, 20k macroparticles (10k Ar+ + 10k e-), 1e16 W/cm2, "
                                "30 fs Gaussian, dt=0.05, softening 0.1 nm, charges frozen"
                                + ("" if args.boundary == "open" else f", {args.boundary} boundaries (cube of 20 R0)"),
-                   "n_particles": n, "pairs_per_step": pairs, "tiling": tuned, "graph_steps": args.graph,
-                   "diagnostic_every": period},
-        "cluster_steps_per_s": round(steps / wall, 2),
+                   "n_particles": n, "pairs_per_md_step": pairs, "tiling": tuned, "graph_steps": args.graph,
+                   "diagnostic_every": period,
+                   "step": f"one diagnostic period: {period} MD steps of dt=0.05/w, the last with the diagnostic pass",
+                   "md_steps_per_step": period},
+        "ms_per_md_step": round(wall / steps_md * 1e3, 5),
+        "cluster_steps_per_s": round(steps_md / wall, 2),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                      "traffic": crec["traffic_bytes_per_launch"] if crec else None,
@@ -924,12 +935,12 @@ def main():
                                                / VALU_ISSUE_PER_S, 4) if crec else None)},
         "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 5) for k, v in prof.items() if v[1]},
     }
-    total_steps = warmup + steps + args.profile_steps
+    total_steps = warmup_md + steps_md + args.profile_steps
     if not args.no_fp64:
         log("bench: fp64 path on the same steps")
         sim64, tuned64 = make_sim("fp64", c, run, st, args.graph, tiling64, args.boundary)
-        sim64.step(warmup)
-        wall64 = timed_steps(sim64, steps)
+        sim64.step(warmup_md)
+        wall64 = timed_steps(sim64, steps_md)
         prof64 = sim64.profile_steps(args.profile_steps)
         rec64 = sim64.diagnostics(0)
         f64_ms, f64_n = prof64["field"]
@@ -944,8 +955,9 @@ def main():
         def rel(col):
             return float(abs(last32[col] - last64[col]) / max(abs(last64[col]), 1e-300))
 
-        out["fp64"] = {"value": round(steps * pairs / wall64 / 1e9, 3), "unit": "Gpair/s",
-                       "ms_per_step": round(wall64 / steps * 1e3, 5), "tiling": tuned64,
+        out["fp64"] = {"value": round(steps_md * pairs / wall64 / 1e9, 3), "unit": "Gpair/s",
+                       "ms_per_step": round(wall64 / args.steps * 1e3, 5),
+                       "ms_per_md_step": round(wall64 / steps_md * 1e3, 5), "tiling": tuned64,
                        "roofline": {"bound": "alu", "achieved": round(ach64, 3), "peak": FP64_PEAK_TFLOPS,
                                     "unit": "TFLOP/s", "frac": round(ach64 / FP64_PEAK_TFLOPS, 4),
                                     "traffic": crec64["traffic_bytes_per_launch"] if crec64 else None,
@@ -957,6 +969,7 @@ def main():
                                                               / VALU_ISSUE_PER_S, 4) if crec64 else None)}}
         out["error_vs_fp64"] = {"after_steps": total_steps, "t": float(last64[0]),
                                 "max_dx_over_R0": float(np.max(np.abs(p32["x"] - p64["x"])) / r0n),
+                                "median_dx_over_R0": float(np.median(np.linalg.norm(p32["x"] - p64["x"], axis=1)) / r0n),
                                 "rel_KE": rel(lc.R_KE_HALF), "rel_PE": rel(lc.R_PE),
                                 "rel_absorbed_eV_per_atom": rel(lc.R_ABS_EV)}
         # both runs to the workload's end (4000 steps), record by record against the FP64
