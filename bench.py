@@ -785,6 +785,21 @@ def bench_surrogate(args):
     print(json.dumps(out), flush=True)
 
 
+PROFILE_STEPS = 400  # MD steps whose dispatches record their own events, after the timed window
+
+
+def default_counts(workload, steps, warmup):
+    """Timed and warmup steps when not given: for the Ar 20k workload a step is one diagnostic
+    period, and 5 + 30 periods plus the profiled steps stay inside the workload's 4000 MD steps,
+    so the default run also reaches the comparison with the oracle's records; other workloads
+    count their own steps."""
+    if steps is None:
+        steps = 30 if workload == "ar20k" else 1000
+    if warmup is None:
+        warmup = 5 if workload == "ar20k" else 100
+    return steps, warmup
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--batches", type=int, default=16, help="surrogate: 256-cluster ensembles of training data")
@@ -812,7 +827,7 @@ def main():
                     help="timed steps (ar20k: diagnostic periods of 100 MD steps, default 30; others: 1000)")
     ap.add_argument("--warmup", type=int, default=None,
                     help="untimed steps before them (ar20k: periods, default 5; others: 100)")
-    ap.add_argument("--profile-steps", type=int, default=400)
+    ap.add_argument("--profile-steps", type=int, default=PROFILE_STEPS)
     ap.add_argument("--graph", type=int, default=100)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -831,10 +846,7 @@ def main():
                     help="only copy a 1 GiB buffer 3 times (HBM counter calibration for rocprofv3)")
     args = ap.parse_args()
     args.steps_given = args.steps is not None
-    if args.steps is None:
-        args.steps = 30 if args.workload == "ar20k" else 1000
-    if args.warmup is None:
-        args.warmup = 5 if args.workload == "ar20k" else 100
+    args.steps, args.warmup = default_counts(args.workload, args.steps, args.warmup)
     if args.steps < 1 or args.warmup < 0:
         print("bench.py: --steps must be at least 1 and --warmup at least 0", file=sys.stderr)
         sys.exit(2)

@@ -87,3 +87,22 @@ def test_pair_evaluations(n):
     assert bench.pair_evaluations(n, {"newton3": 1, "R": 4, "WJ": 4}) == float(cross + inside)
     if n == 20000:
         assert bench.pair_evaluations(n, {"newton3": 1, "R": 4, "WJ": 4}) == 202556416.0
+
+
+def test_step_counts_are_checked_before_any_gpu_work():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "0"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "--steps" in r.stderr and not r.stdout.strip()
+
+
+def test_default_ar20k_run_reaches_the_oracle_records():
+    """A step of the Ar 20k benchmark is one diagnostic period; the default warmup, timed and
+    profiled steps must end inside the workload's MD steps, where the runs continue to the
+    workload's end against the oracle's records."""
+    from workloads import ar_20k
+    c, run = ar_20k()
+    steps, warmup = bench.default_counts("ar20k", None, None)
+    assert (steps + warmup) * run.diag_every + bench.PROFILE_STEPS <= c.n_steps
+    assert bench.default_counts("ar20k", 20, 5) == (20, 5)
+    assert bench.default_counts("ensemble", None, None) == (1000, 100)
