@@ -311,7 +311,15 @@ inline int fold_waves(const RunConst& rc, int B) {
   return fw;
 }
 
-template <typename Tr>
+// The FP64 sum of slot g's pair-once rows m = w, w + ways, ... (the share of wave w of
+// `ways`), in row order.  RPR > 0: rounds of RPR rows whose loads are all issued before the
+// first add (the row bound is wave-uniform); RPR = 0: rounds of four rows, then single rows.
+// Measured on the 20k cluster (79 rows, 8 waves per 64 slots, fold and push together): 1 row
+// per round 11.1 us, 2 rows 10.2 us, 3 rows 10.4 us, RPR = 0 10.7 us, 5 rows 10.9 us, 10 rows
+// 11.0 us (fewer loads in flight per wave are faster, down to two); 2 rows with 16 waves
+// 12.4 us.  On the 256-cluster ensemble (2 waves per 64 slots, about 33 rows) RPR = 0 runs
+// 0.15 % faster over the whole run than four-row rounds with the last one predicated.
+template <typename Tr, int RPR = 0>
 __device__ inline void n3_row_partial(const DevState& s, const RunConst& rc, int B, int64_t g, int c, int w,
                                       int ways, double& e0, double& e1, double& e2) {
   e0 = 0.0; e1 = 0.0; e2 = 0.0;
@@ -322,21 +330,43 @@ __device__ inline void n3_row_partial(const DevState& s, const RunConst& rc, int
   const int64_t nb = (d.n_sched + B - 1) / B;
   const Tr* r = (const Tr*)s.n3part + cp.n3_off + (K * rc.n3_rows + w) * 3 * (int64_t)B + (l - K * B);
   const int64_t step = (int64_t)ways * 3 * B;
-  // four rows per round keep twelve loads in flight per lane; the sums stay in row order
-  int64_t m = w;
-  for (; m + 3 * ways < nb; m += 4 * ways, r += 4 * step) {
-    const double a0 = (double)r[0], a1 = (double)r[B], a2 = (double)r[2 * B];
-    const double b0 = (double)r[step], b1 = (double)r[step + B], b2 = (double)r[step + 2 * B];
-    const double c0 = (double)r[2 * step], c1 = (double)r[2 * step + B], c2 = (double)r[2 * step + 2 * B];
-    const double d0 = (double)r[3 * step], d1 = (double)r[3 * step + B], d2 = (double)r[3 * step + 2 * B];
-    e0 += a0; e0 += b0; e0 += c0; e0 += d0;
-    e1 += a1; e1 += b1; e1 += c1; e1 += d1;
-    e2 += a2; e2 += b2; e2 += c2; e2 += d2;
-  }
-  for (; m < nb; m += ways, r += step) {
-    e0 += (double)r[0];
-    e1 += (double)r[B];
-    e2 += (double)r[2 * B];
+  if constexpr (RPR == 0) {
+    // four-row rounds, then the rows left one at a time
+    int64_t m = w;
+    for (; m + 3 * ways < nb; m += 4 * ways, r += 4 * step) {
+      const double a0 = (double)r[0], a1 = (double)r[B], a2 = (double)r[2 * B];
+      const double b0 = (double)r[step], b1 = (double)r[step + B], b2 = (double)r[step + 2 * B];
+      const double c0 = (double)r[2 * step], c1 = (double)r[2 * step + B], c2 = (double)r[2 * step + 2 * B];
+      const double d0 = (double)r[3 * step], d1 = (double)r[3 * step + B], d2 = (double)r[3 * step + 2 * B];
+      e0 += a0; e0 += b0; e0 += c0; e0 += d0;
+      e1 += a1; e1 += b1; e1 += c1; e1 += d1;
+      e2 += a2; e2 += b2; e2 += c2; e2 += d2;
+    }
+    for (; m < nb; m += ways, r += step) {
+      e0 += (double)r[0];
+      e1 += (double)r[B];
+      e2 += (double)r[2 * B];
+    }
+  } else {
+    for (int64_t m = w; m < nb; m += RPR * ways, r += RPR * step) {
+      Tr a0[RPR], a1[RPR], a2[RPR];
+#pragma unroll
+      for (int i = 0; i < RPR; ++i) {
+        if (m + (int64_t)i * ways < nb) {
+          a0[i] = r[i * step];
+          a1[i] = r[i * step + B];
+          a2[i] = r[i * step + 2 * B];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < RPR; ++i) {
+        if (m + (int64_t)i * ways < nb) {
+          e0 += (double)a0[i];
+          e1 += (double)a1[i];
+          e2 += (double)a2[i];
+        }
+      }
+    }
   }
 }
 

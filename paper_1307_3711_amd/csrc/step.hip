@@ -380,8 +380,10 @@ __global__ __launch_bounds__(64 * FW) void k_fold_push(DevState s, RunConst rc, 
   PState ps;
   if (live) {
     if (w == 0) ps = load_pstate(v, rc, lane);
-    if (PREC == LC_FP64) n3_row_partial<double>(s, rc, B, g0 + lane, c, w, FW, e0, e1, e2);
-    else n3_row_partial<float>(s, rc, B, g0 + lane, c, w, FW, e0, e1, e2);
+    // rounds of two rows with 8 waves (many rows per slot), else four-row rounds and single rows
+    constexpr int RPR = FW >= 8 ? 2 : 0;
+    if (PREC == LC_FP64) n3_row_partial<double, RPR>(s, rc, B, g0 + lane, c, w, FW, e0, e1, e2);
+    else n3_row_partial<float, RPR>(s, rc, B, g0 + lane, c, w, FW, e0, e1, e2);
   }
   if (w > 0) {
     red[w - 1][0][lane] = e0;
