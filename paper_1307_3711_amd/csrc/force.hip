@@ -527,7 +527,9 @@ __device__ inline void decode_pair_tile(const TileMap& m, int t, int& c, int& I,
   c = m.order[lo];
   const int64_t local = t - m.tile_start[lo];
   // tiles of a cluster in J-major order: local = J (J + 1) / 2 + I, 0 <= I <= J
-  int64_t j = (int64_t)((sqrt(8.0 * (double)local + 1.0) - 1.0) * 0.5);
+  // first guess from a single-precision square root (one VALU instruction rather than the
+  // double-precision sequence); the two loops below make j exact
+  int64_t j = (int64_t)((sqrtf(8.0f * (float)local + 1.0f) - 1.0f) * 0.5f);
   while (j * (j + 1) / 2 > local) --j;
   while ((j + 1) * (j + 2) / 2 <= local) ++j;
   J = (int)j;
@@ -673,21 +675,31 @@ __device__ void tile_n3(const N3Args<T>& a, int t, T* lds) {
   const T qT = tvalid ? src[i0].w : T(0);
   T xi[R], yi[R], zi[R], qi[R];
   int same_t = 1;
+  if (i0 + TGT <= n) {
+    // every target of the wave is a live slot: no padding
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int64_t ii = i0 + r * 64 + lane;
-    if (ii < n) {
-      const V4 p = src[ii];
+    for (int r = 0; r < R; ++r) {
+      const V4 p = src[i0 + r * 64 + lane];
       xi[r] = p.x; yi[r] = p.y; zi[r] = p.z; qi[r] = p.w;
       same_t &= (p.w == qT);
-    } else if (PBC) {
-      // the minimum image would bring a far entry close: zero charge at the origin instead
-      xi[r] = yi[r] = zi[r] = 0;
-      qi[r] = 0;
-    } else {
-      // far away: both sides add exactly zero (see N3Type)
-      xi[r] = yi[r] = zi[r] = kFar;
-      qi[r] = qT;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t ii = i0 + r * 64 + lane;
+      if (ii < n) {
+        const V4 p = src[ii];
+        xi[r] = p.x; yi[r] = p.y; zi[r] = p.z; qi[r] = p.w;
+        same_t &= (p.w == qT);
+      } else if (PBC) {
+        // the minimum image would bring a far entry close: zero charge at the origin instead
+        xi[r] = yi[r] = zi[r] = 0;
+        qi[r] = 0;
+      } else {
+        // far away: both sides add exactly zero (see N3Type)
+        xi[r] = yi[r] = zi[r] = kFar;
+        qi[r] = qT;
+      }
     }
   }
   // periodic boundaries: the padding carries charge 0, so the target charge is factored out
@@ -705,12 +717,19 @@ __device__ void tile_n3(const N3Args<T>& a, int t, T* lds) {
       const int64_t jb = (int64_t)J * B + jw * PW + ch * 64;
       if (jb >= n) break;
       const int64_t jj = jb + lane;
-      V4 sv;
-      if (jj < n) sv = src[jj];
-      else if (PBC) { sv.x = 0; sv.y = 0; sv.z = 0; sv.w = 0; }
-      else { sv.x = kFar; sv.y = kFar; sv.z = kFar; sv.w = 0; }
       const T qs0 = src[jb].w;
-      const bool us = PBC ? __all(jj < n && sv.w == qs0) : __all(jj >= n || sv.w == qs0);
+      V4 sv;
+      bool us;
+      if (jb + 64 <= n) {
+        // a chunk of live sources only
+        sv = src[jj];
+        us = __all(sv.w == qs0);
+      } else {
+        if (jj < n) sv = src[jj];
+        else if (PBC) { sv.x = 0; sv.y = 0; sv.z = 0; sv.w = 0; }
+        else { sv.x = kFar; sv.y = kFar; sv.z = kFar; sv.w = 0; }
+        us = PBC ? __all(jj < n && sv.w == qs0) : __all(jj >= n || sv.w == qs0);
+      }
       sb[lane] = sv.x;
       sb[lane + 64] = sv.x;
       sb[kN3Slice + lane] = sv.y;
