@@ -1204,13 +1204,15 @@ int64_t n3_tiles(int64_t n, int B) {
 }
 
 // The one-sided tiling a pair-once tiling's diagnostic steps run with: its own fields when
-// the one-sided kernels have that (R, WJ), else R = 1 (FP32) or 2 (FP64), WJ = 4.
+// the one-sided kernels have that (R, WJ), else R = 1 (FP32) or 2 (FP64), WJ = 4.  With
+// scalar sources (FP32) it is R = 1, WJ = 4, the fastest scalar-source form (on the 20k Ar
+// cluster the one-sided field pass takes 127 us there against 148 us at R = 4, WJ = 4).
 ForceTiling regular_tiling(int precision, const ForceTiling& ft) {
   ForceTiling r = ft;
   r.newton3 = 0;
   const bool wj_ok = ft.WJ == 1 || ft.WJ == 2 || ft.WJ == 4;
   const bool r_ok = ft.R == 1 || ft.R == 2 || ft.R == 4 || (ft.R == 8 && precision != LC_FP64 && ft.WJ == 1);
-  if (!(wj_ok && r_ok)) {
+  if (!(wj_ok && r_ok) || (ft.scalar_src && precision != LC_FP64)) {
     r.R = (precision == LC_FP64) ? 2 : 1;
     r.WJ = 4;
   }
