@@ -299,12 +299,14 @@ __device__ inline DevState group_view(const DevState& s, int64_t g0) {
 constexpr int kFoldWaves = 8;
 
 // Waves per 64 slots of the fused fold and push.  A slot has one row per block of its cluster:
-// with many rows (48 and up for a typical slot) 8 waves keep enough loads in flight; with few,
-// most of 8 waves would idle, so the count is the smallest of 2, 4, 8 that still launches
-// about 4096 waves (4 per SIMD).  Measured: 20k-slot cluster (79 rows) 8 waves; 256-cluster
-// ensemble of 1.4M slots (about 33 rows) 2 waves, 8 % faster than 8.
-inline int fold_waves(const RunConst& rc, int B) {
-  if (rc.cap_slot_mean >= 48.0 * (double)B) return 8;
+// with many rows (48 and up for a typical slot) 8 waves keep enough loads in flight (4 for FP64
+// rows); with few, most of 8 waves would idle, so the count is the smallest of 2, 4, 8 that
+// still launches about 4096 waves (4 per SIMD).  Measured: 20k-slot cluster (79 rows) 8 waves
+// (FP32 rows; 4 waves 11.5 against 10.2 us); 256-cluster ensemble of 1.4M slots (about 33 rows)
+// 2 waves, 8 % faster than 8.
+inline bool fold_many_rows(const RunConst& rc, int B) { return rc.cap_slot_mean >= 48.0 * (double)B; }
+inline int fold_waves(const RunConst& rc, int B, int precision) {
+  if (fold_many_rows(rc, B)) return precision == LC_FP64 ? 4 : 8;
   const int64_t groups = (rc.n_total + 63) / 64;
   int fw = 2;
   while (fw < 8 && groups * fw < 4096) fw *= 2;

@@ -364,7 +364,7 @@ void k_push(DevState s, RunConst rc, FieldLayout fl, int64_t k, int diag) {
 // their share of the rows, wave 0 combines them in order, keeps the field in split 0 (read by
 // the ionization check) and pushes.  Wave 0 loads the particle state before its rows so both
 // latencies overlap.  The group's cluster is uniform over the block (scalar loads).
-template <int PREC, int FW>
+template <int PREC, int FW, int RPR>
 __global__ __launch_bounds__(64 * FW) void k_fold_push(DevState s, RunConst rc, int B, int64_t k, int diag) {
   __shared__ double red[FW - 1][3][64];
   const uint32_t lane = threadIdx.x & 63;
@@ -380,8 +380,6 @@ __global__ __launch_bounds__(64 * FW) void k_fold_push(DevState s, RunConst rc, 
   PState ps;
   if (live) {
     if (w == 0) ps = load_pstate(v, rc, lane);
-    // rounds of two rows with 8 waves (many rows per slot), else four-row rounds and single rows
-    constexpr int RPR = FW >= 8 ? 2 : 0;
     if (PREC == LC_FP64) n3_row_partial<double, RPR>(s, rc, B, g0 + lane, c, w, FW, e0, e1, e2);
     else n3_row_partial<float, RPR>(s, rc, B, g0 + lane, c, w, FW, e0, e1, e2);
   }
@@ -990,15 +988,18 @@ hipError_t launch_push(const DevState& s, const RunConst& rc, int precision, con
 template <int PREC>
 void fold_push_waves(int fw, int blocks, const DevState& s, const RunConst& rc, int B, int64_t k, int diag,
                      hipStream_t st) {
-  if (fw <= 2) k_fold_push<PREC, 2><<<blocks, 128, 0, st>>>(s, rc, B, k, diag);
-  else if (fw <= 4) k_fold_push<PREC, 4><<<blocks, 256, 0, st>>>(s, rc, B, k, diag);
-  else k_fold_push<PREC, 8><<<blocks, 512, 0, st>>>(s, rc, B, k, diag);
+  // rounds of two rows where slots have many rows (fold_many_rows), else four-row rounds and
+  // single rows
+  if (fw <= 2) k_fold_push<PREC, 2, 0><<<blocks, 128, 0, st>>>(s, rc, B, k, diag);
+  else if (fw <= 4 && fold_many_rows(rc, B)) k_fold_push<PREC, 4, 2><<<blocks, 256, 0, st>>>(s, rc, B, k, diag);
+  else if (fw <= 4) k_fold_push<PREC, 4, 0><<<blocks, 256, 0, st>>>(s, rc, B, k, diag);
+  else k_fold_push<PREC, 8, 2><<<blocks, 512, 0, st>>>(s, rc, B, k, diag);
 }
 
 hipError_t launch_fold_push(const DevState& s, const RunConst& rc, int precision, int B, int64_t k, bool diag,
                             hipStream_t st) {
   const int blocks = (int)((rc.n_total + 63) / 64);
-  const int fw = fold_waves(rc, B);
+  const int fw = fold_waves(rc, B, precision);
   if (precision == LC_FP64) fold_push_waves<LC_FP64>(fw, blocks, s, rc, B, k, diag ? 1 : 0, st);
   else fold_push_waves<LC_FP32_ACC64>(fw, blocks, s, rc, B, k, diag ? 1 : 0, st);
   return hipGetLastError();
